@@ -1,0 +1,171 @@
+/*
+ * ap.h - C ABI of the MI355X (gfx950) library for the conservative adaptive-precision EAM/ACE
+ * energy and force evaluation of Immel, Drautz and Sutmann, "Conservative adaptive-precision
+ * interatomic potentials" (arXiv 2512.07693).
+ *
+ * What one evaluation computes (paper's notation):
+ *   E_i   = lambda_i E^f_i + (1 - lambda_i) E^p_i                               Eq. (4)
+ *   lambda_i = f_trans(d_i, d_lo, d_hi)                                          Eq. (2), (S1)
+ *   d_i   = sum_k g_k w(r_ik) / wbar_i - d0,  wbar_i = sum_k w(r_ik)              Eq. (6)
+ *   g_i   = CSP_i^list (pairs fixed at set-up)                                   (B3)
+ *   E^f   = EAM (B1) on every atom; E^p = ACE on the atoms with lambda_i < 1
+ *   F_i   = -grad_i sum_k E_k, assembled in the pair form (A1)-(A2) with the EAM,
+ *           ACE and grad-lambda contributions (S12), (S14), (S21), (S27)-(S29).
+ *
+ * Conventions (all entry points):
+ *   - Metal units: Angstrom, eV, ps, atomic mass units.
+ *   - Per-step arrays (positions, velocities, forces, per-atom outputs) are DEVICE pointers
+ *     owned by the caller. Positions, velocities and forces are FP64 structure-of-arrays
+ *     [3][n]: the x block, then the y block, then the z block. Per-atom arrays are [n].
+ *   - Atom order is the caller's; atom index = the unique identifier the CSP list refers to.
+ *   - Potential parameters (ap_*_params) are HOST structures with HOST arrays; they are copied
+ *     into library-owned device tables by ap_set_potential.
+ *   - Outputs are overwritten, never accumulated. Output pointers documented "optional" may be
+ *     NULL.
+ *   - Each call enqueues its kernels on the context's HIP stream and synchronises that stream
+ *     before returning, so that device-side error flags (neighbour overflow, non-finite values)
+ *     are reported in the return code. The library never allocates memory visible to the caller;
+ *     it owns only scratch (cell lists, neighbour lists, per-atom intermediates, ACE buffers).
+ *   - Return codes: AP_OK (0) or a negative AP_E_* code; ap_last_error() then gives the text.
+ *     No C++ exception crosses the ABI.
+ *   - A context is not thread safe: calls on one context must not overlap.
+ */
+#ifndef AP_H
+#define AP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AP_OK 0
+#define AP_E_ARG -1          /* null pointer, size out of range, unsupported option          */
+#define AP_E_BOX -2          /* a cutoff (+ skin) >= half the box, or < 3 cells per dimension */
+#define AP_E_NBR_OVERFLOW -3 /* an atom has more neighbours than max_nbr                      */
+#define AP_E_NONFINITE -4    /* non-finite energy or force, or non-positive embedding density */
+#define AP_E_HIP -5          /* a HIP runtime call failed                                     */
+#define AP_E_CSP -6          /* n_csp not 8 or 12, list entry out of range, too few neighbours */
+#define AP_E_STATE -7        /* call order: potential or CSP list not set                     */
+
+#define AP_FP64 0
+#define AP_FP32 1
+
+#define AP_LAMBDA_COMPUTED -1 /* lambda from the descriptor, Eq. (2)                    */
+#define AP_LAMBDA_PRECISE 0   /* lambda == 0 everywhere: pure ACE (paper orientation)    */
+#define AP_LAMBDA_FAST 1      /* lambda == 1 everywhere: pure EAM                         */
+
+#define AP_IND_CSP 0 /* g = CSP^list of (B3)                                                  */
+#define AP_IND_MLP 1 /* g = learned indicator (ap_set_indicator_mlp); the CSP list still drives
+                        nothing else                                                          */
+
+/* Orthorhombic periodic box with its origin at 0. */
+typedef struct {
+    double L[3];
+} ap_box;
+
+/* Finnis-Sinclair EAM, (B1): zeta(r) = (r-rc)^2 + beta (r-rc)^3 / rc, Phi(r) = (r-rc)^2
+ * (c0 + c1 r + c2 r^2), both zero for r >= rc; embedding xi(z) = -A sqrt(z). */
+typedef struct {
+    double A, beta, c0, c1, c2, rc;
+} ap_eam_params;
+
+/* ACE (the paper cites the definition; the concrete form is):
+ *   radial channels g_n(r) = T_n(2r/rc - 1) (1 + cos(pi r / rc)) / 2, n < n_max
+ *   atomic basis A_{n l m} = sum_{j: r_ij < rc} g_n(r_ij) Y_l^m(rhat_ij), l <= l_max
+ *   product basis: order 1 A_{n00}; order 2 sum_m (-1)^m A_{n1 l m} A_{n2 l -m};
+ *                  order 3 sum (l1 l2 l3; m1 m2 m3) A_{n1 l1 m1} A_{n2 l2 m2} A_{n3 l3 m3}
+ *   site energy E^p_i = E0 + sum_nu c_nu B_i,nu - emb_A sqrt(phi2_i),
+ *               phi2_i = sum_n b_dens[n] sqrt(4 pi) A_{i,n00}   (no embedding if phi2 <= 0)
+ * func: [n_funcs][6] int32 rows (n1,l1,n2,l2,n3,l3), -1 in unused slots; order-2 rows have
+ * l1 == l2, order-3 rows satisfy the triangle rule with an even l1+l2+l3.
+ * Supported (n_max, l_max): (4,2), (8,4), (12,6). precision: AP_FP64 or AP_FP32 (basis and
+ * product arithmetic in FP32; geometry, energy sums and forces in FP64). */
+typedef struct {
+    int n_max, l_max, n_funcs;
+    double rc;
+    const int32_t *func;
+    const double *c;
+    const double *b_dens;
+    double emb_A, E0;
+    int precision;
+} ap_ace_params;
+
+/* Switching, Eq. (2), (6) and the weighting function of App. B:
+ * w(r) = f_trans(r, r_w - 1 A, r_w); the sums of Eq. (6) include k = i (w(0) = 1).
+ * lambda_mode: AP_LAMBDA_COMPUTED / _PRECISE / _FAST. grad_lambda: 1 conservative forces;
+ * 0 drops the grad-lambda contributions (the non-conservative "AP without grad lambda" force). */
+typedef struct {
+    double d_lo, d_hi, r_w, d0;
+    int n_csp;
+    int lambda_mode;
+    int indicator;
+    int grad_lambda;
+} ap_switch_params;
+
+typedef struct ap_ctx ap_ctx;
+
+/* Create a context for up to n_max_atoms atoms and max_nbr neighbours per atom within the list
+ * radius max(rc_eam, rc_ace, r_w) + skin. hip_stream: a hipStream_t (NULL = default stream).
+ * Returns AP_OK and *out, or an error (then *out = NULL). */
+int ap_ctx_create(ap_ctx **out, int n_max_atoms, int max_nbr, double skin, void *hip_stream);
+void ap_ctx_destroy(ap_ctx *ctx);
+/* Text of the last error on ctx (or of the last failed ap_ctx_create when ctx is NULL). */
+const char *ap_last_error(const ap_ctx *ctx);
+
+/* Copy the potentials and switching parameters into device tables (the coupling tables of the
+ * real-harmonic ACE form are derived here). Must precede every evaluation. */
+int ap_set_potential(ap_ctx *ctx, const ap_eam_params *eam, const ap_ace_params *ace, const ap_switch_params *sw);
+
+/* One-time detection of the CSP opposite-neighbour pairs, (B3): for every atom the n_csp
+ * nearest neighbours by (|u|^2, index) are paired greedily by the smallest |u_a + u_b|^2 (ties:
+ * smaller lower index, then smaller higher index); pairs are written in choice order with the
+ * lower index first, so entries 2p and 2p+1 are opposite partners.
+ * pos_ref: device [3][n], the initial structure. csp_list: device [n][n_csp] int32 output.
+ * The list is also installed in ctx (as by ap_set_csp_list). */
+int ap_csp_pairs_build(ap_ctx *ctx, int n, const double *pos_ref, const ap_box *box, int n_csp, int32_t *csp_list);
+
+/* Install a CSP pair list (device [n][n_csp], same layout) and build its reverse list. */
+int ap_set_csp_list(ap_ctx *ctx, int n, int n_csp, const int32_t *csp_list);
+
+/* Neighbour sets at radius r_list (strict |u|^2 < r_list^2, minimum image, positions wrapped
+ * into the box first): nbr_count device [n]; nbr_idx device [max_nbr][n] (slot-major: the k-th
+ * neighbour of atom i is nbr_idx[k * n + i]); order within a set is unspecified but fixed. */
+int ap_nblist_build(ap_ctx *ctx, int n, const double *pos, const ap_box *box, double r_list, int max_nbr,
+                    int32_t *nbr_count, int32_t *nbr_idx);
+
+/* EAM, (B1) and (S12): E_atom[i] = E^EAM_i, F = sum_k (lambda_i f_ki - lambda_k f_ik) with
+ * lambda = the device array lambda [n] (NULL: lambda == 1, i.e. the plain EAM force (S13)).
+ * E_tot: device [1]; virial9: device [9] row-major W_ab = -sum_e (dE/du_e)_a (u_e)_b over the
+ * relative vectors u_e the energy depends on. All outputs optional. */
+int ap_eam_eval(ap_ctx *ctx, int n, const double *pos, const int32_t *species, const ap_box *box,
+                const double *lambda, double *E_tot, double *E_atom, double *F, double *virial9);
+
+/* Switching quantities, (B3), Eq. (6), Eq. (2): g, d, wbar, lambda, dlambda/dd (device [n],
+ * each optional) and n_precise = |{i : lambda_i < 1}| (device [1], optional). */
+int ap_switch_eval(ap_ctx *ctx, int n, const double *pos, const ap_box *box, double *g, double *d, double *wbar,
+                   double *lambda, double *dlambda, int32_t *n_precise);
+
+/* ACE site energies E^p_i and the pure-ACE force F = sum_k (f_ki - f_ik) (S13 with ACE pair
+ * contributions) on the atoms listed in subset (device [n_subset], NULL = all atoms); atoms not
+ * in the subset contribute no energy. E_atom [n], F [3][n], virial9 [9], E_tot [1]: optional. */
+int ap_ace_eval(ap_ctx *ctx, int n, const double *pos, const int32_t *species, const ap_box *box,
+                const int32_t *subset, int n_subset, double *E_tot, double *E_atom, double *F, double *virial9);
+
+/* The adaptive-precision evaluation: Eq. (4) energies and the conservative force Eq. (5).
+ * E_tot [1], E_atom [n], F [3][n], virial9 [9], lambda_out [n]: device, each optional. */
+int ap_mixed_energy_forces(ap_ctx *ctx, int n, const double *pos, const int32_t *species, const ap_box *box,
+                           double *E_tot, double *E_atom, double *F, double *virial9, double *lambda_out);
+
+/* n_steps of velocity Verlet (NVE, FP64) with the adaptive-precision forces:
+ * v += dt/2 F/m; x += dt v (wrapped); F = F(x); v += dt/2 F/m.  F must hold F(x) on entry (from
+ * ap_mixed_energy_forces) and holds F(x) on exit. mass: atomic mass (u) of the single species.
+ * thermo: device [n_steps][8] rows {E_pot, E_kin, E_tot, P_x, P_y, P_z, n_precise, rebuilt}.
+ * The neighbour list is rebuilt only when an atom moved more than skin/2 since the last build. */
+int ap_vv_step(ap_ctx *ctx, int n, double *pos, double *vel, double *F, double mass, double dt, int n_steps,
+               const ap_box *box, double *thermo);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

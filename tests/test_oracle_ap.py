@@ -1,0 +1,130 @@
+"""Pins of the oracle's adaptive-precision energy and forces: Eq. (4), Eq. (5), (A1)-(A2), (S5)-(S29)."""
+import numpy as np
+import pytest
+
+from tests.helpers import small_system
+
+
+@pytest.fixture(scope="module")
+def sysd(oracle):
+    s = small_system(nc=4, sigma=0.12)
+    s["csp"] = oracle.csp_pairs(s["pos_ref"], s["box"], 8)
+    return s
+
+
+def test_transition_region_is_populated(oracle, sysd):
+    lam = oracle.evaluate(sysd)["aux"]["lam"]
+    assert ((lam > 0) & (lam < 1)).sum() >= 20
+
+
+def test_forces_are_minus_energy_gradient(oracle, sysd):
+    """Central differences of E_AP (h = 1e-5 A) against the pair-form force of (S5)-(S29)."""
+    r = oracle.evaluate(sysd, skip=0)
+    h = 1e-5
+    for i in (0, 9, 40, 101):
+        for a in range(3):
+            p1, p2 = sysd["pos"].copy(), sysd["pos"].copy()
+            p1[i, a] += h
+            p2[i, a] -= h
+            fd = -(oracle.evaluate(sysd, pos=p1)["E"] - oracle.evaluate(sysd, pos=p2)["E"]) / (2 * h)
+            assert r["F"][i, a] == pytest.approx(fd, abs=3e-7 * max(1.0, abs(fd)))
+
+
+def test_each_force_family_sums_to_zero(oracle, sysd):
+    """Antisymmetry of the pair form (A1): the EAM-weighted, ACE-weighted, grad-w and grad-CSP families
+    each have zero net force, so total momentum is conserved."""
+    fam = oracle.evaluate(sysd)["fam"]
+    scale = np.abs(fam).max()
+    assert scale > 0
+    for f in fam:
+        assert np.abs(f.sum(0)).max() < 1e-12 * scale * len(f)
+
+
+def test_limits_reproduce_pure_models_bitwise(oracle, sysd):
+    """Eq. (4) with lambda == 1 is the EAM, with lambda == 0 the ACE, bit for bit."""
+    eam = oracle.evaluate(sysd, lam_mode=1)
+    ace = oracle.evaluate(sysd, lam_mode=0)
+    full = oracle.evaluate(sysd, skip=0)
+    assert np.array_equal(eam["E_atom"], full["aux"]["Ef"])
+    assert np.array_equal(ace["E_atom"], full["aux"]["Ep"])
+    assert np.abs(eam["fam"][1:]).max() == 0 and np.abs(ace["fam"][0]).max() == 0
+
+
+def test_skip_mode_is_bit_identical(oracle, sysd):
+    s = dict(sysd, sw=dict(sysd["sw"], d_lo=1.0, d_hi=1.4))  # some atoms at lambda == 1
+    a, b = oracle.evaluate(s, skip=0), oracle.evaluate(s, skip=1)
+    assert (a["aux"]["lam"] == 1.0).sum() > 5
+    assert np.array_equal(a["F"], b["F"]) and a["E"] == b["E"] and np.array_equal(a["virial"], b["virial"])
+
+
+def test_without_grad_lambda_is_force_minus_grad_lambda_part(oracle, sysd):
+    r = oracle.evaluate(sysd)
+    w = oracle.evaluate(sysd, no_gradlam=1)
+    assert np.allclose(w["F"], r["F"] - r["fam"][2] - r["fam"][3], rtol=0, atol=1e-12)
+    assert np.abs(r["fam"][2]).max() > 0 and np.abs(r["fam"][3]).max() > 0
+
+
+def test_translation_and_cubic_symmetry(oracle, sysd):
+    r = oracle.evaluate(sysd)
+    t = oracle.evaluate(sysd, pos=sysd["pos"] + np.array([1.3, -0.7, 2.9]))
+    assert t["E"] == pytest.approx(r["E"], rel=1e-12)
+    assert np.allclose(t["F"], r["F"], atol=1e-9)
+    # axis permutation x->y->z (box is cubic): energies permute with the atoms, forces rotate
+    P = np.array([[0, 1, 0], [0, 0, 1], [1, 0, 0]], float)
+    s2 = dict(sysd, pos=sysd["pos"] @ P.T, pos_ref=sysd["pos_ref"] @ P.T)
+    q = oracle.evaluate(s2, csp=oracle.csp_pairs(s2["pos_ref"], s2["box"], 8))
+    assert q["E"] == pytest.approx(r["E"], rel=1e-12)
+    assert np.allclose(q["F"], r["F"] @ P.T, atol=1e-9)
+
+
+def test_virial_is_minus_strain_derivative(oracle, sysd):
+    r = oracle.evaluate(sysd)
+    eps = 1e-6
+    for a in range(3):
+        f1, f2 = np.ones(3), np.ones(3)
+        f1[a] += eps
+        f2[a] -= eps
+        e1 = oracle.evaluate(dict(sysd, pos=sysd["pos"] * f1, box=sysd["box"] * f1))["E"]
+        e2 = oracle.evaluate(dict(sysd, pos=sysd["pos"] * f2, box=sysd["box"] * f2))["E"]
+        assert r["virial"][a, a] == pytest.approx(-(e1 - e2) / (2 * eps), rel=1e-6)
+
+
+def test_velocity_verlet_conserves_and_reverses(oracle):
+    """NVE on the calibrated 1024-atom bcc workload (x ~ 5 %): total momentum stays at its initial
+    value, the total energy fluctuates at the O(dt^2) level of velocity Verlet without drifting away,
+    and integrating back with negated velocities returns to the start (time reversibility)."""
+    import synth
+    s = synth.build_system(1)
+    n_steps = 30
+    pos, vel, F, th = oracle.velocity_verlet(s, n_steps)
+    P0 = (s["mass"] * s["vel"]).sum(0)
+    assert np.abs(th[:, 3:6] - P0).max() < 1e-9
+    assert np.ptp(th[:, 2]) / len(pos) < 2e-4
+    back_pos, back_vel, _, _ = oracle.velocity_verlet(dict(s, pos=pos, vel=-vel), n_steps)
+    d = back_pos - s["pos"]
+    d -= s["box"] * np.rint(d / s["box"])
+    assert np.abs(d).max() < 1e-9
+
+
+def test_coefficient_gradient_closed_form_and_fd(oracle, sysd):
+    """dE/dc_nu = sum_i (1 - lambda_i) B_i,nu; checked against finite differences of E_AP in c."""
+    r = oracle.evaluate(sysd)
+    w = 1.0 - r["aux"]["lam"]
+    dEdc, dEdb, _ = oracle.ace_coeff_grad(sysd["pos"], sysd["box"], sysd["ace"], weight=w)
+    rng = np.random.default_rng(0)
+    for f in rng.choice(len(dEdc), 6, replace=False):
+        h = 1e-4
+        c1, c2 = sysd["ace"]["c"].copy(), sysd["ace"]["c"].copy()
+        c1[f] += h
+        c2[f] -= h
+        e1 = oracle.evaluate(dict(sysd, ace=dict(sysd["ace"], c=c1)))["E"]
+        e2 = oracle.evaluate(dict(sysd, ace=dict(sysd["ace"], c=c2)))["E"]
+        assert dEdc[f] == pytest.approx((e1 - e2) / (2 * h), rel=1e-6, abs=5e-8)
+    n = 1
+    h = 1e-5
+    b1, b2 = sysd["ace"]["b_dens"].copy(), sysd["ace"]["b_dens"].copy()
+    b1[n] += h
+    b2[n] -= h
+    e1 = oracle.evaluate(dict(sysd, ace=dict(sysd["ace"], b_dens=b1)))["E"]
+    e2 = oracle.evaluate(dict(sysd, ace=dict(sysd["ace"], b_dens=b2)))["E"]
+    assert dEdb[n] == pytest.approx((e1 - e2) / (2 * h), rel=1e-6)
