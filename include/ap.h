@@ -41,7 +41,7 @@ extern "C" {
 
 #define AP_OK 0
 #define AP_E_ARG -1          /* null pointer, size out of range, unsupported option          */
-#define AP_E_BOX -2          /* a cutoff (+ skin) >= half the box, or < 3 cells per dimension */
+#define AP_E_BOX -2          /* a cutoff (+ skin) >= half the box                             */
 #define AP_E_NBR_OVERFLOW -3 /* an atom has more neighbours than max_nbr                      */
 #define AP_E_NONFINITE -4    /* non-finite energy or force, or non-positive embedding density */
 #define AP_E_HIP -5          /* a HIP runtime call failed                                     */

@@ -1,0 +1,212 @@
+"""ctypes binding of libap.so (include/ap.h): argument marshalling only.
+
+Every computation runs in the library's HIP kernels; PyTorch only provides device memory and the
+stream. Positions, velocities and forces are float64 CUDA tensors of shape (3, n) (structure of
+arrays); per-atom outputs are (n,). There is no CPU fallback: a missing library raises.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libap.so")
+
+AP_FP64, AP_FP32 = 0, 1
+AP_LAMBDA_COMPUTED, AP_LAMBDA_PRECISE, AP_LAMBDA_FAST = -1, 0, 1
+AP_IND_CSP, AP_IND_MLP = 0, 1
+ERRORS = {-1: "AP_E_ARG", -2: "AP_E_BOX", -3: "AP_E_NBR_OVERFLOW", -4: "AP_E_NONFINITE", -5: "AP_E_HIP",
+          -6: "AP_E_CSP", -7: "AP_E_STATE"}
+SYMBOLS = ["ap_ctx_create", "ap_ctx_destroy", "ap_last_error", "ap_set_potential", "ap_csp_pairs_build",
+           "ap_set_csp_list", "ap_nblist_build", "ap_eam_eval", "ap_switch_eval", "ap_ace_eval",
+           "ap_mixed_energy_forces", "ap_vv_step"]
+
+
+class APError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (ERRORS.get(code, "?"), code, msg))
+        self.code = code
+
+
+class Box(C.Structure):
+    _fields_ = [("L", C.c_double * 3)]
+
+
+class EamParams(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ("A", "beta", "c0", "c1", "c2", "rc")]
+
+
+class AceParams(C.Structure):
+    _fields_ = [("n_max", C.c_int), ("l_max", C.c_int), ("n_funcs", C.c_int), ("rc", C.c_double),
+                ("func", C.POINTER(C.c_int32)), ("c", C.POINTER(C.c_double)), ("b_dens", C.POINTER(C.c_double)),
+                ("emb_A", C.c_double), ("E0", C.c_double), ("precision", C.c_int)]
+
+
+class SwitchParams(C.Structure):
+    _fields_ = [("d_lo", C.c_double), ("d_hi", C.c_double), ("r_w", C.c_double), ("d0", C.c_double),
+                ("n_csp", C.c_int), ("lambda_mode", C.c_int), ("indicator", C.c_int), ("grad_lambda", C.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libap.so (built in-tree by __graft_entry__.build()); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libap.so not built: run __graft_entry__.build() (hipcc, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        vp, i, d = C.c_void_p, C.c_int, C.c_double
+        L.ap_ctx_create.argtypes = [C.POINTER(vp), i, i, d, vp]
+        L.ap_ctx_destroy.argtypes = [vp]
+        L.ap_ctx_destroy.restype = None
+        L.ap_last_error.argtypes = [vp]
+        L.ap_last_error.restype = C.c_char_p
+        L.ap_set_potential.argtypes = [vp, C.POINTER(EamParams), C.POINTER(AceParams), C.POINTER(SwitchParams)]
+        L.ap_csp_pairs_build.argtypes = [vp, i, vp, C.POINTER(Box), i, vp]
+        L.ap_set_csp_list.argtypes = [vp, i, i, vp]
+        L.ap_nblist_build.argtypes = [vp, i, vp, C.POINTER(Box), d, i, vp, vp]
+        L.ap_eam_eval.argtypes = [vp, i, vp, vp, C.POINTER(Box), vp, vp, vp, vp, vp]
+        L.ap_switch_eval.argtypes = [vp, i, vp, C.POINTER(Box), vp, vp, vp, vp, vp, vp]
+        L.ap_ace_eval.argtypes = [vp, i, vp, vp, C.POINTER(Box), vp, i, vp, vp, vp, vp]
+        L.ap_mixed_energy_forces.argtypes = [vp, i, vp, vp, C.POINTER(Box), vp, vp, vp, vp, vp]
+        L.ap_vv_step.argtypes = [vp, i, vp, vp, vp, d, d, i, C.POINTER(Box), vp]
+        for s in SYMBOLS:
+            if s not in ("ap_ctx_destroy", "ap_last_error"):
+                getattr(L, s).restype = i
+        _lib = L
+    return _lib
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _box(box):
+    b = Box()
+    for a in range(3):
+        b.L[a] = float(box[a])
+    return b
+
+
+def _dev(t, dtype, shape=None):
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise ValueError("expected a contiguous %s CUDA tensor" % dtype)
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("expected shape %s, got %s" % (shape, tuple(t.shape)))
+    return t
+
+
+class Context:
+    """One library context (scratch buffers for up to n_max_atoms atoms) bound to a HIP stream."""
+
+    def __init__(self, n_max_atoms, max_nbr=128, skin=0.5, stream=None, device=None):
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        s = torch.cuda.current_stream(self.device) if stream is None else stream
+        self.stream = s
+        h = C.c_void_p()
+        rc = lib().ap_ctx_create(C.byref(h), int(n_max_atoms), int(max_nbr), float(skin), C.c_void_p(s.cuda_stream))
+        if rc != 0:
+            raise APError(rc, lib().ap_last_error(None).decode())
+        self.h = h
+        self.max_nbr = int(max_nbr)
+        self._keep = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ap_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, rc):
+        if rc != 0:
+            raise APError(rc, lib().ap_last_error(self.h).decode())
+
+    def _zeros(self, *shape, dtype=torch.float64):
+        return torch.zeros(*shape, dtype=dtype, device=self.device)
+
+    def set_potential(self, eam, ace, sw, lambda_mode=AP_LAMBDA_COMPUTED, grad_lambda=True, precision=None):
+        e = EamParams(*[float(eam[k]) for k in ("A", "beta", "c0", "c1", "c2", "rc")])
+        func = np.ascontiguousarray(ace["func"], dtype=np.int32)
+        c = np.ascontiguousarray(ace["c"], dtype=np.float64)
+        b = np.ascontiguousarray(ace["b_dens"], dtype=np.float64)
+        prec = ace.get("precision", "fp64") if precision is None else precision
+        a = AceParams(int(ace["n_max"]), int(ace["l_max"]), len(func), float(ace["rc"]),
+                      func.ctypes.data_as(C.POINTER(C.c_int32)), c.ctypes.data_as(C.POINTER(C.c_double)),
+                      b.ctypes.data_as(C.POINTER(C.c_double)), float(ace["emb_A"]), float(ace["E0"]),
+                      AP_FP32 if prec in ("fp32", AP_FP32) else AP_FP64)
+        s = SwitchParams(float(sw["d_lo"]), float(sw["d_hi"]), float(sw["r_w"]), float(sw.get("d0", 0.0)),
+                         int(sw["n_csp"]), int(lambda_mode), AP_IND_CSP, 1 if grad_lambda else 0)
+        self._chk(lib().ap_set_potential(self.h, C.byref(e), C.byref(a), C.byref(s)))
+
+    def csp_pairs_build(self, pos_ref, box, n_csp):
+        n = pos_ref.shape[1]
+        _dev(pos_ref, torch.float64, (3, n))
+        out = self._zeros(n, n_csp, dtype=torch.int32)
+        self._chk(lib().ap_csp_pairs_build(self.h, n, _ptr(pos_ref), C.byref(_box(box)), int(n_csp), _ptr(out)))
+        return out
+
+    def set_csp_list(self, csp):
+        _dev(csp, torch.int32)
+        self._keep = csp
+        self._chk(lib().ap_set_csp_list(self.h, csp.shape[0], csp.shape[1], _ptr(csp)))
+
+    def nblist_build(self, pos, box, r_list, max_nbr=None):
+        n = pos.shape[1]
+        _dev(pos, torch.float64, (3, n))
+        m = int(max_nbr or self.max_nbr)
+        cnt = self._zeros(n, dtype=torch.int32)
+        idx = torch.full((m, n), -1, dtype=torch.int32, device=self.device)
+        self._chk(lib().ap_nblist_build(self.h, n, _ptr(pos), C.byref(_box(box)), float(r_list), m, _ptr(cnt),
+                                        _ptr(idx)))
+        return cnt, idx
+
+    def eam_eval(self, pos, box, lam=None):
+        n = pos.shape[1]
+        _dev(pos, torch.float64, (3, n))
+        E, Ea, F, V = self._zeros(1), self._zeros(n), self._zeros(3, n), self._zeros(9)
+        self._chk(lib().ap_eam_eval(self.h, n, _ptr(pos), None, C.byref(_box(box)), _ptr(lam), _ptr(E), _ptr(Ea),
+                                    _ptr(F), _ptr(V)))
+        return dict(E=E, E_atom=Ea, F=F, virial=V.view(3, 3))
+
+    def switch_eval(self, pos, box):
+        n = pos.shape[1]
+        _dev(pos, torch.float64, (3, n))
+        g, d, w, l, dl = (self._zeros(n) for _ in range(5))
+        npr = self._zeros(1, dtype=torch.int32)
+        self._chk(lib().ap_switch_eval(self.h, n, _ptr(pos), C.byref(_box(box)), _ptr(g), _ptr(d), _ptr(w), _ptr(l),
+                                       _ptr(dl), _ptr(npr)))
+        return dict(g=g, d=d, wbar=w, lam=l, dlam=dl, n_precise=npr)
+
+    def ace_eval(self, pos, box, subset=None):
+        n = pos.shape[1]
+        _dev(pos, torch.float64, (3, n))
+        E, Ea, F, V = self._zeros(1), self._zeros(n), self._zeros(3, n), self._zeros(9)
+        ns = 0 if subset is None else int(subset.numel())
+        self._chk(lib().ap_ace_eval(self.h, n, _ptr(pos), None, C.byref(_box(box)), _ptr(subset), ns, _ptr(E),
+                                    _ptr(Ea), _ptr(F), _ptr(V)))
+        return dict(E=E, E_atom=Ea, F=F, virial=V.view(3, 3))
+
+    def mixed_energy_forces(self, pos, box):
+        n = pos.shape[1]
+        _dev(pos, torch.float64, (3, n))
+        E, Ea, F, V, lam = self._zeros(1), self._zeros(n), self._zeros(3, n), self._zeros(9), self._zeros(n)
+        self._chk(lib().ap_mixed_energy_forces(self.h, n, _ptr(pos), None, C.byref(_box(box)), _ptr(E), _ptr(Ea),
+                                               _ptr(F), _ptr(V), _ptr(lam)))
+        return dict(E=E, E_atom=Ea, F=F, virial=V.view(3, 3), lam=lam)
+
+    def vv_step(self, pos, vel, F, mass, dt, n_steps, box, thermo=None):
+        n = pos.shape[1]
+        for t in (pos, vel, F):
+            _dev(t, torch.float64, (3, n))
+        th = self._zeros(max(1, n_steps), 8) if thermo is None else thermo
+        self._chk(lib().ap_vv_step(self.h, n, _ptr(pos), _ptr(vel), _ptr(F), float(mass), float(dt), int(n_steps),
+                                   C.byref(_box(box)), _ptr(th)))
+        return th

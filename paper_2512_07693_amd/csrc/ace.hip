@@ -1,0 +1,746 @@
+// ACE site energies and pair gradients on the precise set S = {i : lambda_i < 1}.
+//
+// Form evaluated (the paper cites ACE; this is the concrete basis of the library, see ap.h):
+//   A_{n l m} = sum_j g_n(r_ij) Y_lm(rhat_ij)   with REAL orthonormal harmonics Y_lm
+//   E = E0 + sum_n c1_n A_{n00} + sum_l sum_{n1 n2} C2_l[n1][n2] sum_m A_{n1 l m} A_{n2 l m}
+//       + sum_blocks sum_M sum_{n1 n2 n3} C3[n1][n2][n3] P_M[n1][n2] A_{n3 L M} - emb_A sqrt(phi2)
+//   P_M[n1][n2] = sum_{m1 m2} kappa(l1 m1, l2 m2, L M) A_{n1 l1 m1} A_{n2 l2 m2}
+// Every order-3 function (l1,l2,l3 sorted so that L <= l1 <= l2) belongs to one block (L, l1, l2);
+// kappa is the real-harmonic form of the Wigner 3j symbol, obtained here as the real Gaunt integral
+// (Gauss-Legendre x uniform-phi quadrature, exact for these degrees) divided by
+// sqrt((2l1+1)(2l2+1)(2L+1)/(4 pi)) (l1 l2 L; 0 0 0). Both forms give the same rotation invariants,
+// so E equals the complex-harmonic definition with the 3j symbol.
+//
+// k_ace_energy (one workgroup per S atom): neighbours -> radial and Y tables in LDS -> A -> energy
+// and G = dE/dA (adjoint of the block contractions); writes E^p, E~ of (S17) and G.
+// k_ace_pairforce (one workgroup per S atom, one thread per neighbour slot):
+// f_ji = dE_i/du_ij = sum_{n,lm} G_{nlm} grad_u [g_n(r) Y_lm(uhat)].
+#include "ap_internal.h"
+
+namespace ap {
+
+constexpr int kAceMaxSlots = 1536;
+
+// ---------------------------------------------------------------------------------------------
+// Basis functions (shared by the host table builder and the kernels)
+// ---------------------------------------------------------------------------------------------
+template <typename T>
+__host__ __device__ __forceinline__ T klm(int l, int m) {
+    double f = 1.0;
+    for (int q = l - m + 1; q <= l + m; q++) f *= q;  // (l+m)!/(l-m)!
+    return (T)sqrt((2.0 * l + 1.0) / (4.0 * kPi) / f);
+}
+
+// Real orthonormal harmonics at the unit vector (x, y, z), index l*l + l + m:
+//   Y_l0 = K Q_l^0(z);  Y_lm = sqrt2 K Q_l^m(z) Re(x+iy)^m;  Y_l,-m = sqrt2 K Q_l^m(z) Im(x+iy)^m
+// with Q_l^m(z) = d^m P_l / dz^m from the Legendre recurrence (no Condon-Shortley phase).
+template <typename T, int LMAX>
+__host__ __device__ __forceinline__ void ylm_real(T x, T y, T z, T *Y) {
+    T C[LMAX + 1], S[LMAX + 1], Q[LMAX + 1][LMAX + 1];
+    C[0] = T(1);
+    S[0] = T(0);
+#pragma unroll
+    for (int m = 1; m <= LMAX; m++) {
+        C[m] = x * C[m - 1] - y * S[m - 1];
+        S[m] = x * S[m - 1] + y * C[m - 1];
+    }
+    T dfm = T(1);
+#pragma unroll
+    for (int m = 0; m <= LMAX; m++) {
+        if (m > 0) dfm *= T(2 * m - 1);
+        Q[m][m] = dfm;
+        if (m + 1 <= LMAX) Q[m + 1][m] = T(2 * m + 1) * z * Q[m][m];
+#pragma unroll
+        for (int l = m + 2; l <= LMAX; l++)
+            Q[l][m] = (T(2 * l - 1) * z * Q[l - 1][m] - T(l + m - 1) * Q[l - 2][m]) / T(l - m);
+    }
+    const T r2 = T(1.4142135623730951);
+#pragma unroll
+    for (int l = 0; l <= LMAX; l++) {
+        Y[l * l + l] = klm<T>(l, 0) * Q[l][0];
+#pragma unroll
+        for (int m = 1; m <= l; m++) {
+            const T k = r2 * klm<T>(l, m) * Q[l][m];
+            Y[l * l + l + m] = k * C[m];
+            Y[l * l + l - m] = k * S[m];
+        }
+    }
+}
+
+// Same harmonics and their gradient with respect to the unnormalised vector u (|u| = r):
+// grad_u Y = (grad_p - (uhat . grad_p) uhat) / r for the polynomial p(x, y, z).
+template <typename T, int LMAX>
+__device__ __forceinline__ void ylm_real_grad(T x, T y, T z, T ir, T *Y, T *dY) {
+    T C[LMAX + 1], S[LMAX + 1], Q[LMAX + 1][LMAX + 1], dQ[LMAX + 1][LMAX + 1];
+    C[0] = T(1);
+    S[0] = T(0);
+#pragma unroll
+    for (int m = 1; m <= LMAX; m++) {
+        C[m] = x * C[m - 1] - y * S[m - 1];
+        S[m] = x * S[m - 1] + y * C[m - 1];
+    }
+    T dfm = T(1);
+#pragma unroll
+    for (int m = 0; m <= LMAX; m++) {
+        if (m > 0) dfm *= T(2 * m - 1);
+        Q[m][m] = dfm;
+        dQ[m][m] = T(0);
+        if (m + 1 <= LMAX) {
+            Q[m + 1][m] = T(2 * m + 1) * z * Q[m][m];
+            dQ[m + 1][m] = T(2 * m + 1) * Q[m][m];
+        }
+#pragma unroll
+        for (int l = m + 2; l <= LMAX; l++) {
+            const T inv = T(1) / T(l - m);
+            Q[l][m] = (T(2 * l - 1) * z * Q[l - 1][m] - T(l + m - 1) * Q[l - 2][m]) * inv;
+            dQ[l][m] = (T(2 * l - 1) * (Q[l - 1][m] + z * dQ[l - 1][m]) - T(l + m - 1) * dQ[l - 2][m]) * inv;
+        }
+    }
+    const T r2 = T(1.4142135623730951);
+#pragma unroll
+    for (int l = 0; l <= LMAX; l++) {
+#pragma unroll
+        for (int m = 0; m <= l; m++) {
+            T px[2], py[2], pz[2], val[2];
+            int idx[2];
+            int cnt = 1;
+            if (m == 0) {
+                const T k = klm<T>(l, 0);
+                val[0] = k * Q[l][0];
+                px[0] = T(0);
+                py[0] = T(0);
+                pz[0] = k * dQ[l][0];
+                idx[0] = l * l + l;
+            } else {
+                const T k = r2 * klm<T>(l, m);
+                const T q = k * Q[l][m], dq = k * dQ[l][m], mm = T(m);
+                val[0] = q * C[m];
+                px[0] = q * mm * C[m - 1];
+                py[0] = -q * mm * S[m - 1];
+                pz[0] = dq * C[m];
+                idx[0] = l * l + l + m;
+                val[1] = q * S[m];
+                px[1] = q * mm * S[m - 1];
+                py[1] = q * mm * C[m - 1];
+                pz[1] = dq * S[m];
+                idx[1] = l * l + l - m;
+                cnt = 2;
+            }
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                if (h >= cnt) break;
+                const T rad = px[h] * x + py[h] * y + pz[h] * z;
+                Y[idx[h]] = val[h];
+                dY[3 * idx[h] + 0] = (px[h] - rad * x) * ir;
+                dY[3 * idx[h] + 1] = (py[h] - rad * y) * ir;
+                dY[3 * idx[h] + 2] = (pz[h] - rad * z) * ir;
+            }
+        }
+    }
+}
+
+// Chebyshev radial channels g_n = T_n(2r/rc - 1) fc(r), fc = (1 + cos(pi r/rc))/2, and derivatives.
+template <typename T, int NMAX>
+__device__ __forceinline__ void radial(T r, T rc, T *g, T *dg) {
+    const T x = T(2) * r / rc - T(1), dx = T(2) / rc;
+    const T a = T(kPi) * r / rc;
+    const T fc = T(0.5) * (T(1) + cos(a)), dfc = -T(0.5) * T(kPi) / rc * sin(a);
+    T t0 = T(1), t1 = x, d0 = T(0), d1 = T(1);
+    g[0] = fc;
+    if (dg) dg[0] = dfc;
+#pragma unroll
+    for (int n = 1; n < NMAX; n++) {
+        if (n > 1) {
+            const T t2 = T(2) * x * t1 - t0, d2 = T(2) * t1 + T(2) * x * d1 - d0;
+            t0 = t1;
+            t1 = t2;
+            d0 = d1;
+            d1 = d2;
+        }
+        g[n] = t1 * fc;
+        if (dg) dg[n] = d1 * dx * fc + t1 * dfc;
+    }
+}
+
+struct AceArgs {
+    const double *pos;
+    int n;
+    double L[3];
+    double rc;
+    const int32_t *ncount, *nidx;
+    int max_nbr;
+    const int *slist, *scount;
+    const double *dlam, *wbar, *Ef;
+    const double *c1d, *bdd;
+    double *Ep, *Et;
+    void *gbuf;   // [S][n_max * nlm] G = dE/dA
+    void *fpair;  // [S][max_nbr][3]
+    const void *c1, *bd, *c2, *c3, *kval;
+    const int *kidx, *blk;
+    int nblk;
+    double emb_A, E0;
+    int *flags;
+};
+
+__device__ __forceinline__ double block_sum_d(double v, double *sh) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int q = 0; q < (int)(blockDim.x >> 6); q++) s += sh[q];
+    return s;
+}
+
+template <typename T, int NMAX, int LMAX>
+__global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
+    constexpr int NLM = (LMAX + 1) * (LMAX + 1), NA = NMAX * NLM, NN = NMAX * NMAX, MM = 2 * LMAX + 1;
+    constexpr int V = kAceMaxValid;
+    __shared__ T sA[NA], sG[NA];
+    __shared__ T sR[V * NMAX];
+    __shared__ T sY[V * NLM];
+    __shared__ T sU[V * 4];
+    __shared__ double sRd[V], sR64[V * NMAX], sS[NMAX];
+    __shared__ T sP[MM * NN], sQ[MM * NN];
+    __shared__ int sCnt[5];
+    __shared__ double sRed[kBlock / 64];
+    __shared__ T sEmbD;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const T *c1 = (const T *)a.c1, *bd = (const T *)a.bd, *c2 = (const T *)a.c2, *c3 = (const T *)a.c3;
+    const T *kval = (const T *)a.kval;
+    const int n = a.n;
+    const int S = *a.scount;
+    const double rc2 = a.rc * a.rc;
+    const T rcT = (T)a.rc;
+    for (int s = blockIdx.x; s < S; s += gridDim.x) {
+        const int i = a.slist[s];
+        const double xi = a.pos[i], yi = a.pos[n + i], zi = a.pos[2 * n + i];
+        const int cnt = a.ncount[i];
+        if (tid == 0) sCnt[4] = 0;
+        __syncthreads();
+        // ---- phase 0: neighbours inside rc, compacted in list order (ballot prefix) ----
+        for (int base = 0; base < cnt; base += kBlock) {
+            const int slot = base + tid;
+            bool valid = false;
+            double ux = 0, uy = 0, uz = 0, r2 = 0;
+            if (slot < cnt) {
+                const int j = a.nidx[(size_t)slot * n + i];
+                ux = min_image(a.pos[j] - xi, a.L[0]);
+                uy = min_image(a.pos[n + j] - yi, a.L[1]);
+                uz = min_image(a.pos[2 * n + j] - zi, a.L[2]);
+                r2 = ux * ux + uy * uy + uz * uz;
+                valid = r2 < rc2;
+            }
+            const unsigned long long m = __ballot(valid);
+            if (lane == 0) sCnt[wv] = __popcll(m);
+            __syncthreads();
+            int off = sCnt[4];
+            for (int q = 0; q < wv; q++) off += sCnt[q];
+            const int p = off + __popcll(m & ((1ull << lane) - 1ull));
+            if (valid) {
+                if (p < V) {
+                    sU[4 * p + 0] = (T)ux;
+                    sU[4 * p + 1] = (T)uy;
+                    sU[4 * p + 2] = (T)uz;
+                    sU[4 * p + 3] = (T)sqrt(r2);
+                    sRd[p] = sqrt(r2);
+                } else {
+                    atomicOr(&a.flags[1], kErrAceNbr);
+                }
+            }
+            __syncthreads();
+            if (tid == 0) sCnt[4] += sCnt[0] + sCnt[1] + sCnt[2] + sCnt[3];
+            __syncthreads();
+        }
+        const int nv = min(sCnt[4], V);
+        // ---- phase 1: radial channels and harmonics per neighbour ----
+        for (int v = tid; v < nv; v += kBlock) {
+            const T r = sU[4 * v + 3], ir = T(1) / r;
+            T g[NMAX];
+            radial<T, NMAX>(r, rcT, g, (T *)nullptr);
+#pragma unroll
+            for (int q = 0; q < NMAX; q++) sR[v * NMAX + q] = g[q];
+            // the l = 0 radial sums feed the two-body and density terms, whose large fitted
+            // coefficients cancel: they are kept in FP64 whatever T is
+            double gd[NMAX];
+            radial<double, NMAX>(sRd[v], a.rc, gd, (double *)nullptr);
+#pragma unroll
+            for (int q = 0; q < NMAX; q++) sR64[v * NMAX + q] = gd[q];
+            T Y[NLM];
+            ylm_real<T, LMAX>(sU[4 * v] * ir, sU[4 * v + 1] * ir, sU[4 * v + 2] * ir, Y);
+#pragma unroll
+            for (int q = 0; q < NLM; q++) sY[v * NLM + q] = Y[q];
+        }
+        for (int o = tid; o < NA; o += kBlock) sG[o] = T(0);
+        __syncthreads();
+        // ---- phase 2: atomic basis A[n][lm] ----
+        for (int o = tid; o < NA; o += kBlock) {
+            const int q = o / NLM, lm = o - q * NLM;
+            T acc = T(0);
+            for (int v = 0; v < nv; v++) acc += sR[v * NMAX + q] * sY[v * NLM + lm];
+            sA[o] = acc;
+        }
+        __syncthreads();
+        // ---- phase 3a: orders 1 and 2, embedding ----
+        if (tid < NMAX) {
+            double s0 = 0.0;
+            for (int v = 0; v < nv; v++) s0 += sR64[v * NMAX + tid];
+            sS[tid] = s0;
+        }
+        __syncthreads();
+        double e = 0.0;
+        if (tid == 0) {
+            const double y00 = 0.28209479177387814;  // 1 / sqrt(4 pi)
+            double phi2 = 0.0, e1 = 0.0;
+            for (int q = 0; q < NMAX; q++) {
+                phi2 += a.bdd[q] * sS[q];  // b_n sqrt(4 pi) A_n00 with A_n00 = s_n / sqrt(4 pi)
+                e1 += a.c1d[q] * (sS[q] * y00);
+            }
+            double emb = 0.0, demb = 0.0;
+            if (phi2 > 0.0) {
+                const double sq = sqrt(phi2);
+                emb = -a.emb_A * sq;
+                demb = -0.5 * a.emb_A / sq;
+            }
+            sEmbD = (T)demb;
+            e = a.E0 + e1 + emb;
+        }
+        __syncthreads();
+        for (int o = tid; o < NA; o += kBlock) {
+            const int q = o / NLM, lm = o - q * NLM;
+            int l = 0;
+            while ((l + 1) * (l + 1) <= lm) l++;
+            const T *row = c2 + ((size_t)l * NMAX + q) * NMAX;
+            T g2 = T(0);
+#pragma unroll
+            for (int q2 = 0; q2 < NMAX; q2++) g2 += row[q2] * sA[q2 * NLM + lm];
+            g2 *= T(2);
+            e += 0.5 * (double)(sA[o] * g2);
+            sG[o] += g2 + (lm == 0 ? c1[q] + sEmbD * bd[q] : T(0));  // order-1 and density parts of dE/dA
+        }
+        __syncthreads();
+        // ---- phase 3b: order-3 blocks ----
+        for (int b = 0; b < a.nblk; b++) {
+            const int *bk = a.blk + b * kBlkInts;
+            const int L = bk[0], l1 = bk[1], l2 = bk[2];
+            const T *C = c3 + bk[3];
+            const int nM = 2 * L + 1, n1m = 2 * l1 + 1, n2m = 2 * l2 + 1;
+            const int bL = L * L + L, b1 = l1 * l1 + l1, b2 = l2 * l2 + l2;
+            for (int o = tid; o < nM * NN; o += kBlock) {
+                const int Mi = o / NN, rem = o - Mi * NN, n1 = rem / NMAX, n2 = rem - n1 * NMAX;
+                T P = T(0);
+                const int e0 = bk[4 + Mi], e1 = bk[4 + Mi + 1];
+                for (int q = e0; q < e1; q++) {
+                    const int code = a.kidx[q];
+                    const int m1 = (code & 255) - 8, m2 = ((code >> 8) & 255) - 8;
+                    P += kval[q] * sA[n1 * NLM + b1 + m1] * sA[n2 * NLM + b2 + m2];
+                }
+                const T *cc = C + (size_t)rem * NMAX;
+                T Q = T(0);
+#pragma unroll
+                for (int q3 = 0; q3 < NMAX; q3++) Q += cc[q3] * sA[q3 * NLM + bL + Mi - L];
+                sP[o] = P;
+                sQ[o] = Q;
+                e += (double)(P * Q);
+            }
+            __syncthreads();
+            for (int o = tid; o < NMAX * nM; o += kBlock) {
+                const int q3 = o / nM, Mi = o - q3 * nM;
+                T acc = T(0);
+                for (int p = 0; p < NN; p++) acc += C[(size_t)p * NMAX + q3] * sP[Mi * NN + p];
+                sG[q3 * NLM + bL + Mi - L] += acc;
+            }
+            __syncthreads();
+            for (int o = tid; o < NMAX * n1m; o += kBlock) {
+                const int q1 = o / n1m, i1 = o - q1 * n1m;
+                T acc = T(0);
+                const int e0 = bk[18 + i1], e1 = bk[18 + i1 + 1];
+                for (int q = e0; q < e1; q++) {
+                    const int code = a.kidx[q];
+                    const int m2 = ((code >> 8) & 255) - 8, Mi = ((code >> 16) & 255) - 8 + L;
+                    const T *qr = sQ + Mi * NN + q1 * NMAX;
+                    T s2 = T(0);
+#pragma unroll
+                    for (int q2 = 0; q2 < NMAX; q2++) s2 += qr[q2] * sA[q2 * NLM + b2 + m2];
+                    acc += kval[q] * s2;
+                }
+                sG[q1 * NLM + b1 + i1 - l1] += acc;
+            }
+            __syncthreads();
+            for (int o = tid; o < NMAX * n2m; o += kBlock) {
+                const int q2 = o / n2m, i2 = o - q2 * n2m;
+                T acc = T(0);
+                const int e0 = bk[32 + i2], e1 = bk[32 + i2 + 1];
+                for (int q = e0; q < e1; q++) {
+                    const int code = a.kidx[q];
+                    const int m1 = (code & 255) - 8, Mi = ((code >> 16) & 255) - 8 + L;
+                    const T *qc = sQ + Mi * NN + q2;
+                    T s1 = T(0);
+#pragma unroll
+                    for (int q1 = 0; q1 < NMAX; q1++) s1 += qc[q1 * NMAX] * sA[q1 * NLM + b1 + m1];
+                    acc += kval[q] * s1;
+                }
+                sG[q2 * NLM + b2 + i2 - l2] += acc;
+            }
+            __syncthreads();
+        }
+        // ---- outputs ----
+        const double E = block_sum_d(e, sRed);
+        T *gout = (T *)a.gbuf + (size_t)s * NA;
+        for (int o = tid; o < NA; o += kBlock) gout[o] = sG[o];
+        if (tid == 0) {
+            a.Ep[i] = E;
+            a.Et[i] = (E - a.Ef[i]) * a.dlam[i] / a.wbar[i];
+            if (!isfinite(E)) atomicOr(&a.flags[1], kErrNonFinite);
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T, int NMAX, int LMAX>
+__global__ __launch_bounds__(128) void k_ace_pairforce(AceArgs a) {
+    constexpr int NLM = (LMAX + 1) * (LMAX + 1), NA = NMAX * NLM;
+    __shared__ T sG[NA];
+    const int n = a.n;
+    const int S = *a.scount;
+    const double rc2 = a.rc * a.rc;
+    const T rcT = (T)a.rc;
+    for (int s = blockIdx.x; s < S; s += gridDim.x) {
+        const int i = a.slist[s];
+        const T *gin = (const T *)a.gbuf + (size_t)s * NA;
+        for (int o = threadIdx.x; o < NA; o += blockDim.x) sG[o] = gin[o];
+        __syncthreads();
+        const double xi = a.pos[i], yi = a.pos[n + i], zi = a.pos[2 * n + i];
+        const int cnt = a.ncount[i];
+        T *fo = (T *)a.fpair + (size_t)s * a.max_nbr * 3;
+        for (int slot = threadIdx.x; slot < cnt; slot += blockDim.x) {
+            const int j = a.nidx[(size_t)slot * n + i];
+            const double ux = min_image(a.pos[j] - xi, a.L[0]), uy = min_image(a.pos[n + j] - yi, a.L[1]),
+                         uz = min_image(a.pos[2 * n + j] - zi, a.L[2]);
+            const double r2 = ux * ux + uy * uy + uz * uz;
+            T f0 = T(0), f1 = T(0), f2 = T(0);
+            if (r2 < rc2) {
+                const T r = (T)sqrt(r2), ir = T(1) / r;
+                const T x = (T)ux * ir, y = (T)uy * ir, z = (T)uz * ir;
+                T g[NMAX], dg[NMAX];
+                radial<T, NMAX>(r, rcT, g, dg);
+                T Y[NLM], dY[3 * NLM];
+                ylm_real_grad<T, LMAX>(x, y, z, ir, Y, dY);
+#pragma unroll
+                for (int lm = 0; lm < NLM; lm++) {
+                    T sg = T(0), sdg = T(0);
+#pragma unroll
+                    for (int q = 0; q < NMAX; q++) {
+                        const T G = sG[q * NLM + lm];
+                        sg += G * g[q];
+                        sdg += G * dg[q];
+                    }
+                    const T t = sdg * Y[lm];
+                    f0 += t * x + sg * dY[3 * lm];
+                    f1 += t * y + sg * dY[3 * lm + 1];
+                    f2 += t * z + sg * dY[3 * lm + 2];
+                }
+            }
+            fo[3 * slot] = f0;
+            fo[3 * slot + 1] = f1;
+            fo[3 * slot + 2] = f2;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Host: tables
+// ---------------------------------------------------------------------------------------------
+static double w3j000(int l1, int l2, int l3) {
+    const int J = l1 + l2 + l3;
+    if (J % 2) return 0.0;
+    const int g = J / 2;
+    auto f = [](int k) {
+        double r = 1;
+        for (int q = 2; q <= k; q++) r *= q;
+        return r;
+    };
+    const double s = (g % 2) ? -1.0 : 1.0;
+    return s * std::sqrt(f(J - 2 * l1) * f(J - 2 * l2) * f(J - 2 * l3) / f(J + 1)) * f(g) /
+           (f(g - l1) * f(g - l2) * f(g - l3));
+}
+
+// Gauss-Legendre nodes and weights on [-1, 1] by Newton iteration on P_n.
+static void gauss_legendre(int npt, std::vector<double> &x, std::vector<double> &w) {
+    x.resize(npt);
+    w.resize(npt);
+    for (int k = 0; k < npt; k++) {
+        double t = std::cos(kPi * (k + 0.75) / (npt + 0.5));
+        for (int it = 0; it < 100; it++) {
+            double p0 = 1, p1 = t;
+            for (int q = 2; q <= npt; q++) {
+                double p2 = ((2 * q - 1) * t * p1 - (q - 1) * p0) / q;
+                p0 = p1;
+                p1 = p2;
+            }
+            const double dp = npt * (t * p1 - p0) / (t * t - 1);
+            const double dt = p1 / dp;
+            t -= dt;
+            if (std::fabs(dt) < 1e-16) break;
+        }
+        double p0 = 1, p1 = t;
+        for (int q = 2; q <= npt; q++) {
+            double p2 = ((2 * q - 1) * t * p1 - (q - 1) * p0) / q;
+            p0 = p1;
+            p1 = p2;
+        }
+        const double dp = npt * (t * p1 - p0) / (t * t - 1);
+        x[k] = t;
+        w[k] = 2.0 / ((1 - t * t) * dp * dp);
+    }
+}
+
+struct Kap {
+    int m1, m2, M;
+    double v;
+};
+
+// kappa(l1 m1, l2 m2, L M) for every (m1, m2, M): real Gaunt integral / (N3 (l1 l2 L; 0 0 0)).
+static std::vector<Kap> coupling(int l1, int l2, int L) {
+    const int nth = 16, nph = 32;
+    std::vector<double> x, w;
+    gauss_legendre(nth, x, w);
+    constexpr int NLM = 49;
+    std::vector<Kap> out;
+    const double N3 = std::sqrt((2.0 * l1 + 1) * (2.0 * l2 + 1) * (2.0 * L + 1) / (4 * kPi)) * w3j000(l1, l2, L);
+    std::vector<double> G((2 * l1 + 1) * (2 * l2 + 1) * (2 * L + 1), 0.0);
+    for (int a = 0; a < nth; a++)
+        for (int b = 0; b < nph; b++) {
+            const double ph = 2 * kPi * b / nph, st = std::sqrt(1 - x[a] * x[a]);
+            double Y[NLM];
+            ylm_real<double, 6>(st * std::cos(ph), st * std::sin(ph), x[a], Y);
+            const double wq = w[a] * 2 * kPi / nph;
+            for (int m1 = -l1; m1 <= l1; m1++)
+                for (int m2 = -l2; m2 <= l2; m2++)
+                    for (int M = -L; M <= L; M++)
+                        G[((m1 + l1) * (2 * l2 + 1) + (m2 + l2)) * (2 * L + 1) + (M + L)] +=
+                            wq * Y[l1 * l1 + l1 + m1] * Y[l2 * l2 + l2 + m2] * Y[L * L + L + M];
+        }
+    for (int m1 = -l1; m1 <= l1; m1++)
+        for (int m2 = -l2; m2 <= l2; m2++)
+            for (int M = -L; M <= L; M++) {
+                const double g = G[((m1 + l1) * (2 * l2 + 1) + (m2 + l2)) * (2 * L + 1) + (M + L)];
+                if (std::fabs(g) > 1e-12) out.push_back({m1, m2, M, g / N3});
+            }
+    return out;
+}
+
+template <typename T>
+static int upload(ap_ctx *c, void **dst, const std::vector<double> &src) {
+    std::vector<T> h(src.begin(), src.end());
+    if (h.empty()) h.push_back(T(0));
+    int rc = hip_check(c, hipMalloc(dst, sizeof(T) * h.size()), "ace tables");
+    if (!rc) rc = hip_check(c, hipMemcpy(*dst, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice), "ace tables");
+    return rc;
+}
+
+void ace_free(ap_ctx *c) {
+    AceTables &t = c->ace;
+    (void)hipFree(t.c1);
+    (void)hipFree(t.bd);
+    (void)hipFree(t.c1d);
+    (void)hipFree(t.bdd);
+    (void)hipFree(t.c2);
+    (void)hipFree(t.c3);
+    (void)hipFree(t.kval);
+    (void)hipFree(t.kidx);
+    (void)hipFree(t.blk);
+    t = AceTables();
+}
+
+int ace_setup(ap_ctx *c, const ap_ace_params *p) {
+    const int N = p->n_max, Lm = p->l_max;
+    if (!((N == 4 && Lm == 2) || (N == 8 && Lm == 4) || (N == 12 && Lm == 6)))
+        return set_error(c, AP_E_ARG, "supported (n_max, l_max): (4,2), (8,4), (12,6)");
+    if (p->precision != AP_FP64 && p->precision != AP_FP32) return set_error(c, AP_E_ARG, "precision");
+    if (p->n_funcs < 0 || (p->n_funcs > 0 && (!p->func || !p->c)) || !p->b_dens)
+        return set_error(c, AP_E_ARG, "ACE tables");
+    ace_free(c);
+    AceTables &t = c->ace;
+    t.n_max = N;
+    t.l_max = Lm;
+    t.n_funcs = p->n_funcs;
+    t.precision = p->precision;
+    t.rc = p->rc;
+    t.emb_A = p->emb_A;
+    t.E0 = p->E0;
+    std::vector<double> c1(N, 0.0), bd(N, 0.0), c2((size_t)(Lm + 1) * N * N, 0.0);
+    for (int q = 0; q < N; q++) bd[q] = p->b_dens[q] * std::sqrt(4 * kPi);
+    // blocks (L <= l1 <= l2)
+    struct Blk {
+        int L, l1, l2;
+    };
+    std::vector<Blk> blocks;
+    std::vector<int> bindex((Lm + 1) * (Lm + 1) * (Lm + 1), -1);
+    for (int L = 0; L <= Lm; L++)
+        for (int l1 = L; l1 <= Lm; l1++)
+            for (int l2 = l1; l2 <= Lm; l2++)
+                if ((L + l1 + l2) % 2 == 0 && l2 <= l1 + L) {
+                    bindex[(L * (Lm + 1) + l1) * (Lm + 1) + l2] = (int)blocks.size();
+                    blocks.push_back({L, l1, l2});
+                }
+    std::vector<double> c3(blocks.size() * (size_t)N * N * N, 0.0);
+    std::vector<char> used(blocks.size(), 0);
+    for (int f = 0; f < p->n_funcs; f++) {
+        const int32_t *r = p->func + 6 * f;
+        const double cf = p->c[f];
+        if (r[2] < 0) {
+            if (r[0] < 0 || r[0] >= N || r[1] != 0) return set_error(c, AP_E_ARG, "order-1 basis row");
+            c1[r[0]] += cf;
+        } else if (r[4] < 0) {
+            const int n1 = r[0], l = r[1], n2 = r[2];
+            if (r[3] != l || l < 0 || l > Lm || n1 < 0 || n2 < 0 || n1 >= N || n2 >= N)
+                return set_error(c, AP_E_ARG, "order-2 basis row");
+            if (n1 == n2) {
+                c2[((size_t)l * N + n1) * N + n2] += cf;
+            } else {
+                c2[((size_t)l * N + n1) * N + n2] += 0.5 * cf;
+                c2[((size_t)l * N + n2) * N + n1] += 0.5 * cf;
+            }
+        } else {
+            int ln[3][2] = {{r[1], r[0]}, {r[3], r[2]}, {r[5], r[4]}};
+            for (int q = 0; q < 3; q++)
+                if (ln[q][0] < 0 || ln[q][0] > Lm || ln[q][1] < 0 || ln[q][1] >= N)
+                    return set_error(c, AP_E_ARG, "order-3 basis row");
+            // stable sort of the three channels by l
+            for (int a = 1; a < 3; a++)
+                for (int q = a; q > 0 && ln[q][0] < ln[q - 1][0]; q--) {
+                    std::swap(ln[q][0], ln[q - 1][0]);
+                    std::swap(ln[q][1], ln[q - 1][1]);
+                }
+            const int L = ln[0][0], l1 = ln[1][0], l2 = ln[2][0];
+            const int bi = bindex[(L * (Lm + 1) + l1) * (Lm + 1) + l2];
+            if (bi < 0) return set_error(c, AP_E_ARG, "order-3 row violates the triangle or parity rule");
+            c3[(((size_t)bi * N + ln[1][1]) * N + ln[2][1]) * N + ln[0][1]] += cf;
+            used[bi] = 1;
+        }
+    }
+    // keep only blocks with coefficients; build coupling tables in three orderings
+    std::vector<int> hblk;
+    std::vector<int> kidx;
+    std::vector<double> kval, c3u;
+    int nb = 0;
+    for (size_t bi = 0; bi < blocks.size(); bi++) {
+        if (!used[bi]) continue;
+        const Blk &B = blocks[bi];
+        std::vector<Kap> k = coupling(B.l1, B.l2, B.L);
+        std::vector<int> d(kBlkInts, 0);
+        d[0] = B.L;
+        d[1] = B.l1;
+        d[2] = B.l2;
+        d[3] = (int)c3u.size();
+        c3u.insert(c3u.end(), c3.begin() + bi * (size_t)N * N * N, c3.begin() + (bi + 1) * (size_t)N * N * N);
+        auto emit = [&](int base, int key_lo, int key_hi, int which) {
+            for (int key = key_lo; key <= key_hi; key++) {
+                d[base + key - key_lo] = (int)kidx.size();
+                for (const Kap &e : k) {
+                    const int kv = which == 0 ? e.M : (which == 1 ? e.m1 : e.m2);
+                    if (kv != key) continue;
+                    kidx.push_back((e.m1 + 8) | ((e.m2 + 8) << 8) | ((e.M + 8) << 16));
+                    kval.push_back(e.v);
+                }
+            }
+            d[base + key_hi - key_lo + 1] = (int)kidx.size();
+        };
+        emit(4, -B.L, B.L, 0);
+        emit(18, -B.l1, B.l1, 1);
+        emit(32, -B.l2, B.l2, 2);
+        hblk.insert(hblk.end(), d.begin(), d.end());
+        nb++;
+    }
+    t.nblk = nb;
+    t.h_blk = hblk;
+    int rc;
+    if (p->precision == AP_FP32) {
+        rc = upload<float>(c, &t.c1, c1);
+        if (!rc) rc = upload<float>(c, &t.bd, bd);
+        if (!rc) rc = upload<float>(c, &t.c2, c2);
+        if (!rc) rc = upload<float>(c, &t.c3, c3u);
+        if (!rc) rc = upload<float>(c, &t.kval, kval);
+    } else {
+        rc = upload<double>(c, &t.c1, c1);
+        if (!rc) rc = upload<double>(c, &t.bd, bd);
+        if (!rc) rc = upload<double>(c, &t.c2, c2);
+        if (!rc) rc = upload<double>(c, &t.c3, c3u);
+        if (!rc) rc = upload<double>(c, &t.kval, kval);
+    }
+    if (!rc) rc = upload<double>(c, (void **)&t.c1d, c1);
+    if (!rc) rc = upload<double>(c, (void **)&t.bdd, std::vector<double>(p->b_dens, p->b_dens + N));
+    if (rc) return rc;
+    if (kidx.empty()) kidx.push_back(0);
+    if (hblk.empty()) hblk.push_back(0);
+    rc = hip_check(c, hipMalloc(&t.kidx, sizeof(int) * kidx.size()), "ace tables");
+    if (!rc) rc = hip_check(c, hipMemcpy(t.kidx, kidx.data(), sizeof(int) * kidx.size(), hipMemcpyHostToDevice), "ace");
+    if (!rc) rc = hip_check(c, hipMalloc(&t.blk, sizeof(int) * hblk.size()), "ace tables");
+    if (!rc) rc = hip_check(c, hipMemcpy(t.blk, hblk.data(), sizeof(int) * hblk.size(), hipMemcpyHostToDevice), "ace");
+    return rc;
+}
+
+template <typename T, int NMAX, int LMAX>
+static void launch_t(ap_ctx *c, const AceArgs &a, int grid) {
+    k_ace_energy<T, NMAX, LMAX><<<grid, kBlock, 0, c->stream>>>(a);
+    k_ace_pairforce<T, NMAX, LMAX><<<grid, 128, 0, c->stream>>>(a);
+}
+
+int launch_ace(ap_ctx *c, int n, const double *box, int grid_cap) {
+    const AceTables &t = c->ace;
+    AceArgs a;
+    a.pos = c->pos;
+    a.n = n;
+    for (int q = 0; q < 3; q++) a.L[q] = box[q];
+    a.rc = t.rc;
+    a.ncount = c->nbr_cnt;
+    a.nidx = c->nbr_idx;
+    a.max_nbr = c->max_nbr;
+    a.slist = c->slist;
+    a.scount = c->d_flags + 2;
+    a.dlam = c->dlam;
+    a.wbar = c->wbar;
+    a.Ef = c->Ef;
+    a.Ep = c->Ep;
+    a.Et = c->Et;
+    a.gbuf = c->gbuf;
+    a.fpair = c->fpair;
+    a.c1 = t.c1;
+    a.bd = t.bd;
+    a.c2 = t.c2;
+    a.c3 = t.c3;
+    a.kval = t.kval;
+    a.kidx = t.kidx;
+    a.blk = t.blk;
+    a.nblk = t.nblk;
+    a.emb_A = t.emb_A;
+    a.E0 = t.E0;
+    a.c1d = t.c1d;
+    a.bdd = t.bdd;
+    a.flags = c->d_flags;
+    const int grid = grid_cap < 1 ? 1 : grid_cap;
+    const bool f32 = t.precision == AP_FP32;
+    if (t.n_max == 12) {
+        if (f32)
+            launch_t<float, 12, 6>(c, a, grid);
+        else
+            launch_t<double, 12, 6>(c, a, grid);
+    } else if (t.n_max == 8) {
+        if (f32)
+            launch_t<float, 8, 4>(c, a, grid);
+        else
+            launch_t<double, 8, 4>(c, a, grid);
+    } else {
+        if (f32)
+            launch_t<float, 4, 2>(c, a, grid);
+        else
+            launch_t<double, 4, 2>(c, a, grid);
+    }
+    return hip_check(c, hipGetLastError(), "ace");
+}
+
+}  // namespace ap

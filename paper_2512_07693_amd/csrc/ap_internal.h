@@ -1,0 +1,175 @@
+// Library-internal declarations of the MI355X adaptive-precision EAM/ACE library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "ap.h"
+
+namespace ap {
+
+constexpr int kBlock = 256;      // threads per workgroup of the per-atom kernels (4 wavefronts)
+constexpr int kAceMaxValid = 128; // neighbours within the ACE cutoff held per site in LDS
+constexpr double kConv = 9648.533212;  // eV / (A u) in A / ps^2
+constexpr double kPi = 3.14159265358979323846;
+
+// Error bits raised by kernels in ctx->d_flags[1].
+enum : int { kErrOverflow = 1, kErrNonFinite = 2, kErrCsp = 4, kErrAceNbr = 8, kErrDensity = 16 };
+
+// Block b of nb runs on XCD (b % 8); giving each XCD a contiguous range of atoms keeps the
+// neighbour gathers of one XCD inside its own L2.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    const int per = (nb + 7) / 8;
+    const int x = b % 8, q = b / 8;
+    const int full = nb - (per - 1) * 8;  // XCDs that get `per` blocks (the rest get per-1)
+    const int start = x < full ? x * per : full * per + (x - full) * (per - 1);
+    return start + q;
+}
+
+__device__ __forceinline__ double wrap_coord(double x, double L) {
+#pragma clang fp contract(off)
+    double y = x - L * floor(x / L);
+    if (y >= L) y = 0.0;
+    return y;
+}
+
+__device__ __forceinline__ double min_image(double d, double L) {
+#pragma clang fp contract(off)
+    return d - L * rint(d / L);
+}
+
+// |u|^2 as the plain left-to-right sum of products, never fused: the neighbour test must give the
+// same set as any IEEE implementation of the same expression.
+__device__ __forceinline__ double norm2_nofma(double x, double y, double z) {
+#pragma clang fp contract(off)
+    return x * x + y * y + z * z;
+}
+
+// f_trans of Eq. (S1) and its derivative.
+template <typename T>
+__host__ __device__ __forceinline__ T ftrans(T x, T lo, T hi) {
+    if (x <= lo) return T(1);
+    if (x >= hi) return T(0);
+    T y = (hi + lo - T(2) * x) / (hi - lo);
+    T y2 = y * y;
+    return T(0.5) + y * (T(0.9375) + y2 * (T(-0.625) + T(0.1875) * y2));
+}
+template <typename T>
+__host__ __device__ __forceinline__ T ftrans_d(T x, T lo, T hi) {
+    if (x <= lo || x >= hi) return T(0);
+    T y = (hi + lo - T(2) * x) / (hi - lo);
+    T s = T(1) - y * y;
+    return T(0.9375) * s * s * (T(-2) / (hi - lo));
+}
+
+struct AceTables {
+    int n_max = 0, l_max = 0, n_funcs = 0, precision = AP_FP64;
+    double rc = 0, emb_A = 0, E0 = 0;
+    int nblk = 0;
+    // device, element type double or float according to precision
+    void *c1 = nullptr;   // [n_max]          coefficient of A_{n00}
+    void *bd = nullptr;   // [n_max]          b_dens * sqrt(4 pi)
+    double *c1d = nullptr, *bdd = nullptr;  // FP64 copies: the l = 0 two-body and density sums
+    void *c2 = nullptr;   // [l_max+1][n][n]  symmetric order-2 matrix
+    void *c3 = nullptr;   // [nblk][n][n][n]  order-3 coefficients of block (L, l1, l2)
+    void *kval = nullptr; // coupling values, three orderings (by M, by m1, by m2)
+    int *kidx = nullptr;  // packed (m1 + 8) | (m2 + 8) << 8 | (M + 8) << 16, same three orderings
+    int *blk = nullptr;   // [nblk][kBlkInts] block descriptors
+    std::vector<int> h_blk;
+};
+constexpr int kBlkInts = 48;  // L, l1, l2, c3 offset, then 3 x 14 start offsets (by M, m1, m2)
+
+struct Geometry {
+    double L[3];
+    int nc[3];
+    int ncell;
+};
+
+}  // namespace ap
+
+struct ap_ctx {
+    hipStream_t stream = nullptr;
+    int n_cap = 0, max_nbr = 0;
+    double skin = 0;
+    std::string err;
+    int device = 0;
+
+    bool have_pot = false;
+    ap_eam_params eam{};
+    ap_switch_params sw{};
+    ap::AceTables ace;
+
+    // CSP pair list and its reverse (fixed at set-up)
+    int csp_n = 0, n_csp = 0;
+    int32_t *csp_t = nullptr;     // [n_csp][n] slot-major
+    int32_t *rev_start = nullptr; // [n+1]
+    int32_t *rev_code = nullptr;  // [n * n_csp]: j * 16 + t (atom j holds this atom in its slot t)
+
+    // positions as used internally (wrapped), build-time positions, flags
+    double *pos = nullptr;       // [3][n_cap]
+    double *pos_build = nullptr; // [3][n_cap]
+    int *d_flags = nullptr;      // [0] rebuild needed, [1] error bits, [2] n_precise, [3] rebuilt in step
+    double list_r = -1;          // radius of the current list
+    int list_n = -1;
+    double list_box[3] = {0, 0, 0};
+
+    // cell list
+    int ncell_cap = 0;
+    int *cell_of = nullptr, *cell_cnt = nullptr, *cell_start = nullptr, *cell_fill = nullptr, *cell_atoms = nullptr;
+    int *scan_tmp = nullptr;
+
+    // neighbour list (slot-major) and reverse slot index
+    int32_t *nbr_cnt = nullptr, *nbr_idx = nullptr, *nbr_rev = nullptr;
+
+    // per-atom intermediates
+    double *g = nullptr, *d = nullptr, *wbar = nullptr, *lam = nullptr, *dlam = nullptr;
+    double *Ef = nullptr, *Ep = nullptr, *Et = nullptr, *W = nullptr, *xip = nullptr;
+    int *sidx = nullptr, *slist = nullptr, *blk_cnt = nullptr, *mark = nullptr;
+    void *fpair = nullptr;       // [n_cap][max_nbr][3] ACE pair gradients (double or float)
+    void *gbuf = nullptr;        // [n_cap][n_max * (l_max+1)^2] dE/dA of the S atoms
+    size_t fpair_bytes = 0, gbuf_bytes = 0;
+    double *partials = nullptr;  // per-block partial sums [nblk][16]
+    double *scalars = nullptr;   // [0] E_tot, [1..9] virial, [10] E_kin, [11..13] P
+};
+
+namespace ap {
+
+int set_error(ap_ctx *c, int code, const std::string &msg);
+int hip_check(ap_ctx *c, hipError_t e, const char *what);
+
+// geometry.hip
+int ensure_list(ap_ctx *c, int n, const double *box, double r_list, bool force);
+int prepare_positions(ap_ctx *c, int n, const double *pos_in, const double *box);
+void launch_csp_value(ap_ctx *c, int n, const double *box);
+int build_csp_pairs(ap_ctx *c, int n, const double *box, int n_csp, int32_t *out);
+int install_csp(ap_ctx *c, int n, int n_csp, const int32_t *list);
+void launch_fill_int(ap_ctx *c, int *p, int v, int count);
+void launch_fill_double(ap_ctx *c, double *p, double v, int count);
+void launch_scan(ap_ctx *c, const int *in, int *out, int len, int *total, const int *gate);
+
+// ace.hip
+int ace_setup(ap_ctx *c, const ap_ace_params *p);
+void ace_free(ap_ctx *c);
+int launch_ace(ap_ctx *c, int n, const double *box, int grid_cap);
+
+// forces.hip
+struct EvalFlags {
+    bool switching;   // lambda computed from the descriptor
+    bool grad_lambda; // include the grad-lambda forces
+    double lam_const; // value of lambda when not computed
+    bool eam_forces;  // EAM family included
+    bool ace_forces;  // ACE family included
+};
+void launch_dens_desc(ap_ctx *c, int n, const double *box, const EvalFlags &f, const double *lam_in);
+void launch_compact(ap_ctx *c, int n, const int32_t *subset, int n_subset);
+void launch_W(ap_ctx *c, int n, const double *box);
+void launch_force(ap_ctx *c, int n, const double *box, const EvalFlags &f, double *E_atom, double *F);
+void launch_reduce(ap_ctx *c, int nblocks, double *E_tot, double *virial9);
+
+int sync_and_check(ap_ctx *c);
+
+}  // namespace ap

@@ -1,0 +1,433 @@
+// C ABI entry points (include/ap.h): argument checks, the evaluation pipeline and velocity Verlet.
+#include <algorithm>
+#include <cstring>
+
+#include "ap_internal.h"
+
+static thread_local std::string g_create_error;
+
+namespace ap {
+
+int set_error(ap_ctx *c, int code, const std::string &msg) {
+    if (c)
+        c->err = msg;
+    else
+        g_create_error = msg;
+    return code;
+}
+
+int hip_check(ap_ctx *c, hipError_t e, const char *what) {
+    if (e == hipSuccess) return AP_OK;
+    return set_error(c, AP_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int sync_and_check(ap_ctx *c) {
+    int rc = hip_check(c, hipStreamSynchronize(c->stream), "stream synchronize");
+    if (rc) return rc;
+    int flags[4];
+    rc = hip_check(c, hipMemcpy(flags, c->d_flags, sizeof(flags), hipMemcpyDeviceToHost), "flags");
+    if (rc) return rc;
+    const int e = flags[1];
+    if (e & kErrOverflow) return set_error(c, AP_E_NBR_OVERFLOW, "neighbour count above max_nbr, or index out of range");
+    if (e & kErrAceNbr) return set_error(c, AP_E_NBR_OVERFLOW, "more than 128 neighbours inside the ACE cutoff");
+    if (e & kErrCsp) return set_error(c, AP_E_CSP, "CSP list invalid or too few neighbours for the CSP pairs");
+    if (e & kErrNonFinite) return set_error(c, AP_E_NONFINITE, "non-finite energy or force");
+    return AP_OK;
+}
+
+static double list_radius(const ap_ctx *c, bool switching) {
+    double r = std::max(c->eam.rc, c->ace.rc);
+    if (switching) r = std::max(r, c->sw.r_w);
+    return r + c->skin;
+}
+
+static int nblocks(int n) { return (n + kBlock - 1) / kBlock; }
+
+// The force evaluation on the positions already in c->pos.
+static int evaluate(ap_ctx *c, int n, const double *box, const EvalFlags &f, const double *lam_in,
+                    const int32_t *subset, int n_subset, bool run_ace, double *E_tot, double *E_atom, double *F,
+                    double *virial, bool force_list) {
+    int rc = ensure_list(c, n, box, list_radius(c, f.switching), force_list);
+    if (rc) return rc;
+    if (f.switching) launch_csp_value(c, n, box);
+    launch_dens_desc(c, n, box, f, lam_in);
+    if (run_ace) {
+        launch_compact(c, n, subset, n_subset);
+        rc = launch_ace(c, n, box, std::min(n, 8192));
+        if (rc) return rc;
+    } else {
+        launch_fill_int(c, c->sidx, -1, n);
+        launch_fill_int(c, c->d_flags + 2, 0, 1);
+    }
+    if (f.switching && f.grad_lambda) launch_W(c, n, box);
+    launch_force(c, n, box, f, E_atom, F);
+    launch_reduce(c, nblocks(n), E_tot, virial);
+    return hip_check(c, hipGetLastError(), "evaluate");
+}
+
+static int check_common(ap_ctx *c, int n, const double *pos, const ap_box *box, bool need_pot) {
+    if (!c) return AP_E_ARG;
+    if (n <= 0 || n > c->n_cap) return set_error(c, AP_E_ARG, "n out of range (1..n_max_atoms)");
+    if (!pos || !box) return set_error(c, AP_E_ARG, "null positions or box");
+    for (int a = 0; a < 3; a++)
+        if (!(box->L[a] > 0) || !std::isfinite(box->L[a])) return set_error(c, AP_E_ARG, "box lengths must be > 0");
+    if (need_pot && !c->have_pot) return set_error(c, AP_E_STATE, "ap_set_potential has not been called");
+    return AP_OK;
+}
+
+static int check_csp(ap_ctx *c, int n) {
+    if (!c->csp_t || c->csp_n != n) return set_error(c, AP_E_STATE, "no CSP pair list for this atom count");
+    return AP_OK;
+}
+
+static EvalFlags mixed_flags(const ap_ctx *c) {
+    EvalFlags f;
+    f.switching = c->sw.lambda_mode == AP_LAMBDA_COMPUTED;
+    f.grad_lambda = c->sw.grad_lambda != 0;
+    f.lam_const = c->sw.lambda_mode == AP_LAMBDA_FAST ? 1.0 : 0.0;
+    f.eam_forces = true;
+    f.ace_forces = true;
+    return f;
+}
+
+// ------------------------------------------------------------------------------------------
+// Velocity Verlet kernels
+// ------------------------------------------------------------------------------------------
+__global__ void k_vv_first(double *pos, double *vel, const double *F, double *ipos, int n, double hdtm, double dt,
+                           double Lx, double Ly, double Lz) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double L[3] = {Lx, Ly, Lz};
+    for (int a = 0; a < 3; a++) {
+        const size_t o = (size_t)a * n + i;
+        const double v = vel[o] + hdtm * F[o];
+        vel[o] = v;
+        const double x = wrap_coord(pos[o] + dt * v, L[a]);
+        pos[o] = x;
+        ipos[o] = x;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_vv_second(double *vel, const double *F, int n, double hdtm, double mass,
+                                                      double *partials) {
+    __shared__ double sh[kBlock / 64];
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double ek = 0, p[3] = {0, 0, 0};
+    if (i < n) {
+        for (int a = 0; a < 3; a++) {
+            const size_t o = (size_t)a * n + i;
+            const double v = vel[o] + hdtm * F[o];
+            vel[o] = v;
+            ek += 0.5 * mass * v * v / kConv;
+            p[a] = mass * v;
+        }
+    }
+    double vals[4] = {ek, p[0], p[1], p[2]};
+    for (int q = 0; q < 4; q++) {
+        double v = vals[q];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s = 0;
+            for (int w = 0; w < kBlock / 64; w++) s += sh[w];
+            partials[(size_t)blockIdx.x * 16 + 10 + q] = s;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_thermo(const double *partials, int nb, const double *scalars,
+                                                   const int *flags, double *row) {
+    __shared__ double sh[kBlock / 64];
+    for (int q = 0; q < 4; q++) {
+        double s = 0;
+        for (int b = threadIdx.x; b < nb; b += kBlock) s += partials[(size_t)b * 16 + 10 + q];
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0;
+            for (int w = 0; w < kBlock / 64; w++) t += sh[w];
+            if (q == 0) {
+                row[0] = scalars[0];
+                row[1] = t;
+                row[2] = scalars[0] + t;
+            } else {
+                row[2 + q] = t;
+            }
+        }
+    }
+    if (threadIdx.x == 0) {
+        row[6] = (double)flags[2];
+        row[7] = (double)flags[3];
+    }
+}
+
+}  // namespace ap
+
+using namespace ap;
+
+extern "C" {
+
+const char *ap_last_error(const ap_ctx *ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
+
+void ap_ctx_destroy(ap_ctx *c) {
+    if (!c) return;
+    ace_free(c);
+    void *bufs[] = {c->csp_t, c->rev_start, c->rev_code, c->pos, c->pos_build, c->d_flags, c->cell_of, c->cell_cnt,
+                    c->cell_start, c->cell_fill, c->cell_atoms, c->nbr_cnt, c->nbr_idx, c->nbr_rev, c->g, c->d,
+                    c->wbar, c->lam, c->dlam, c->Ef, c->Ep, c->Et, c->W, c->xip, c->sidx, c->slist, c->blk_cnt,
+                    c->mark, c->fpair, c->gbuf, c->partials, c->scalars};
+    for (void *p : bufs) hipFree(p);
+    delete c;
+}
+
+int ap_ctx_create(ap_ctx **out, int n_max_atoms, int max_nbr, double skin, void *hip_stream) {
+    if (!out) return set_error(nullptr, AP_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (n_max_atoms <= 0 || max_nbr <= 0 || max_nbr > 1536 || !(skin >= 0.0))
+        return set_error(nullptr, AP_E_ARG, "n_max_atoms > 0, 0 < max_nbr <= 1536, skin >= 0 required");
+    ap_ctx *c = new ap_ctx();
+    c->stream = (hipStream_t)hip_stream;
+    c->n_cap = n_max_atoms;
+    c->max_nbr = max_nbr;
+    c->skin = skin;
+    hipGetDevice(&c->device);
+    const size_t n = (size_t)n_max_atoms, nb = (size_t)nblocks(n_max_atoms);
+    int rc = AP_OK;
+    auto alloc = [&](auto **p, size_t count, size_t elem) {
+        if (rc) return;
+        rc = hip_check(c, hipMalloc((void **)p, std::max<size_t>(1, count * elem)), "context allocation");
+    };
+    alloc(&c->pos, 3 * n, 8);
+    alloc(&c->pos_build, 3 * n, 8);
+    alloc(&c->d_flags, 8, 4);
+    alloc(&c->cell_of, n + 1, 4);
+    alloc(&c->cell_atoms, n, 4);
+    alloc(&c->nbr_cnt, n, 4);
+    alloc(&c->nbr_idx, n * max_nbr, 4);
+    alloc(&c->nbr_rev, n * max_nbr, 4);
+    double **per_atom[] = {&c->g, &c->d, &c->wbar, &c->lam, &c->dlam, &c->Ef, &c->Ep, &c->Et, &c->W, &c->xip};
+    for (double **p : per_atom) alloc(p, n, 8);
+    alloc(&c->sidx, n, 4);
+    alloc(&c->slist, n, 4);
+    alloc(&c->mark, n, 4);
+    alloc(&c->blk_cnt, 2 * nb + 2, 4);
+    alloc(&c->partials, nb * 16, 8);
+    alloc(&c->scalars, 16, 8);
+    if (rc) {
+        g_create_error = c->err;
+        ap_ctx_destroy(c);
+        return rc;
+    }
+    launch_fill_int(c, c->d_flags, 0, 8);
+    launch_fill_double(c, c->g, 0.0, (int)n);
+    launch_fill_double(c, c->W, 0.0, (int)n);
+    launch_fill_double(c, c->d, 0.0, (int)n);
+    rc = hip_check(c, hipStreamSynchronize(c->stream), "context init");
+    if (rc) {
+        g_create_error = c->err;
+        ap_ctx_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return AP_OK;
+}
+
+int ap_set_potential(ap_ctx *c, const ap_eam_params *eam, const ap_ace_params *ace, const ap_switch_params *sw) {
+    if (!c) return AP_E_ARG;
+    if (!eam || !ace || !sw) return set_error(c, AP_E_ARG, "null parameter struct");
+    if (!(eam->rc > 0) || !(ace->rc > 0)) return set_error(c, AP_E_ARG, "cutoffs must be > 0");
+    if (sw->lambda_mode != AP_LAMBDA_COMPUTED && sw->lambda_mode != AP_LAMBDA_PRECISE &&
+        sw->lambda_mode != AP_LAMBDA_FAST)
+        return set_error(c, AP_E_ARG, "lambda_mode");
+    if (sw->indicator != AP_IND_CSP) return set_error(c, AP_E_ARG, "only the CSP indicator is available here");
+    if (sw->lambda_mode == AP_LAMBDA_COMPUTED && (!(sw->d_hi > sw->d_lo) || !(sw->r_w > 1.0)))
+        return set_error(c, AP_E_ARG, "switching parameters need d_hi > d_lo and r_w > 1 A");
+    int rc = ace_setup(c, ace);
+    if (rc) return rc;
+    const int NA = ace->n_max * (ace->l_max + 1) * (ace->l_max + 1);
+    const size_t es = ace->precision == AP_FP32 ? 4 : 8;
+    const size_t fb = (size_t)c->n_cap * c->max_nbr * 3 * es, gb = (size_t)c->n_cap * NA * es;
+    if (fb != c->fpair_bytes) {
+        hipFree(c->fpair);
+        c->fpair = nullptr;
+        rc = hip_check(c, hipMalloc(&c->fpair, fb), "ACE pair buffer");
+        if (rc) return rc;
+        c->fpair_bytes = fb;
+    }
+    if (gb != c->gbuf_bytes) {
+        hipFree(c->gbuf);
+        c->gbuf = nullptr;
+        rc = hip_check(c, hipMalloc(&c->gbuf, gb), "ACE adjoint buffer");
+        if (rc) return rc;
+        c->gbuf_bytes = gb;
+    }
+    c->eam = *eam;
+    c->sw = *sw;
+    c->have_pot = true;
+    c->list_r = -1;
+    return AP_OK;
+}
+
+int ap_csp_pairs_build(ap_ctx *c, int n, const double *pos_ref, const ap_box *box, int n_csp, int32_t *csp_list) {
+    int rc = check_common(c, n, pos_ref, box, false);
+    if (rc) return rc;
+    if (!csp_list) return set_error(c, AP_E_ARG, "csp_list is NULL");
+    if (n_csp != 8 && n_csp != 12) return set_error(c, AP_E_CSP, "n_csp must be 8 or 12");
+    launch_fill_int(c, c->d_flags + 1, 0, 1);
+    rc = prepare_positions(c, n, pos_ref, box->L);
+    if (!rc) rc = build_csp_pairs(c, n, box->L, n_csp, csp_list);
+    if (!rc) rc = sync_and_check(c);
+    if (!rc) rc = install_csp(c, n, n_csp, csp_list);
+    return rc;
+}
+
+int ap_set_csp_list(ap_ctx *c, int n, int n_csp, const int32_t *csp_list) {
+    if (!c) return AP_E_ARG;
+    if (n <= 0 || n > c->n_cap || !csp_list) return set_error(c, AP_E_ARG, "n or csp_list");
+    int rc = install_csp(c, n, n_csp, csp_list);
+    return rc;
+}
+
+__global__ void k_copy_list(const int32_t *cnt, const int32_t *idx, int n, int max_out, int32_t *ocnt, int32_t *oidx,
+                            int *flags) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int k = cnt[i];
+    if (k > max_out) {
+        atomicOr(&flags[1], kErrOverflow);
+        k = max_out;
+    }
+    ocnt[i] = cnt[i];
+    for (int q = 0; q < k; q++) oidx[(size_t)q * n + i] = idx[(size_t)q * n + i];
+}
+
+int ap_nblist_build(ap_ctx *c, int n, const double *pos, const ap_box *box, double r_list, int max_nbr,
+                    int32_t *nbr_count, int32_t *nbr_idx) {
+    int rc = check_common(c, n, pos, box, false);
+    if (rc) return rc;
+    if (!(r_list > 0) || max_nbr <= 0 || !nbr_count || !nbr_idx) return set_error(c, AP_E_ARG, "list arguments");
+    launch_fill_int(c, c->d_flags + 1, 0, 1);
+    rc = prepare_positions(c, n, pos, box->L);
+    if (!rc) rc = ensure_list(c, n, box->L, r_list, true);
+    if (!rc) {
+        k_copy_list<<<nblocks(n), kBlock, 0, c->stream>>>(c->nbr_cnt, c->nbr_idx, n, max_nbr, nbr_count, nbr_idx,
+                                                          c->d_flags);
+        rc = hip_check(c, hipGetLastError(), "copy list");
+    }
+    if (!rc) rc = sync_and_check(c);
+    c->list_r = -1;  // the evaluation list uses its own radius
+    return rc;
+}
+
+int ap_eam_eval(ap_ctx *c, int n, const double *pos, const int32_t *species, const ap_box *box,
+                const double *lambda, double *E_tot, double *E_atom, double *F, double *virial9) {
+    int rc = check_common(c, n, pos, box, true);
+    if (rc) return rc;
+    if (species) return set_error(c, AP_E_ARG, "single-species potentials: species must be NULL");
+    EvalFlags f{false, false, 1.0, true, false};
+    launch_fill_int(c, c->d_flags + 1, 0, 1);
+    rc = prepare_positions(c, n, pos, box->L);
+    if (!rc) rc = evaluate(c, n, box->L, f, lambda, nullptr, 0, false, E_tot, E_atom, F, virial9, true);
+    if (!rc) rc = sync_and_check(c);
+    return rc;
+}
+
+__global__ void k_copy_d(const double *src, double *dst, int n) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+int ap_switch_eval(ap_ctx *c, int n, const double *pos, const ap_box *box, double *g, double *d, double *wbar,
+                   double *lambda, double *dlambda, int32_t *n_precise) {
+    int rc = check_common(c, n, pos, box, true);
+    if (rc) return rc;
+    rc = check_csp(c, n);
+    if (rc) return rc;
+    EvalFlags f{true, false, 1.0, true, false};
+    launch_fill_int(c, c->d_flags + 1, 0, 1);
+    rc = prepare_positions(c, n, pos, box->L);
+    if (!rc) rc = ensure_list(c, n, box->L, list_radius(c, true), true);
+    if (rc) return rc;
+    launch_csp_value(c, n, box->L);
+    launch_dens_desc(c, n, box->L, f, nullptr);
+    launch_compact(c, n, nullptr, 0);
+    const int nb = nblocks(n);
+    if (g) k_copy_d<<<nb, kBlock, 0, c->stream>>>(c->g, g, n);
+    if (d) k_copy_d<<<nb, kBlock, 0, c->stream>>>(c->d, d, n);
+    if (wbar) k_copy_d<<<nb, kBlock, 0, c->stream>>>(c->wbar, wbar, n);
+    if (lambda) k_copy_d<<<nb, kBlock, 0, c->stream>>>(c->lam, lambda, n);
+    if (dlambda) k_copy_d<<<nb, kBlock, 0, c->stream>>>(c->dlam, dlambda, n);
+    if (n_precise) hipMemcpyAsync(n_precise, c->d_flags + 2, sizeof(int32_t), hipMemcpyDeviceToDevice, c->stream);
+    rc = hip_check(c, hipGetLastError(), "switch");
+    if (!rc) rc = sync_and_check(c);
+    return rc;
+}
+
+int ap_ace_eval(ap_ctx *c, int n, const double *pos, const int32_t *species, const ap_box *box,
+                const int32_t *subset, int n_subset, double *E_tot, double *E_atom, double *F, double *virial9) {
+    int rc = check_common(c, n, pos, box, true);
+    if (rc) return rc;
+    if (species) return set_error(c, AP_E_ARG, "single-species potentials: species must be NULL");
+    if (subset && (n_subset < 0 || n_subset > n)) return set_error(c, AP_E_ARG, "n_subset");
+    EvalFlags f{false, false, 0.0, false, true};
+    launch_fill_int(c, c->d_flags + 1, 0, 1);
+    rc = prepare_positions(c, n, pos, box->L);
+    if (!rc) rc = evaluate(c, n, box->L, f, nullptr, subset, n_subset, true, E_tot, E_atom, F, virial9, true);
+    if (!rc) rc = sync_and_check(c);
+    return rc;
+}
+
+int ap_mixed_energy_forces(ap_ctx *c, int n, const double *pos, const int32_t *species, const ap_box *box,
+                           double *E_tot, double *E_atom, double *F, double *virial9, double *lambda_out) {
+    int rc = check_common(c, n, pos, box, true);
+    if (rc) return rc;
+    if (species) return set_error(c, AP_E_ARG, "single-species potentials: species must be NULL");
+    const EvalFlags f = mixed_flags(c);
+    if (f.switching) {
+        rc = check_csp(c, n);
+        if (rc) return rc;
+    }
+    launch_fill_int(c, c->d_flags + 1, 0, 1);
+    rc = prepare_positions(c, n, pos, box->L);
+    const bool run_ace = !(c->sw.lambda_mode == AP_LAMBDA_FAST);
+    if (!rc) rc = evaluate(c, n, box->L, f, nullptr, nullptr, 0, run_ace, E_tot, E_atom, F, virial9, true);
+    if (!rc && lambda_out) k_copy_d<<<nblocks(n), kBlock, 0, c->stream>>>(c->lam, lambda_out, n);
+    if (!rc) rc = sync_and_check(c);
+    return rc;
+}
+
+int ap_vv_step(ap_ctx *c, int n, double *pos, double *vel, double *F, double mass, double dt, int n_steps,
+               const ap_box *box, double *thermo) {
+    int rc = check_common(c, n, pos, box, true);
+    if (rc) return rc;
+    if (!vel || !F || !thermo || n_steps < 0 || !(mass > 0) || !(dt > 0))
+        return set_error(c, AP_E_ARG, "vel, F, thermo, n_steps >= 0, mass > 0, dt > 0 required");
+    const EvalFlags f = mixed_flags(c);
+    if (f.switching) {
+        rc = check_csp(c, n);
+        if (rc) return rc;
+    }
+    const bool run_ace = !(c->sw.lambda_mode == AP_LAMBDA_FAST);
+    const double hdtm = 0.5 * dt / mass * kConv;
+    const int nb = nblocks(n);
+    launch_fill_int(c, c->d_flags + 1, 0, 1);
+    // the list must describe these positions: rebuild on the first step of every call
+    bool force = true;
+    for (int s = 0; s < n_steps; s++) {
+        k_vv_first<<<nb, kBlock, 0, c->stream>>>(pos, vel, F, c->pos, n, hdtm, dt, box->L[0], box->L[1], box->L[2]);
+        rc = evaluate(c, n, box->L, f, nullptr, nullptr, 0, run_ace, nullptr, nullptr, F, nullptr, force);
+        if (rc) return rc;
+        force = false;
+        k_vv_second<<<nb, kBlock, 0, c->stream>>>(vel, F, n, hdtm, mass, c->partials);
+        k_thermo<<<1, kBlock, 0, c->stream>>>(c->partials, nb, c->scalars, c->d_flags, thermo + (size_t)8 * s);
+    }
+    rc = hip_check(c, hipGetLastError(), "vv");
+    if (!rc) rc = sync_and_check(c);
+    return rc;
+}
+
+}  // extern "C"

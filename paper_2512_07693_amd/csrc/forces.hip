@@ -1,0 +1,431 @@
+// Switching parameter, EAM and the conservative force assembly.
+//
+//   k_dens_desc : one pass over the neighbour list per atom gives the EAM density and pair energy
+//                 (B1) and, when switching, the descriptor Eq. (6) and lambda Eq. (2).
+//   k_compact   : ordered compaction of S = {i : lambda_i < 1} (device-side count).
+//   k_W         : W_j = sum_k E~_k w(r_kj) of (S25), E~ of (S17) written by the ACE kernel.
+//   k_force     : gather-only assembly of F_i = sum_k (f_ki - f_ik), (A1)-(A2), with the EAM (S12),
+//                 ACE (S14), weight (S21) and CSP (S27) families; E_i of Eq. (4); per-block partial
+//                 sums of the energy and of the virial.
+// Every sum runs in a fixed order, so results are bit-reproducible run to run.
+#include "ap_internal.h"
+
+namespace ap {
+
+struct EamP {
+    double A, beta, c0, c1, c2, rc, rc2;
+};
+static EamP eamp(const ap_eam_params &e) { return {e.A, e.beta, e.c0, e.c1, e.c2, e.rc, e.rc * e.rc}; }
+
+__device__ __forceinline__ void eam_pair(const EamP &p, double r, double &z, double &dz, double &ph, double &dph) {
+    const double x = r - p.rc;
+    const double q = p.c0 + r * (p.c1 + p.c2 * r);
+    z = x * x * (1.0 + p.beta * x / p.rc);
+    dz = x * (2.0 + 3.0 * p.beta * x / p.rc);
+    ph = x * x * q;
+    dph = x * (2.0 * q + x * (p.c1 + 2.0 * p.c2 * r));
+}
+
+struct SwP {
+    double d_lo, d_hi, r_w, r_w2, d0;
+};
+
+__global__ __launch_bounds__(kBlock) void k_dens_desc(const double *__restrict__ pos, int n, double Lx, double Ly,
+                                                      double Lz, EamP ep, SwP sp, int switching, double lam_const,
+                                                      const double *__restrict__ lam_in,
+                                                      const int32_t *__restrict__ ncount,
+                                                      const int32_t *__restrict__ nidx, const double *__restrict__ g,
+                                                      double *__restrict__ Ef, double *__restrict__ xip,
+                                                      double *__restrict__ wbar, double *__restrict__ dd,
+                                                      double *__restrict__ lam, double *__restrict__ dlam,
+                                                      double *__restrict__ Ep, double *__restrict__ Et, int *flags) {
+    const int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
+    const int cnt = ncount[i];
+    double z = 0.0, pair = 0.0, ws = 1.0, gs = switching ? g[i] : 0.0;  // self term of Eq. (6): w(0) = 1
+    for (int k = 0; k < cnt; k++) {
+        const int j = nidx[(size_t)k * n + i];
+        const double ux = min_image(pos[j] - xi, Lx), uy = min_image(pos[n + j] - yi, Ly),
+                     uz = min_image(pos[2 * n + j] - zi, Lz);
+        const double r2 = ux * ux + uy * uy + uz * uz;
+        if (r2 < ep.rc2) {
+            double zz, dz, ph, dph;
+            eam_pair(ep, sqrt(r2), zz, dz, ph, dph);
+            z += zz;
+            pair += ph;
+        }
+        if (switching && r2 < sp.r_w2) {
+            const double w = ftrans(sqrt(r2), sp.r_w - 1.0, sp.r_w);
+            ws += w;
+            gs += g[j] * w;
+        }
+    }
+    double emb = 0.0, demb = 0.0;
+    if (z > 0.0) {
+        const double s = sqrt(z);
+        emb = -ep.A * s;
+        demb = -0.5 * ep.A / s;
+    }
+    Ef[i] = emb + 0.5 * pair;
+    xip[i] = demb;
+    double l, dl = 0.0, d = 0.0;
+    if (switching) {
+        d = gs / ws - sp.d0;
+        l = ftrans(d, sp.d_lo, sp.d_hi);
+        dl = ftrans_d(d, sp.d_lo, sp.d_hi);
+    } else {
+        l = lam_in ? lam_in[i] : lam_const;
+        ws = 1.0;
+    }
+    wbar[i] = ws;
+    dd[i] = d;
+    lam[i] = l;
+    dlam[i] = dl;
+    Ep[i] = 0.0;
+    Et[i] = 0.0;
+}
+
+void launch_dens_desc(ap_ctx *c, int n, const double *box, const EvalFlags &f, const double *lam_in) {
+    const SwP sp{c->sw.d_lo, c->sw.d_hi, c->sw.r_w, c->sw.r_w * c->sw.r_w, c->sw.d0};
+    k_dens_desc<<<(n + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(
+        c->pos, n, box[0], box[1], box[2], eamp(c->eam), sp, f.switching ? 1 : 0, f.lam_const, lam_in, c->nbr_cnt,
+        c->nbr_idx, c->g, c->Ef, c->xip, c->wbar, c->d, c->lam, c->dlam, c->Ep, c->Et, c->d_flags);
+}
+
+// ------------------------------------------------------------------------------------------
+// Ordered compaction of S = {i : lambda_i < 1}, or of an explicit subset.
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ bool in_s(const double *lam, const int *mark, int i) {
+    return mark ? mark[i] != 0 : lam[i] < 1.0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_compact_count(int n, const double *__restrict__ lam,
+                                                          const int *__restrict__ mark, int *__restrict__ bcnt) {
+    __shared__ int sh[kBlock / 64];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool f = i < n && in_s(lam, mark, i);
+    const unsigned long long m = __ballot(f);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = __popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int s = 0;
+        for (int w = 0; w < kBlock / 64; w++) s += sh[w];
+        bcnt[blockIdx.x] = s;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_compact_scatter(int n, const double *__restrict__ lam,
+                                                            const int *__restrict__ mark, const int *__restrict__ boff,
+                                                            int *__restrict__ sidx, int *__restrict__ slist) {
+    __shared__ int sh[kBlock / 64];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool f = i < n && in_s(lam, mark, i);
+    const unsigned long long m = __ballot(f);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) sh[w] = __popcll(m);
+    __syncthreads();
+    int off = boff[blockIdx.x];
+    for (int q = 0; q < w; q++) off += sh[q];
+    const int rank = __popcll(m & ((1ull << lane) - 1ull));
+    if (i < n) {
+        if (f) {
+            slist[off + rank] = i;
+            sidx[i] = off + rank;
+        } else {
+            sidx[i] = -1;
+        }
+    }
+}
+
+__global__ void k_mark_subset(const int32_t *__restrict__ subset, int m, int n, int *mark, int *flags) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= m) return;
+    int i = subset[q];
+    if (i < 0 || i >= n) {
+        atomicOr(&flags[1], kErrOverflow);
+        return;
+    }
+    mark[i] = 1;
+}
+
+void launch_compact(ap_ctx *c, int n, const int32_t *subset, int n_subset) {
+    const int nb = (n + kBlock - 1) / kBlock;
+    int *mark = nullptr;
+    if (subset) {
+        mark = c->mark;
+        launch_fill_int(c, mark, 0, n);
+        if (n_subset > 0)
+            k_mark_subset<<<(n_subset + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(subset, n_subset, n, mark,
+                                                                                       c->d_flags);
+    }
+    k_compact_count<<<nb, kBlock, 0, c->stream>>>(n, c->lam, mark, c->blk_cnt);
+    launch_scan(c, c->blk_cnt, c->blk_cnt + nb, nb, c->d_flags + 2, nullptr);
+    k_compact_scatter<<<nb, kBlock, 0, c->stream>>>(n, c->lam, mark, c->blk_cnt + nb, c->sidx, c->slist);
+}
+
+// ------------------------------------------------------------------------------------------
+// W_j = sum_k E~_k w(r_kj), including k = j (w(0) = 1).
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_W(const double *__restrict__ pos, int n, double Lx, double Ly, double Lz,
+                                              double r_w, const int32_t *__restrict__ ncount,
+                                              const int32_t *__restrict__ nidx, const double *__restrict__ Et,
+                                              double *__restrict__ W) {
+    const int j = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const double xj = pos[j], yj = pos[n + j], zj = pos[2 * n + j];
+    double s = Et[j];
+    const double r_w2 = r_w * r_w;
+    const int cnt = ncount[j];
+    for (int q = 0; q < cnt; q++) {
+        const int k = nidx[(size_t)q * n + j];
+        const double e = Et[k];
+        if (e == 0.0) continue;
+        const double ux = min_image(pos[k] - xj, Lx), uy = min_image(pos[n + k] - yj, Ly),
+                     uz = min_image(pos[2 * n + k] - zj, Lz);
+        const double r2 = ux * ux + uy * uy + uz * uz;
+        if (r2 < r_w2) s += e * ftrans(sqrt(r2), r_w - 1.0, r_w);
+    }
+    W[j] = s;
+}
+
+void launch_W(ap_ctx *c, int n, const double *box) {
+    k_W<<<(n + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(c->pos, n, box[0], box[1], box[2], c->sw.r_w, c->nbr_cnt,
+                                                             c->nbr_idx, c->Et, c->W);
+}
+
+// ------------------------------------------------------------------------------------------
+// Force assembly
+// ------------------------------------------------------------------------------------------
+struct ForceArgs {
+    const double *pos;
+    int n;
+    double L[3];
+    EamP ep;
+    SwP sp;
+    int switching, grad_lambda, eam_on, ace_on;
+    const int32_t *ncount, *nidx, *nrev;
+    const double *lam, *xip, *Ef, *Ep, *Et, *W, *g, *d;
+    const int *sidx;
+    const void *fpair;
+    int fp32, max_nbr, n_csp;
+    const int32_t *csp_t, *rev_start, *rev_code;
+    double *E_atom, *F, *partials;
+    int *flags;
+};
+
+template <typename TF>
+__device__ __forceinline__ void load_f(const TF *fp, size_t o, double &a, double &b, double &c) {
+    a = (double)fp[o];
+    b = (double)fp[o + 1];
+    c = (double)fp[o + 2];
+}
+
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+    // deterministic block reduction (fixed tree)
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int q = 0; q < kBlock / 64; q++) s += sh[q];
+    return s;
+}
+
+template <typename TF>
+__global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
+    __shared__ double sh[kBlock / 64];
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int i = blk * blockDim.x + threadIdx.x;
+    const int n = a.n;
+    double F0 = 0, F1 = 0, F2 = 0, Ei = 0;
+    double v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (i < n) {
+        const double xi = a.pos[i], yi = a.pos[n + i], zi = a.pos[2 * n + i];
+        const double li = a.lam[i], xpi = a.xip[i];
+        const double Eti = a.Et[i], gi = a.g[i], di = a.d[i];
+        const int si = a.sidx[i];
+        const TF *fp = reinterpret_cast<const TF *>(a.fpair);
+        const int cnt = a.ncount[i];
+        const bool gl = a.switching && a.grad_lambda;
+        for (int k = 0; k < cnt; k++) {
+            const int j = a.nidx[(size_t)k * n + i];
+            const double ux = min_image(a.pos[j] - xi, a.L[0]), uy = min_image(a.pos[n + j] - yi, a.L[1]),
+                         uz = min_image(a.pos[2 * n + j] - zi, a.L[2]);
+            const double r2 = ux * ux + uy * uy + uz * uz;
+            const double r = sqrt(r2), ir = 1.0 / r;
+            const double ex = ux * ir, ey = uy * ir, ez = uz * ir;
+            const double lj = a.lam[j];
+            if (a.eam_on && r2 < a.ep.rc2) {
+                double zz, dz, ph, dph;
+                eam_pair(a.ep, r, zz, dz, ph, dph);
+                // lambda_i f_ki - lambda_k f_ik, (S12), along rhat_ki = u / r
+                const double own = li * (xpi * dz + 0.5 * dph);
+                const double s = own + lj * (a.xip[j] * dz + 0.5 * dph);
+                F0 += s * ex;
+                F1 += s * ey;
+                F2 += s * ez;
+                // virial of the edge owned by i: -(d(lambda_i E_i)/du)_a u_b
+                const double t = -own * ir;
+                v[0] += t * ux * ux; v[1] += t * ux * uy; v[2] += t * ux * uz;
+                v[3] += t * uy * ux; v[4] += t * uy * uy; v[5] += t * uy * uz;
+                v[6] += t * uz * ux; v[7] += t * uz * uy; v[8] += t * uz * uz;
+            }
+            if (gl && r2 < a.sp.r_w2) {
+                // weight part (S19)-(S21): F_i -= (s_i + s_k) u / r
+                const double dw = ftrans_d(r, a.sp.r_w - 1.0, a.sp.r_w);
+                const double s_i = Eti * (a.g[j] - di - a.sp.d0) * dw;
+                const double s_k = a.Et[j] * (gi - a.d[j] - a.sp.d0) * dw;
+                const double s = -(s_i + s_k);
+                F0 += s * ex;
+                F1 += s * ey;
+                F2 += s * ez;
+                const double t = s_i * ir;
+                v[0] += t * ux * ux; v[1] += t * ux * uy; v[2] += t * ux * uz;
+                v[3] += t * uy * ux; v[4] += t * uy * uy; v[5] += t * uy * uz;
+                v[6] += t * uz * ux; v[7] += t * uz * uy; v[8] += t * uz * uz;
+            }
+            if (a.ace_on) {
+                // (S14): (1 - lambda_i) f_ki from i's own site, minus (1 - lambda_k) f_ik from k's site
+                if (si >= 0) {
+                    double fx, fy, fz;
+                    load_f(fp, ((size_t)si * a.max_nbr + k) * 3, fx, fy, fz);
+                    const double wgt = 1.0 - li;
+                    F0 += wgt * fx;
+                    F1 += wgt * fy;
+                    F2 += wgt * fz;
+                    v[0] -= wgt * fx * ux; v[1] -= wgt * fx * uy; v[2] -= wgt * fx * uz;
+                    v[3] -= wgt * fy * ux; v[4] -= wgt * fy * uy; v[5] -= wgt * fy * uz;
+                    v[6] -= wgt * fz * ux; v[7] -= wgt * fz * uy; v[8] -= wgt * fz * uz;
+                }
+                const int sj = a.sidx[j];
+                const int q = sj >= 0 ? a.nrev[(size_t)k * n + i] : -1;
+                if (q >= 0) {
+                    double fx, fy, fz;
+                    load_f(fp, ((size_t)sj * a.max_nbr + q) * 3, fx, fy, fz);
+                    const double wgt = 1.0 - lj;
+                    F0 -= wgt * fx;
+                    F1 -= wgt * fy;
+                    F2 -= wgt * fz;
+                }
+            }
+        }
+        if (gl) {
+            // CSP part (S24)-(S27): own list 2 W_i sum_l (r_il + r_i,opp(l)); reverse entries
+            // -2 W_j (r_ji + r_j,opp(i)).
+            const double Wi = a.W[i];
+            if (Wi != 0.0) {
+                for (int t = 0; t < a.n_csp; t++) {
+                    const int l = a.csp_t[(size_t)t * n + i], o = a.csp_t[(size_t)(t ^ 1) * n + i];
+                    const double lx = min_image(a.pos[l] - xi, a.L[0]), ly = min_image(a.pos[n + l] - yi, a.L[1]),
+                                 lz = min_image(a.pos[2 * n + l] - zi, a.L[2]);
+                    const double ox = min_image(a.pos[o] - xi, a.L[0]), oy = min_image(a.pos[n + o] - yi, a.L[1]),
+                                 oz = min_image(a.pos[2 * n + o] - zi, a.L[2]);
+                    const double sx = lx + ox, sy = ly + oy, sz = lz + oz;
+                    F0 -= 2.0 * Wi * sx;
+                    F1 -= 2.0 * Wi * sy;
+                    F2 -= 2.0 * Wi * sz;
+                    const double t2 = 2.0 * Wi;
+                    v[0] += t2 * sx * lx; v[1] += t2 * sx * ly; v[2] += t2 * sx * lz;
+                    v[3] += t2 * sy * lx; v[4] += t2 * sy * ly; v[5] += t2 * sy * lz;
+                    v[6] += t2 * sz * lx; v[7] += t2 * sz * ly; v[8] += t2 * sz * lz;
+                }
+            }
+            const int rb = a.rev_start[i], re = a.rev_start[i + 1];
+            for (int q = rb; q < re; q++) {
+                const int code = a.rev_code[q];
+                const int jj = code >> 4, t = code & 15;
+                const double Wj = a.W[jj];
+                if (Wj == 0.0) continue;
+                const int o = a.csp_t[(size_t)(t ^ 1) * n + jj];
+                const double xj = a.pos[jj], yj = a.pos[n + jj], zj = a.pos[2 * n + jj];
+                const double sx = min_image(xi - xj, a.L[0]) + min_image(a.pos[o] - xj, a.L[0]);
+                const double sy = min_image(yi - yj, a.L[1]) + min_image(a.pos[n + o] - yj, a.L[1]);
+                const double sz = min_image(zi - zj, a.L[2]) + min_image(a.pos[2 * n + o] - zj, a.L[2]);
+                F0 += 2.0 * Wj * sx;
+                F1 += 2.0 * Wj * sy;
+                F2 += 2.0 * Wj * sz;
+            }
+        }
+        Ei = li * a.Ef[i] + (1.0 - li) * a.Ep[i];
+        if (a.E_atom) a.E_atom[i] = Ei;
+        if (a.F) {
+            a.F[i] = F0;
+            a.F[n + i] = F1;
+            a.F[2 * n + i] = F2;
+        }
+        if (!(isfinite(F0) && isfinite(F1) && isfinite(F2) && isfinite(Ei))) atomicOr(&a.flags[1], kErrNonFinite);
+    }
+    double s = block_sum(Ei, sh);
+    if (threadIdx.x == 0) a.partials[(size_t)blk * 16] = s;
+    for (int q = 0; q < 9; q++) {
+        s = block_sum(v[q], sh);
+        if (threadIdx.x == 0) a.partials[(size_t)blk * 16 + 1 + q] = s;
+    }
+}
+
+void launch_force(ap_ctx *c, int n, const double *box, const EvalFlags &f, double *E_atom, double *F) {
+    ForceArgs a;
+    a.pos = c->pos;
+    a.n = n;
+    for (int q = 0; q < 3; q++) a.L[q] = box[q];
+    a.ep = eamp(c->eam);
+    a.sp = SwP{c->sw.d_lo, c->sw.d_hi, c->sw.r_w, c->sw.r_w * c->sw.r_w, c->sw.d0};
+    a.switching = f.switching;
+    a.grad_lambda = f.grad_lambda;
+    a.eam_on = f.eam_forces;
+    a.ace_on = f.ace_forces;
+    a.ncount = c->nbr_cnt;
+    a.nidx = c->nbr_idx;
+    a.nrev = c->nbr_rev;
+    a.lam = c->lam;
+    a.xip = c->xip;
+    a.Ef = c->Ef;
+    a.Ep = c->Ep;
+    a.Et = c->Et;
+    a.W = c->W;
+    a.g = c->g;
+    a.d = c->d;
+    a.sidx = c->sidx;
+    a.fpair = c->fpair;
+    a.fp32 = c->ace.precision == AP_FP32;
+    a.max_nbr = c->max_nbr;
+    a.n_csp = c->n_csp;
+    a.csp_t = c->csp_t;
+    a.rev_start = c->rev_start;
+    a.rev_code = c->rev_code;
+    a.E_atom = E_atom;
+    a.F = F;
+    a.partials = c->partials;
+    a.flags = c->d_flags;
+    const int nb = (n + kBlock - 1) / kBlock;
+    if (a.fp32)
+        k_force<float><<<nb, kBlock, 0, c->stream>>>(a);
+    else
+        k_force<double><<<nb, kBlock, 0, c->stream>>>(a);
+}
+
+// Sums the per-block partials [nb][16] (energy, virial) in a fixed order.
+__global__ __launch_bounds__(kBlock) void k_reduce_partials(const double *__restrict__ part, int nb, int ncol,
+                                                            double *__restrict__ out, int *flags) {
+    __shared__ double sh[kBlock / 64];
+    for (int col = 0; col < ncol; col++) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nb; b += kBlock) s += part[(size_t)b * 16 + col];
+        s = block_sum(s, sh);
+        if (threadIdx.x == 0) {
+            out[col] = s;
+            if (!isfinite(s)) atomicOr(&flags[1], kErrNonFinite);
+        }
+    }
+}
+
+void launch_reduce(ap_ctx *c, int nblocks, double *E_tot, double *virial9) {
+    k_reduce_partials<<<1, kBlock, 0, c->stream>>>(c->partials, nblocks, 10, c->scalars, c->d_flags);
+    if (E_tot) hipMemcpyAsync(E_tot, c->scalars, sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+    if (virial9) hipMemcpyAsync(virial9, c->scalars + 1, 9 * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+}
+
+}  // namespace ap

@@ -1,0 +1,462 @@
+// Periodic geometry, cell lists, neighbour lists and the CSP pair list of (B3).
+//
+// Neighbour lists are slot-major (nbr_idx[k * n + i] is the k-th neighbour of atom i) so that a
+// wavefront of consecutive atoms reads one coalesced row per slot. All lists are deterministic:
+// atoms inside a cell are sorted by index and the 27 cells are visited in a fixed order.
+#include "ap_internal.h"
+
+namespace ap {
+
+__global__ void k_fill_int(int *p, int v, int count) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+__global__ void k_fill_double(double *p, double v, int count) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+void launch_fill_int(ap_ctx *c, int *p, int v, int count) {
+    if (count > 0) k_fill_int<<<(count + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(p, v, count);
+}
+void launch_fill_double(ap_ctx *c, double *p, double v, int count) {
+    if (count > 0) k_fill_double<<<(count + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(p, v, count);
+}
+
+// Wrapped copy of the caller's positions into the context (x - L floor(x/L), L -> 0).
+__global__ void k_wrap_copy(const double *__restrict__ in, double *__restrict__ out, int n, double Lx, double Ly,
+                            double Lz) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    out[i] = wrap_coord(in[i], Lx);
+    out[n + i] = wrap_coord(in[n + i], Ly);
+    out[2 * n + i] = wrap_coord(in[2 * n + i], Lz);
+}
+
+int prepare_positions(ap_ctx *c, int n, const double *pos_in, const double *box) {
+    k_wrap_copy<<<(n + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(pos_in, c->pos, n, box[0], box[1], box[2]);
+    return hip_check(c, hipGetLastError(), "wrap");
+}
+
+// ------------------------------------------------------------------------------------------
+// Exclusive scan of len ints in one workgroup of 1024 threads; total written to *total.
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_scan_excl(const int *__restrict__ in, int *__restrict__ out, int len,
+                                                    int *total, const int *gate) {
+    if (gate && gate[0] == 0) return;
+    __shared__ int sh[1024];
+    const int t = threadIdx.x;
+    const int chunk = (len + 1023) / 1024;
+    const int b = t * chunk, e = min(len, b + chunk);
+    int s = 0;
+    for (int q = b; q < e; q++) s += in[q];
+    sh[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int v = t >= off ? sh[t - off] : 0;
+        __syncthreads();
+        sh[t] += v;
+        __syncthreads();
+    }
+    int run = sh[t] - s;
+    for (int q = b; q < e; q++) {
+        int v = in[q];
+        out[q] = run;
+        run += v;
+    }
+    if (t == 1023 && total) *total = sh[1023];
+}
+
+void launch_scan(ap_ctx *c, const int *in, int *out, int len, int *total, const int *gate) {
+    k_scan_excl<<<1, 1024, 0, c->stream>>>(in, out, len, total, gate);
+}
+
+// ------------------------------------------------------------------------------------------
+// Cell list (rebuilt only when d_flags[0] != 0)
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ int cell_coord(double x, double L, int nc) {
+    int q = (int)floor(x / L * nc);
+    return q < 0 ? 0 : (q >= nc ? nc - 1 : q);
+}
+
+__global__ void k_cell_clear(int *cnt, int *fill, int ncell, const int *flags) {
+    if (flags[0] == 0) return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ncell) {
+        cnt[i] = 0;
+        fill[i] = 0;
+    }
+}
+
+__global__ void k_cell_assign(const double *__restrict__ pos, int n, Geometry g, int *cell_of, int *cnt,
+                              const int *flags) {
+    if (flags[0] == 0) return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int cx = cell_coord(pos[i], g.L[0], g.nc[0]);
+    int cy = cell_coord(pos[n + i], g.L[1], g.nc[1]);
+    int cz = cell_coord(pos[2 * n + i], g.L[2], g.nc[2]);
+    int cc = (cx * g.nc[1] + cy) * g.nc[2] + cz;
+    cell_of[i] = cc;
+    atomicAdd(&cnt[cc], 1);
+}
+
+__global__ void k_cell_fill(int n, const int *cell_of, const int *start, int *fill, int *atoms, const int *flags) {
+    if (flags[0] == 0) return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int cc = cell_of[i];
+    atoms[start[cc] + atomicAdd(&fill[cc], 1)] = i;
+}
+
+// Insertion sort of every cell's atoms by index (the fill order above is not deterministic).
+__global__ void k_cell_sort(int ncell, const int *start, const int *cnt, int *atoms, const int *flags) {
+    if (flags[0] == 0) return;
+    int cc = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cc >= ncell) return;
+    int *a = atoms + start[cc];
+    int m = cnt[cc];
+    for (int p = 1; p < m; p++) {
+        int v = a[p], q = p - 1;
+        while (q >= 0 && a[q] > v) {
+            a[q + 1] = a[q];
+            q--;
+        }
+        a[q + 1] = v;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_nbr_build(const double *__restrict__ pos, int n, Geometry g, double r2,
+                                                      const int *__restrict__ start, const int *__restrict__ cnt,
+                                                      const int *__restrict__ atoms, const int *__restrict__ cell_of,
+                                                      int max_nbr, int32_t *__restrict__ ncount,
+                                                      int32_t *__restrict__ nidx, double *__restrict__ pos_build,
+                                                      int *flags) {
+    if (flags[0] == 0) return;
+    int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
+    const int cc = cell_of[i];
+    const int c0 = cc / (g.nc[1] * g.nc[2]), c1 = (cc / g.nc[2]) % g.nc[1], c2 = cc % g.nc[2];
+    int k = 0;
+    const int rx = g.nc[0] > 1 ? 1 : 0, ry = g.nc[1] > 1 ? 1 : 0, rz = g.nc[2] > 1 ? 1 : 0;
+    for (int dx = -rx; dx <= rx; dx++)
+        for (int dy = -ry; dy <= ry; dy++)
+            for (int dz = -rz; dz <= rz; dz++) {
+                int x = c0 + dx, y = c1 + dy, z = c2 + dz;
+                x += x < 0 ? g.nc[0] : (x >= g.nc[0] ? -g.nc[0] : 0);
+                y += y < 0 ? g.nc[1] : (y >= g.nc[1] ? -g.nc[1] : 0);
+                z += z < 0 ? g.nc[2] : (z >= g.nc[2] ? -g.nc[2] : 0);
+                const int q = (x * g.nc[1] + y) * g.nc[2] + z;
+                const int b = start[q], e = b + cnt[q];
+                for (int p = b; p < e; p++) {
+                    const int j = atoms[p];
+                    if (j == i) continue;
+                    double ux = min_image(pos[j] - xi, g.L[0]);
+                    double uy = min_image(pos[n + j] - yi, g.L[1]);
+                    double uz = min_image(pos[2 * n + j] - zi, g.L[2]);
+                    if (norm2_nofma(ux, uy, uz) < r2) {
+                        if (k < max_nbr) nidx[(size_t)k * n + i] = j;
+                        k++;
+                    }
+                }
+            }
+    if (k > max_nbr) {
+        atomicOr(&flags[1], kErrOverflow);
+        k = max_nbr;
+    }
+    ncount[i] = k;
+    pos_build[i] = xi;
+    pos_build[n + i] = yi;
+    pos_build[2 * n + i] = zi;
+}
+
+// rev[k * n + i] = slot of atom i in the list of its k-th neighbour (lists are symmetric).
+__global__ __launch_bounds__(kBlock) void k_nbr_rev(int n, const int32_t *__restrict__ ncount,
+                                                    const int32_t *__restrict__ nidx, int32_t *__restrict__ rev,
+                                                    const int *flags) {
+    if (flags[0] == 0) return;
+    int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int ci = ncount[i];
+    for (int k = 0; k < ci; k++) {
+        const int j = nidx[(size_t)k * n + i];
+        const int cj = ncount[j];
+        int s = -1;
+        for (int q = 0; q < cj; q++)
+            if (nidx[(size_t)q * n + j] == i) {
+                s = q;
+                break;
+            }
+        rev[(size_t)k * n + i] = s;
+    }
+}
+
+__global__ void k_commit(int *flags) {
+    flags[3] = flags[0];
+    flags[0] = 0;
+}
+
+// Marks a rebuild when any atom moved more than skin/2 from its position at the last build.
+__global__ void k_skin_check(const double *__restrict__ pos, const double *__restrict__ pos_build, int n,
+                             double Lx, double Ly, double Lz, double half_skin2, int *flags) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double ux = min_image(pos[i] - pos_build[i], Lx);
+    double uy = min_image(pos[n + i] - pos_build[n + i], Ly);
+    double uz = min_image(pos[2 * n + i] - pos_build[2 * n + i], Lz);
+    if (ux * ux + uy * uy + uz * uz > half_skin2) atomicOr(&flags[0], 1);
+}
+
+static int make_geometry(ap_ctx *c, const double *box, double r_list, Geometry &g) {
+    for (int a = 0; a < 3; a++) {
+        g.L[a] = box[a];
+        if (!(r_list < 0.5 * box[a]))
+            return set_error(c, AP_E_BOX, "list radius (cutoff + skin) must be below half the box");
+        g.nc[a] = (int)floor(box[a] / r_list);
+        if (g.nc[a] < 3) g.nc[a] = 1;  // one cell spans the box: every atom is a candidate
+    }
+    g.ncell = g.nc[0] * g.nc[1] * g.nc[2];
+    return AP_OK;
+}
+
+static int grow_cells(ap_ctx *c, int ncell) {
+    if (ncell <= c->ncell_cap) return AP_OK;
+    hipFree(c->cell_cnt);
+    hipFree(c->cell_start);
+    hipFree(c->cell_fill);
+    int rc = hip_check(c, hipMalloc(&c->cell_cnt, sizeof(int) * ncell), "cells");
+    if (!rc) rc = hip_check(c, hipMalloc(&c->cell_start, sizeof(int) * (ncell + 1)), "cells");
+    if (!rc) rc = hip_check(c, hipMalloc(&c->cell_fill, sizeof(int) * ncell), "cells");
+    if (!rc) c->ncell_cap = ncell;
+    return rc;
+}
+
+// (Re)builds the neighbour list of the positions in c->pos at radius r_list when forced, when the
+// list parameters changed, or when the device-side skin check flagged it.
+int ensure_list(ap_ctx *c, int n, const double *box, double r_list, bool force) {
+    Geometry g;
+    int rc = make_geometry(c, box, r_list, g);
+    if (rc) return rc;
+    rc = grow_cells(c, g.ncell);
+    if (rc) return rc;
+    bool changed = force || r_list != c->list_r || n != c->list_n || box[0] != c->list_box[0] ||
+                   box[1] != c->list_box[1] || box[2] != c->list_box[2];
+    const int nb = (n + kBlock - 1) / kBlock;
+    if (changed) {
+        launch_fill_int(c, c->d_flags, 1, 1);
+    } else {
+        k_skin_check<<<nb, kBlock, 0, c->stream>>>(c->pos, c->pos_build, n, box[0], box[1], box[2],
+                                                   0.25 * c->skin * c->skin, c->d_flags);
+    }
+    const int cb = (g.ncell + kBlock - 1) / kBlock;
+    k_cell_clear<<<cb, kBlock, 0, c->stream>>>(c->cell_cnt, c->cell_fill, g.ncell, c->d_flags);
+    k_cell_assign<<<nb, kBlock, 0, c->stream>>>(c->pos, n, g, c->cell_of, c->cell_cnt, c->d_flags);
+    k_scan_excl<<<1, 1024, 0, c->stream>>>(c->cell_cnt, c->cell_start, g.ncell, nullptr, c->d_flags);
+    k_cell_fill<<<nb, kBlock, 0, c->stream>>>(n, c->cell_of, c->cell_start, c->cell_fill, c->cell_atoms, c->d_flags);
+    k_cell_sort<<<cb, kBlock, 0, c->stream>>>(g.ncell, c->cell_start, c->cell_cnt, c->cell_atoms, c->d_flags);
+    k_nbr_build<<<nb, kBlock, 0, c->stream>>>(c->pos, n, g, r_list * r_list, c->cell_start, c->cell_cnt,
+                                              c->cell_atoms, c->cell_of, c->max_nbr, c->nbr_cnt, c->nbr_idx,
+                                              c->pos_build, c->d_flags);
+    k_nbr_rev<<<nb, kBlock, 0, c->stream>>>(n, c->nbr_cnt, c->nbr_idx, c->nbr_rev, c->d_flags);
+    k_commit<<<1, 1, 0, c->stream>>>(c->d_flags);
+    c->list_r = r_list;
+    c->list_n = n;
+    for (int a = 0; a < 3; a++) c->list_box[a] = box[a];
+    return hip_check(c, hipGetLastError(), "neighbour list");
+}
+
+// ------------------------------------------------------------------------------------------
+// CSP^list of (B3)
+// ------------------------------------------------------------------------------------------
+// One-time pair detection: n_csp nearest by (d2, index) via repeated minimum search; greedy
+// pairing by the smallest |u_a + u_b|^2 with index tie-breaks; written in choice order.
+// NC (8 or 12) is a compile-time constant so that every loop over the selected neighbours unrolls
+// and the per-thread tables stay in registers.
+template <int NC>
+__global__ __launch_bounds__(kBlock) void k_csp_pairs(const double *__restrict__ pos, int n, Geometry g,
+                                                      const int32_t *__restrict__ ncount,
+                                                      const int32_t *__restrict__ nidx, int32_t *__restrict__ out,
+                                                      int *flags) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int cnt = ncount[i];
+    if (cnt < NC) {
+        atomicOr(&flags[1], kErrCsp);
+        return;
+    }
+    const double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
+    int sel[NC];
+    double sx_[NC], sy_[NC], sz_[NC];
+    // the s-th nearest is the smallest key (d2, j) above the (s-1)-th one: keys are unique
+    double pd = -1.0;
+    int pj = -1;
+#pragma unroll
+    for (int s = 0; s < NC; s++) {
+        int bj = -1;
+        double bd = 0;
+        for (int q = 0; q < cnt; q++) {
+            const int j = nidx[(size_t)q * n + i];
+            double ux = min_image(pos[j] - xi, g.L[0]);
+            double uy = min_image(pos[n + j] - yi, g.L[1]);
+            double uz = min_image(pos[2 * n + j] - zi, g.L[2]);
+            double d2 = norm2_nofma(ux, uy, uz);
+            const bool above = d2 > pd || (d2 == pd && j > pj);
+            if (above && (bj < 0 || d2 < bd || (d2 == bd && j < bj))) {
+                bd = d2;
+                bj = j;
+            }
+        }
+        pd = bd;
+        pj = bj;
+        sel[s] = bj;
+        sx_[s] = min_image(pos[bj] - xi, g.L[0]);
+        sy_[s] = min_image(pos[n + bj] - yi, g.L[1]);
+        sz_[s] = min_image(pos[2 * n + bj] - zi, g.L[2]);
+    }
+    unsigned used = 0u;
+#pragma unroll
+    for (int p = 0; p < NC / 2; p++) {
+        int ba = 0, bb = 0, blo = 0, bhi = 0;
+        bool have = false;
+        double bs = 0;
+#pragma unroll
+        for (int a = 0; a < NC; a++) {
+#pragma unroll
+            for (int b = a + 1; b < NC; b++) {
+                const bool avail = ((used >> a) & 1u) == 0u && ((used >> b) & 1u) == 0u;
+                double s;
+                {
+#pragma clang fp contract(off)
+                    const double px = sx_[a] + sx_[b], py = sy_[a] + sy_[b], pz = sz_[a] + sz_[b];
+                    s = px * px + py * py + pz * pz;
+                }
+                const int lo = sel[a] < sel[b] ? sel[a] : sel[b], hi = sel[a] < sel[b] ? sel[b] : sel[a];
+                const bool better = !have || s < bs || (s == bs && (lo < blo || (lo == blo && hi < bhi)));
+                if (avail && better) {
+                    have = true;
+                    ba = a;
+                    bb = b;
+                    bs = s;
+                    blo = lo;
+                    bhi = hi;
+                }
+            }
+        }
+        used |= (1u << ba) | (1u << bb);
+        out[(size_t)i * NC + 2 * p] = blo;
+        out[(size_t)i * NC + 2 * p + 1] = bhi;
+    }
+}
+
+int build_csp_pairs(ap_ctx *c, int n, const double *box, int n_csp, int32_t *out) {
+    const double r_search = 5.0;
+    int rc = ensure_list(c, n, box, r_search, true);
+    if (rc) return rc;
+    Geometry g;
+    rc = make_geometry(c, box, r_search, g);
+    if (rc) return rc;
+    const int nb = (n + kBlock - 1) / kBlock;
+    if (n_csp == 8)
+        k_csp_pairs<8><<<nb, kBlock, 0, c->stream>>>(c->pos, n, g, c->nbr_cnt, c->nbr_idx, out, c->d_flags);
+    else
+        k_csp_pairs<12><<<nb, kBlock, 0, c->stream>>>(c->pos, n, g, c->nbr_cnt, c->nbr_idx, out, c->d_flags);
+    c->list_r = -1;  // the list at r_search is not the evaluation list
+    return hip_check(c, hipGetLastError(), "csp pairs");
+}
+
+__global__ void k_csp_check_transpose(const int32_t *__restrict__ list, int n, int n_csp, int32_t *__restrict__ lt,
+                                      int *rcnt, int *flags) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int t = 0; t < n_csp; t++) {
+        int j = list[(size_t)i * n_csp + t];
+        if (j < 0 || j >= n || j == i) {
+            atomicOr(&flags[1], kErrCsp);
+            j = i;
+        }
+        lt[(size_t)t * n + i] = j;
+        atomicAdd(&rcnt[j], 1);
+    }
+}
+
+__global__ void k_csp_rev_fill(int n, int n_csp, const int32_t *__restrict__ lt, const int *rstart, int *rfill,
+                               int32_t *rcode) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    for (int t = 0; t < n_csp; t++) {
+        int i = lt[(size_t)t * n + j];
+        rcode[rstart[i] + atomicAdd(&rfill[i], 1)] = j * 16 + t;
+    }
+}
+
+__global__ void k_csp_rev_sort(int n, const int *rstart, int32_t *rcode) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int b = rstart[i], m = rstart[i + 1] - b;
+    int32_t *a = rcode + b;
+    for (int p = 1; p < m; p++) {
+        int v = a[p], q = p - 1;
+        while (q >= 0 && a[q] > v) {
+            a[q + 1] = a[q];
+            q--;
+        }
+        a[q + 1] = v;
+    }
+}
+
+int install_csp(ap_ctx *c, int n, int n_csp, const int32_t *list) {
+    if (n_csp != 8 && n_csp != 12) return set_error(c, AP_E_CSP, "n_csp must be 8 or 12");
+    hipFree(c->csp_t);
+    hipFree(c->rev_start);
+    hipFree(c->rev_code);
+    c->csp_t = nullptr;
+    c->rev_start = nullptr;
+    c->rev_code = nullptr;
+    int rc = hip_check(c, hipMalloc(&c->csp_t, sizeof(int32_t) * (size_t)n * n_csp), "csp");
+    if (!rc) rc = hip_check(c, hipMalloc(&c->rev_start, sizeof(int32_t) * (size_t)(n + 1)), "csp");
+    if (!rc) rc = hip_check(c, hipMalloc(&c->rev_code, sizeof(int32_t) * (size_t)n * n_csp), "csp");
+    if (rc) return rc;
+    const int nb = (n + kBlock - 1) / kBlock;
+    int *cnt = c->cell_of;  // scratch [n_cap] ints, free outside of list builds
+    int *fill = c->sidx;
+    launch_fill_int(c, cnt, 0, n + 1);
+    launch_fill_int(c, fill, 0, n);
+    launch_fill_int(c, c->d_flags + 1, 0, 1);
+    k_csp_check_transpose<<<nb, kBlock, 0, c->stream>>>(list, n, n_csp, c->csp_t, cnt, c->d_flags);
+    k_scan_excl<<<1, 1024, 0, c->stream>>>(cnt, c->rev_start, n + 1, nullptr, nullptr);
+    k_csp_rev_fill<<<nb, kBlock, 0, c->stream>>>(n, n_csp, c->csp_t, c->rev_start, fill, c->rev_code);
+    k_csp_rev_sort<<<nb, kBlock, 0, c->stream>>>(n, c->rev_start, c->rev_code);
+    rc = hip_check(c, hipGetLastError(), "csp reverse");
+    if (rc) return rc;
+    rc = sync_and_check(c);
+    if (rc) return rc;
+    c->csp_n = n;
+    c->n_csp = n_csp;
+    c->list_r = -1;  // cell_of was used as scratch
+    return AP_OK;
+}
+
+// g_i = sum over the stored pairs (a, b) of |u_ia + u_ib|^2.
+__global__ __launch_bounds__(kBlock) void k_csp_value(const double *__restrict__ pos, int n, double Lx, double Ly,
+                                                      double Lz, int n_csp, const int32_t *__restrict__ lt,
+                                                      double *__restrict__ g) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
+    double s = 0.0;
+    for (int p = 0; p < n_csp / 2; p++) {
+        const int a = lt[(size_t)(2 * p) * n + i], b = lt[(size_t)(2 * p + 1) * n + i];
+        double vx = min_image(pos[a] - xi, Lx) + min_image(pos[b] - xi, Lx);
+        double vy = min_image(pos[n + a] - yi, Ly) + min_image(pos[n + b] - yi, Ly);
+        double vz = min_image(pos[2 * n + a] - zi, Lz) + min_image(pos[2 * n + b] - zi, Lz);
+        s += vx * vx + vy * vy + vz * vz;
+    }
+    g[i] = s;
+}
+
+void launch_csp_value(ap_ctx *c, int n, const double *box) {
+    k_csp_value<<<(n + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(c->pos, n, box[0], box[1], box[2], c->n_csp,
+                                                                     c->csp_t, c->g);
+}
+
+}  // namespace ap

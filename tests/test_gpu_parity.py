@@ -1,0 +1,190 @@
+"""GPU parity of the HIP path against the FP64 CPU oracle, through the C ABI.
+
+Bars: neighbour sets and CSP pair lists bit-exact; FP64 forces max|dF|/max|F| <= 1e-11; FP32 ACE
+forces rms|dF|/rms|F| <= 2e-5; energies |dE|/N <= 1e-6 eV/atom.
+"""
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_util import (TOL_ENERGY, TOL_F32_FORCE, TOL_F64_FORCE, force_err_max, force_err_rms, make_ctx,
+                            soa_to_aos, to_dev)
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _lt(name, value, tol):
+    _say("  %-10s %.3e (bar %.1e)" % (name, value, tol))
+    assert value < tol, "%s = %.3e exceeds %.1e" % (name, value, tol)
+
+
+def _rel(gpu, ref):
+    g = gpu.detach().cpu().numpy() if hasattr(gpu, "detach") else np.asarray(gpu)
+    ref = np.asarray(ref)
+    return float(np.abs(g - ref).max() / max(np.abs(ref).max(), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    return synth.build_system(1)
+
+
+@pytest.fixture(scope="module")
+def cfg1_oracle(oracle, cfg1):
+    csp = oracle.csp_pairs(cfg1["pos_ref"], cfg1["box"], 8)
+    return csp, oracle.evaluate(cfg1, csp=csp)
+
+
+def test_nblist_bit_exact(oracle, cfg1):
+    import torch
+    from paper_2512_07693_amd import ap
+    rng = np.random.default_rng(0)
+    for r, pos in ((7.0, cfg1["pos"]), (5.5, cfg1["pos"] + rng.uniform(-40, 40, 3)),
+                   (6.0, cfg1["pos"] + rng.normal(0, 0.3, cfg1["pos"].shape))):
+        _say("nblist r=%.1f n=%d" % (r, len(pos)))
+        ctx = ap.Context(len(pos), max_nbr=160)
+        cnt, idx = ctx.nblist_build(to_dev(pos), cfg1["box"], r)
+        torch.cuda.synchronize()
+        cnt, idx = cnt.cpu().numpy(), idx.cpu().numpy()
+        want = oracle.nblist(pos, cfg1["box"], r)
+        for i in range(len(pos)):
+            assert np.array_equal(np.sort(idx[:cnt[i], i]), want[i]), i
+        ctx.close()
+
+
+def test_csp_pairs_bit_exact(oracle, cfg1, cfg1_oracle):
+    _say("csp pairs cfg1")
+    ctx, csp = make_ctx(cfg1)
+    assert np.array_equal(csp.cpu().numpy(), cfg1_oracle[0])
+    ctx.close()
+
+
+def test_switching_matches_oracle(cfg1, cfg1_oracle):
+    _say("switch_eval cfg1")
+    ctx, _ = make_ctx(cfg1)
+    out = ctx.switch_eval(to_dev(cfg1["pos"]), cfg1["box"])
+    aux = cfg1_oracle[1]["aux"]
+    for k in ("g", "d", "wbar", "lam", "dlam"):
+        assert np.allclose(out[k].cpu().numpy(), aux[k], rtol=1e-12, atol=1e-13), k
+    assert int(out["n_precise"].item()) == int((aux["lam"] < 1).sum())
+    ctx.close()
+
+
+def test_eam_matches_oracle(oracle, cfg1):
+    _say("eam_eval cfg1")
+    ctx, _ = make_ctx(cfg1, lambda_mode=1)
+    out = ctx.eam_eval(to_dev(cfg1["pos"]), cfg1["box"])
+    want = oracle.evaluate(cfg1, lam_mode=1)
+    _lt("F", force_err_max(soa_to_aos(out["F"]), want["F"]), TOL_F64_FORCE)
+    _lt("E_atom", _rel(out["E_atom"], want["E_atom"]), 1e-13)
+    _lt("E/N", abs(out["E"].item() - want["E"]) / len(cfg1["pos"]), TOL_ENERGY)
+    _lt("virial", _rel(out["virial"], want["virial"]), 1e-11)
+    ctx.close()
+
+
+def test_ace_fp64_matches_oracle(oracle, cfg1):
+    _say("ace_eval cfg1 fp64 all atoms")
+    ctx, _ = make_ctx(cfg1, lambda_mode=0)
+    out = ctx.ace_eval(to_dev(cfg1["pos"]), cfg1["box"])
+    want = oracle.evaluate(cfg1, lam_mode=0)
+    _lt("E_atom", _rel(out["E_atom"], want["E_atom"]), 1e-12)
+    _lt("F", force_err_max(soa_to_aos(out["F"]), want["F"]), TOL_F64_FORCE)
+    _lt("virial", _rel(out["virial"], want["virial"]), 1e-10)
+    ctx.close()
+
+
+def test_mixed_fp64_matches_oracle(cfg1, cfg1_oracle):
+    _say("mixed cfg1 fp64")
+    ctx, _ = make_ctx(cfg1)
+    out = ctx.mixed_energy_forces(to_dev(cfg1["pos"]), cfg1["box"])
+    want = cfg1_oracle[1]
+    assert ((want["aux"]["lam"] > 0) & (want["aux"]["lam"] < 1)).sum() > 10
+    _lt("F", force_err_max(soa_to_aos(out["F"]), want["F"]), TOL_F64_FORCE)
+    _lt("E/N", abs(out["E"].item() - want["E"]) / len(cfg1["pos"]), TOL_ENERGY)
+    _lt("E_atom", _rel(out["E_atom"], want["E_atom"]), 1e-12)
+    _lt("virial", _rel(out["virial"], want["virial"]), 1e-10)
+    assert np.array_equal(out["lam"].cpu().numpy() < 1, want["aux"]["lam"] < 1)
+    ctx.close()
+
+
+def test_mixed_is_deterministic(cfg1):
+    _say("determinism cfg1")
+    ctx, _ = make_ctx(cfg1)
+    a = ctx.mixed_energy_forces(to_dev(cfg1["pos"]), cfg1["box"])
+    b = ctx.mixed_energy_forces(to_dev(cfg1["pos"]), cfg1["box"])
+    assert np.array_equal(a["F"].cpu().numpy(), b["F"].cpu().numpy())
+    assert a["E"].item() == b["E"].item()
+    ctx.close()
+
+
+def test_velocity_verlet_10_steps(oracle, cfg1, cfg1_oracle):
+    _say("vv 10 steps cfg1")
+    ctx, _ = make_ctx(cfg1)
+    pos, vel = to_dev(cfg1["pos"]), to_dev(cfg1["vel"])
+    F = ctx.mixed_energy_forces(pos, cfg1["box"])["F"]
+    th = ctx.vv_step(pos, vel, F, cfg1["mass"], 1e-3, 10, cfg1["box"]).cpu().numpy()
+    p_ref, v_ref, F_ref, th_ref = oracle.velocity_verlet(cfg1, 10, csp=cfg1_oracle[0])
+    d = soa_to_aos(pos) - p_ref
+    d -= cfg1["box"] * np.rint(d / cfg1["box"])
+    _lt("pos", float(np.abs(d).max()), 1e-10)
+    _lt("vel", float(np.abs(soa_to_aos(vel) - v_ref).max()), 1e-8)
+    _lt("thermo", float(np.abs(th[:, :6] - th_ref).max()), 1e-7)
+    ctx.close()
+
+
+def test_ace_fp32_large_basis(oracle):
+    """Pure ACE with the n_max 12 / l_max 6 basis (32,686 functions) in FP32 on a 250-atom cell."""
+    s = synth.build_system(2, nc=5)
+    _say("ace fp32 n12l6 250 atoms")
+    ctx, _ = make_ctx(s, lambda_mode=0, precision="fp32")
+    out = ctx.ace_eval(to_dev(s["pos"]), s["box"])
+    want = oracle.evaluate(s, lam_mode=0)
+    _lt("F rms", force_err_rms(soa_to_aos(out["F"]), want["F"]), TOL_F32_FORCE)
+    _lt("E/N", abs(out["E"].item() - want["E"]) / len(s["pos"]), TOL_ENERGY)
+    _lt("E_atom max", float(np.abs(out["E_atom"].cpu().numpy() - want["E_atom"]).max()), 1e-5)
+    ctx.close()
+
+
+def test_mixed_fp32_full_screw_dipole(oracle):
+    """The 128,000-atom bcc workload with the screw dipole (x ~ 1 %), FP32 ACE: every atom's force
+    against the oracle (S-skip mode)."""
+    s = synth.build_system(2, with_velocities=False)
+    n = len(s["pos"])
+    _say("mixed fp32 cfg2 n=%d" % n)
+    ctx, csp = make_ctx(s)
+    out = ctx.mixed_energy_forces(to_dev(s["pos"]), s["box"])
+    csp_ref = oracle.csp_pairs(s["pos_ref"], s["box"], 8)
+    assert np.array_equal(csp.cpu().numpy(), csp_ref)
+    _say("  oracle ...")
+    want = oracle.evaluate(s, csp=csp_ref)
+    x = float((want["aux"]["lam"] < 1).mean())
+    _say("  x = %.4f" % x)
+    F = soa_to_aos(out["F"])
+    _lt("F rms", force_err_rms(F, want["F"]), TOL_F32_FORCE)
+    _lt("E/N", abs(out["E"].item() - want["E"]) / n, TOL_ENERGY)
+    _lt("sum F", float(np.abs(F.sum(0)).max()), 1e-9 * n)
+    ctx.close()
+
+
+def test_error_codes(cfg1):
+    from paper_2512_07693_amd import ap
+    _say("error codes")
+    ctx, _ = make_ctx(cfg1)
+    with pytest.raises(ap.APError) as e:
+        ctx.nblist_build(to_dev(cfg1["pos"]), cfg1["box"], 13.0)
+    assert e.value.code == -2
+    with pytest.raises(ap.APError) as e:
+        ctx.nblist_build(to_dev(cfg1["pos"]), cfg1["box"], 7.0, max_nbr=20)
+    assert e.value.code == -3
+    ctx.close()
+    small = ap.Context(len(cfg1["pos"]), max_nbr=40)
+    small.set_potential(cfg1["eam"], cfg1["ace"], cfg1["sw"])
+    small.csp_pairs_build(to_dev(cfg1["pos_ref"]), cfg1["box"], 8)
+    with pytest.raises(ap.APError) as e:
+        small.mixed_energy_forces(to_dev(cfg1["pos"]), cfg1["box"])
+    assert e.value.code == -3
+    small.close()
