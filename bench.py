@@ -1,0 +1,211 @@
+"""Benchmark: adaptive-precision EAM/ACE NVE steps on one MI355X.
+
+Workload: bcc a = 3.16 A, 40^3 cells = 128,000 atoms with a planted screw dipole (Burgers vector
+a*sqrt(3)/2 along z) and sigma = 0.08 A noise; Finnis-Sinclair EAM on every atom; ACE n_max 12,
+l_max 6 (32,686 functions, FP32 arithmetic) on the precise atoms (x ~ 1 %); r_w = 6.5 A; 300 K
+Maxwell velocities; velocity Verlet at dt = 1 fs in FP64. One step = one velocity-Verlet step over the
+whole hot path (neighbour-list check/rebuild, CSP, descriptor, lambda, EAM, ACE on S, grad-lambda
+forces, assembly, reductions, integration), inputs resident in HBM.
+
+Printed: one JSON line with the mixed atom-steps/s (value), the pure-ACE rate on the same GPU and
+potential, the NVE drift, the roofline of the dominant kernel (timed with HIP events on the library's
+stream) and the CPU oracle baseline on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "mixed EAM/ACE atom-steps/s vs pure-ACE at x=1%, 1 GPU; NVE drift eV/atom/ps"
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def drift_fit(thermo, n, dt_ps):
+    e = thermo[:, 2] / n
+    t = (np.arange(len(e)) + 1) * dt_ps
+    slope = float(np.polyfit(t, e, 1)[0]) if len(e) > 2 else 0.0
+    return dict(drift_eV_per_atom_per_ps=slope, max_abs_dE_per_atom=float(np.abs(e - e[0]).max()),
+                max_abs_dP=float(np.abs(thermo[:, 3:6] - thermo[0, 3:6]).max()),
+                steps=int(len(e)), rebuilds=int(thermo[:, 7].sum()),
+                x_mean=float(thermo[:, 6].mean() / n), x_max=float(thermo[:, 6].max() / n))
+
+
+def algorithmic_bytes(kernel, n, nnb, n_s, nnb_rc, n_csp):
+    """Minimal HBM bytes per launch of the HBM-bound kernels: the slot-major lists are
+    read once (4 B per entry), every per-atom array once, outputs written once."""
+    per_atom = {
+        "dens_desc": 4 * nnb + 4 + 24 + 8 + 8 * 8,        # list + count, position, g; 8 outputs
+        "force": 8 * nnb + 4 + 24 + 9 * 8 + 4 + 32,      # list + reverse slots, own data, F and E_i
+        "W": 4 * nnb + 4 + 24 + 8 + 8,
+        "csp_value": 4 * n_csp + 24 + 8,
+        "vv_first": 6 * 8 + 3 * 8 + 6 * 8,
+        "vv_second": 6 * 8 + 3 * 8,
+    }.get(kernel)
+    if per_atom is None:
+        return None
+    b = per_atom * n
+    if kernel == "force":
+        b += n_s * nnb_rc * 3 * 4 * 2  # FP32 pair gradients of S read from both sides
+    return float(b)
+
+
+def run_md(ctx, s, pos0, vel0, steps, warmup, profile_steps):
+    import torch
+    box = s["box"]
+    pos = pos0.clone()
+    vel = vel0.clone()
+    F = ctx.mixed_energy_forces(pos, box)["F"]
+    if warmup:
+        ctx.vv_step(pos, vel, F, s["mass"], s["run"]["dt"], warmup, box)
+    stream = ctx.stream
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    ctx.set_profiling(True)
+    t0.record(stream)
+    thermo = ctx.vv_step(pos, vel, F, s["mass"], s["run"]["dt"], steps, box)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    prof = ctx.get_profile()
+    ctx.set_profiling(False)
+    return ms, thermo.cpu().numpy(), prof
+
+
+def cpu_baseline(s, steps):
+    from oracle import oracle as O
+    cores = O.set_threads(0)
+    t = time.time()
+    O.velocity_verlet(s, steps)
+    dt = time.time() - t
+    # the velocity_verlet call also evaluates the initial forces once: steps + 1 evaluations
+    return dict(value=len(s["pos"]) * steps / dt, unit="atom-steps/s", cores=int(cores), kind="oracle",
+                sample="%d velocity-Verlet steps (plus the initial force evaluation) of the full %d-atom "
+                       "workload, FP64 oracle in S-skip mode, %.1f s" % (steps, len(s["pos"]), dt))
+
+
+def main():
+    ap_ = argparse.ArgumentParser()
+    ap_.add_argument("--gpus", type=int, default=1)
+    ap_.add_argument("--steps", type=int, default=1000)
+    ap_.add_argument("--warmup", type=int, default=20)
+    ap_.add_argument("--pure-steps", type=int, default=20)
+    ap_.add_argument("--cpu-steps", type=int, default=2)
+    ap_.add_argument("--no-cpu", action="store_true")
+    args = ap_.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import synth
+    from paper_2512_07693_amd import ap
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    log("building workload ...")
+    s = synth.build_system(2)
+    n = len(s["pos"])
+    box = s["box"]
+    pos0 = torch.tensor(np.ascontiguousarray(s["pos"].T), device=dev)
+    vel0 = torch.tensor(np.ascontiguousarray(s["vel"].T), device=dev)
+    ref = torch.tensor(np.ascontiguousarray(s["pos_ref"].T), device=dev)
+
+    ctx = ap.Context(n, max_nbr=128, skin=s["run"]["skin"])
+    ctx.set_potential(s["eam"], s["ace"], s["sw"])
+    ctx.csp_pairs_build(ref, box, s["sw"]["n_csp"])
+    log("mixed: %d warmup + %d timed steps ..." % (args.warmup, args.steps))
+    ms, thermo, prof = run_md(ctx, s, pos0, vel0, args.steps, args.warmup, 0)
+    value = n * args.steps / (ms / 1e3)
+    nve = drift_fit(thermo, n, s["run"]["dt"])
+    log("mixed: %.3f ms/step, %.3e atom-steps/s, x=%.4f" % (ms / args.steps, value, nve["x_mean"]))
+
+    # pure ACE: the same potential with lambda == 0 everywhere
+    ctx_p = ap.Context(n, max_nbr=128, skin=s["run"]["skin"])
+    ctx_p.set_potential(s["eam"], s["ace"], s["sw"], lambda_mode=ap.AP_LAMBDA_PRECISE)
+    log("pure ACE: %d timed steps ..." % args.pure_steps)
+    ms_p, thermo_p, prof_p = run_md(ctx_p, s, pos0, vel0, args.pure_steps, 2, 0)
+    value_p = n * args.pure_steps / (ms_p / 1e3)
+    log("pure ACE: %.3f ms/step, %.3e atom-steps/s" % (ms_p / args.pure_steps, value_p))
+
+    # roofline of the dominant kernel of the mixed step
+    cost = ctx.ace_cost()
+    cnt_rc, _ = ctx.nblist_build(pos0, box, s["ace"]["rc"], 128)
+    cnt_w, _ = ctx.nblist_build(pos0, box, max(s["ace"]["rc"], s["sw"]["r_w"]) + s["run"]["skin"], 128)
+    nnb_rc = float(cnt_rc.double().mean().item())
+    nnb = float(cnt_w.double().mean().item())
+    n_s = nve["x_mean"] * n
+    tot = {k: v[0] * v[1] for k, v in prof.items()}
+    dom = max(tot, key=tot.get)
+    avg_ms, launches = prof[dom]
+    if dom in ("ace_energy", "ace_pairforce"):
+        per = cost["fixed_per_atom"] + nnb_rc * cost["per_neighbor_energy"] if dom == "ace_energy" else \
+            nnb_rc * cost["per_neighbor_force"]
+        flops = per * n_s
+        achieved = flops / (avg_ms * 1e-3) / 1e12
+        roof = dict(bound="alu", achieved=achieved, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=achieved / FP32_PEAK_TFLOPS, traffic=None, kernel=dom, avg_ms=avg_ms,
+                    work_per_launch="%.4g flop (%.0f precise atoms x %.4g flop)" % (flops, n_s, per))
+    else:
+        b = algorithmic_bytes(dom, n, nnb, n_s, nnb_rc, s["sw"]["n_csp"])
+        achieved = b / (avg_ms * 1e-3) / 1e9 if b else None
+        roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=(achieved / HBM_PEAK_GBS) if achieved else None, traffic=None, kernel=dom,
+                    avg_ms=avg_ms, work_per_launch="%.4g B" % (b or 0))
+    kernels = {k: dict(avg_ms=round(v[0], 5), launches=int(v[1]), share=round(tot[k] / sum(tot.values()), 4))
+               for k, v in sorted(prof.items(), key=lambda kv: -tot[kv[0]])}
+    hbm = {}
+    for k in ("dens_desc", "force", "W"):
+        if k in prof:
+            b = algorithmic_bytes(k, n, nnb, n_s, nnb_rc, s["sw"]["n_csp"])
+            hbm[k] = dict(GBs=b / (prof[k][0] * 1e-3) / 1e9, frac=b / (prof[k][0] * 1e-3) / 1e9 / HBM_PEAK_GBS)
+    ace_e = prof.get("ace_energy")
+    ace_p = prof_p.get("ace_energy")
+    ace_roof = {}
+    for tag, pr, ns in (("mixed", ace_e, n_s), ("pure_ace", ace_p, float(n))):
+        if pr:
+            per = cost["fixed_per_atom"] + nnb_rc * cost["per_neighbor_energy"]
+            tf = per * ns / (pr[0] * 1e-3) / 1e12
+            ace_roof[tag] = dict(TFLOPs=tf, frac=tf / FP32_PEAK_TFLOPS, avg_ms=pr[0])
+
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline (oracle, %d steps) ..." % args.cpu_steps)
+        cpu = cpu_baseline(s, args.cpu_steps)
+        log("cpu: %.3e atom-steps/s on %d threads" % (cpu["value"], cpu["cores"]))
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "atom-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 (ACE) + f64 (EAM, switching, forces, integration)",
+        "data": "synthetic (seeded; see synth/configs.py)",
+        "config": {"workload": s["name"], "n_atoms": n, "lattice": "bcc a=3.16 40^3, screw dipole",
+                   "ace_basis": int(len(s["ace"]["func"])), "n_max": 12, "l_max": 6, "r_w": s["sw"]["r_w"],
+                   "dt_fs": 1.0, "x": nve["x_mean"]},
+        "pure_ace": {"value": value_p, "unit": "atom-steps/s", "steps": args.pure_steps,
+                     "ms_per_step": ms_p / args.pure_steps},
+        "speedup_vs_pure_ace": value / value_p,
+        "nve": nve,
+        "roofline": roof,
+        "ace_roofline": ace_roof,
+        "hbm_kernels": hbm,
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

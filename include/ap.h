@@ -165,6 +165,21 @@ int ap_mixed_energy_forces(ap_ctx *ctx, int n, const double *pos, const int32_t 
 int ap_vv_step(ap_ctx *ctx, int n, double *pos, double *vel, double *F, double mass, double dt, int n_steps,
                const ap_box *box, double *thermo);
 
+/* Measurement support (not part of the method).
+ * ap_set_profiling: on != 0 records HIP events on the context stream around every kernel group
+ * (neighbour list, CSP value, density/descriptor, compaction, ACE energy, ACE pair gradients, W,
+ * force assembly, reductions, velocity-Verlet kernels) and clears the accumulated times.
+ * ap_get_profile: returns the number of kernel groups m (or an error) and fills, for the first
+ * max_entries of them, names [m][32] (NUL-terminated), the average duration in ms and the count of
+ * timed launches (host arrays, each optional). */
+int ap_set_profiling(ap_ctx *ctx, int on);
+int ap_get_profile(ap_ctx *ctx, int max_entries, char *names, double *avg_ms, int64_t *count);
+
+/* Floating-point operations the ACE kernels perform with the installed basis (host doubles):
+ * per precise atom independent of its neighbours (orders 2-3 values and adjoints), per neighbour
+ * inside the ACE cutoff in the energy kernel, and per neighbour in the pair-gradient kernel. */
+int ap_ace_cost(ap_ctx *ctx, double *fixed_per_atom, double *per_neighbor_energy, double *per_neighbor_force);
+
 #ifdef __cplusplus
 }
 #endif

@@ -20,7 +20,7 @@ ERRORS = {-1: "AP_E_ARG", -2: "AP_E_BOX", -3: "AP_E_NBR_OVERFLOW", -4: "AP_E_NON
           -6: "AP_E_CSP", -7: "AP_E_STATE"}
 SYMBOLS = ["ap_ctx_create", "ap_ctx_destroy", "ap_last_error", "ap_set_potential", "ap_csp_pairs_build",
            "ap_set_csp_list", "ap_nblist_build", "ap_eam_eval", "ap_switch_eval", "ap_ace_eval",
-           "ap_mixed_energy_forces", "ap_vv_step"]
+           "ap_mixed_energy_forces", "ap_vv_step", "ap_set_profiling", "ap_get_profile", "ap_ace_cost"]
 
 
 class APError(RuntimeError):
@@ -73,6 +73,9 @@ def lib():
         L.ap_ace_eval.argtypes = [vp, i, vp, vp, C.POINTER(Box), vp, i, vp, vp, vp, vp]
         L.ap_mixed_energy_forces.argtypes = [vp, i, vp, vp, C.POINTER(Box), vp, vp, vp, vp, vp]
         L.ap_vv_step.argtypes = [vp, i, vp, vp, vp, d, d, i, C.POINTER(Box), vp]
+        L.ap_set_profiling.argtypes = [vp, i]
+        L.ap_get_profile.argtypes = [vp, i, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.ap_ace_cost.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]
         for s in SYMBOLS:
             if s not in ("ap_ctx_destroy", "ap_last_error"):
                 getattr(L, s).restype = i
@@ -201,6 +204,26 @@ class Context:
         self._chk(lib().ap_mixed_energy_forces(self.h, n, _ptr(pos), None, C.byref(_box(box)), _ptr(E), _ptr(Ea),
                                                _ptr(F), _ptr(V), _ptr(lam)))
         return dict(E=E, E_atom=Ea, F=F, virial=V.view(3, 3), lam=lam)
+
+    def set_profiling(self, on=True):
+        self._chk(lib().ap_set_profiling(self.h, 1 if on else 0))
+
+    def get_profile(self):
+        """{kernel group: (average ms, launches)} from the HIP events recorded while profiling."""
+        m = 64
+        names = C.create_string_buffer(32 * m)
+        avg = (C.c_double * m)()
+        cnt = (C.c_int64 * m)()
+        k = lib().ap_get_profile(self.h, m, names, avg, cnt)
+        if k < 0:
+            self._chk(k)
+        raw = names.raw
+        return {raw[32 * q:32 * q + 32].split(b"\0")[0].decode(): (avg[q], cnt[q]) for q in range(min(k, m))}
+
+    def ace_cost(self):
+        a, b, c = C.c_double(), C.c_double(), C.c_double()
+        self._chk(lib().ap_ace_cost(self.h, C.byref(a), C.byref(b), C.byref(c)))
+        return dict(fixed_per_atom=a.value, per_neighbor_energy=b.value, per_neighbor_force=c.value)
 
     def vv_step(self, pos, vel, F, mass, dt, n_steps, box, thermo=None):
         n = pos.shape[1]

@@ -686,8 +686,35 @@ int ace_setup(ap_ctx *c, const ap_ace_params *p) {
 
 template <typename T, int NMAX, int LMAX>
 static void launch_t(ap_ctx *c, const AceArgs &a, int grid) {
-    k_ace_energy<T, NMAX, LMAX><<<grid, kBlock, 0, c->stream>>>(a);
+    {
+        ProfScope p(c, "ace_energy");
+        k_ace_energy<T, NMAX, LMAX><<<grid, kBlock, 0, c->stream>>>(a);
+    }
+    ProfScope p(c, "ace_pairforce");
     k_ace_pairforce<T, NMAX, LMAX><<<grid, 128, 0, c->stream>>>(a);
+}
+
+// Floating-point operations of the ACE kernels, counted from the tables: per S atom independent of
+// the neighbour count (orders 2 and 3 with their adjoints), per neighbour inside rc in the energy
+// kernel (radial channels, harmonics, A accumulation) and per neighbour in the pair-gradient kernel.
+void ace_cost(const ap_ctx *c, double *fixed, double *per_nbr_energy, double *per_nbr_force) {
+    const AceTables &t = c->ace;
+    const double N = t.n_max, NLM = (t.l_max + 1.0) * (t.l_max + 1.0), NA = N * NLM, NN = N * N;
+    double f = NA * (2.0 * N + 4.0);  // order 2 value and adjoint
+    for (int b = 0; b < t.nblk; b++) {
+        const int *d = t.h_blk.data() + b * kBlkInts;
+        const int L = d[0], l1 = d[1], l2 = d[2];
+        const double nkap = d[4 + 2 * L + 1] - d[4];
+        f += NN * nkap * 3.0;                          // P
+        f += (2 * L + 1) * NN * (2.0 * N + 2.0);       // Q and the energy P.Q
+        f += N * (2 * L + 1) * NN * 2.0;               // adjoint into A_{n3 L M}
+        f += N * nkap * (2.0 * N + 2.0) * 2.0;         // adjoints into A_{n1 l1} and A_{n2 l2}
+        (void)l1;
+        (void)l2;
+    }
+    *fixed = f;
+    *per_nbr_energy = 2.0 * NA + 8.0 * N + 10.0 * NLM;
+    *per_nbr_force = NLM * (4.0 * N + 12.0) + 6.0 * N + 20.0 * NLM;
 }
 
 int launch_ace(ap_ctx *c, int n, const double *box, int grid_cap) {

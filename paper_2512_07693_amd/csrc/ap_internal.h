@@ -134,12 +134,35 @@ struct ap_ctx {
     size_t fpair_bytes = 0, gbuf_bytes = 0;
     double *partials = nullptr;  // per-block partial sums [nblk][16]
     double *scalars = nullptr;   // [0] E_tot, [1..9] virial, [10] E_kin, [11..13] P
+
+    // kernel timing with HIP events on the context stream (ap_set_profiling)
+    bool prof_on = false;
+    struct Pending {
+        int label;
+        hipEvent_t a, b;
+    };
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<Pending> pending;
+    std::vector<std::string> prof_names;
+    std::vector<double> prof_ms;
+    std::vector<long long> prof_cnt;
 };
 
 namespace ap {
 
 int set_error(ap_ctx *c, int code, const std::string &msg);
 int hip_check(ap_ctx *c, hipError_t e, const char *what);
+
+// Records HIP events around the launches made during its lifetime when profiling is on; the
+// elapsed times are accumulated under `name` at the next stream synchronisation.
+struct ProfScope {
+    ap_ctx *c;
+    int label = -1;
+    hipEvent_t a = nullptr;
+    ProfScope(ap_ctx *ctx, const char *name);
+    ~ProfScope();
+};
+void prof_resolve(ap_ctx *c);
 
 // geometry.hip
 int ensure_list(ap_ctx *c, int n, const double *box, double r_list, bool force);
@@ -155,6 +178,7 @@ void launch_scan(ap_ctx *c, const int *in, int *out, int len, int *total, const 
 int ace_setup(ap_ctx *c, const ap_ace_params *p);
 void ace_free(ap_ctx *c);
 int launch_ace(ap_ctx *c, int n, const double *box, int grid_cap);
+void ace_cost(const ap_ctx *c, double *fixed, double *per_nbr_energy, double *per_nbr_force);
 
 // forces.hip
 struct EvalFlags {

@@ -21,9 +21,56 @@ int hip_check(ap_ctx *c, hipError_t e, const char *what) {
     return set_error(c, AP_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+static hipEvent_t take_event(ap_ctx *c) {
+    if (!c->ev_pool.empty()) {
+        hipEvent_t e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+ProfScope::ProfScope(ap_ctx *ctx, const char *name) : c(ctx) {
+    if (!c->prof_on) return;
+    for (size_t q = 0; q < c->prof_names.size(); q++)
+        if (c->prof_names[q] == name) label = (int)q;
+    if (label < 0) {
+        label = (int)c->prof_names.size();
+        c->prof_names.push_back(name);
+        c->prof_ms.push_back(0.0);
+        c->prof_cnt.push_back(0);
+    }
+    a = take_event(c);
+    if (a) (void)hipEventRecord(a, c->stream);
+}
+
+ProfScope::~ProfScope() {
+    if (!c->prof_on || !a) return;
+    hipEvent_t b = take_event(c);
+    if (!b) return;
+    (void)hipEventRecord(b, c->stream);
+    c->pending.push_back({label, a, b});
+}
+
+void prof_resolve(ap_ctx *c) {
+    for (const auto &p : c->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            c->prof_ms[p.label] += ms;
+            c->prof_cnt[p.label] += 1;
+        }
+        c->ev_pool.push_back(p.a);
+        c->ev_pool.push_back(p.b);
+    }
+    c->pending.clear();
+}
+
 int sync_and_check(ap_ctx *c) {
     int rc = hip_check(c, hipStreamSynchronize(c->stream), "stream synchronize");
     if (rc) return rc;
+    prof_resolve(c);
     int flags[4];
     rc = hip_check(c, hipMemcpy(flags, c->d_flags, sizeof(flags), hipMemcpyDeviceToHost), "flags");
     if (rc) return rc;
@@ -47,21 +94,43 @@ static int nblocks(int n) { return (n + kBlock - 1) / kBlock; }
 static int evaluate(ap_ctx *c, int n, const double *box, const EvalFlags &f, const double *lam_in,
                     const int32_t *subset, int n_subset, bool run_ace, double *E_tot, double *E_atom, double *F,
                     double *virial, bool force_list) {
-    int rc = ensure_list(c, n, box, list_radius(c, f.switching), force_list);
+    int rc;
+    {
+        ProfScope p(c, "nbr_list");
+        rc = ensure_list(c, n, box, list_radius(c, f.switching), force_list);
+    }
     if (rc) return rc;
-    if (f.switching) launch_csp_value(c, n, box);
-    launch_dens_desc(c, n, box, f, lam_in);
+    if (f.switching) {
+        ProfScope p(c, "csp_value");
+        launch_csp_value(c, n, box);
+    }
+    {
+        ProfScope p(c, "dens_desc");
+        launch_dens_desc(c, n, box, f, lam_in);
+    }
     if (run_ace) {
-        launch_compact(c, n, subset, n_subset);
+        {
+            ProfScope p(c, "compact");
+            launch_compact(c, n, subset, n_subset);
+        }
         rc = launch_ace(c, n, box, std::min(n, 8192));
         if (rc) return rc;
     } else {
         launch_fill_int(c, c->sidx, -1, n);
         launch_fill_int(c, c->d_flags + 2, 0, 1);
     }
-    if (f.switching && f.grad_lambda) launch_W(c, n, box);
-    launch_force(c, n, box, f, E_atom, F);
-    launch_reduce(c, nblocks(n), E_tot, virial);
+    if (f.switching && f.grad_lambda) {
+        ProfScope p(c, "W");
+        launch_W(c, n, box);
+    }
+    {
+        ProfScope p(c, "force");
+        launch_force(c, n, box, f, E_atom, F);
+    }
+    {
+        ProfScope p(c, "reduce");
+        launch_reduce(c, nblocks(n), E_tot, virial);
+    }
     return hip_check(c, hipGetLastError(), "evaluate");
 }
 
@@ -175,6 +244,9 @@ const char *ap_last_error(const ap_ctx *ctx) { return ctx ? ctx->err.c_str() : g
 
 void ap_ctx_destroy(ap_ctx *c) {
     if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    prof_resolve(c);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     ace_free(c);
     void *bufs[] = {c->csp_t, c->rev_start, c->rev_code, c->pos, c->pos_build, c->d_flags, c->cell_of, c->cell_cnt,
                     c->cell_start, c->cell_fill, c->cell_atoms, c->nbr_cnt, c->nbr_idx, c->nbr_rev, c->g, c->d,
@@ -400,6 +472,45 @@ int ap_mixed_energy_forces(ap_ctx *c, int n, const double *pos, const int32_t *s
     return rc;
 }
 
+int ap_set_profiling(ap_ctx *c, int on) {
+    if (!c) return AP_E_ARG;
+    int rc = hip_check(c, hipStreamSynchronize(c->stream), "stream synchronize");
+    prof_resolve(c);
+    c->prof_on = on != 0;
+    c->prof_names.clear();
+    c->prof_ms.clear();
+    c->prof_cnt.clear();
+    return rc;
+}
+
+int ap_get_profile(ap_ctx *c, int max_entries, char *names, double *avg_ms, int64_t *count) {
+    if (!c) return AP_E_ARG;
+    int rc = hip_check(c, hipStreamSynchronize(c->stream), "stream synchronize");
+    if (rc) return rc;
+    prof_resolve(c);
+    const int m = (int)c->prof_names.size();
+    for (int q = 0; q < m && q < max_entries; q++) {
+        if (names) {
+            std::memset(names + 32 * q, 0, 32);
+            std::strncpy(names + 32 * q, c->prof_names[q].c_str(), 31);
+        }
+        if (avg_ms) avg_ms[q] = c->prof_cnt[q] ? c->prof_ms[q] / c->prof_cnt[q] : 0.0;
+        if (count) count[q] = c->prof_cnt[q];
+    }
+    return m;
+}
+
+int ap_ace_cost(ap_ctx *c, double *fixed_per_atom, double *per_neighbor_energy, double *per_neighbor_force) {
+    if (!c) return AP_E_ARG;
+    if (!c->have_pot) return set_error(c, AP_E_STATE, "ap_set_potential has not been called");
+    double a, b, d;
+    ace_cost(c, &a, &b, &d);
+    if (fixed_per_atom) *fixed_per_atom = a;
+    if (per_neighbor_energy) *per_neighbor_energy = b;
+    if (per_neighbor_force) *per_neighbor_force = d;
+    return AP_OK;
+}
+
 int ap_vv_step(ap_ctx *c, int n, double *pos, double *vel, double *F, double mass, double dt, int n_steps,
                const ap_box *box, double *thermo) {
     int rc = check_common(c, n, pos, box, true);
@@ -418,10 +529,15 @@ int ap_vv_step(ap_ctx *c, int n, double *pos, double *vel, double *F, double mas
     // the list must describe these positions: rebuild on the first step of every call
     bool force = true;
     for (int s = 0; s < n_steps; s++) {
-        k_vv_first<<<nb, kBlock, 0, c->stream>>>(pos, vel, F, c->pos, n, hdtm, dt, box->L[0], box->L[1], box->L[2]);
+        {
+            ProfScope p(c, "vv_first");
+            k_vv_first<<<nb, kBlock, 0, c->stream>>>(pos, vel, F, c->pos, n, hdtm, dt, box->L[0], box->L[1],
+                                                     box->L[2]);
+        }
         rc = evaluate(c, n, box->L, f, nullptr, nullptr, 0, run_ace, nullptr, nullptr, F, nullptr, force);
         if (rc) return rc;
         force = false;
+        ProfScope p(c, "vv_second");
         k_vv_second<<<nb, kBlock, 0, c->stream>>>(vel, F, n, hdtm, mass, c->partials);
         k_thermo<<<1, kBlock, 0, c->stream>>>(c->partials, nb, c->scalars, c->d_flags, thermo + (size_t)8 * s);
     }
