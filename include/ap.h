@@ -64,10 +64,11 @@ typedef struct {
     double L[3];
 } ap_box;
 
-/* Finnis-Sinclair EAM, (B1): zeta(r) = (r-rc)^2 + beta (r-rc)^3 / rc, Phi(r) = (r-rc)^2
- * (c0 + c1 r + c2 r^2), both zero for r >= rc; embedding xi(z) = -A sqrt(z). */
+/* Finnis-Sinclair EAM, (B1): density zeta(r) = (r-r_rho)^2 + beta (r-r_rho)^3 / r_rho for r < r_rho,
+ * pair Phi(r) = (r-r_phi)^2 (c0 + c1 r + c2 r^2) for r < r_phi (both zero beyond), embedding
+ * xi(z) = -A sqrt(z). */
 typedef struct {
-    double A, beta, c0, c1, c2, rc;
+    double A, beta, c0, c1, c2, r_rho, r_phi;
 } ap_eam_params;
 
 /* ACE (the paper cites the definition; the concrete form is):

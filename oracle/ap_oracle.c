@@ -341,22 +341,24 @@ static double csp_value(const double *pos, const double *L, int i, int n_csp, co
 }
 
 /* ------------------------------------------------------------------------------------------ */
-/* EAM, Finnis-Sinclair form of (B1): zeta(r) = (r-rc)^2 + beta (r-rc)^3/rc,                    */
-/* Phi(r) = (r-rc)^2 (c0 + c1 r + c2 r^2), xi(z) = -A sqrt(z); all zero beyond rc.             */
-/* eam_p = {A, beta, c0, c1, c2, rc}.                                                           */
+/* EAM, Finnis-Sinclair form of (B1): zeta(r) = (r-r_rho)^2 + beta (r-r_rho)^3/r_rho for r < r_rho, */
+/* Phi(r) = (r-r_phi)^2 (c0 + c1 r + c2 r^2) for r < r_phi, xi(z) = -A sqrt(z).                   */
+/* eam_p = {A, beta, c0, c1, c2, r_rho, r_phi}.                                                   */
 /* ------------------------------------------------------------------------------------------ */
 static void eam_pair(const double *p, double r, double *z, double *dz, double *ph, double *dph) {
-    double rc = p[5];
-    if (r >= rc) {
-        *z = *dz = *ph = *dph = 0.0;
-        return;
+    double rr = p[5], rp = p[6];
+    *z = *dz = *ph = *dph = 0.0;
+    if (r < rr) {
+        double x = r - rr;
+        *z = x * x + p[1] * x * x * x / rr;
+        *dz = 2.0 * x + 3.0 * p[1] * x * x / rr;
     }
-    double x = r - rc;
-    *z = x * x + p[1] * x * x * x / rc;
-    *dz = 2.0 * x + 3.0 * p[1] * x * x / rc;
-    double q = p[2] + p[3] * r + p[4] * r * r;
-    *ph = x * x * q;
-    *dph = 2.0 * x * q + x * x * (p[3] + 2.0 * p[4] * r);
+    if (r < rp) {
+        double y = r - rp;
+        double q = p[2] + p[3] * r + p[4] * r * r;
+        *ph = y * y * q;
+        *dph = 2.0 * y * q + y * y * (p[3] + 2.0 * p[4] * r);
+    }
 }
 
 static void embed(double A, double z, double *f, double *df) {
@@ -684,7 +686,8 @@ int ora_eval(int n, const double *pos_in, const double *L, const double *eam_p, 
              double *E_atom, double *F, double *virial, double *aux, double *Ffam) {
     if (n <= 0 || !pos_in || !L || !eam_p || !sw_p || !E_tot || !E_atom || !F || !virial) return ORA_E_ARG;
     if (n_max > 32 || l_max > 12) return ORA_E_ARG;
-    double rc_eam = eam_p[5], d_lo = sw_p[0], d_hi = sw_p[1], r_w = sw_p[2], d0 = sw_p[3];
+    double rc_eam = eam_p[5] > eam_p[6] ? eam_p[5] : eam_p[6];
+    double d_lo = sw_p[0], d_hi = sw_p[1], r_w = sw_p[2], d0 = sw_p[3];
     int need_sw = (lam_mode < 0);
     double rmax = rc_eam > ace_rc ? rc_eam : ace_rc;
     if (need_sw && r_w > rmax) rmax = r_w;

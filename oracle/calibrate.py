@@ -33,9 +33,10 @@ PI = np.pi
 
 def eam_funcs(p, r):
     """zeta(r), Phi(r) of the Finnis-Sinclair form (zero beyond rc)."""
-    x = np.where(r < p["rc"], r - p["rc"], 0.0)
-    z = x * x + p["beta"] * x ** 3 / p["rc"]
-    ph = x * x * (p["c0"] + p["c1"] * r + p["c2"] * r * r)
+    x = np.where(r < p["r_rho"], r - p["r_rho"], 0.0)
+    z = x * x + p["beta"] * x ** 3 / p["r_rho"]
+    y = np.where(r < p["r_phi"], r - p["r_phi"], 0.0)
+    ph = y * y * (p["c0"] + p["c1"] * r + p["c2"] * r * r)
     return z, ph
 
 
@@ -85,9 +86,9 @@ def calibrate(k, target_x=None):
     lattice = "bcc" if rc["lattice"] in ("bcc", "batch") else "fcc"
     a = rc["a"] if rc["lattice"] != "batch" else 3.16
     out = dict(config=cf.CONFIG_NAMES[k])
-    eam = dict(cf.eam_draw(k, lattice), rc=5.5)
+    eam = dict(cf.eam_draw(k, lattice))
     eam["c0"] = solve_c0(lattice, a, eam)
-    out["eam"] = {kk: eam[kk] for kk in ("A", "beta", "c0", "c1", "c2")}
+    out["eam"] = {kk: eam[kk] for kk in ("A", "beta", "c0", "c1", "c2", "r_rho", "r_phi")}
     n_max, l_max = rc["n_max"], rc["l_max"]
     c1, b_n, ea, eb = fit_two_body(eam, n_max)
     out["fit_maxerr"] = dict(half_phi=ea, zeta=eb)
@@ -117,15 +118,18 @@ def calibrate(k, target_x=None):
         json.dump(out, fh, indent=1)
     if rc["lattice"] == "batch":
         return out
-    # thresholds from the defect-free reference of the same size, noise and seed + 1
-    nc = rc["nc"]
+    # thresholds from a thermalised defect-free reference (seed + 1): same lattice, noise and
+    # temperature, integrated with the EAM alone; d is sampled after equilibration
+    d_max, d_mean = thermal_descriptor_max(k, rc, lattice, a, eam)
+    # the static noisy reference of the full size (the initial state of the run) as well
     mk = st.bcc if lattice == "bcc" else st.fcc
-    ref, box = mk(a, nc)
+    ref, box = mk(a, rc["nc"])
     noisy = st.gaussian_displace(ref, rc["sigma"], np.random.default_rng(1000 + k + 1))
     sw = dict(d_lo=1e9, d_hi=2e9, r_w=rc["r_w"], d0=0.0, n_csp=8 if lattice == "bcc" else 12)
-    aux = O.evaluate(_sysd(noisy, box, eam, _trivial_ace(), sw, pos_ref=ref), skip=2)["aux"]
-    d_lo = 1.25 * float(aux["d"].max())
-    out["sw"] = dict(d_lo=d_lo, d_hi=d_lo + 1.0, ref_d_max=float(aux["d"].max()), ref_d_mean=float(aux["d"].mean()))
+    d_static = float(O.evaluate(_sysd(noisy, box, eam, _trivial_ace(), sw, pos_ref=ref), skip=2)["aux"]["d"].max())
+    d_lo = 1.25 * max(d_max, d_static)
+    out["sw"] = dict(d_lo=d_lo, d_hi=d_lo + 1.0, ref_d_max_thermal=d_max, ref_d_mean_thermal=d_mean,
+                     ref_d_max_static=d_static)
     with open(_path(k), "w") as fh:
         json.dump(out, fh, indent=1)
     if target_x is not None:
@@ -139,6 +143,30 @@ def calibrate(k, target_x=None):
     with open(_path(k), "w") as fh:
         json.dump(out, fh, indent=1)
     return out
+
+
+def thermal_descriptor_max(k, rc, lattice, a, eam, nc_ref=14, steps=400, sample_from=150, every=25):
+    """Largest descriptor d_i seen in an NVE run of a defect-free cell of nc_ref^3 cells with the
+    workload's noise sigma and Maxwell temperature (seed + 1), after sample_from steps."""
+    mk = st.bcc if lattice == "bcc" else st.fcc
+    ref, box = mk(a, nc_ref)
+    pos = st.gaussian_displace(ref, rc["sigma"], np.random.default_rng(1000 + k + 1))
+    vel = st.maxwell_velocities(len(pos), rc["mass"], rc["T"], np.random.default_rng(4000 + k + 1))
+    n_csp = 8 if lattice == "bcc" else 12
+    sw = dict(d_lo=1e9, d_hi=2e9, r_w=rc["r_w"], d0=0.0, n_csp=n_csp)
+    sysd = dict(_sysd(pos, box, eam, _trivial_ace(), sw, pos_ref=ref), mass=rc["mass"], run=dict(dt=rc["dt"]))
+    csp = O.csp_pairs(ref, box, n_csp)
+    d_max, d_sum, n_s = 0.0, 0.0, 0
+    p, v = pos, vel
+    for step in range(0, steps, every):
+        p, v, _, _ = O.velocity_verlet(sysd, every, pos=p, vel=v, csp=csp, lam_mode=1)
+        if step + every >= sample_from:
+            d = O.evaluate(dict(sysd, pos=p), csp=csp, skip=2)["aux"]["d"]
+            d_max = max(d_max, float(d.max()))
+            d_sum += float(d.sum())
+            n_s += len(d)
+        print("  reference step %d d_max %.4f" % (step + every, d_max), flush=True)
+    return d_max, d_sum / max(n_s, 1)
 
 
 def precise_fraction(s):

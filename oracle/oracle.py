@@ -155,7 +155,7 @@ def ace_env(u, ace):
 
 
 def _eam_vec(eam):
-    return _f64([eam["A"], eam["beta"], eam["c0"], eam["c1"], eam["c2"], eam["rc"]])
+    return _f64([eam["A"], eam["beta"], eam["c0"], eam["c1"], eam["c2"], eam["r_rho"], eam["r_phi"]])
 
 
 def _sw_vec(sw):

@@ -33,8 +33,11 @@ class Box(C.Structure):
     _fields_ = [("L", C.c_double * 3)]
 
 
+EAM_KEYS = ("A", "beta", "c0", "c1", "c2", "r_rho", "r_phi")
+
+
 class EamParams(C.Structure):
-    _fields_ = [(k, C.c_double) for k in ("A", "beta", "c0", "c1", "c2", "rc")]
+    _fields_ = [(k, C.c_double) for k in EAM_KEYS]
 
 
 class AceParams(C.Structure):
@@ -136,7 +139,7 @@ class Context:
         return torch.zeros(*shape, dtype=dtype, device=self.device)
 
     def set_potential(self, eam, ace, sw, lambda_mode=AP_LAMBDA_COMPUTED, grad_lambda=True, precision=None):
-        e = EamParams(*[float(eam[k]) for k in ("A", "beta", "c0", "c1", "c2", "rc")])
+        e = EamParams(*[float(eam[k]) for k in EAM_KEYS])
         func = np.ascontiguousarray(ace["func"], dtype=np.int32)
         c = np.ascontiguousarray(ace["c"], dtype=np.float64)
         b = np.ascontiguousarray(ace["b_dens"], dtype=np.float64)

@@ -83,7 +83,7 @@ int sync_and_check(ap_ctx *c) {
 }
 
 static double list_radius(const ap_ctx *c, bool switching) {
-    double r = std::max(c->eam.rc, c->ace.rc);
+    double r = std::max(std::max(c->eam.r_rho, c->eam.r_phi), c->ace.rc);
     if (switching) r = std::max(r, c->sw.r_w);
     return r + c->skin;
 }
@@ -311,7 +311,7 @@ int ap_ctx_create(ap_ctx **out, int n_max_atoms, int max_nbr, double skin, void 
 int ap_set_potential(ap_ctx *c, const ap_eam_params *eam, const ap_ace_params *ace, const ap_switch_params *sw) {
     if (!c) return AP_E_ARG;
     if (!eam || !ace || !sw) return set_error(c, AP_E_ARG, "null parameter struct");
-    if (!(eam->rc > 0) || !(ace->rc > 0)) return set_error(c, AP_E_ARG, "cutoffs must be > 0");
+    if (!(eam->r_rho > 0) || !(eam->r_phi > 0) || !(ace->rc > 0)) return set_error(c, AP_E_ARG, "cutoffs must be > 0");
     if (sw->lambda_mode != AP_LAMBDA_COMPUTED && sw->lambda_mode != AP_LAMBDA_PRECISE &&
         sw->lambda_mode != AP_LAMBDA_FAST)
         return set_error(c, AP_E_ARG, "lambda_mode");

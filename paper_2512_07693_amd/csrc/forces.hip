@@ -13,17 +13,27 @@
 namespace ap {
 
 struct EamP {
-    double A, beta, c0, c1, c2, rc, rc2;
+    double A, beta, c0, c1, c2, r_rho, r_phi, rc2;  // rc2 = max(r_rho, r_phi)^2
 };
-static EamP eamp(const ap_eam_params &e) { return {e.A, e.beta, e.c0, e.c1, e.c2, e.rc, e.rc * e.rc}; }
+static EamP eamp(const ap_eam_params &e) {
+    const double m = e.r_rho > e.r_phi ? e.r_rho : e.r_phi;
+    return {e.A, e.beta, e.c0, e.c1, e.c2, e.r_rho, e.r_phi, m * m};
+}
 
+// zeta, zeta', Phi, Phi' of the Finnis-Sinclair form at r (each zero beyond its own cutoff)
 __device__ __forceinline__ void eam_pair(const EamP &p, double r, double &z, double &dz, double &ph, double &dph) {
-    const double x = r - p.rc;
-    const double q = p.c0 + r * (p.c1 + p.c2 * r);
-    z = x * x * (1.0 + p.beta * x / p.rc);
-    dz = x * (2.0 + 3.0 * p.beta * x / p.rc);
-    ph = x * x * q;
-    dph = x * (2.0 * q + x * (p.c1 + 2.0 * p.c2 * r));
+    z = dz = ph = dph = 0.0;
+    if (r < p.r_rho) {
+        const double x = r - p.r_rho;
+        z = x * x * (1.0 + p.beta * x / p.r_rho);
+        dz = x * (2.0 + 3.0 * p.beta * x / p.r_rho);
+    }
+    if (r < p.r_phi) {
+        const double y = r - p.r_phi;
+        const double q = p.c0 + r * (p.c1 + p.c2 * r);
+        ph = y * y * q;
+        dph = y * (2.0 * q + y * (p.c1 + 2.0 * p.c2 * r));
+    }
 }
 
 struct SwP {

@@ -29,10 +29,13 @@ CONFIG_NAMES = {
 _DATA = os.path.join(os.path.dirname(__file__), "data")
 
 # EAM draw ranges (analytic Finnis-Sinclair form); c0 is solved for zero pressure.
-_EAM_RANGES = {
-    "bcc": dict(A=(1.95, 2.05), beta=(0.45, 0.55), c1=(-3.03, -2.97), c2=(0.398, 0.402)),
-    "fcc": dict(A=(1.85, 1.95), beta=(0.95, 1.05), c1=(-1.03, -0.97), c2=(0.098, 0.102)),
+# EAM draws: the Finnis-Sinclair form with tungsten-like nominal values (density cutoff 4.400224 A,
+# pair cutoff 3.25 A; bcc ground state at a = 3.165 A, cohesive energy 8.90 eV); A is drawn +-2 %
+# and beta in [0, 0.02], c0 is then solved for zero pressure at the workload's lattice constant.
+_EAM_NOMINAL = {
+    "bcc": dict(A=1.896373, c1=-33.7665655, c2=6.2541999, r_rho=4.400224, r_phi=3.25),
 }
+_EAM_RANGES = {"bcc": dict(A=(0.98, 1.02), beta=(0.0, 0.02))}
 
 _RECIPES = {
     1: dict(lattice="bcc", a=3.16, nc=8, sigma=0.05, mass=183.84, n_max=8, l_max=4, caps={},
@@ -67,10 +70,14 @@ def recipe(k):
 
 
 def eam_draw(k, lattice):
-    """Seeded (A, beta, c1, c2) of the Finnis-Sinclair EAM of workload k."""
+    """Seeded Finnis-Sinclair EAM parameters of workload k (c0 still to be solved)."""
+    if lattice not in _EAM_NOMINAL:
+        raise NotImplementedError("no EAM parameter set for the %s lattice" % lattice)
     rng = np.random.default_rng(2000 + k)
-    r = _EAM_RANGES[lattice]
-    return {name: float(rng.uniform(*r[name])) for name in ("A", "beta", "c1", "c2")}
+    p = dict(_EAM_NOMINAL[lattice])
+    p["A"] *= float(rng.uniform(*_EAM_RANGES[lattice]["A"]))
+    p["beta"] = float(rng.uniform(*_EAM_RANGES[lattice]["beta"]))
+    return p
 
 
 def ace_unit_draw(k, n_funcs):
@@ -120,8 +127,7 @@ def build_system(k, nc=None, with_velocities=True):
     lattice = "bcc" if rc["lattice"] in ("bcc", "batch") else "fcc"
     eam = dict(eam_draw(k, lattice))
     eam.update(cal.get("eam", {}))
-    eam.setdefault("c0", 0.0)
-    eam["rc"] = 5.5
+    eam.setdefault("c0", 47.1346499)
     func = ace_basis(rc["n_max"], rc["l_max"], **rc["caps"])
     n1 = int((func[:, 2] < 0).sum())
     ace_cal = cal.get("ace", {})

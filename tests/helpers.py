@@ -15,7 +15,7 @@ def small_ace(n_max=4, l_max=2, seed=0, scale=0.01):
     return dict(n_max=n_max, l_max=l_max, rc=5.5, func=func, c=c, b_dens=b, emb_A=2.0, E0=0.1, precision="fp64")
 
 
-EAM = dict(A=2.0, beta=0.5, c0=5.04, c1=-3.0, c2=0.4, rc=5.5)
+EAM = dict(A=1.896373, beta=0.01, c0=47.1346499, c1=-33.7665655, c2=6.2541999, r_rho=4.400224, r_phi=3.25)
 
 
 def small_system(nc=4, sigma=0.12, seed=0, d_lo=0.7, d_hi=1.6, r_w=6.0, lattice="bcc", n_max=4, l_max=2):

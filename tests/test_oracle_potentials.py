@@ -12,9 +12,10 @@ SHELLS_BCC = [(1.0, 8), (2 / math.sqrt(3), 6), (math.sqrt(8 / 3), 12), (math.sqr
 
 
 def _fs(r, p):
-    x = r - p["rc"]
-    return (x * x + p["beta"] * x ** 3 / p["rc"], x * x * (p["c0"] + p["c1"] * r + p["c2"] * r * r)) if r < p["rc"] \
-        else (0.0, 0.0)
+    x, y = r - p["r_rho"], r - p["r_phi"]
+    z = x * x + p["beta"] * x ** 3 / p["r_rho"] if r < p["r_rho"] else 0.0
+    ph = y * y * (p["c0"] + p["c1"] * r + p["c2"] * r * r) if r < p["r_phi"] else 0.0
+    return z, ph
 
 
 def _sys(pos, box, ace=None, lam_sw=None):
