@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE: this script only calls the CPU oracle (and the seeded gener
 What it fixes, per workload k:
   eam.c0      zero pressure of the perfect lattice at the nominal lattice constant
   ace.c_order1, ace.b_dens
-              least-squares fit on r in [2.0, 5.5] A of the Chebyshev channels to the EAM
+              ridge-regularised least-squares fit on r in [2.0, 5.5] A of the Chebyshev channels to the EAM
               pair term Phi/2 and density zeta, so that the ACE two-body part and embedding
               follow the EAM (the fast model is a surrogate of the precise one near the lattice)
   ace.c_scale scale of the seeded N(0,1) order-2/3 coefficients such that the rms over a
@@ -29,6 +29,7 @@ from synth import structures as st  # noqa: E402
 from oracle import oracle as O  # noqa: E402
 
 PI = np.pi
+RIDGE = 1e-8  # Tikhonov weight of the two-body fit, per sample
 
 
 def eam_funcs(p, r):
@@ -75,8 +76,13 @@ def fit_two_body(eam, n_max, rc=5.5):
     r = np.linspace(2.0, rc, 701)
     G = np.array([O.radial(n_max, rc, x)[0] for x in r])
     z, ph = eam_funcs(eam, r)
-    a_n = np.linalg.lstsq(G, 0.5 * ph, rcond=None)[0]
-    b_n = np.linalg.lstsq(G, z, rcond=None)[0]
+    # The Chebyshev-times-cutoff channels are nearly collinear on [2, rc] (condition number ~1e7
+    # at n_max = 12); plain least squares returns alternating coefficients of order 1e4 whose
+    # cancellation no FP32 evaluation survives. A Tikhonov term of 1e-8 per sample keeps them
+    # of order 10 at a fit error within a factor 1.5 of the unregularised one.
+    A = G.T @ G + RIDGE * len(r) * np.eye(n_max)
+    a_n = np.linalg.solve(A, G.T @ (0.5 * ph))
+    b_n = np.linalg.solve(A, G.T @ z)
     # order-1 basis function A_n00 = sum_j g_n / sqrt(4 pi): coefficient sqrt(4 pi) a_n
     return np.sqrt(4 * PI) * a_n, b_n, float(np.abs(G @ a_n - 0.5 * ph).max()), float(np.abs(G @ b_n - z).max())
 
