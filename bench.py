@@ -67,8 +67,9 @@ def run_md(ctx, s, pos0, vel0, steps, warmup, profile_steps):
     pos = pos0.clone()
     vel = vel0.clone()
     F = ctx.mixed_energy_forces(pos, box)["F"]
+    th_w = None
     if warmup:
-        ctx.vv_step(pos, vel, F, s["mass"], s["run"]["dt"], warmup, box)
+        th_w = ctx.vv_step(pos, vel, F, s["mass"], s["run"]["dt"], warmup, box).cpu().numpy()
     stream = ctx.stream
     torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
@@ -81,7 +82,7 @@ def run_md(ctx, s, pos0, vel0, steps, warmup, profile_steps):
     ms = t0.elapsed_time(t1)
     prof = ctx.get_profile()
     ctx.set_profiling(False)
-    return ms, thermo.cpu().numpy(), prof
+    return ms, thermo.cpu().numpy(), prof, th_w
 
 
 def cpu_baseline(s, steps):
@@ -100,7 +101,7 @@ def main():
     ap_ = argparse.ArgumentParser()
     ap_.add_argument("--gpus", type=int, default=1)
     ap_.add_argument("--steps", type=int, default=1000)
-    ap_.add_argument("--warmup", type=int, default=20)
+    ap_.add_argument("--warmup", type=int, default=200)
     ap_.add_argument("--pure-steps", type=int, default=20)
     ap_.add_argument("--cpu-steps", type=int, default=2)
     ap_.add_argument("--no-cpu", action="store_true")
@@ -127,16 +128,20 @@ def main():
     ctx.set_potential(s["eam"], s["ace"], s["sw"])
     ctx.csp_pairs_build(ref, box, s["sw"]["n_csp"])
     log("mixed: %d warmup + %d timed steps ..." % (args.warmup, args.steps))
-    ms, thermo, prof = run_md(ctx, s, pos0, vel0, args.steps, args.warmup, 0)
+    ms, thermo, prof, th_w = run_md(ctx, s, pos0, vel0, args.steps, args.warmup, 0)
     value = n * args.steps / (ms / 1e3)
     nve = drift_fit(thermo, n, s["run"]["dt"])
+    if th_w is not None:
+        # the same fit from the first step on, equilibration transient included
+        nve["from_step_0"] = {k: v for k, v in drift_fit(np.concatenate([th_w, thermo]), n, s["run"]["dt"]).items()
+                              if k in ("drift_eV_per_atom_per_ps", "max_abs_dE_per_atom", "steps", "x_max")}
     log("mixed: %.3f ms/step, %.3e atom-steps/s, x=%.4f" % (ms / args.steps, value, nve["x_mean"]))
 
     # pure ACE: the same potential with lambda == 0 everywhere
     ctx_p = ap.Context(n, max_nbr=128, skin=s["run"]["skin"])
     ctx_p.set_potential(s["eam"], s["ace"], s["sw"], lambda_mode=ap.AP_LAMBDA_PRECISE)
     log("pure ACE: %d timed steps ..." % args.pure_steps)
-    ms_p, thermo_p, prof_p = run_md(ctx_p, s, pos0, vel0, args.pure_steps, 2, 0)
+    ms_p, thermo_p, prof_p, _ = run_md(ctx_p, s, pos0, vel0, args.pure_steps, 2, 0)
     value_p = n * args.pure_steps / (ms_p / 1e3)
     log("pure ACE: %.3f ms/step, %.3e atom-steps/s" % (ms_p / args.pure_steps, value_p))
 

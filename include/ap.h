@@ -153,6 +153,19 @@ int ap_switch_eval(ap_ctx *ctx, int n, const double *pos, const ap_box *box, dou
 int ap_ace_eval(ap_ctx *ctx, int n, const double *pos, const int32_t *species, const ap_box *box,
                 const int32_t *subset, int n_subset, double *E_tot, double *E_atom, double *F, double *virial9);
 
+/* ACE on a ragged batch of periodic cells in one launch, with the adjoint with respect to the ACE
+ * coefficients: structure s holds atoms offsets[s] .. offsets[s+1]-1 of pos (device [3][n],
+ * n = offsets[n_struct]) in the orthorhombic box boxes[3s..3s+2] (host arrays offsets [n_struct+1],
+ * boxes [n_struct][3]). With w_i = weight[i] (device [n], NULL = 1), i.e. the ACE weight 1 - lambda_i
+ * of Eq. (4):
+ *   E_struct[s]      = sum_{i in s} w_i E^p_i                        device [n_struct]
+ *   F                = -grad of sum_s E_struct[s]                    device [3][n]          (optional)
+ *   dEdc[s][nu]      = sum_{i in s} w_i B_i,nu = dE_struct/dc_nu     device [n_struct][n_funcs] (opt.)
+ *   dEdb[s][n]       = sum_{i in s} w_i xi'(phi2_i) sqrt(4 pi) A_i,n00  device [n_struct][n_max] (opt.)
+ * where nu indexes the rows of ap_ace_params.func. The coefficients are those of ap_set_potential. */
+int ap_ace_batch_eval(ap_ctx *ctx, int n_struct, const int32_t *offsets, const double *boxes, const double *pos,
+                      const double *weight, double *E_struct, double *F, double *dEdc, double *dEdb);
+
 /* The adaptive-precision evaluation: Eq. (4) energies and the conservative force Eq. (5).
  * E_tot [1], E_atom [n], F [3][n], virial9 [9], lambda_out [n]: device, each optional. */
 int ap_mixed_energy_forces(ap_ctx *ctx, int n, const double *pos, const int32_t *species, const ap_box *box,

@@ -20,7 +20,8 @@ ERRORS = {-1: "AP_E_ARG", -2: "AP_E_BOX", -3: "AP_E_NBR_OVERFLOW", -4: "AP_E_NON
           -6: "AP_E_CSP", -7: "AP_E_STATE"}
 SYMBOLS = ["ap_ctx_create", "ap_ctx_destroy", "ap_last_error", "ap_set_potential", "ap_csp_pairs_build",
            "ap_set_csp_list", "ap_nblist_build", "ap_eam_eval", "ap_switch_eval", "ap_ace_eval",
-           "ap_mixed_energy_forces", "ap_vv_step", "ap_set_profiling", "ap_get_profile", "ap_ace_cost"]
+           "ap_mixed_energy_forces", "ap_vv_step", "ap_set_profiling", "ap_get_profile", "ap_ace_cost",
+           "ap_ace_batch_eval"]
 
 
 class APError(RuntimeError):
@@ -79,6 +80,7 @@ def lib():
         L.ap_set_profiling.argtypes = [vp, i]
         L.ap_get_profile.argtypes = [vp, i, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.ap_ace_cost.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.ap_ace_batch_eval.argtypes = [vp, i, C.POINTER(C.c_int32), C.POINTER(C.c_double), vp, vp, vp, vp, vp, vp]
         for s in SYMBOLS:
             if s not in ("ap_ctx_destroy", "ap_last_error"):
                 getattr(L, s).restype = i
@@ -151,6 +153,7 @@ class Context:
         s = SwitchParams(float(sw["d_lo"]), float(sw["d_hi"]), float(sw["r_w"]), float(sw.get("d0", 0.0)),
                          int(sw["n_csp"]), int(lambda_mode), AP_IND_CSP, 1 if grad_lambda else 0)
         self._chk(lib().ap_set_potential(self.h, C.byref(e), C.byref(a), C.byref(s)))
+        self._nf, self._nm = len(func), int(ace["n_max"])
 
     def csp_pairs_build(self, pos_ref, box, n_csp):
         n = pos_ref.shape[1]
@@ -207,6 +210,25 @@ class Context:
         self._chk(lib().ap_mixed_energy_forces(self.h, n, _ptr(pos), None, C.byref(_box(box)), _ptr(E), _ptr(Ea),
                                                _ptr(F), _ptr(V), _ptr(lam)))
         return dict(E=E, E_atom=Ea, F=F, virial=V.view(3, 3), lam=lam)
+
+    def ace_batch_eval(self, pos, offsets, boxes, weight=None, forces=True, coeff_grad=True):
+        """ACE over a ragged batch of periodic cells (one launch): per-structure energies, forces and
+        dE/dc, dE/db per structure. offsets: int sequence [n_struct + 1]; boxes: (n_struct, 3)."""
+        off = np.ascontiguousarray(offsets, dtype=np.int32)
+        bx = np.ascontiguousarray(boxes, dtype=np.float64).reshape(-1, 3)
+        ns, n = len(off) - 1, int(off[-1])
+        _dev(pos, torch.float64, (3, n))
+        if weight is not None:
+            _dev(weight, torch.float64, (n,))
+        E = self._zeros(ns)
+        F = self._zeros(3, n) if forces else None
+        nf, nm = self._nf, self._nm
+        dc = self._zeros(ns, nf) if coeff_grad else None
+        db = self._zeros(ns, nm) if coeff_grad else None
+        self._chk(lib().ap_ace_batch_eval(self.h, ns, off.ctypes.data_as(C.POINTER(C.c_int32)),
+                                          bx.ctypes.data_as(C.POINTER(C.c_double)), _ptr(pos), _ptr(weight),
+                                          _ptr(E), _ptr(F), _ptr(dc), _ptr(db)))
+        return dict(E=E, F=F, dEdc=dc, dEdb=db)
 
     def set_profiling(self, on=True):
         self._chk(lib().ap_set_profiling(self.h, 1 if on else 0))

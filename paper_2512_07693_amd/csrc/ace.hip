@@ -180,7 +180,28 @@ struct AceArgs {
     int nblk;
     double emb_A, E0;
     int *flags;
+    // batches of periodic cells: box of structure sid[i] (null: the single box L)
+    const double *sbox;
+    const int *sid;
+    // coefficient gradients: bval[s][nu] = dE_i/dc_nu, bval[s][n_funcs + n] = dE_i/db_n (null: off)
+    void *bval;
+    int bstride, n_funcs;
+    const int *g1, *g2, *g3;
+    int ng1, ng2;
 };
+
+__device__ __forceinline__ void atom_box(const AceArgs &a, int i, double &Lx, double &Ly, double &Lz) {
+    if (a.sbox) {
+        const double *b = a.sbox + 3 * a.sid[i];
+        Lx = b[0];
+        Ly = b[1];
+        Lz = b[2];
+    } else {
+        Lx = a.L[0];
+        Ly = a.L[1];
+        Lz = a.L[2];
+    }
+}
 
 __device__ __forceinline__ double block_sum_d(double v, double *sh) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -207,6 +228,7 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
     __shared__ int sCnt[5];
     __shared__ double sRed[kBlock / 64];
     __shared__ T sEmbD;
+    __shared__ double sEmbD64;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const T *c1 = (const T *)a.c1, *bd = (const T *)a.bd, *c2 = (const T *)a.c2, *c3 = (const T *)a.c3;
     const T *kval = (const T *)a.kval;
@@ -217,6 +239,8 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
     for (int s = blockIdx.x; s < S; s += gridDim.x) {
         const int i = a.slist[s];
         const double xi = a.pos[i], yi = a.pos[n + i], zi = a.pos[2 * n + i];
+        double Lx, Ly, Lz;
+        atom_box(a, i, Lx, Ly, Lz);
         const int cnt = a.ncount[i];
         if (tid == 0) sCnt[4] = 0;
         __syncthreads();
@@ -227,9 +251,9 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
             double ux = 0, uy = 0, uz = 0, r2 = 0;
             if (slot < cnt) {
                 const int j = a.nidx[(size_t)slot * n + i];
-                ux = min_image(a.pos[j] - xi, a.L[0]);
-                uy = min_image(a.pos[n + j] - yi, a.L[1]);
-                uz = min_image(a.pos[2 * n + j] - zi, a.L[2]);
+                ux = min_image(a.pos[j] - xi, Lx);
+                uy = min_image(a.pos[n + j] - yi, Ly);
+                uz = min_image(a.pos[2 * n + j] - zi, Lz);
                 r2 = ux * ux + uy * uy + uz * uz;
                 valid = r2 < rc2;
             }
@@ -305,9 +329,24 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
                 demb = -0.5 * a.emb_A / sq;
             }
             sEmbD = (T)demb;
+            sEmbD64 = demb;
             e = a.E0 + e1 + emb;
         }
         __syncthreads();
+        T *bout = a.bval ? (T *)a.bval + (size_t)s * a.bstride : nullptr;
+        if (bout) {
+            // dE/dc for orders 1 and 2 (B values) and dE/db_n = xi'(phi2) s_n
+            const double y00 = 0.28209479177387814;
+            for (int q = tid; q < a.ng1; q += kBlock) bout[a.g1[2 * q + 1]] = (T)(sS[a.g1[2 * q]] * y00);
+            for (int q = tid; q < NMAX; q += kBlock) bout[a.n_funcs + q] = (T)(sEmbD64 * sS[q]);
+            for (int q = tid; q < a.ng2; q += kBlock) {
+                const int code = a.g2[2 * q];
+                const int q1 = code & 255, q2 = (code >> 8) & 255, l = code >> 16;
+                T bsum = T(0);
+                for (int m = l * l; m <= l * l + 2 * l; m++) bsum += sA[q1 * NLM + m] * sA[q2 * NLM + m];
+                bout[a.g2[2 * q + 1]] = bsum;
+            }
+        }
         for (int o = tid; o < NA; o += kBlock) {
             const int q = o / NLM, lm = o - q * NLM;
             int l = 0;
@@ -346,6 +385,16 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
                 e += (double)(P * Q);
             }
             __syncthreads();
+            if (bout) {
+                // B of the block's basis functions: sum_M P_M[n1][n2] A_{n3 L M}
+                for (int q = bk[46] + tid; q < bk[47]; q += kBlock) {
+                    const int code = a.g3[2 * q];
+                    const int rem = code & 0xffff, q3 = code >> 16;
+                    T bsum = T(0);
+                    for (int Mi = 0; Mi < nM; Mi++) bsum += sP[Mi * NN + rem] * sA[q3 * NLM + bL + Mi - L];
+                    bout[a.g3[2 * q + 1]] = bsum;
+                }
+            }
             for (int o = tid; o < NMAX * nM; o += kBlock) {
                 const int q3 = o / nM, Mi = o - q3 * nM;
                 T acc = T(0);
@@ -412,13 +461,15 @@ __global__ __launch_bounds__(128) void k_ace_pairforce(AceArgs a) {
         const T *gin = (const T *)a.gbuf + (size_t)s * NA;
         for (int o = threadIdx.x; o < NA; o += blockDim.x) sG[o] = gin[o];
         __syncthreads();
+        double Lx, Ly, Lz;
+        atom_box(a, i, Lx, Ly, Lz);
         const double xi = a.pos[i], yi = a.pos[n + i], zi = a.pos[2 * n + i];
         const int cnt = a.ncount[i];
         T *fo = (T *)a.fpair + (size_t)s * a.max_nbr * 3;
         for (int slot = threadIdx.x; slot < cnt; slot += blockDim.x) {
             const int j = a.nidx[(size_t)slot * n + i];
-            const double ux = min_image(a.pos[j] - xi, a.L[0]), uy = min_image(a.pos[n + j] - yi, a.L[1]),
-                         uz = min_image(a.pos[2 * n + j] - zi, a.L[2]);
+            const double ux = min_image(a.pos[j] - xi, Lx), uy = min_image(a.pos[n + j] - yi, Ly),
+                         uz = min_image(a.pos[2 * n + j] - zi, Lz);
             const double r2 = ux * ux + uy * uy + uz * uz;
             T f0 = T(0), f1 = T(0), f2 = T(0);
             if (r2 < rc2) {
@@ -548,6 +599,9 @@ void ace_free(ap_ctx *c) {
     (void)hipFree(t.bd);
     (void)hipFree(t.c1d);
     (void)hipFree(t.bdd);
+    (void)hipFree(t.g1);
+    (void)hipFree(t.g2);
+    (void)hipFree(t.g3);
     (void)hipFree(t.c2);
     (void)hipFree(t.c3);
     (void)hipFree(t.kval);
@@ -589,16 +643,24 @@ int ace_setup(ap_ctx *c, const ap_ace_params *p) {
                 }
     std::vector<double> c3(blocks.size() * (size_t)N * N * N, 0.0);
     std::vector<char> used(blocks.size(), 0);
+    // gradient lists (function index nu with where its B value lives): order 1 (n, nu),
+    // order 2 (n1 | n2 << 8 | l << 16, nu), order 3 per block (n1 * N + n2 | n3 << 16, nu)
+    std::vector<int> g1, g2;
+    std::vector<std::vector<int>> g3(blocks.size());
     for (int f = 0; f < p->n_funcs; f++) {
         const int32_t *r = p->func + 6 * f;
         const double cf = p->c[f];
         if (r[2] < 0) {
             if (r[0] < 0 || r[0] >= N || r[1] != 0) return set_error(c, AP_E_ARG, "order-1 basis row");
             c1[r[0]] += cf;
+            g1.push_back(r[0]);
+            g1.push_back(f);
         } else if (r[4] < 0) {
             const int n1 = r[0], l = r[1], n2 = r[2];
             if (r[3] != l || l < 0 || l > Lm || n1 < 0 || n2 < 0 || n1 >= N || n2 >= N)
                 return set_error(c, AP_E_ARG, "order-2 basis row");
+            g2.push_back(n1 | (n2 << 8) | (l << 16));
+            g2.push_back(f);
             if (n1 == n2) {
                 c2[((size_t)l * N + n1) * N + n2] += cf;
             } else {
@@ -621,8 +683,11 @@ int ace_setup(ap_ctx *c, const ap_ace_params *p) {
             if (bi < 0) return set_error(c, AP_E_ARG, "order-3 row violates the triangle or parity rule");
             c3[(((size_t)bi * N + ln[1][1]) * N + ln[2][1]) * N + ln[0][1]] += cf;
             used[bi] = 1;
+            g3[bi].push_back((ln[1][1] * N + ln[2][1]) | (ln[0][1] << 16));
+            g3[bi].push_back(f);
         }
     }
+    std::vector<int> g3flat;
     // keep only blocks with coefficients; build coupling tables in three orderings
     std::vector<int> hblk;
     std::vector<int> kidx;
@@ -653,12 +718,27 @@ int ace_setup(ap_ctx *c, const ap_ace_params *p) {
         emit(4, -B.L, B.L, 0);
         emit(18, -B.l1, B.l1, 1);
         emit(32, -B.l2, B.l2, 2);
+        d[46] = (int)g3flat.size() / 2;
+        g3flat.insert(g3flat.end(), g3[bi].begin(), g3[bi].end());
+        d[47] = (int)g3flat.size() / 2;
         hblk.insert(hblk.end(), d.begin(), d.end());
         nb++;
     }
     t.nblk = nb;
     t.h_blk = hblk;
+    t.ng1 = (int)g1.size() / 2;
+    t.ng2 = (int)g2.size() / 2;
     int rc;
+    auto up_int = [&](int **dst, std::vector<int> v) {
+        if (v.empty()) v.push_back(0);
+        int r = hip_check(c, hipMalloc(dst, sizeof(int) * v.size()), "ace tables");
+        if (!r) r = hip_check(c, hipMemcpy(*dst, v.data(), sizeof(int) * v.size(), hipMemcpyHostToDevice), "ace");
+        return r;
+    };
+    rc = up_int(&t.g1, g1);
+    if (!rc) rc = up_int(&t.g2, g2);
+    if (!rc) rc = up_int(&t.g3, g3flat);
+    if (rc) return rc;
     if (p->precision == AP_FP32) {
         rc = upload<float>(c, &t.c1, c1);
         if (!rc) rc = upload<float>(c, &t.bd, bd);
@@ -717,7 +797,7 @@ void ace_cost(const ap_ctx *c, double *fixed, double *per_nbr_energy, double *pe
     *per_nbr_force = NLM * (4.0 * N + 12.0) + 6.0 * N + 20.0 * NLM;
 }
 
-int launch_ace(ap_ctx *c, int n, const double *box, int grid_cap) {
+int launch_ace(ap_ctx *c, int n, const double *box, int grid_cap, const double *sbox, bool want_bval) {
     const AceTables &t = c->ace;
     AceArgs a;
     a.pos = c->pos;
@@ -749,6 +829,16 @@ int launch_ace(ap_ctx *c, int n, const double *box, int grid_cap) {
     a.c1d = t.c1d;
     a.bdd = t.bdd;
     a.flags = c->d_flags;
+    a.sbox = sbox;
+    a.sid = sbox ? c->sid : nullptr;
+    a.bval = want_bval ? c->bval : nullptr;
+    a.bstride = t.n_funcs + t.n_max;
+    a.n_funcs = t.n_funcs;
+    a.g1 = t.g1;
+    a.g2 = t.g2;
+    a.g3 = t.g3;
+    a.ng1 = t.ng1;
+    a.ng2 = t.ng2;
     const int grid = grid_cap < 1 ? 1 : grid_cap;
     const bool f32 = t.precision == AP_FP32;
     if (t.n_max == 12) {

@@ -79,9 +79,12 @@ struct AceTables {
     void *kval = nullptr; // coupling values, three orderings (by M, by m1, by m2)
     int *kidx = nullptr;  // packed (m1 + 8) | (m2 + 8) << 8 | (M + 8) << 16, same three orderings
     int *blk = nullptr;   // [nblk][kBlkInts] block descriptors
+    int *g1 = nullptr, *g2 = nullptr, *g3 = nullptr;  // coefficient-gradient lists (see ace_setup)
+    int ng1 = 0, ng2 = 0;
     std::vector<int> h_blk;
 };
-constexpr int kBlkInts = 48;  // L, l1, l2, c3 offset, then 3 x 14 start offsets (by M, m1, m2)
+// L, l1, l2, c3 offset, 3 x 14 coupling start offsets (by M, m1, m2), order-3 gradient list range
+constexpr int kBlkInts = 48;
 
 struct Geometry {
     double L[3];
@@ -122,13 +125,19 @@ struct ap_ctx {
     int *cell_of = nullptr, *cell_cnt = nullptr, *cell_start = nullptr, *cell_fill = nullptr, *cell_atoms = nullptr;
     int *scan_tmp = nullptr;
 
-    // neighbour list (slot-major) and reverse slot index
-    int32_t *nbr_cnt = nullptr, *nbr_idx = nullptr, *nbr_rev = nullptr;
+    // neighbour list (slot-major)
+    int32_t *nbr_cnt = nullptr, *nbr_idx = nullptr;
 
     // per-atom intermediates
     double *g = nullptr, *d = nullptr, *wbar = nullptr, *lam = nullptr, *dlam = nullptr;
     double *Ef = nullptr, *Ep = nullptr, *Et = nullptr, *W = nullptr, *xip = nullptr;
     int *sidx = nullptr, *slist = nullptr, *blk_cnt = nullptr, *mark = nullptr;
+    int *sid = nullptr;          // [n_cap] structure of each atom in a batch evaluation
+    int *b_off = nullptr;        // [n_struct + 1] device copy of the batch offsets
+    double *b_box = nullptr;     // [n_struct][3] device copy of the batch boxes
+    int b_cap = 0;
+    void *bval = nullptr;        // [n_cap][n_funcs + n_max] dE_i/dc and dE_i/db (batch gradients)
+    size_t bval_bytes = 0;
     void *fpair = nullptr;       // [n_cap][max_nbr][3] ACE pair gradients (double or float)
     void *gbuf = nullptr;        // [n_cap][n_max * (l_max+1)^2] dE/dA of the S atoms
     size_t fpair_bytes = 0, gbuf_bytes = 0;
@@ -173,11 +182,16 @@ int install_csp(ap_ctx *c, int n, int n_csp, const int32_t *list);
 void launch_fill_int(ap_ctx *c, int *p, int v, int count);
 void launch_fill_double(ap_ctx *c, double *p, double v, int count);
 void launch_scan(ap_ctx *c, const int *in, int *out, int len, int *total, const int *gate);
+int batch_lists(ap_ctx *c, int n, int n_struct, const int *d_off, const double *d_box, const double *pos_in,
+                double r_list);
 
 // ace.hip
 int ace_setup(ap_ctx *c, const ap_ace_params *p);
 void ace_free(ap_ctx *c);
-int launch_ace(ap_ctx *c, int n, const double *box, int grid_cap);
+// sbox: per-structure boxes of a batch (atom i uses sbox[3 * sid[i]]), null for the single box;
+// want_bval: also write the per-atom coefficient gradients into c->bval
+int launch_ace(ap_ctx *c, int n, const double *box, int grid_cap, const double *sbox = nullptr,
+               bool want_bval = false);
 void ace_cost(const ap_ctx *c, double *fixed, double *per_nbr_energy, double *per_nbr_force);
 
 // forces.hip
@@ -191,7 +205,11 @@ struct EvalFlags {
 void launch_dens_desc(ap_ctx *c, int n, const double *box, const EvalFlags &f, const double *lam_in);
 void launch_compact(ap_ctx *c, int n, const int32_t *subset, int n_subset);
 void launch_W(ap_ctx *c, int n, const double *box);
-void launch_force(ap_ctx *c, int n, const double *box, const EvalFlags &f, double *E_atom, double *F);
+void launch_force(ap_ctx *c, int n, const double *box, const EvalFlags &f, double *E_atom, double *F,
+                  const double *sbox = nullptr);
+// per-structure sums of weight_i x (E^p_i, dE_i/dc, dE_i/db) over a batch (deterministic order)
+void launch_struct_reduce(ap_ctx *c, int n, int n_struct, const int *d_off, const double *weight, double *E_struct,
+                          double *dEdc, double *dEdb);
 void launch_reduce(ap_ctx *c, int nblocks, double *E_tot, double *virial9);
 
 int sync_and_check(ap_ctx *c);

@@ -249,9 +249,9 @@ void ap_ctx_destroy(ap_ctx *c) {
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     ace_free(c);
     void *bufs[] = {c->csp_t, c->rev_start, c->rev_code, c->pos, c->pos_build, c->d_flags, c->cell_of, c->cell_cnt,
-                    c->cell_start, c->cell_fill, c->cell_atoms, c->nbr_cnt, c->nbr_idx, c->nbr_rev, c->g, c->d,
+                    c->cell_start, c->cell_fill, c->cell_atoms, c->nbr_cnt, c->nbr_idx, c->g, c->d,
                     c->wbar, c->lam, c->dlam, c->Ef, c->Ep, c->Et, c->W, c->xip, c->sidx, c->slist, c->blk_cnt,
-                    c->mark, c->fpair, c->gbuf, c->partials, c->scalars};
+                    c->mark, c->fpair, c->gbuf, c->partials, c->scalars, c->sid, c->b_off, c->b_box, c->bval};
     for (void *p : bufs) hipFree(p);
     delete c;
 }
@@ -280,12 +280,12 @@ int ap_ctx_create(ap_ctx **out, int n_max_atoms, int max_nbr, double skin, void 
     alloc(&c->cell_atoms, n, 4);
     alloc(&c->nbr_cnt, n, 4);
     alloc(&c->nbr_idx, n * max_nbr, 4);
-    alloc(&c->nbr_rev, n * max_nbr, 4);
     double **per_atom[] = {&c->g, &c->d, &c->wbar, &c->lam, &c->dlam, &c->Ef, &c->Ep, &c->Et, &c->W, &c->xip};
     for (double **p : per_atom) alloc(p, n, 8);
     alloc(&c->sidx, n, 4);
     alloc(&c->slist, n, 4);
     alloc(&c->mark, n, 4);
+    alloc(&c->sid, n, 4);
     alloc(&c->blk_cnt, 2 * nb + 2, 4);
     alloc(&c->partials, nb * 16, 8);
     alloc(&c->scalars, 16, 8);
@@ -468,6 +468,85 @@ int ap_mixed_energy_forces(ap_ctx *c, int n, const double *pos, const int32_t *s
     const bool run_ace = !(c->sw.lambda_mode == AP_LAMBDA_FAST);
     if (!rc) rc = evaluate(c, n, box->L, f, nullptr, nullptr, 0, run_ace, E_tot, E_atom, F, virial9, true);
     if (!rc && lambda_out) k_copy_d<<<nblocks(n), kBlock, 0, c->stream>>>(c->lam, lambda_out, n);
+    if (!rc) rc = sync_and_check(c);
+    return rc;
+}
+
+__global__ void k_batch_fill(int n, const double *weight, double *lam, double *dlam, double *wbar, double *Ef,
+                             double *xip, double *Et) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    lam[i] = weight ? 1.0 - weight[i] : 0.0;  // the ACE weight of Eq. (4) is 1 - lambda
+    dlam[i] = 0.0;
+    wbar[i] = 1.0;
+    Ef[i] = 0.0;
+    xip[i] = 0.0;
+    Et[i] = 0.0;
+}
+
+int ap_ace_batch_eval(ap_ctx *c, int n_struct, const int32_t *offsets, const double *boxes, const double *pos,
+                      const double *weight, double *E_struct, double *F, double *dEdc, double *dEdb) {
+    if (!c) return AP_E_ARG;
+    if (!c->have_pot) return set_error(c, AP_E_STATE, "ap_set_potential has not been called");
+    if (n_struct <= 0 || !offsets || !boxes || !pos) return set_error(c, AP_E_ARG, "batch arguments");
+    if (offsets[0] != 0) return set_error(c, AP_E_ARG, "offsets[0] must be 0");
+    for (int s = 0; s < n_struct; s++) {
+        if (offsets[s + 1] < offsets[s]) return set_error(c, AP_E_ARG, "offsets must not decrease");
+        for (int a = 0; a < 3; a++)
+            if (!(c->ace.rc < 0.5 * boxes[3 * s + a])) return set_error(c, AP_E_BOX, "ACE cutoff >= half a cell");
+    }
+    const int n = offsets[n_struct];
+    if (n <= 0 || n > c->n_cap) return set_error(c, AP_E_ARG, "total atom count out of range (1..n_max_atoms)");
+    int rc = AP_OK;
+    if (n_struct > c->b_cap) {
+        (void)hipFree(c->b_off);
+        (void)hipFree(c->b_box);
+        c->b_off = nullptr;
+        c->b_box = nullptr;
+        rc = hip_check(c, hipMalloc(&c->b_off, sizeof(int) * (n_struct + 1)), "batch");
+        if (!rc) rc = hip_check(c, hipMalloc(&c->b_box, sizeof(double) * 3 * n_struct), "batch");
+        if (rc) return rc;
+        c->b_cap = n_struct;
+    }
+    const bool want_b = dEdc || dEdb;
+    const size_t es = c->ace.precision == AP_FP32 ? 4 : 8;
+    const size_t bb = (size_t)c->n_cap * (c->ace.n_funcs + c->ace.n_max) * es;
+    if (want_b && bb != c->bval_bytes) {
+        (void)hipFree(c->bval);
+        c->bval = nullptr;
+        rc = hip_check(c, hipMalloc(&c->bval, bb), "coefficient-gradient buffer");
+        if (rc) return rc;
+        c->bval_bytes = bb;
+    }
+    rc = hip_check(c, hipMemcpyAsync(c->b_off, offsets, sizeof(int) * (n_struct + 1), hipMemcpyHostToDevice, c->stream),
+                   "batch");
+    if (!rc)
+        rc = hip_check(c, hipMemcpyAsync(c->b_box, boxes, sizeof(double) * 3 * n_struct, hipMemcpyHostToDevice, c->stream),
+                       "batch");
+    if (rc) return rc;
+    launch_fill_int(c, c->d_flags + 1, 0, 1);
+    {
+        ProfScope p(c, "batch_list");
+        rc = batch_lists(c, n, n_struct, c->b_off, c->b_box, pos, c->ace.rc);
+    }
+    if (rc) return rc;
+    k_batch_fill<<<nblocks(n), kBlock, 0, c->stream>>>(n, weight, c->lam, c->dlam, c->wbar, c->Ef, c->xip, c->Et);
+    {
+        ProfScope p(c, "compact");
+        launch_compact(c, n, nullptr, 0);
+    }
+    rc = launch_ace(c, n, boxes, std::min(n, 8192), c->b_box, want_b);
+    if (rc) return rc;
+    if (F) {
+        const EvalFlags f{false, false, 0.0, false, true};
+        ProfScope p(c, "force");
+        launch_force(c, n, boxes, f, nullptr, F, c->b_box);
+    }
+    {
+        ProfScope p(c, "struct_reduce");
+        launch_struct_reduce(c, n, n_struct, c->b_off, weight, E_struct, dEdc, dEdb);
+    }
+    rc = hip_check(c, hipGetLastError(), "batch");
     if (!rc) rc = sync_and_check(c);
     return rc;
 }

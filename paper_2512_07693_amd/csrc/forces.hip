@@ -214,7 +214,7 @@ struct ForceArgs {
     EamP ep;
     SwP sp;
     int switching, grad_lambda, eam_on, ace_on;
-    const int32_t *ncount, *nidx, *nrev;
+    const int32_t *ncount, *nidx;
     const double *lam, *xip, *Ef, *Ep, *Et, *W, *g, *d;
     const int *sidx;
     const void *fpair;
@@ -222,6 +222,8 @@ struct ForceArgs {
     const int32_t *csp_t, *rev_start, *rev_code;
     double *E_atom, *F, *partials;
     int *flags;
+    const double *sbox;  // per-structure boxes of a batch (null: L)
+    const int *sid;
 };
 
 template <typename TF>
@@ -260,10 +262,12 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
         const TF *fp = reinterpret_cast<const TF *>(a.fpair);
         const int cnt = a.ncount[i];
         const bool gl = a.switching && a.grad_lambda;
+        const double *Lb = a.sbox ? a.sbox + 3 * a.sid[i] : a.L;  // own cell in a batch of cells
+        const double Lx = Lb[0], Ly = Lb[1], Lz = Lb[2];
         for (int k = 0; k < cnt; k++) {
             const int j = a.nidx[(size_t)k * n + i];
-            const double ux = min_image(a.pos[j] - xi, a.L[0]), uy = min_image(a.pos[n + j] - yi, a.L[1]),
-                         uz = min_image(a.pos[2 * n + j] - zi, a.L[2]);
+            const double ux = min_image(a.pos[j] - xi, Lx), uy = min_image(a.pos[n + j] - yi, Ly),
+                         uz = min_image(a.pos[2 * n + j] - zi, Lz);
             const double r2 = ux * ux + uy * uy + uz * uz;
             const double r = sqrt(r2), ir = 1.0 / r;
             const double ex = ux * ir, ey = uy * ir, ez = uz * ir;
@@ -311,7 +315,15 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
                     v[6] -= wgt * fz * ux; v[7] -= wgt * fz * uy; v[8] -= wgt * fz * uz;
                 }
                 const int sj = a.sidx[j];
-                const int q = sj >= 0 ? a.nrev[(size_t)k * n + i] : -1;
+                int q = -1;
+                if (sj >= 0) {  // slot of i in j's list (lists are symmetric); only for precise j
+                    const int cj = a.ncount[j];
+                    for (int t = 0; t < cj; t++)
+                        if (a.nidx[(size_t)t * n + j] == i) {
+                            q = t;
+                            break;
+                        }
+                }
                 if (q >= 0) {
                     double fx, fy, fz;
                     load_f(fp, ((size_t)sj * a.max_nbr + q) * 3, fx, fy, fz);
@@ -376,8 +388,11 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
     }
 }
 
-void launch_force(ap_ctx *c, int n, const double *box, const EvalFlags &f, double *E_atom, double *F) {
+void launch_force(ap_ctx *c, int n, const double *box, const EvalFlags &f, double *E_atom, double *F,
+                  const double *sbox) {
     ForceArgs a;
+    a.sbox = sbox;
+    a.sid = c->sid;
     a.pos = c->pos;
     a.n = n;
     for (int q = 0; q < 3; q++) a.L[q] = box[q];
@@ -389,7 +404,6 @@ void launch_force(ap_ctx *c, int n, const double *box, const EvalFlags &f, doubl
     a.ace_on = f.ace_forces;
     a.ncount = c->nbr_cnt;
     a.nidx = c->nbr_idx;
-    a.nrev = c->nbr_rev;
     a.lam = c->lam;
     a.xip = c->xip;
     a.Ef = c->Ef;
@@ -436,6 +450,48 @@ void launch_reduce(ap_ctx *c, int nblocks, double *E_tot, double *virial9) {
     k_reduce_partials<<<1, kBlock, 0, c->stream>>>(c->partials, nblocks, 10, c->scalars, c->d_flags);
     if (E_tot) hipMemcpyAsync(E_tot, c->scalars, sizeof(double), hipMemcpyDeviceToDevice, c->stream);
     if (virial9) hipMemcpyAsync(virial9, c->scalars + 1, 9 * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+}
+
+// One thread per (structure, column): column 0 sums E^p_i, the next n_funcs columns dE_i/dc and the
+// last n_max columns dE_i/db, each weighted by weight_i (1 when null), over the structure's atoms
+// in index order.
+template <typename TB>
+__global__ void k_struct_reduce(int n_struct, int ncol, int n_funcs, const int *__restrict__ off,
+                                const int *__restrict__ sidx, const double *__restrict__ weight,
+                                const double *__restrict__ Ep, const TB *__restrict__ bval, int bstride,
+                                double *E_struct, double *dEdc, double *dEdb) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)n_struct * ncol) return;
+    const int s = (int)(t / ncol), col = (int)(t % ncol);
+    double acc = 0.0;
+    for (int i = off[s]; i < off[s + 1]; i++) {
+        const int si = sidx[i];
+        if (si < 0) continue;
+        const double w = weight ? weight[i] : 1.0;
+        acc += w * (col == 0 ? Ep[i] : (double)bval[(size_t)si * bstride + col - 1]);
+    }
+    if (col == 0) {
+        if (E_struct) E_struct[s] = acc;
+    } else if (col - 1 < n_funcs) {
+        if (dEdc) dEdc[(size_t)s * n_funcs + col - 1] = acc;
+    } else if (dEdb) {
+        dEdb[(size_t)s * (ncol - 1 - n_funcs) + col - 1 - n_funcs] = acc;
+    }
+}
+
+void launch_struct_reduce(ap_ctx *c, int n, int n_struct, const int *d_off, const double *weight, double *E_struct,
+                          double *dEdc, double *dEdb) {
+    (void)n;
+    const int nf = c->ace.n_funcs, nm = c->ace.n_max;
+    const int ncol = (dEdc || dEdb) ? 1 + nf + nm : 1;
+    const long long tot = (long long)n_struct * ncol;
+    const int nb = (int)((tot + kBlock - 1) / kBlock);
+    if (c->ace.precision == AP_FP32)
+        k_struct_reduce<float><<<nb, kBlock, 0, c->stream>>>(n_struct, ncol, nf, d_off, c->sidx, weight, c->Ep,
+                                                            (const float *)c->bval, nf + nm, E_struct, dEdc, dEdb);
+    else
+        k_struct_reduce<double><<<nb, kBlock, 0, c->stream>>>(n_struct, ncol, nf, d_off, c->sidx, weight, c->Ep,
+                                                             (const double *)c->bval, nf + nm, E_struct, dEdc, dEdb);
 }
 
 }  // namespace ap

@@ -170,27 +170,6 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(const double *__restrict__
     pos_build[2 * n + i] = zi;
 }
 
-// rev[k * n + i] = slot of atom i in the list of its k-th neighbour (lists are symmetric).
-__global__ __launch_bounds__(kBlock) void k_nbr_rev(int n, const int32_t *__restrict__ ncount,
-                                                    const int32_t *__restrict__ nidx, int32_t *__restrict__ rev,
-                                                    const int *flags) {
-    if (flags[0] == 0) return;
-    int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int ci = ncount[i];
-    for (int k = 0; k < ci; k++) {
-        const int j = nidx[(size_t)k * n + i];
-        const int cj = ncount[j];
-        int s = -1;
-        for (int q = 0; q < cj; q++)
-            if (nidx[(size_t)q * n + j] == i) {
-                s = q;
-                break;
-            }
-        rev[(size_t)k * n + i] = s;
-    }
-}
-
 __global__ void k_commit(int *flags) {
     flags[3] = flags[0];
     flags[0] = 0;
@@ -257,12 +236,68 @@ int ensure_list(ap_ctx *c, int n, const double *box, double r_list, bool force) 
     k_nbr_build<<<nb, kBlock, 0, c->stream>>>(c->pos, n, g, r_list * r_list, c->cell_start, c->cell_cnt,
                                               c->cell_atoms, c->cell_of, c->max_nbr, c->nbr_cnt, c->nbr_idx,
                                               c->pos_build, c->d_flags);
-    k_nbr_rev<<<nb, kBlock, 0, c->stream>>>(n, c->nbr_cnt, c->nbr_idx, c->nbr_rev, c->d_flags);
     k_commit<<<1, 1, 0, c->stream>>>(c->d_flags);
     c->list_r = r_list;
     c->list_n = n;
     for (int a = 0; a < 3; a++) c->list_box[a] = box[a];
     return hip_check(c, hipGetLastError(), "neighbour list");
+}
+
+// ------------------------------------------------------------------------------------------
+// Ragged batch of periodic cells: structure id per atom, wrapped positions and, for every atom,
+// the neighbours inside its own cell (every atom of the cell is a candidate).
+// ------------------------------------------------------------------------------------------
+__global__ void k_batch_prepare(const double *__restrict__ pos_in, int n, int n_struct, const int *__restrict__ off,
+                                const double *__restrict__ sbox, int *__restrict__ sid, double *__restrict__ pos) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int lo = 0, hi = n_struct - 1;  // the structure s with off[s] <= i < off[s+1]
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= i)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    sid[i] = lo;
+    for (int a = 0; a < 3; a++) pos[(size_t)a * n + i] = wrap_coord(pos_in[(size_t)a * n + i], sbox[3 * lo + a]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_batch_nbr(const double *__restrict__ pos, int n,
+                                                      const int *__restrict__ off, const double *__restrict__ sbox,
+                                                      const int *__restrict__ sid, double r2, int max_nbr,
+                                                      int32_t *__restrict__ ncount, int32_t *__restrict__ nidx,
+                                                      int *flags) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int s = sid[i];
+    const double Lx = sbox[3 * s], Ly = sbox[3 * s + 1], Lz = sbox[3 * s + 2];
+    const double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
+    int k = 0;
+    for (int j = off[s]; j < off[s + 1]; j++) {
+        if (j == i) continue;
+        const double ux = min_image(pos[j] - xi, Lx), uy = min_image(pos[n + j] - yi, Ly),
+                     uz = min_image(pos[2 * n + j] - zi, Lz);
+        if (norm2_nofma(ux, uy, uz) < r2) {
+            if (k < max_nbr) nidx[(size_t)k * n + i] = j;
+            k++;
+        }
+    }
+    if (k > max_nbr) {
+        atomicOr(&flags[1], kErrOverflow);
+        k = max_nbr;
+    }
+    ncount[i] = k;
+}
+
+int batch_lists(ap_ctx *c, int n, int n_struct, const int *d_off, const double *d_box, const double *pos_in,
+                double r_list) {
+    const int nb = (n + kBlock - 1) / kBlock;
+    k_batch_prepare<<<nb, kBlock, 0, c->stream>>>(pos_in, n, n_struct, d_off, d_box, c->sid, c->pos);
+    k_batch_nbr<<<nb, kBlock, 0, c->stream>>>(c->pos, n, d_off, d_box, c->sid, r_list * r_list, c->max_nbr, c->nbr_cnt,
+                                              c->nbr_idx, c->d_flags);
+    c->list_r = -1;  // not a list of the single-box evaluation
+    return hip_check(c, hipGetLastError(), "batch lists");
 }
 
 // ------------------------------------------------------------------------------------------
