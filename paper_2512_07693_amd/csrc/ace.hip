@@ -175,6 +175,7 @@ struct AceArgs {
     double *Ep, *Et;
     void *gbuf;   // [S][n_max * nlm] G = dE/dA
     void *fpair;  // [S][max_nbr][3]
+    void *frev;   // [3][max_nbr][n]: f of pair (i, j) stored at slot k of i in j's list
     const void *c1, *bd, *c2, *c3, *kval;
     const int *kidx, *blk;
     int nblk;
@@ -497,6 +498,27 @@ __global__ __launch_bounds__(128) void k_ace_pairforce(AceArgs a) {
             fo[3 * slot] = f0;
             fo[3 * slot + 1] = f1;
             fo[3 * slot + 2] = f2;
+            // the slot k of i in j's list (lists are symmetric): j's gather reads the term at (k, j),
+            // coalesced over j. Loads go out eight at a time so the search is not one long chain.
+            const int cj = a.ncount[j];
+            int kk = -1;
+            for (int b0 = 0; b0 < cj && kk < 0; b0 += 8) {
+                int v[8];
+#pragma unroll
+                for (int u = 0; u < 8; u++) v[u] = b0 + u < cj ? a.nidx[(size_t)(b0 + u) * n + j] : -1;
+#pragma unroll
+                for (int u = 0; u < 8; u++)
+                    if (v[u] == i && kk < 0) kk = b0 + u;
+            }
+            if (kk < 0) {
+                atomicOr(&a.flags[1], kErrAsym);
+            } else {
+                T *fr = (T *)a.frev;
+                const size_t st = (size_t)a.max_nbr * n, o = (size_t)kk * n + j;
+                fr[o] = f0;
+                fr[st + o] = f1;
+                fr[2 * st + o] = f2;
+            }
         }
         __syncthreads();
     }
@@ -816,6 +838,7 @@ int launch_ace(ap_ctx *c, int n, const double *box, int grid_cap, const double *
     a.Et = c->Et;
     a.gbuf = c->gbuf;
     a.fpair = c->fpair;
+    a.frev = c->frev;
     a.c1 = t.c1;
     a.bd = t.bd;
     a.c2 = t.c2;

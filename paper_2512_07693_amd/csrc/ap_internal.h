@@ -18,7 +18,7 @@ constexpr double kConv = 9648.533212;  // eV / (A u) in A / ps^2
 constexpr double kPi = 3.14159265358979323846;
 
 // Error bits raised by kernels in ctx->d_flags[1].
-enum : int { kErrOverflow = 1, kErrNonFinite = 2, kErrCsp = 4, kErrAceNbr = 8, kErrDensity = 16 };
+enum : int { kErrOverflow = 1, kErrNonFinite = 2, kErrCsp = 4, kErrAceNbr = 8, kErrDensity = 16, kErrAsym = 32 };
 
 // Block b of nb runs on XCD (b % 8); giving each XCD a contiguous range of atoms keeps the
 // neighbour gathers of one XCD inside its own L2.
@@ -139,6 +139,7 @@ struct ap_ctx {
     void *bval = nullptr;        // [n_cap][n_funcs + n_max] dE_i/dc and dE_i/db (batch gradients)
     size_t bval_bytes = 0;
     void *fpair = nullptr;       // [n_cap][max_nbr][3] ACE pair gradients (double or float)
+    void *frev = nullptr;        // [3][max_nbr][n] the same pair terms at the neighbour's slot (k, j)
     void *gbuf = nullptr;        // [n_cap][n_max * (l_max+1)^2] dE/dA of the S atoms
     size_t fpair_bytes = 0, gbuf_bytes = 0;
     double *partials = nullptr;  // per-block partial sums [nblk][16]

@@ -78,6 +78,7 @@ int sync_and_check(ap_ctx *c) {
     if (e & kErrOverflow) return set_error(c, AP_E_NBR_OVERFLOW, "neighbour count above max_nbr, or index out of range");
     if (e & kErrAceNbr) return set_error(c, AP_E_NBR_OVERFLOW, "more than 128 neighbours inside the ACE cutoff");
     if (e & kErrCsp) return set_error(c, AP_E_CSP, "CSP list invalid or too few neighbours for the CSP pairs");
+    if (e & kErrAsym) return set_error(c, AP_E_NBR_OVERFLOW, "neighbour lists not symmetric (truncated list)");
     if (e & kErrNonFinite) return set_error(c, AP_E_NONFINITE, "non-finite energy or force");
     return AP_OK;
 }
@@ -251,7 +252,7 @@ void ap_ctx_destroy(ap_ctx *c) {
     void *bufs[] = {c->csp_t, c->rev_start, c->rev_code, c->pos, c->pos_build, c->d_flags, c->cell_of, c->cell_cnt,
                     c->cell_start, c->cell_fill, c->cell_atoms, c->nbr_cnt, c->nbr_idx, c->g, c->d,
                     c->wbar, c->lam, c->dlam, c->Ef, c->Ep, c->Et, c->W, c->xip, c->sidx, c->slist, c->blk_cnt,
-                    c->mark, c->fpair, c->gbuf, c->partials, c->scalars, c->sid, c->b_off, c->b_box, c->bval};
+                    c->mark, c->fpair, c->frev, c->gbuf, c->partials, c->scalars, c->sid, c->b_off, c->b_box, c->bval};
     for (void *p : bufs) hipFree(p);
     delete c;
 }
@@ -324,14 +325,17 @@ int ap_set_potential(ap_ctx *c, const ap_eam_params *eam, const ap_ace_params *a
     const size_t es = ace->precision == AP_FP32 ? 4 : 8;
     const size_t fb = (size_t)c->n_cap * c->max_nbr * 3 * es, gb = (size_t)c->n_cap * NA * es;
     if (fb != c->fpair_bytes) {
-        hipFree(c->fpair);
+        (void)hipFree(c->fpair);
         c->fpair = nullptr;
+        (void)hipFree(c->frev);
+        c->frev = nullptr;
         rc = hip_check(c, hipMalloc(&c->fpair, fb), "ACE pair buffer");
+        if (!rc) rc = hip_check(c, hipMalloc(&c->frev, fb), "ACE reverse pair buffer");
         if (rc) return rc;
         c->fpair_bytes = fb;
     }
     if (gb != c->gbuf_bytes) {
-        hipFree(c->gbuf);
+        (void)hipFree(c->gbuf);
         c->gbuf = nullptr;
         rc = hip_check(c, hipMalloc(&c->gbuf, gb), "ACE adjoint buffer");
         if (rc) return rc;

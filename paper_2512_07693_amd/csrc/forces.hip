@@ -217,7 +217,7 @@ struct ForceArgs {
     const int32_t *ncount, *nidx;
     const double *lam, *xip, *Ef, *Ep, *Et, *W, *g, *d;
     const int *sidx;
-    const void *fpair;
+    const void *fpair, *frev;
     int fp32, max_nbr, n_csp;
     const int32_t *csp_t, *rev_start, *rev_code;
     double *E_atom, *F, *partials;
@@ -314,19 +314,10 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
                     v[3] -= wgt * fy * ux; v[4] -= wgt * fy * uy; v[5] -= wgt * fy * uz;
                     v[6] -= wgt * fz * ux; v[7] -= wgt * fz * uy; v[8] -= wgt * fz * uz;
                 }
-                const int sj = a.sidx[j];
-                int q = -1;
-                if (sj >= 0) {  // slot of i in j's list (lists are symmetric); only for precise j
-                    const int cj = a.ncount[j];
-                    for (int t = 0; t < cj; t++)
-                        if (a.nidx[(size_t)t * n + j] == i) {
-                            q = t;
-                            break;
-                        }
-                }
-                if (q >= 0) {
-                    double fx, fy, fz;
-                    load_f(fp, ((size_t)sj * a.max_nbr + q) * 3, fx, fy, fz);
+                if (a.sidx[j] >= 0) {  // precise j: its term for this pair, stored at (k, i)
+                    const TF *fr = reinterpret_cast<const TF *>(a.frev);
+                    const size_t st = (size_t)a.max_nbr * n, o = (size_t)k * n + i;
+                    const double fx = (double)fr[o], fy = (double)fr[st + o], fz = (double)fr[2 * st + o];
                     const double wgt = 1.0 - lj;
                     F0 -= wgt * fx;
                     F1 -= wgt * fy;
@@ -414,6 +405,7 @@ void launch_force(ap_ctx *c, int n, const double *box, const EvalFlags &f, doubl
     a.d = c->d;
     a.sidx = c->sidx;
     a.fpair = c->fpair;
+    a.frev = c->frev;
     a.fp32 = c->ace.precision == AP_FP32;
     a.max_nbr = c->max_nbr;
     a.n_csp = c->n_csp;

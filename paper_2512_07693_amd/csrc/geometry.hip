@@ -200,9 +200,9 @@ static int make_geometry(ap_ctx *c, const double *box, double r_list, Geometry &
 
 static int grow_cells(ap_ctx *c, int ncell) {
     if (ncell <= c->ncell_cap) return AP_OK;
-    hipFree(c->cell_cnt);
-    hipFree(c->cell_start);
-    hipFree(c->cell_fill);
+    (void)hipFree(c->cell_cnt);
+    (void)hipFree(c->cell_start);
+    (void)hipFree(c->cell_fill);
     int rc = hip_check(c, hipMalloc(&c->cell_cnt, sizeof(int) * ncell), "cells");
     if (!rc) rc = hip_check(c, hipMalloc(&c->cell_start, sizeof(int) * (ncell + 1)), "cells");
     if (!rc) rc = hip_check(c, hipMalloc(&c->cell_fill, sizeof(int) * ncell), "cells");
@@ -441,9 +441,9 @@ __global__ void k_csp_rev_sort(int n, const int *rstart, int32_t *rcode) {
 
 int install_csp(ap_ctx *c, int n, int n_csp, const int32_t *list) {
     if (n_csp != 8 && n_csp != 12) return set_error(c, AP_E_CSP, "n_csp must be 8 or 12");
-    hipFree(c->csp_t);
-    hipFree(c->rev_start);
-    hipFree(c->rev_code);
+    (void)hipFree(c->csp_t);
+    (void)hipFree(c->rev_start);
+    (void)hipFree(c->rev_code);
     c->csp_t = nullptr;
     c->rev_start = nullptr;
     c->rev_code = nullptr;
