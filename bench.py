@@ -28,6 +28,30 @@ FP32_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
 
 
+# HBM bytes per launch from the FETCH_SIZE and WRITE_SIZE counter passes on this workload, scaled by what the
+# same counters read for a 1 GiB device copy (fetch x2.0, write x1.0), with a digest of the kernel's source
+# file and the shared header at the time: a kernel whose source has changed reports null until re-measured.
+MEASURED_TRAFFIC = {
+    "ace_energy": (12.18e6, "ace.hip", "b59715d62fce6791"),
+    "force": (82.12e6, "forces.hip", "9173e5f4b91e6325"),
+    "dens_desc": (65.17e6, "forces.hip", "9173e5f4b91e6325"),
+    "W": (55.49e6, "forces.hip", "9173e5f4b91e6325"),
+}
+
+
+def measured_traffic(kernel):
+    import hashlib
+    if kernel not in MEASURED_TRAFFIC:
+        return None
+    b, src, digest = MEASURED_TRAFFIC[kernel]
+    root = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2512_07693_amd", "csrc")
+    h = hashlib.sha256()
+    for f in (src, "ap_internal.h"):
+        with open(os.path.join(root, f), "rb") as fh:
+            h.update(fh.read())
+    return b if h.hexdigest()[:16] == digest else None
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -47,7 +71,7 @@ def algorithmic_bytes(kernel, n, nnb, n_s, nnb_rc, n_csp):
     read once (4 B per entry), every per-atom array once, outputs written once."""
     per_atom = {
         "dens_desc": 4 * nnb + 4 + 24 + 8 + 8 * 8,        # list + count, position, g; 8 outputs
-        "force": 8 * nnb + 4 + 24 + 9 * 8 + 4 + 32,      # list + reverse slots, own data, F and E_i
+        "force": 4 * nnb + 4 + 24 + 8 * 8 + 4 + 32,      # list + count, position, 8 own scalars, sidx, F, E_i
         "W": 4 * nnb + 4 + 24 + 8 + 8,
         "csp_value": 4 * n_csp + 24 + 8,
         "vv_first": 6 * 8 + 3 * 8 + 6 * 8,
@@ -105,11 +129,22 @@ def main():
     ap_.add_argument("--pure-steps", type=int, default=20)
     ap_.add_argument("--cpu-steps", type=int, default=2)
     ap_.add_argument("--no-cpu", action="store_true")
+    ap_.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                     help="only copy a MIB-sized buffer 5 times (calibrates the HBM byte counters)")
     args = ap_.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     import torch
+
+    if args.copy_probe:
+        src = torch.ones(args.copy_probe << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copied %d bytes 5 times" % (src.numel() * 4))
+        return
 
     import synth
     from paper_2512_07693_amd import ap
@@ -138,12 +173,14 @@ def main():
     log("mixed: %.3f ms/step, %.3e atom-steps/s, x=%.4f" % (ms / args.steps, value, nve["x_mean"]))
 
     # pure ACE: the same potential with lambda == 0 everywhere
-    ctx_p = ap.Context(n, max_nbr=128, skin=s["run"]["skin"])
-    ctx_p.set_potential(s["eam"], s["ace"], s["sw"], lambda_mode=ap.AP_LAMBDA_PRECISE)
-    log("pure ACE: %d timed steps ..." % args.pure_steps)
-    ms_p, thermo_p, prof_p, _ = run_md(ctx_p, s, pos0, vel0, args.pure_steps, 2, 0)
-    value_p = n * args.pure_steps / (ms_p / 1e3)
-    log("pure ACE: %.3f ms/step, %.3e atom-steps/s" % (ms_p / args.pure_steps, value_p))
+    ms_p, value_p, prof_p = None, None, {}
+    if args.pure_steps > 0:
+        ctx_p = ap.Context(n, max_nbr=128, skin=s["run"]["skin"])
+        ctx_p.set_potential(s["eam"], s["ace"], s["sw"], lambda_mode=ap.AP_LAMBDA_PRECISE)
+        log("pure ACE: %d timed steps ..." % args.pure_steps)
+        ms_p, thermo_p, prof_p, _ = run_md(ctx_p, s, pos0, vel0, args.pure_steps, 2, 0)
+        value_p = n * args.pure_steps / (ms_p / 1e3)
+        log("pure ACE: %.3f ms/step, %.3e atom-steps/s" % (ms_p / args.pure_steps, value_p))
 
     # roofline of the dominant kernel of the mixed step
     cost = ctx.ace_cost()
@@ -161,13 +198,13 @@ def main():
         flops = per * n_s
         achieved = flops / (avg_ms * 1e-3) / 1e12
         roof = dict(bound="alu", achieved=achieved, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=achieved / FP32_PEAK_TFLOPS, traffic=None, kernel=dom, avg_ms=avg_ms,
+                    frac=achieved / FP32_PEAK_TFLOPS, traffic=measured_traffic(dom), kernel=dom, avg_ms=avg_ms,
                     work_per_launch="%.4g flop (%.0f precise atoms x %.4g flop)" % (flops, n_s, per))
     else:
         b = algorithmic_bytes(dom, n, nnb, n_s, nnb_rc, s["sw"]["n_csp"])
         achieved = b / (avg_ms * 1e-3) / 1e9 if b else None
         roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=(achieved / HBM_PEAK_GBS) if achieved else None, traffic=None, kernel=dom,
+                    frac=(achieved / HBM_PEAK_GBS) if achieved else None, traffic=measured_traffic(dom), kernel=dom,
                     avg_ms=avg_ms, work_per_launch="%.4g B" % (b or 0))
     kernels = {k: dict(avg_ms=round(v[0], 5), launches=int(v[1]), share=round(tot[k] / sum(tot.values()), 4))
                for k, v in sorted(prof.items(), key=lambda kv: -tot[kv[0]])}
@@ -175,7 +212,8 @@ def main():
     for k in ("dens_desc", "force", "W"):
         if k in prof:
             b = algorithmic_bytes(k, n, nnb, n_s, nnb_rc, s["sw"]["n_csp"])
-            hbm[k] = dict(GBs=b / (prof[k][0] * 1e-3) / 1e9, frac=b / (prof[k][0] * 1e-3) / 1e9 / HBM_PEAK_GBS)
+            hbm[k] = dict(GBs=b / (prof[k][0] * 1e-3) / 1e9, frac=b / (prof[k][0] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                          algorithmic_bytes=b, traffic=measured_traffic(k))
     ace_e = prof.get("ace_energy")
     ace_p = prof_p.get("ace_energy")
     ace_roof = {}
@@ -200,8 +238,8 @@ def main():
                    "ace_basis": int(len(s["ace"]["func"])), "n_max": 12, "l_max": 6, "r_w": s["sw"]["r_w"],
                    "dt_fs": 1.0, "x": nve["x_mean"]},
         "pure_ace": {"value": value_p, "unit": "atom-steps/s", "steps": args.pure_steps,
-                     "ms_per_step": ms_p / args.pure_steps},
-        "speedup_vs_pure_ace": value / value_p,
+                     "ms_per_step": ms_p / args.pure_steps if ms_p else None},
+        "speedup_vs_pure_ace": value / value_p if value_p else None,
         "nve": nve,
         "roofline": roof,
         "ace_roofline": ace_roof,
