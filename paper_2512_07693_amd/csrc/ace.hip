@@ -216,16 +216,33 @@ __device__ __forceinline__ double block_sum_d(double v, double *sh) {
     return s;
 }
 
+// Couplings of one (l1, l2, L) block in its three orderings, staged in LDS per block.
+constexpr int kKapStage = 672;
+
 template <typename T, int NMAX, int LMAX>
 __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
     constexpr int NLM = (LMAX + 1) * (LMAX + 1), NA = NMAX * NLM, NN = NMAX * NMAX, MM = 2 * LMAX + 1;
-    constexpr int V = kAceMaxValid;
-    __shared__ T sA[NA], sG[NA];
-    __shared__ T sR[V * NMAX];
-    __shared__ T sY[V * NLM];
+    constexpr int V = kAceMaxValid, CH = 64;  // neighbours kept per site; harmonics computed CH at a time
+    // neighbour phase and block phase share one LDS region
+    struct NbrBuf {
+        T R[CH * NMAX];
+        T Y[CH * NLM];
+        double R64[CH * NMAX];
+    };
+    struct BlkBuf {
+        T P[MM * NN], Q[MM * NN];
+        T C[NN * NMAX];
+        T kv[kKapStage];
+        int kc[kKapStage];
+    };
+    union Work {
+        NbrBuf nb;
+        BlkBuf bb;
+    };
+    __shared__ Work W;
+    __shared__ T sA[NA], sAt[NA], sG[NA];  // A[n][lm], its transpose At[lm][n], dE/dA[n][lm]
     __shared__ T sU[V * 4];
-    __shared__ double sRd[V], sR64[V * NMAX], sS[NMAX];
-    __shared__ T sP[MM * NN], sQ[MM * NN];
+    __shared__ double sRd[V], sS[NMAX];
     __shared__ int sCnt[5];
     __shared__ double sRed[kBlock / 64];
     __shared__ T sEmbD;
@@ -244,6 +261,11 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
         atom_box(a, i, Lx, Ly, Lz);
         const int cnt = a.ncount[i];
         if (tid == 0) sCnt[4] = 0;
+        if (tid < NMAX) sS[tid] = 0.0;
+        for (int o = tid; o < NA; o += kBlock) {
+            sA[o] = T(0);
+            sG[o] = T(0);
+        }
         __syncthreads();
         // ---- phase 0: neighbours inside rc, compacted in list order (ballot prefix) ----
         for (int base = 0; base < cnt; base += kBlock) {
@@ -280,41 +302,46 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
             __syncthreads();
         }
         const int nv = min(sCnt[4], V);
-        // ---- phase 1: radial channels and harmonics per neighbour ----
-        for (int v = tid; v < nv; v += kBlock) {
-            const T r = sU[4 * v + 3], ir = T(1) / r;
-            T g[NMAX];
-            radial<T, NMAX>(r, rcT, g, (T *)nullptr);
+        // ---- phases 1-2: radial channels and harmonics, CH neighbours at a time, into A[n][lm] ----
+        for (int v0 = 0; v0 < nv; v0 += CH) {
+            const int nc = min(CH, nv - v0);
+            for (int v = tid; v < nc; v += kBlock) {
+                const int u = v0 + v;
+                const T r = sU[4 * u + 3], ir = T(1) / r;
+                T g[NMAX];
+                radial<T, NMAX>(r, rcT, g, (T *)nullptr);
 #pragma unroll
-            for (int q = 0; q < NMAX; q++) sR[v * NMAX + q] = g[q];
-            // the l = 0 radial sums feed the two-body and density terms, whose large fitted
-            // coefficients cancel: they are kept in FP64 whatever T is
-            double gd[NMAX];
-            radial<double, NMAX>(sRd[v], a.rc, gd, (double *)nullptr);
+                for (int q = 0; q < NMAX; q++) W.nb.R[v * NMAX + q] = g[q];
+                // the l = 0 radial sums feed the two-body and density terms, whose fitted
+                // coefficients cancel strongly: they are kept in FP64 whatever T is
+                double gd[NMAX];
+                radial<double, NMAX>(sRd[u], a.rc, gd, (double *)nullptr);
 #pragma unroll
-            for (int q = 0; q < NMAX; q++) sR64[v * NMAX + q] = gd[q];
-            T Y[NLM];
-            ylm_real<T, LMAX>(sU[4 * v] * ir, sU[4 * v + 1] * ir, sU[4 * v + 2] * ir, Y);
+                for (int q = 0; q < NMAX; q++) W.nb.R64[v * NMAX + q] = gd[q];
+                T Y[NLM];
+                ylm_real<T, LMAX>(sU[4 * u] * ir, sU[4 * u + 1] * ir, sU[4 * u + 2] * ir, Y);
 #pragma unroll
-            for (int q = 0; q < NLM; q++) sY[v * NLM + q] = Y[q];
+                for (int q = 0; q < NLM; q++) W.nb.Y[v * NLM + q] = Y[q];
+            }
+            __syncthreads();
+            for (int o = tid; o < NA; o += kBlock) {
+                const int q = o / NLM, lm = o - q * NLM;
+                T acc = sA[o];
+                for (int v = 0; v < nc; v++) acc += W.nb.R[v * NMAX + q] * W.nb.Y[v * NLM + lm];
+                sA[o] = acc;
+            }
+            if (tid < NMAX) {
+                double s0 = sS[tid];
+                for (int v = 0; v < nc; v++) s0 += W.nb.R64[v * NMAX + tid];
+                sS[tid] = s0;
+            }
+            __syncthreads();
         }
-        for (int o = tid; o < NA; o += kBlock) sG[o] = T(0);
-        __syncthreads();
-        // ---- phase 2: atomic basis A[n][lm] ----
         for (int o = tid; o < NA; o += kBlock) {
             const int q = o / NLM, lm = o - q * NLM;
-            T acc = T(0);
-            for (int v = 0; v < nv; v++) acc += sR[v * NMAX + q] * sY[v * NLM + lm];
-            sA[o] = acc;
+            sAt[lm * NMAX + q] = sA[o];
         }
-        __syncthreads();
         // ---- phase 3a: orders 1 and 2, embedding ----
-        if (tid < NMAX) {
-            double s0 = 0.0;
-            for (int v = 0; v < nv; v++) s0 += sR64[v * NMAX + tid];
-            sS[tid] = s0;
-        }
-        __syncthreads();
         double e = 0.0;
         if (tid == 0) {
             const double y00 = 0.28209479177387814;  // 1 / sqrt(4 pi)
@@ -353,37 +380,67 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
             int l = 0;
             while ((l + 1) * (l + 1) <= lm) l++;
             const T *row = c2 + ((size_t)l * NMAX + q) * NMAX;
+            const T *acol = sAt + lm * NMAX;
             T g2 = T(0);
 #pragma unroll
-            for (int q2 = 0; q2 < NMAX; q2++) g2 += row[q2] * sA[q2 * NLM + lm];
+            for (int q2 = 0; q2 < NMAX; q2++) g2 += row[q2] * acol[q2];
             g2 *= T(2);
             e += 0.5 * (double)(sA[o] * g2);
             sG[o] += g2 + (lm == 0 ? c1[q] + sEmbD * bd[q] : T(0));  // order-1 and density parts of dE/dA
         }
-        __syncthreads();
         // ---- phase 3b: order-3 blocks ----
         for (int b = 0; b < a.nblk; b++) {
             const int *bk = a.blk + b * kBlkInts;
             const int L = bk[0], l1 = bk[1], l2 = bk[2];
-            const T *C = c3 + bk[3];
             const int nM = 2 * L + 1, n1m = 2 * l1 + 1, n2m = 2 * l2 + 1;
             const int bL = L * L + L, b1 = l1 * l1 + l1, b2 = l2 * l2 + l2;
-            for (int o = tid; o < nM * NN; o += kBlock) {
-                const int Mi = o / NN, rem = o - Mi * NN, n1 = rem / NMAX, n2 = rem - n1 * NMAX;
-                T P = T(0);
-                const int e0 = bk[4 + Mi], e1 = bk[4 + Mi + 1];
-                for (int q = e0; q < e1; q++) {
-                    const int code = a.kidx[q];
-                    const int m1 = (code & 255) - 8, m2 = ((code >> 8) & 255) - 8;
-                    P += kval[q] * sA[n1 * NLM + b1 + m1] * sA[n2 * NLM + b2 + m2];
-                }
-                const T *cc = C + (size_t)rem * NMAX;
-                T Q = T(0);
+            const int k0 = bk[4], k1 = bk[32 + n2m];
+            // stage the block's couplings (host checks k1 - k0 <= kKapStage) and coefficients
+            __syncthreads();
+            for (int q = k0 + tid; q < k1; q += kBlock) {
+                W.bb.kc[q - k0] = a.kidx[q];
+                W.bb.kv[q - k0] = kval[q];
+            }
+            {
+                const T *C = c3 + bk[3];
+                for (int q = tid; q < NN * NMAX; q += kBlock) W.bb.C[q] = C[q];
+            }
+            __syncthreads();
+            // P_M[n1][n2] = sum kappa A[n1][l1 m1] A[n2][l2 m2]; Q_M[n1][n2] = sum_n3 C A[n3][L M];
+            // one thread per (M, n1) holds the twelve n2 in registers
+            for (int w = tid; w < nM * NMAX; w += kBlock) {
+                const int Mi = w / NMAX, n1 = w - Mi * NMAX;
+                T P[NMAX], Q[NMAX];
 #pragma unroll
-                for (int q3 = 0; q3 < NMAX; q3++) Q += cc[q3] * sA[q3 * NLM + bL + Mi - L];
-                sP[o] = P;
-                sQ[o] = Q;
-                e += (double)(P * Q);
+                for (int q = 0; q < NMAX; q++) P[q] = T(0);
+                const int e0 = bk[4 + Mi] - k0, e1 = bk[4 + Mi + 1] - k0;
+                for (int q = e0; q < e1; q++) {
+                    const int code = W.bb.kc[q];
+                    const int m1 = (code & 255) - 8, m2 = ((code >> 8) & 255) - 8;
+                    const T a1 = W.bb.kv[q] * sA[n1 * NLM + b1 + m1];
+                    const T *a2 = sAt + (b2 + m2) * NMAX;
+#pragma unroll
+                    for (int q2 = 0; q2 < NMAX; q2++) P[q2] += a1 * a2[q2];
+                }
+                const T *a3 = sAt + (bL + Mi - L) * NMAX;
+                T A3[NMAX];
+#pragma unroll
+                for (int q = 0; q < NMAX; q++) A3[q] = a3[q];
+                const T *cr = W.bb.C + n1 * NN;
+#pragma unroll
+                for (int q2 = 0; q2 < NMAX; q2++) {
+                    T acc = T(0);
+#pragma unroll
+                    for (int q3 = 0; q3 < NMAX; q3++) acc += cr[q2 * NMAX + q3] * A3[q3];
+                    Q[q2] = acc;
+                }
+                T *pp = W.bb.P + Mi * NN + n1 * NMAX, *qq = W.bb.Q + Mi * NN + n1 * NMAX;
+#pragma unroll
+                for (int q2 = 0; q2 < NMAX; q2++) {
+                    e += (double)(P[q2] * Q[q2]);
+                    pp[q2] = P[q2];
+                    qq[q2] = Q[q2];
+                }
             }
             __syncthreads();
             if (bout) {
@@ -392,50 +449,57 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
                     const int code = a.g3[2 * q];
                     const int rem = code & 0xffff, q3 = code >> 16;
                     T bsum = T(0);
-                    for (int Mi = 0; Mi < nM; Mi++) bsum += sP[Mi * NN + rem] * sA[q3 * NLM + bL + Mi - L];
+                    for (int Mi = 0; Mi < nM; Mi++) bsum += W.bb.P[Mi * NN + rem] * sA[q3 * NLM + bL + Mi - L];
                     bout[a.g3[2 * q + 1]] = bsum;
                 }
             }
-            for (int o = tid; o < NMAX * nM; o += kBlock) {
-                const int q3 = o / nM, Mi = o - q3 * nM;
+            // dE/dA[n3][L M] = sum_{n1 n2} C[n1][n2][n3] P_M[n1][n2]
+            for (int w = tid; w < NMAX * nM; w += kBlock) {
+                const int q3 = w / nM, Mi = w - q3 * nM;
+                const T *pp = W.bb.P + Mi * NN;
                 T acc = T(0);
-                for (int p = 0; p < NN; p++) acc += C[(size_t)p * NMAX + q3] * sP[Mi * NN + p];
+#pragma unroll 12
+                for (int p = 0; p < NN; p++) acc += W.bb.C[p * NMAX + q3] * pp[p];
                 sG[q3 * NLM + bL + Mi - L] += acc;
             }
             __syncthreads();
-            for (int o = tid; o < NMAX * n1m; o += kBlock) {
-                const int q1 = o / n1m, i1 = o - q1 * n1m;
+            // dE/dA[n1][l1 m1] = sum kappa sum_n2 Q_M[n1][n2] A[n2][l2 m2]
+            for (int w = tid; w < NMAX * n1m; w += kBlock) {
+                const int q1 = w / n1m, i1 = w - q1 * n1m;
                 T acc = T(0);
-                const int e0 = bk[18 + i1], e1 = bk[18 + i1 + 1];
+                const int e0 = bk[18 + i1] - k0, e1 = bk[18 + i1 + 1] - k0;
                 for (int q = e0; q < e1; q++) {
-                    const int code = a.kidx[q];
+                    const int code = W.bb.kc[q];
                     const int m2 = ((code >> 8) & 255) - 8, Mi = ((code >> 16) & 255) - 8 + L;
-                    const T *qr = sQ + Mi * NN + q1 * NMAX;
+                    const T *qr = W.bb.Q + Mi * NN + q1 * NMAX;
+                    const T *a2 = sAt + (b2 + m2) * NMAX;
                     T s2 = T(0);
 #pragma unroll
-                    for (int q2 = 0; q2 < NMAX; q2++) s2 += qr[q2] * sA[q2 * NLM + b2 + m2];
-                    acc += kval[q] * s2;
+                    for (int q2 = 0; q2 < NMAX; q2++) s2 += qr[q2] * a2[q2];
+                    acc += W.bb.kv[q] * s2;
                 }
                 sG[q1 * NLM + b1 + i1 - l1] += acc;
             }
             __syncthreads();
-            for (int o = tid; o < NMAX * n2m; o += kBlock) {
-                const int q2 = o / n2m, i2 = o - q2 * n2m;
+            // dE/dA[n2][l2 m2] = sum kappa sum_n1 Q_M[n1][n2] A[n1][l1 m1]
+            for (int w = tid; w < NMAX * n2m; w += kBlock) {
+                const int q2 = w / n2m, i2 = w - q2 * n2m;
                 T acc = T(0);
-                const int e0 = bk[32 + i2], e1 = bk[32 + i2 + 1];
+                const int e0 = bk[32 + i2] - k0, e1 = bk[32 + i2 + 1] - k0;
                 for (int q = e0; q < e1; q++) {
-                    const int code = a.kidx[q];
+                    const int code = W.bb.kc[q];
                     const int m1 = (code & 255) - 8, Mi = ((code >> 16) & 255) - 8 + L;
-                    const T *qc = sQ + Mi * NN + q2;
+                    const T *qc = W.bb.Q + Mi * NN + q2;
+                    const T *a1 = sAt + (b1 + m1) * NMAX;
                     T s1 = T(0);
 #pragma unroll
-                    for (int q1 = 0; q1 < NMAX; q1++) s1 += qc[q1 * NMAX] * sA[q1 * NLM + b1 + m1];
-                    acc += kval[q] * s1;
+                    for (int q1 = 0; q1 < NMAX; q1++) s1 += qc[q1 * NMAX] * a1[q1];
+                    acc += W.bb.kv[q] * s1;
                 }
                 sG[q2 * NLM + b2 + i2 - l2] += acc;
             }
-            __syncthreads();
         }
+        __syncthreads();
         // ---- outputs ----
         const double E = block_sum_d(e, sRed);
         T *gout = (T *)a.gbuf + (size_t)s * NA;
@@ -740,6 +804,7 @@ int ace_setup(ap_ctx *c, const ap_ace_params *p) {
         emit(4, -B.L, B.L, 0);
         emit(18, -B.l1, B.l1, 1);
         emit(32, -B.l2, B.l2, 2);
+        if ((int)kidx.size() - d[4] > kKapStage) return set_error(c, AP_E_ARG, "coupling block too large for LDS");
         d[46] = (int)g3flat.size() / 2;
         g3flat.insert(g3flat.end(), g3[bi].begin(), g3[bi].end());
         d[47] = (int)g3flat.size() / 2;
