@@ -16,6 +16,7 @@
  *   grad-lambda forces ..................... (S15)-(S21) (weight part), (S22)-(S27) (CSP part),
  *                                            (S28)-(S29)
  *   differentiable CSP with a fixed list ... (B3) / (S22)
+ *   learned indicator g (network) .......... Eq. (6) with a general g, force term (S16)
  *   velocity Verlet NVE .................... main text, time integration paragraph
  * The paper defines ACE only by reference; the concrete form used here (Chebyshev radial
  * channels, complex spherical harmonics with the Condon-Shortley phase, product basis of
@@ -652,6 +653,221 @@ int ora_ace_env(int nn, const double *u, int n_max, int l_max, double rc, int n_
 }
 
 /* ------------------------------------------------------------------------------------------ */
+/* Learned indicator: a small network in place of CSP as the per-atom quantity g of Eq. (6)     */
+/* ------------------------------------------------------------------------------------------ */
+/* Eq. (6) admits any per-atom scalar g. With g_j a smooth function of the neighbourhood of j,
+ * E depends on g_j only through the descriptors d_k, and dE/dg_j = -sum_k E~_k w(r_kj) = -W_j
+ * with E~ of (S17); the general grad-g term of (S16) is then F_i += sum_j W_j grad_i g_j, the
+ * same W_j as in the CSP part (S25), with grad_i g_j from the network instead of (S24).
+ *
+ * Features: sixteen rotation invariants of the neighbours inside rc, built from the same
+ * Chebyshev radial channels g_n and complex harmonics as the ACE reading above:
+ *   q[n]               = sum_j g_n(r_ij),                       n = 0..7
+ *   q[8 + 4 n + l - 1] = sum_m |A_nlm|^2,  A_nlm = sum_j g_n(r_ij) Y_l^m(u_ij),   n = 0, 1; l = 1..4
+ * Network: z = (q - mu) / sig, h1 = silu(W1 z + b1), h2 = silu(W2 h1 + b2), o = w3 . h2 + b3,
+ * g = softplus(o), with silu(a) = a / (1 + e^-a). Trained on o against log(|E^ACE - E^EAM| + eps).
+ * Parameter block (MLP_NP doubles): mu[16] sig[16] W1[64][16] b1[64] W2[64][64] b2[64] w3[64] b3.
+ */
+#define MLP_NQ 16
+#define MLP_NH 64
+#define MLP_MU 0
+#define MLP_SIG 16
+#define MLP_W1 32
+#define MLP_B1 (MLP_W1 + MLP_NH * MLP_NQ)
+#define MLP_W2 (MLP_B1 + MLP_NH)
+#define MLP_B2 (MLP_W2 + MLP_NH * MLP_NH)
+#define MLP_W3 (MLP_B2 + MLP_NH)
+#define MLP_B3 (MLP_W3 + MLP_NH)
+#define MLP_NP (MLP_B3 + 1)
+
+int ora_mlp_nparams(void) { return MLP_NP; }
+
+/* features q[16] of one environment (nn neighbour vectors u, any distance; r >= rc ignored) and,
+ * if dq != NULL, dq[j][f][a] = d q_f / d u_j,a. */
+static void mlp_site_features(int nn, const double *u, double rc, double *q, double *dq) {
+    double complex A[2][25];
+    memset(A, 0, sizeof(A));
+    for (int f = 0; f < MLP_NQ; f++) q[f] = 0.0;
+    for (int j = 0; j < nn; j++) {
+        const double *uj = u + 3 * j;
+        double r = sqrt(sq3(uj));
+        if (r >= rc) continue;
+        double g[8], dg[8];
+        ora_radial(8, rc, r, g, dg);
+        double complex Y[25];
+        ora_ylm_c(4, uj, Y, NULL);
+        for (int n = 0; n < 8; n++) q[n] += g[n];
+        for (int n = 0; n < 2; n++)
+            for (int t = 1; t < 25; t++) A[n][t] += g[n] * Y[t];
+    }
+    for (int n = 0; n < 2; n++)
+        for (int l = 1; l <= 4; l++) {
+            double s = 0.0;
+            for (int m = -l; m <= l; m++) {
+                double complex a = A[n][l * l + l + m];
+                s += creal(a) * creal(a) + cimag(a) * cimag(a);
+            }
+            q[8 + 4 * n + l - 1] = s;
+        }
+    if (!dq) return;
+    for (int j = 0; j < nn; j++) {
+        const double *uj = u + 3 * j;
+        double *d = dq + (size_t)j * MLP_NQ * 3;
+        for (int f = 0; f < 3 * MLP_NQ; f++) d[f] = 0.0;
+        double r = sqrt(sq3(uj));
+        if (r >= rc) continue;
+        double g[8], dg[8];
+        ora_radial(8, rc, r, g, dg);
+        double complex Y[25], dY[75];
+        ora_ylm_c(4, uj, Y, dY);
+        double e[3] = {uj[0] / r, uj[1] / r, uj[2] / r};
+        for (int n = 0; n < 8; n++)
+            for (int a = 0; a < 3; a++) d[3 * n + a] = dg[n] * e[a];
+        /* d sum_m |A|^2 / du = 2 Re sum_m conj(A) d(g_n Y)/du */
+        for (int n = 0; n < 2; n++)
+            for (int l = 1; l <= 4; l++)
+                for (int m = -l; m <= l; m++) {
+                    int t = l * l + l + m;
+                    double complex a = conj(A[n][t]);
+                    for (int c = 0; c < 3; c++) {
+                        double complex dgy = dg[n] * e[c] * Y[t] + g[n] * dY[3 * t + c];
+                        d[3 * (8 + 4 * n + l - 1) + c] += 2.0 * creal(a * dgy);
+                    }
+                }
+    }
+}
+
+static double sigm(double a) { return 1.0 / (1.0 + exp(-a)); }
+
+/* one sample: o, g = softplus(o) and dg/dq (NULL allowed) */
+static void mlp_forward1(const double *P, const double *q, double *o_out, double *g_out, double *dgdq) {
+    double z[MLP_NQ], a1[MLP_NH], h1[MLP_NH], a2[MLP_NH], h2[MLP_NH];
+    for (int f = 0; f < MLP_NQ; f++) z[f] = (q[f] - P[MLP_MU + f]) / P[MLP_SIG + f];
+    for (int c = 0; c < MLP_NH; c++) {
+        double s = P[MLP_B1 + c];
+        for (int f = 0; f < MLP_NQ; f++) s += P[MLP_W1 + c * MLP_NQ + f] * z[f];
+        a1[c] = s;
+        h1[c] = s * sigm(s);
+    }
+    for (int c = 0; c < MLP_NH; c++) {
+        double s = P[MLP_B2 + c];
+        for (int k = 0; k < MLP_NH; k++) s += P[MLP_W2 + c * MLP_NH + k] * h1[k];
+        a2[c] = s;
+        h2[c] = s * sigm(s);
+    }
+    double o = P[MLP_B3];
+    for (int c = 0; c < MLP_NH; c++) o += P[MLP_W3 + c] * h2[c];
+    *o_out = o;
+    *g_out = o > 0.0 ? o + log1p(exp(-o)) : log1p(exp(o));
+    if (!dgdq) return;
+    /* backward from dg/do = sigmoid(o); silu'(a) = s (1 + a (1 - s)), s = sigmoid(a) */
+    double d2[MLP_NH], d1[MLP_NH];
+    double go = sigm(o);
+    for (int c = 0; c < MLP_NH; c++) {
+        double s = sigm(a2[c]);
+        d2[c] = go * P[MLP_W3 + c] * s * (1.0 + a2[c] * (1.0 - s));
+    }
+    for (int k = 0; k < MLP_NH; k++) {
+        double t = 0.0;
+        for (int c = 0; c < MLP_NH; c++) t += P[MLP_W2 + c * MLP_NH + k] * d2[c];
+        double s = sigm(a1[k]);
+        d1[k] = t * s * (1.0 + a1[k] * (1.0 - s));
+    }
+    for (int f = 0; f < MLP_NQ; f++) {
+        double t = 0.0;
+        for (int c = 0; c < MLP_NH; c++) t += P[MLP_W1 + c * MLP_NQ + f] * d1[c];
+        dgdq[f] = t / P[MLP_SIG + f];
+    }
+}
+
+/* features of every atom of a periodic cell (q[n][16]) */
+int ora_mlp_features(int n, const double *pos_in, const double *L, double rc, double *q) {
+    int rc_ = check_box(L, rc);
+    if (rc_) return rc_;
+    double *pos = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    memcpy(pos, pos_in, sizeof(double) * 3 * (size_t)n);
+    ora_wrap(n, pos, L);
+    csr_t nb;
+    rc_ = build_csr(n, pos, L, rc, &nb);
+    if (!rc_) {
+#pragma omp parallel
+        {
+            double *u = (double *)malloc(sizeof(double) * 3 * 4096);
+#pragma omp for schedule(static)
+            for (int i = 0; i < n; i++) {
+                int nn = nb.start[i + 1] - nb.start[i];
+                if (nn > 4096) nn = 4096;
+                for (int k = 0; k < nn; k++) mic(pos, L, i, nb.idx[nb.start[i] + k], u + 3 * k);
+                mlp_site_features(nn, u, rc, q + (size_t)i * MLP_NQ, NULL);
+            }
+            free(u);
+        }
+        csr_free(&nb);
+    }
+    free(pos);
+    return rc_;
+}
+
+/* network outputs for m samples: o[m], g[m], dgdq[m][16] (may be NULL) */
+void ora_mlp_forward(int m, const double *q, const double *P, double *o, double *g, double *dgdq) {
+#pragma omp parallel for schedule(static)
+    for (int s = 0; s < m; s++)
+        mlp_forward1(P, q + (size_t)s * MLP_NQ, o + s, g + s, dgdq ? dgdq + (size_t)s * MLP_NQ : NULL);
+}
+
+/* training loss L = (1/m) sum_s (o_s - t_s)^2 and its gradient with respect to every parameter
+ * (grad[MLP_NP]; the normalisation entries mu, sig are not trained and get 0). Written as the
+ * chain rule layer by layer for each sample and summed over samples in order. */
+double ora_mlp_loss_grad(int m, const double *q, const double *t, const double *P, double *grad) {
+    for (int k = 0; k < MLP_NP; k++) grad[k] = 0.0;
+    double loss = 0.0;
+    for (int s = 0; s < m; s++) {
+        const double *qs = q + (size_t)s * MLP_NQ;
+        double z[MLP_NQ], a1[MLP_NH], h1[MLP_NH], a2[MLP_NH], h2[MLP_NH];
+        for (int f = 0; f < MLP_NQ; f++) z[f] = (qs[f] - P[MLP_MU + f]) / P[MLP_SIG + f];
+        for (int c = 0; c < MLP_NH; c++) {
+            double v = P[MLP_B1 + c];
+            for (int f = 0; f < MLP_NQ; f++) v += P[MLP_W1 + c * MLP_NQ + f] * z[f];
+            a1[c] = v;
+            h1[c] = v * sigm(v);
+        }
+        for (int c = 0; c < MLP_NH; c++) {
+            double v = P[MLP_B2 + c];
+            for (int k = 0; k < MLP_NH; k++) v += P[MLP_W2 + c * MLP_NH + k] * h1[k];
+            a2[c] = v;
+            h2[c] = v * sigm(v);
+        }
+        double o = P[MLP_B3];
+        for (int c = 0; c < MLP_NH; c++) o += P[MLP_W3 + c] * h2[c];
+        double r = o - t[s];
+        loss += r * r / m;
+        double go = 2.0 * r / m;
+        double d2[MLP_NH], d1[MLP_NH];
+        grad[MLP_B3] += go;
+        for (int c = 0; c < MLP_NH; c++) {
+            grad[MLP_W3 + c] += go * h2[c];
+            double sg = sigm(a2[c]);
+            d2[c] = go * P[MLP_W3 + c] * sg * (1.0 + a2[c] * (1.0 - sg));
+        }
+        for (int c = 0; c < MLP_NH; c++) {
+            grad[MLP_B2 + c] += d2[c];
+            for (int k = 0; k < MLP_NH; k++) grad[MLP_W2 + c * MLP_NH + k] += d2[c] * h1[k];
+        }
+        for (int k = 0; k < MLP_NH; k++) {
+            double v = 0.0;
+            for (int c = 0; c < MLP_NH; c++) v += P[MLP_W2 + c * MLP_NH + k] * d2[c];
+            double sg = sigm(a1[k]);
+            d1[k] = v * sg * (1.0 + a1[k] * (1.0 - sg));
+        }
+        for (int c = 0; c < MLP_NH; c++) {
+            grad[MLP_B1 + c] += d1[c];
+            for (int f = 0; f < MLP_NQ; f++) grad[MLP_W1 + c * MLP_NQ + f] += d1[c] * z[f];
+        }
+    }
+    return loss;
+}
+
+/* ------------------------------------------------------------------------------------------ */
 /* Full AP evaluation                                                                            */
 /* ------------------------------------------------------------------------------------------ */
 /* aux columns per atom */
@@ -665,6 +881,7 @@ enum { AX_G, AX_D, AX_WBAR, AX_LAM, AX_DLAM, AX_EF, AX_EP, AX_ET, AX_W, AX_XIP, 
  *   weight part  F_i += sum_j (E~_i (g_j - d_i - d0) w'(r_ij) rhat_ij
  *                              - E~_j (g_i - d_j - d0) w'(r_ji) rhat_ji)  (S19)-(S21)
  *   CSP part     F_i += sum_j W_j grad_i g_j, W_j = sum_k E~_k w(r_kj)     (S24)-(S27)
+ *                (learned indicator: the same sum with grad_i g_j through the network, (S16))
  * with E~_k = (E^p_k - E^f_k) lam'_k / wbar_k                                (S17)
  * and the descriptor d_k = sum_j g_j w(r_kj) / wbar_k - d0, wbar_k = sum_j w(r_kj), where
  * both sums include j = k with w(0) = 1                                      Eq. (6)
@@ -680,20 +897,25 @@ enum { AX_G, AX_D, AX_WBAR, AX_LAM, AX_DLAM, AX_EF, AX_EP, AX_ET, AX_W, AX_XIP, 
  * Outputs: E_tot[1], E_atom[n], F[n][3], virial[9] (W_ab = -sum_e (dE/du_e)_a (u_e)_b),
  *          aux[n][AUX_W] (may be NULL), Ffam[4][n][3] (may be NULL).
  */
-int ora_eval(int n, const double *pos_in, const double *L, const double *eam_p, int n_max, int l_max, double ace_rc,
-             int n_funcs, const int *func, const double *c, const double *b_dens, double emb_A, double E0,
-             const double *sw_p, int n_csp, const int *csp, int lam_mode, int skip, int no_gradlam, double *E_tot,
-             double *E_atom, double *F, double *virial, double *aux, double *Ffam) {
+/* indicator: 0 = CSP^list with the list csp; 1 = the learned indicator with parameters mlp_P
+ * (MLP_NP doubles) on features inside mlp_rc (csp unused). */
+int ora_eval_ind(int n, const double *pos_in, const double *L, const double *eam_p, int n_max, int l_max,
+                 double ace_rc, int n_funcs, const int *func, const double *c, const double *b_dens, double emb_A,
+                 double E0, const double *sw_p, int n_csp, const int *csp, int lam_mode, int skip, int no_gradlam,
+                 double *E_tot, double *E_atom, double *F, double *virial, double *aux, double *Ffam, int indicator,
+                 const double *mlp_P, double mlp_rc) {
     if (n <= 0 || !pos_in || !L || !eam_p || !sw_p || !E_tot || !E_atom || !F || !virial) return ORA_E_ARG;
     if (n_max > 32 || l_max > 12) return ORA_E_ARG;
+    if (indicator != 0 && (indicator != 1 || !mlp_P || !(mlp_rc > 0.0))) return ORA_E_ARG;
     double rc_eam = eam_p[5] > eam_p[6] ? eam_p[5] : eam_p[6];
     double d_lo = sw_p[0], d_hi = sw_p[1], r_w = sw_p[2], d0 = sw_p[3];
     int need_sw = (lam_mode < 0);
     double rmax = rc_eam > ace_rc ? rc_eam : ace_rc;
     if (need_sw && r_w > rmax) rmax = r_w;
+    if (need_sw && indicator == 1 && mlp_rc > rmax) rmax = mlp_rc;
     int rc = check_box(L, rmax);
     if (rc) return rc;
-    if (need_sw) {
+    if (need_sw && indicator == 0) {
         if (n_csp != 8 && n_csp != 12) return ORA_E_CSP;
         for (long q = 0; q < (long)n * n_csp; q++)
             if (csp[q] < 0 || csp[q] >= n) return ORA_E_CSP;
@@ -715,9 +937,29 @@ int ora_eval(int n, const double *pos_in, const double *L, const double *eam_p, 
 #define AX(i, k) ax[(size_t)(i) * AUX_W + (k)]
 
     /* 1. switching: g (B3), descriptor Eq. (6), lambda Eq. (2) */
-    if (need_sw) {
+    if (need_sw && indicator == 0) {
 #pragma omp parallel for schedule(static)
         for (int i = 0; i < n; i++) AX(i, AX_G) = csp_value(pos, L, i, n_csp, csp);
+    } else if (need_sw) {
+        for (int i = 0; i < n; i++)
+            if (nb.start[i + 1] - nb.start[i] > 4096) rc = ORA_E_NBR;
+#pragma omp parallel if (!rc)
+        {
+            double *u = (double *)malloc(sizeof(double) * 3 * 4096);
+#pragma omp for schedule(static)
+            for (int i = 0; i < n; i++) {
+                if (rc) continue;
+                int nn = nb.start[i + 1] - nb.start[i];
+                for (int q = 0; q < nn; q++) mic(pos, L, i, nb.idx[nb.start[i] + q], u + 3 * q);
+                double qf[MLP_NQ], o, g;
+                mlp_site_features(nn, u, mlp_rc, qf, NULL);
+                mlp_forward1(mlp_P, qf, &o, &g, NULL);
+                AX(i, AX_G) = g;
+            }
+            free(u);
+        }
+    }
+    if (need_sw) {
 #pragma omp parallel for schedule(static)
         for (int i = 0; i < n; i++) {
             double wsum = 1.0, gsum = AX(i, AX_G); /* self term, w(0) = 1 */
@@ -864,7 +1106,7 @@ int ora_eval(int n, const double *pos_in, const double *L, const double *eam_p, 
         }
     }
     /* CSP part: grad_i g_j = 2 sum_l Theta_jl (r_jl + r_j,opp(l)) (delta_ij - delta_il)   (S24) */
-    if (need_sw && !no_gradlam) {
+    if (need_sw && !no_gradlam && indicator == 0) {
         for (int j = 0; j < n; j++) {
             double Wj = AX(j, AX_W);
             if (Wj == 0.0) continue;
@@ -886,6 +1128,35 @@ int ora_eval(int n, const double *pos_in, const double *L, const double *eam_p, 
             }
         }
     }
+    /* learned indicator: grad_i g_j through the features, h_jk = d g_j / d u_jk:
+     * F_j -= W_j sum_k h_jk, F_k += W_j h_jk; the edge u_jk carries dE/du = -W_j h_jk */
+    if (need_sw && !no_gradlam && indicator == 1) {
+        double *u = (double *)malloc(sizeof(double) * 3 * 4096);
+        double *dq = (double *)malloc(sizeof(double) * 3 * MLP_NQ * 4096);
+        for (int j = 0; j < n && !rc; j++) {
+            double Wj = AX(j, AX_W);
+            if (Wj == 0.0) continue;
+            int nn = nb.start[j + 1] - nb.start[j];
+            for (int q = 0; q < nn; q++) mic(pos, L, j, nb.idx[nb.start[j] + q], u + 3 * q);
+            double qf[MLP_NQ], o, g, dgdq[MLP_NQ];
+            mlp_site_features(nn, u, mlp_rc, qf, dq);
+            mlp_forward1(mlp_P, qf, &o, &g, dgdq);
+            for (int q = 0; q < nn; q++) {
+                int k = nb.idx[nb.start[j] + q];
+                double h[3] = {0.0, 0.0, 0.0};
+                for (int f = 0; f < MLP_NQ; f++)
+                    for (int a = 0; a < 3; a++) h[a] += dgdq[f] * dq[((size_t)q * MLP_NQ + f) * 3 + a];
+                for (int a = 0; a < 3; a++) {
+                    fC[3 * j + a] -= Wj * h[a];
+                    fC[3 * k + a] += Wj * h[a];
+                }
+                for (int a = 0; a < 3; a++)
+                    for (int b = 0; b < 3; b++) vir[3 * a + b] += Wj * h[a] * u[3 * q + b];
+            }
+        }
+        free(dq);
+        free(u);
+    }
     for (int i = 0; i < n; i++)
         for (int a = 0; a < 3; a++)
             F[3 * i + a] = fE[3 * i + a] + fA[3 * i + a] + fW[3 * i + a] + fC[3 * i + a];
@@ -903,6 +1174,14 @@ int ora_eval(int n, const double *pos_in, const double *L, const double *eam_p, 
     csr_free(&nb);
     free(pos);
     return rc;
+}
+
+int ora_eval(int n, const double *pos_in, const double *L, const double *eam_p, int n_max, int l_max, double ace_rc,
+             int n_funcs, const int *func, const double *c, const double *b_dens, double emb_A, double E0,
+             const double *sw_p, int n_csp, const int *csp, int lam_mode, int skip, int no_gradlam, double *E_tot,
+             double *E_atom, double *F, double *virial, double *aux, double *Ffam) {
+    return ora_eval_ind(n, pos_in, L, eam_p, n_max, l_max, ace_rc, n_funcs, func, c, b_dens, emb_A, E0, sw_p, n_csp,
+                        csp, lam_mode, skip, no_gradlam, E_tot, E_atom, F, virial, aux, Ffam, 0, NULL, 0.0);
 }
 
 /* Gradient of E_AP with respect to the ACE coefficients:

@@ -58,6 +58,15 @@ def lib():
         L.ora_eval.argtypes = [i, _dp, _dp, _dp, i, i, d, i, _ip, _dp, _dp, d, d, _dp, i, _ip, i, i, i,
                                _dp, _dp, _dp, _dp, _dp, _dp]
         L.ora_eval.restype = i
+        L.ora_eval_ind.argtypes = L.ora_eval.argtypes + [i, C.c_void_p, d]
+        L.ora_eval_ind.restype = i
+        L.ora_mlp_nparams.restype = i
+        L.ora_mlp_features.argtypes = [i, _dp, _dp, d, _dp]
+        L.ora_mlp_features.restype = i
+        L.ora_mlp_forward.argtypes = [i, _dp, _dp, _dp, _dp, C.c_void_p]
+        L.ora_mlp_forward.restype = None
+        L.ora_mlp_loss_grad.argtypes = [i, _dp, _dp, _dp, _dp]
+        L.ora_mlp_loss_grad.restype = d
         L.ora_ace_coeff_grad.argtypes = [i, _dp, _dp, i, i, d, i, _ip, _dp, _dp, d, C.c_void_p, _dp, _dp, _dp]
         L.ora_ace_coeff_grad.restype = i
         L.ora_vv.argtypes = [i, _dp, _dp, _dp, d, d, i, _dp, _dp, i, i, d, i, _ip, _dp, _dp, d, d, _dp, i, _ip,
@@ -162,10 +171,11 @@ def _sw_vec(sw):
     return _f64([sw["d_lo"], sw["d_hi"], sw["r_w"], sw.get("d0", 0.0)])
 
 
-def evaluate(sys, pos=None, csp=None, lam_mode=-1, skip=1, no_gradlam=0):
+def evaluate(sys, pos=None, csp=None, lam_mode=-1, skip=1, no_gradlam=0, mlp=None):
     """Full AP evaluation of a system dict (synth.build_system). Returns a dict with E, E_atom,
     F (n,3), virial (3,3), aux (dict of per-atom arrays) and fam (4, n, 3): EAM-weighted,
-    ACE-weighted, grad-w and grad-CSP force families."""
+    ACE-weighted, grad-w and grad-indicator force families. mlp = (params, rc) selects the
+    learned indicator instead of CSP."""
     pos = _f64(sys["pos"] if pos is None else pos)
     n = len(pos)
     box = _f64(sys["box"])
@@ -174,15 +184,19 @@ def evaluate(sys, pos=None, csp=None, lam_mode=-1, skip=1, no_gradlam=0):
         csp = sys.get("csp")
     if csp is None:
         ref = _f64(sys.get("pos_ref", pos))
-        csp = np.zeros((n, sw["n_csp"]), np.int32) if lam_mode >= 0 else csp_pairs(ref, box, sw["n_csp"])
+        csp = np.zeros((n, sw["n_csp"]), np.int32) if (lam_mode >= 0 or mlp is not None) else \
+            csp_pairs(ref, box, sw["n_csp"])
     E = np.zeros(1)
     Ea = np.zeros(n)
     F = np.zeros(3 * n)
     vir = np.zeros(9)
     aux = np.zeros(n * len(AUX_COLS))
     fam = np.zeros(12 * n)
-    rc = lib().ora_eval(n, pos, box, _eam_vec(sys["eam"]), *_ace_args(sys["ace"]), _sw_vec(sw), int(sw["n_csp"]),
-                        _i32(csp), int(lam_mode), int(skip), int(no_gradlam), E, Ea, F, vir, aux, fam)
+    P = None if mlp is None else _f64(mlp[0])
+    rc = lib().ora_eval_ind(n, pos, box, _eam_vec(sys["eam"]), *_ace_args(sys["ace"]), _sw_vec(sw),
+                            int(sw["n_csp"]), _i32(csp), int(lam_mode), int(skip), int(no_gradlam), E, Ea, F, vir,
+                            aux, fam, 0 if mlp is None else 1, None if P is None else P.ctypes.data,
+                            0.0 if mlp is None else float(mlp[1]))
     _chk(rc, "ora_eval")
     aux = aux.reshape(n, len(AUX_COLS))
     return dict(E=E[0], E_atom=Ea, F=F.reshape(n, 3), virial=vir.reshape(3, 3),
@@ -224,3 +238,36 @@ def velocity_verlet(sys, n_steps, pos=None, vel=None, csp=None, lam_mode=-1, dt=
     _chk(rc, "ora_vv")
     n = len(pos)
     return flat_pos.reshape(n, 3), flat_vel.reshape(n, 3), F.reshape(n, 3), th.reshape(n_steps, 6)
+
+
+MLP_NQ, MLP_NH = 16, 64
+
+
+def mlp_nparams():
+    return int(lib().ora_mlp_nparams())
+
+
+def mlp_features(pos, box, rc=5.5):
+    """The sixteen invariant features q (n, 16) of every atom."""
+    pos = _f64(pos)
+    q = np.zeros(len(pos) * MLP_NQ)
+    _chk(lib().ora_mlp_features(len(pos), pos, _f64(box), float(rc), q), "ora_mlp_features")
+    return q.reshape(-1, MLP_NQ)
+
+
+def mlp_forward(q, params, grad=True):
+    """Network output o, indicator g = softplus(o) and dg/dq (m, 16) for features q (m, 16)."""
+    q = _f64(np.asarray(q).reshape(-1, MLP_NQ))
+    m = len(q)
+    o, g = np.zeros(m), np.zeros(m)
+    dg = np.zeros(m * MLP_NQ) if grad else None
+    lib().ora_mlp_forward(m, q, _f64(params), o, g, dg.ctypes.data if grad else None)
+    return o, g, (dg.reshape(m, MLP_NQ) if grad else None)
+
+
+def mlp_loss_grad(q, target, params):
+    """Training loss mean((o - t)^2) and its gradient over the parameter block."""
+    q = _f64(np.asarray(q).reshape(-1, MLP_NQ))
+    grad = np.zeros(mlp_nparams())
+    loss = lib().ora_mlp_loss_grad(len(q), q, _f64(target), _f64(params), grad)
+    return float(loss), grad

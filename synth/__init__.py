@@ -10,6 +10,7 @@ from .structures import (bcc, fcc, gaussian_displace, screw_dipole_z, local_nois
                          strain_cell)
 from .basis import ace_basis, basis_counts
 from .configs import load_config, build_system, CONFIG_NAMES
+from . import learned
 
 __all__ = ["bcc", "fcc", "gaussian_displace", "screw_dipole_z", "local_noise", "remove_atoms",
            "vacancy_clusters", "penny_crack", "maxwell_velocities", "strain_cell", "ace_basis",
