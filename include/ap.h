@@ -56,8 +56,7 @@ extern "C" {
 #define AP_LAMBDA_FAST 1      /* lambda == 1 everywhere: pure EAM                         */
 
 #define AP_IND_CSP 0 /* g = CSP^list of (B3)                                                  */
-#define AP_IND_MLP 1 /* g = learned indicator (ap_set_indicator_mlp); the CSP list still drives
-                        nothing else                                                          */
+#define AP_IND_MLP 1 /* g = learned indicator: the network set by ap_set_mlp (no CSP list needed) */
 
 /* Orthorhombic periodic box with its origin at 0. */
 typedef struct {
@@ -193,6 +192,39 @@ int ap_get_profile(ap_ctx *ctx, int max_entries, char *names, double *avg_ms, in
  * per precise atom independent of its neighbours (orders 2-3 values and adjoints), per neighbour
  * inside the ACE cutoff in the energy kernel, and per neighbour in the pair-gradient kernel. */
 int ap_ace_cost(ap_ctx *ctx, double *fixed_per_atom, double *per_neighbor_energy, double *per_neighbor_force);
+
+/* ---------------------------------------------------------------------------------------------
+ * Learned switching indicator. Eq. (6) accepts any per-atom g; here g_i = softplus(o_i) of a
+ * 16-64-64-1 network (SiLU, FP32) on sixteen rotation invariants of the neighbours inside rc:
+ *   q[n] = sum_j g_n(r_ij) (n = 0..7, the Chebyshev channels of the ACE basis, cutoff rc);
+ *   q[8 + 4n + l - 1] = sum_m A_nlm^2 with A_nlm = sum_j g_n(r_ij) Y_lm(rhat_ij), n = 0, 1, l = 1..4.
+ * Its force is the general grad-g term of (S16): F_i += sum_j W_j grad_i g_j, W_j of (S25).
+ * Parameter block (AP_MLP_NPARAMS floats, device memory):
+ *   mu[16] sig[16] W1[64][16] b1[64] W2[64][64] b2[64] w3[64] b3;  z = (q - mu) / sig,
+ *   h1 = silu(W1 z + b1), h2 = silu(W2 h1 + b2), o = w3 . h2 + b3, g = softplus(o).
+ * The network is trained on o against log(|E^ACE_i - E^EAM_i| + eps) (the caller builds targets).
+ * ------------------------------------------------------------------------------------------- */
+#define AP_MLP_NQ 16
+#define AP_MLP_NPARAMS 5345
+
+/* Copies the parameter block (device pointer) into the context and sets the feature cutoff rc;
+ * used by every evaluation whose switching parameters select AP_IND_MLP. */
+int ap_set_mlp(ap_ctx *ctx, const float *params, double rc);
+/* Features q[n][16] (device, FP32) of every atom of one periodic cell (pos device SoA [3][n]). */
+int ap_mlp_features(ap_ctx *ctx, int n, const double *pos, const ap_box *box, double rc, float *q);
+/* g[m] and, if dgdq != NULL, dg/dq [m][16] of m feature rows q[m][16] (all device, FP32). */
+int ap_mlp_eval(ap_ctx *ctx, int m, const float *q, const float *params, float *g, float *dgdq);
+/* Loss L = (1/m) sum_s (o_s - t_s)^2 over m samples (device q[m][16], t[m]) and its gradient with
+ * respect to every parameter (device grad[AP_MLP_NPARAMS]; 0 for mu and sig); *loss on the host.
+ * m is limited only by device memory (274 floats of scratch per sample). */
+int ap_mlp_loss_grad(ap_ctx *ctx, int m, const float *q, const float *target, const float *params, float *grad,
+                     double *loss);
+/* Adam training (beta 0.9 / 0.999, eps 1e-8, learning rate lr) over epochs x floor(m / batch)
+ * mini-batches in the given sample order (the ragged tail of each epoch is left out). fit_norm != 0
+ * first sets mu and sig to the mean and standard deviation of the features. params (device) are
+ * updated in place; loss_hist (host, may be NULL) receives the mean batch loss of each epoch. */
+int ap_mlp_train(ap_ctx *ctx, int m, const float *q, const float *target, int batch, int epochs, double lr,
+                 int fit_norm, float *params, double *loss_hist);
 
 #ifdef __cplusplus
 }

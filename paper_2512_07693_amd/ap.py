@@ -21,7 +21,9 @@ ERRORS = {-1: "AP_E_ARG", -2: "AP_E_BOX", -3: "AP_E_NBR_OVERFLOW", -4: "AP_E_NON
 SYMBOLS = ["ap_ctx_create", "ap_ctx_destroy", "ap_last_error", "ap_set_potential", "ap_csp_pairs_build",
            "ap_set_csp_list", "ap_nblist_build", "ap_eam_eval", "ap_switch_eval", "ap_ace_eval",
            "ap_mixed_energy_forces", "ap_vv_step", "ap_set_profiling", "ap_get_profile", "ap_ace_cost",
-           "ap_ace_batch_eval"]
+           "ap_ace_batch_eval", "ap_set_mlp", "ap_mlp_features", "ap_mlp_eval", "ap_mlp_loss_grad",
+           "ap_mlp_train"]
+MLP_NQ, MLP_NPARAMS = 16, 5345
 
 
 class APError(RuntimeError):
@@ -81,6 +83,11 @@ def lib():
         L.ap_get_profile.argtypes = [vp, i, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.ap_ace_cost.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.ap_ace_batch_eval.argtypes = [vp, i, C.POINTER(C.c_int32), C.POINTER(C.c_double), vp, vp, vp, vp, vp, vp]
+        L.ap_set_mlp.argtypes = [vp, vp, d]
+        L.ap_mlp_features.argtypes = [vp, i, vp, C.POINTER(Box), d, vp]
+        L.ap_mlp_eval.argtypes = [vp, i, vp, vp, vp, vp]
+        L.ap_mlp_loss_grad.argtypes = [vp, i, vp, vp, vp, vp, C.POINTER(C.c_double)]
+        L.ap_mlp_train.argtypes = [vp, i, vp, vp, i, i, d, i, vp, C.POINTER(C.c_double)]
         for s in SYMBOLS:
             if s not in ("ap_ctx_destroy", "ap_last_error"):
                 getattr(L, s).restype = i
@@ -140,7 +147,8 @@ class Context:
     def _zeros(self, *shape, dtype=torch.float64):
         return torch.zeros(*shape, dtype=dtype, device=self.device)
 
-    def set_potential(self, eam, ace, sw, lambda_mode=AP_LAMBDA_COMPUTED, grad_lambda=True, precision=None):
+    def set_potential(self, eam, ace, sw, lambda_mode=AP_LAMBDA_COMPUTED, grad_lambda=True, precision=None,
+                      indicator=AP_IND_CSP):
         e = EamParams(*[float(eam[k]) for k in EAM_KEYS])
         func = np.ascontiguousarray(ace["func"], dtype=np.int32)
         c = np.ascontiguousarray(ace["c"], dtype=np.float64)
@@ -151,7 +159,7 @@ class Context:
                       b.ctypes.data_as(C.POINTER(C.c_double)), float(ace["emb_A"]), float(ace["E0"]),
                       AP_FP32 if prec in ("fp32", AP_FP32) else AP_FP64)
         s = SwitchParams(float(sw["d_lo"]), float(sw["d_hi"]), float(sw["r_w"]), float(sw.get("d0", 0.0)),
-                         int(sw["n_csp"]), int(lambda_mode), AP_IND_CSP, 1 if grad_lambda else 0)
+                         int(sw["n_csp"]), int(lambda_mode), int(indicator), 1 if grad_lambda else 0)
         self._chk(lib().ap_set_potential(self.h, C.byref(e), C.byref(a), C.byref(s)))
         self._nf, self._nm = len(func), int(ace["n_max"])
 
@@ -229,6 +237,51 @@ class Context:
                                           bx.ctypes.data_as(C.POINTER(C.c_double)), _ptr(pos), _ptr(weight),
                                           _ptr(E), _ptr(F), _ptr(dc), _ptr(db)))
         return dict(E=E, F=F, dEdc=dc, dEdb=db)
+
+    # ---- learned indicator ----
+    def set_mlp(self, params, rc=5.5):
+        """Install the network (float32 CUDA tensor of MLP_NPARAMS) used when the indicator is AP_IND_MLP."""
+        _dev(params, torch.float32, (MLP_NPARAMS,))
+        self._chk(lib().ap_set_mlp(self.h, _ptr(params), float(rc)))
+
+    def mlp_features(self, pos, box, rc=5.5):
+        n = pos.shape[1]
+        _dev(pos, torch.float64, (3, n))
+        q = self._zeros(n, MLP_NQ, dtype=torch.float32)
+        self._chk(lib().ap_mlp_features(self.h, n, _ptr(pos), C.byref(_box(box)), float(rc), _ptr(q)))
+        return q
+
+    def mlp_eval(self, q, params, grad=True):
+        m = q.shape[0]
+        _dev(q, torch.float32, (m, MLP_NQ))
+        _dev(params, torch.float32, (MLP_NPARAMS,))
+        g = self._zeros(m, dtype=torch.float32)
+        dg = self._zeros(m, MLP_NQ, dtype=torch.float32) if grad else None
+        self._chk(lib().ap_mlp_eval(self.h, m, _ptr(q), _ptr(params), _ptr(g), _ptr(dg) if grad else None))
+        return g, dg
+
+    def mlp_loss_grad(self, q, target, params):
+        m = q.shape[0]
+        _dev(q, torch.float32, (m, MLP_NQ))
+        _dev(target, torch.float32, (m,))
+        _dev(params, torch.float32, (MLP_NPARAMS,))
+        grad = self._zeros(MLP_NPARAMS, dtype=torch.float32)
+        loss = C.c_double()
+        self._chk(lib().ap_mlp_loss_grad(self.h, m, _ptr(q), _ptr(target), _ptr(params), _ptr(grad),
+                                         C.byref(loss)))
+        return loss.value, grad
+
+    def mlp_train(self, q, target, params, batch=4096, epochs=20, lr=1e-3, fit_norm=True):
+        """Adam on the library's forward/backward kernels; params (float32 CUDA) is updated in place.
+        Returns the mean batch loss of every epoch."""
+        m = q.shape[0]
+        _dev(q, torch.float32, (m, MLP_NQ))
+        _dev(target, torch.float32, (m,))
+        _dev(params, torch.float32, (MLP_NPARAMS,))
+        hist = (C.c_double * max(1, epochs))()
+        self._chk(lib().ap_mlp_train(self.h, m, _ptr(q), _ptr(target), int(batch), int(epochs), float(lr),
+                                     1 if fit_norm else 0, _ptr(params), hist))
+        return np.array(hist[:epochs])
 
     def set_profiling(self, on=True):
         self._chk(lib().ap_set_profiling(self.h, 1 if on else 0))

@@ -142,6 +142,17 @@ struct ap_ctx {
     void *frev = nullptr;        // [3][max_nbr][n] the same pair terms at the neighbour's slot (k, j)
     void *gbuf = nullptr;        // [n_cap][n_max * (l_max+1)^2] dE/dA of the S atoms
     size_t fpair_bytes = 0, gbuf_bytes = 0;
+    // learned indicator
+    bool have_mlp = false;
+    double mlp_rc = 0;
+    float *mlp_p = nullptr;      // [AP_MLP_NPARAMS]
+    float *hpair = nullptr;      // [n_cap][max_nbr][3] W_j dg_j/du_jk of the atoms with W != 0
+    float *hrev = nullptr;       // [3][max_nbr][n] the same terms at the neighbour's slot
+    int *widx = nullptr, *wlist = nullptr;
+    float *mlp_T = nullptr;      // training scratch [274][batch]
+    int mlp_T_cap = 0;
+    float *mlp_grad = nullptr, *mlp_m1 = nullptr, *mlp_m2 = nullptr;
+    double *mlp_loss = nullptr;
     double *partials = nullptr;  // per-block partial sums [nblk][16]
     double *scalars = nullptr;   // [0] E_tot, [1..9] virial, [10] E_kin, [11..13] P
 
@@ -214,5 +225,11 @@ void launch_struct_reduce(ap_ctx *c, int n, int n_struct, const int *d_off, cons
 void launch_reduce(ap_ctx *c, int nblocks, double *E_tot, double *virial9);
 
 int sync_and_check(ap_ctx *c);
+
+// mlp.hip
+void launch_mlp_indicator(ap_ctx *c, int n, const double *box);
+void launch_mlp_gradg(ap_ctx *c, int n, const double *box);
+int mlp_alloc(ap_ctx *c);
+void mlp_free(ap_ctx *c);
 
 }  // namespace ap

@@ -86,6 +86,7 @@ int sync_and_check(ap_ctx *c) {
 static double list_radius(const ap_ctx *c, bool switching) {
     double r = std::max(std::max(c->eam.r_rho, c->eam.r_phi), c->ace.rc);
     if (switching) r = std::max(r, c->sw.r_w);
+    if (switching && c->sw.indicator == AP_IND_MLP) r = std::max(r, c->mlp_rc);
     return r + c->skin;
 }
 
@@ -101,7 +102,10 @@ static int evaluate(ap_ctx *c, int n, const double *box, const EvalFlags &f, con
         rc = ensure_list(c, n, box, list_radius(c, f.switching), force_list);
     }
     if (rc) return rc;
-    if (f.switching) {
+    if (f.switching && c->sw.indicator == AP_IND_MLP) {
+        ProfScope p(c, "mlp_indicator");
+        launch_mlp_indicator(c, n, box);
+    } else if (f.switching) {
         ProfScope p(c, "csp_value");
         launch_csp_value(c, n, box);
     }
@@ -123,6 +127,10 @@ static int evaluate(ap_ctx *c, int n, const double *box, const EvalFlags &f, con
     if (f.switching && f.grad_lambda) {
         ProfScope p(c, "W");
         launch_W(c, n, box);
+    }
+    if (f.switching && f.grad_lambda && c->sw.indicator == AP_IND_MLP) {
+        ProfScope p(c, "mlp_gradg");
+        launch_mlp_gradg(c, n, box);
     }
     {
         ProfScope p(c, "force");
@@ -146,6 +154,10 @@ static int check_common(ap_ctx *c, int n, const double *pos, const ap_box *box, 
 }
 
 static int check_csp(ap_ctx *c, int n) {
+    if (c->sw.indicator == AP_IND_MLP) {
+        if (!c->have_mlp) return set_error(c, AP_E_STATE, "the learned indicator needs ap_set_mlp");
+        return AP_OK;
+    }
     if (!c->csp_t || c->csp_n != n) return set_error(c, AP_E_STATE, "no CSP pair list for this atom count");
     return AP_OK;
 }
@@ -249,6 +261,7 @@ void ap_ctx_destroy(ap_ctx *c) {
     prof_resolve(c);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     ace_free(c);
+    mlp_free(c);
     void *bufs[] = {c->csp_t, c->rev_start, c->rev_code, c->pos, c->pos_build, c->d_flags, c->cell_of, c->cell_cnt,
                     c->cell_start, c->cell_fill, c->cell_atoms, c->nbr_cnt, c->nbr_idx, c->g, c->d,
                     c->wbar, c->lam, c->dlam, c->Ef, c->Ep, c->Et, c->W, c->xip, c->sidx, c->slist, c->blk_cnt,
@@ -316,7 +329,7 @@ int ap_set_potential(ap_ctx *c, const ap_eam_params *eam, const ap_ace_params *a
     if (sw->lambda_mode != AP_LAMBDA_COMPUTED && sw->lambda_mode != AP_LAMBDA_PRECISE &&
         sw->lambda_mode != AP_LAMBDA_FAST)
         return set_error(c, AP_E_ARG, "lambda_mode");
-    if (sw->indicator != AP_IND_CSP) return set_error(c, AP_E_ARG, "only the CSP indicator is available here");
+    if (sw->indicator != AP_IND_CSP && sw->indicator != AP_IND_MLP) return set_error(c, AP_E_ARG, "indicator");
     if (sw->lambda_mode == AP_LAMBDA_COMPUTED && (!(sw->d_hi > sw->d_lo) || !(sw->r_w > 1.0)))
         return set_error(c, AP_E_ARG, "switching parameters need d_hi > d_lo and r_w > 1 A");
     int rc = ace_setup(c, ace);
@@ -428,7 +441,10 @@ int ap_switch_eval(ap_ctx *c, int n, const double *pos, const ap_box *box, doubl
     rc = prepare_positions(c, n, pos, box->L);
     if (!rc) rc = ensure_list(c, n, box->L, list_radius(c, true), true);
     if (rc) return rc;
-    launch_csp_value(c, n, box->L);
+    if (c->sw.indicator == AP_IND_MLP)
+        launch_mlp_indicator(c, n, box->L);
+    else
+        launch_csp_value(c, n, box->L);
     launch_dens_desc(c, n, box->L, f, nullptr);
     launch_compact(c, n, nullptr, 0);
     const int nb = nblocks(n);

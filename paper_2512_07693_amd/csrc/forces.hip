@@ -224,6 +224,9 @@ struct ForceArgs {
     int *flags;
     const double *sbox;  // per-structure boxes of a batch (null: L)
     const int *sid;
+    int ind_mlp;                      // learned indicator: grad-g terms from hpair / hrev
+    const float *hpair, *hrev;
+    const int *widx;
 };
 
 template <typename TF>
@@ -262,6 +265,7 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
         const TF *fp = reinterpret_cast<const TF *>(a.fpair);
         const int cnt = a.ncount[i];
         const bool gl = a.switching && a.grad_lambda;
+        const int wi = (gl && a.ind_mlp) ? a.widx[i] : -1;
         const double *Lb = a.sbox ? a.sbox + 3 * a.sid[i] : a.L;  // own cell in a batch of cells
         const double Lx = Lb[0], Ly = Lb[1], Lz = Lb[2];
         for (int k = 0; k < cnt; k++) {
@@ -301,6 +305,25 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
                 v[3] += t * uy * ux; v[4] += t * uy * uy; v[5] += t * uy * uz;
                 v[6] += t * uz * ux; v[7] += t * uz * uy; v[8] += t * uz * uz;
             }
+            if (gl && a.ind_mlp) {
+                // learned indicator, (S16): F_i -= W_i dg_i/du_ik (own), F_i += W_j dg_j/du_ji (j's)
+                if (wi >= 0) {
+                    const float *h = a.hpair + ((size_t)wi * a.max_nbr + k) * 3;
+                    const double hx = (double)h[0], hy = (double)h[1], hz = (double)h[2];
+                    F0 -= hx;
+                    F1 -= hy;
+                    F2 -= hz;
+                    v[0] += hx * ux; v[1] += hx * uy; v[2] += hx * uz;
+                    v[3] += hy * ux; v[4] += hy * uy; v[5] += hy * uz;
+                    v[6] += hz * ux; v[7] += hz * uy; v[8] += hz * uz;
+                }
+                if (a.widx[j] >= 0) {
+                    const size_t st = (size_t)a.max_nbr * n, o = (size_t)k * n + i;
+                    F0 += (double)a.hrev[o];
+                    F1 += (double)a.hrev[st + o];
+                    F2 += (double)a.hrev[2 * st + o];
+                }
+            }
             if (a.ace_on) {
                 // (S14): (1 - lambda_i) f_ki from i's own site, minus (1 - lambda_k) f_ik from k's site
                 if (si >= 0) {
@@ -325,7 +348,7 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
                 }
             }
         }
-        if (gl) {
+        if (gl && !a.ind_mlp) {
             // CSP part (S24)-(S27): own list 2 W_i sum_l (r_il + r_i,opp(l)); reverse entries
             // -2 W_j (r_ji + r_j,opp(i)).
             const double Wi = a.W[i];
@@ -416,6 +439,10 @@ void launch_force(ap_ctx *c, int n, const double *box, const EvalFlags &f, doubl
     a.F = F;
     a.partials = c->partials;
     a.flags = c->d_flags;
+    a.ind_mlp = f.switching && c->sw.indicator == AP_IND_MLP;
+    a.hpair = c->hpair;
+    a.hrev = c->hrev;
+    a.widx = c->widx;
     const int nb = (n + kBlock - 1) / kBlock;
     if (a.fp32)
         k_force<float><<<nb, kBlock, 0, c->stream>>>(a);

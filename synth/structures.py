@@ -101,3 +101,13 @@ def maxwell_velocities(n, mass, temperature, rng):
     ekin = 0.5 * (m[:, None] * v * v).sum() / EV_PER_U_A2_PS2
     t_now = 2.0 * ekin / ((3 * n - 3) * KB_EV)
     return v * np.sqrt(temperature / t_now)
+
+
+def dilatation_inclusion(pos, box, centre, radius, eps):
+    """Spherical inclusion with a uniform dilatation eps inside radius R (u = eps d) and the
+    continuous far field u = eps R^3 d / r^3 outside; d is the minimum-image vector from centre."""
+    d = pos - centre
+    d -= box * np.rint(d / box)
+    r = np.sqrt((d * d).sum(1))
+    f = np.where(r < radius, eps, eps * radius ** 3 / np.maximum(r, 1e-12) ** 3)
+    return (pos + f[:, None] * d) % box

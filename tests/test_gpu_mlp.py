@@ -1,0 +1,147 @@
+"""GPU parity of the learned indicator against the FP64 oracle, through the C ABI: features, the
+network and its input gradient, the training gradient, and the AP forces with the network as g of
+Eq. (6). The network is FP32, so the bars are the FP32 ones (forces rms 2e-5, energies 1e-6 eV/atom);
+features, outputs and gradients are compared relative to their largest magnitude at 1e-5 (forward
+quantities: sums of at most ~100 FP32 terms) and 1e-4 (backward quantities: two more layers of
+64-term FP32 sums in the chain rule)."""
+import numpy as np
+import pytest
+
+from synth.learned import OFF, mlp_init
+from tests.gpu_util import TOL_ENERGY, TOL_F32_FORCE, force_err_rms, soa_to_aos, to_dev
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _lt(name, value, tol):
+    _say("  %-12s %.3e (bar %.1e)" % (name, value, tol))
+    assert value < tol, "%s = %.3e exceeds %.1e" % (name, value, tol)
+
+
+def _rel(a, b):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def mlp_case(oracle):
+    # the calibrated 1,024-atom workload: there E^f - E^p is what a fitted ACE gives (~10 meV), so the
+    # FP32 rounding of g moves the energy by far less than the bar (with an unfitted ACE, several eV
+    # apart from the EAM, the same rounding would show as ~1e-5 eV/atom)
+    s = synth.build_system(1, with_velocities=False)
+    q = oracle.mlp_features(s["pos"], s["box"])
+    p = mlp_init(7, b3=0.3)
+    p[OFF["mu"]:OFF["mu"] + 16] = q.mean(0)
+    p[OFF["sig"]:OFF["sig"] + 16] = q.std(0) + 1e-3
+    p = p.astype(np.float32).astype(np.float64)  # the values the FP32 library holds
+    probe = oracle.evaluate(dict(s, sw=dict(s["sw"], d_lo=1e9, d_hi=2e9)), skip=2, mlp=(p, 5.5))
+    d = probe["aux"]["d"]
+    s["sw"] = dict(s["sw"], d_lo=float(np.quantile(d, 0.3)), d_hi=float(np.quantile(d, 0.9)))
+    return s, q, p
+
+
+def _ptensor(p):
+    import torch
+    return torch.tensor(p, dtype=torch.float32, device="cuda")
+
+
+def _ctx(s, p, grad_lambda=True):
+    from paper_2512_07693_amd import ap
+    ctx = ap.Context(len(s["pos"]), max_nbr=128, skin=s["run"]["skin"])
+    ctx.set_potential(s["eam"], s["ace"], s["sw"], grad_lambda=grad_lambda, indicator=ap.AP_IND_MLP)
+    ctx.set_mlp(_ptensor(p), 5.5)
+    return ctx
+
+
+def test_features_match_oracle(mlp_case):
+    from paper_2512_07693_amd import ap
+    s, q, _ = mlp_case
+    _say("features, %d atoms" % len(s["pos"]))
+    ctx = ap.Context(len(s["pos"]), max_nbr=128, skin=0.5)
+    qg = ctx.mlp_features(to_dev(s["pos"]), s["box"]).cpu().numpy()
+    worst = max(_rel(qg[:, f], q[:, f]) for f in range(16))
+    _lt("features", worst, 1e-5)
+    ctx.close()
+
+
+def test_network_and_input_gradient_match_oracle(oracle, mlp_case):
+    import torch
+    from paper_2512_07693_amd import ap
+    s, q, p = mlp_case
+    ctx = ap.Context(16, max_nbr=8, skin=0.5)
+    qd = torch.tensor(q, dtype=torch.float32, device="cuda")
+    q32 = qd.cpu().numpy().astype(np.float64)
+    g, dg = ctx.mlp_eval(qd, _ptensor(p))
+    _, g_ref, dg_ref = oracle.mlp_forward(q32, p)
+    _lt("g", _rel(g.cpu().numpy(), g_ref), 1e-5)
+    _lt("dg/dq", _rel(dg.cpu().numpy(), dg_ref), 1e-4)
+    ctx.close()
+
+
+def test_training_gradient_matches_oracle(oracle, mlp_case):
+    import torch
+    from paper_2512_07693_amd import ap
+    s, q, p = mlp_case
+    rng = np.random.default_rng(12)
+    t = rng.normal(-4.0, 1.0, len(q))
+    ctx = ap.Context(16, max_nbr=8, skin=0.5)
+    qd = torch.tensor(q, dtype=torch.float32, device="cuda")
+    td = torch.tensor(t, dtype=torch.float32, device="cuda")
+    loss, grad = ctx.mlp_loss_grad(qd, td, _ptensor(p))
+    loss_ref, grad_ref = oracle.mlp_loss_grad(qd.cpu().numpy().astype(np.float64),
+                                              td.cpu().numpy().astype(np.float64), p)
+    _lt("loss", abs(loss - loss_ref) / loss_ref, 1e-5)
+    g = grad.cpu().numpy()
+    for name, a, b in (("dW1", OFF["W1"], OFF["b1"]), ("db1", OFF["b1"], OFF["W2"]), ("dW2", OFF["W2"], OFF["b2"]),
+                       ("db2", OFF["b2"], OFF["w3"]), ("dw3,db3", OFF["w3"], OFF["b3"] + 1)):
+        _lt(name, _rel(g[a:b], grad_ref[a:b]), 1e-4)
+    assert np.all(g[:32] == 0)
+    ctx.close()
+
+
+def test_mixed_with_learned_indicator_matches_oracle(oracle, mlp_case):
+    s, _, p = mlp_case
+    want = oracle.evaluate(s, mlp=(p, 5.5))
+    lam = want["aux"]["lam"]
+    _say("mixed, learned indicator: %d transition atoms, %d with W != 0" %
+         (((lam > 0) & (lam < 1)).sum(), (want["aux"]["W"] != 0).sum()))
+    assert ((lam > 0) & (lam < 1)).sum() >= 20
+    ctx = _ctx(s, p)
+    out = ctx.mixed_energy_forces(to_dev(s["pos"]), s["box"])
+    F = soa_to_aos(out["F"])
+    _lt("F rms", force_err_rms(F, want["F"]), TOL_F32_FORCE)
+    _lt("E/N", abs(float(out["E"]) - want["E"]) / len(F), TOL_ENERGY)
+    # the grad-lambda families alone (weight part and indicator part) against the oracle's
+    ctx0 = _ctx(s, p, grad_lambda=False)
+    F0 = soa_to_aos(ctx0.mixed_energy_forces(to_dev(s["pos"]), s["box"])["F"])
+    _lt("F grad-lam", force_err_rms(F - F0, want["fam"][2] + want["fam"][3]), TOL_F32_FORCE)
+    _lt("sum F", float(np.abs(F.sum(0)).max() / np.abs(F).max()), 1e-6)
+    ctx.close()
+    ctx0.close()
+
+
+def test_training_decreases_loss_and_is_deterministic(mlp_case):
+    import torch
+    from paper_2512_07693_amd import ap
+    s, q, _ = mlp_case
+    rng = np.random.default_rng(5)
+    # targets with structure: a smooth function of two features plus noise
+    t = -4.0 + 0.8 * np.tanh((q[:, 0] - q[:, 0].mean()) / q[:, 0].std()) + 0.3 * rng.normal(size=len(q))
+    qd = torch.tensor(np.tile(q, (8, 1)), dtype=torch.float32, device="cuda")
+    td = torch.tensor(np.tile(t, 8), dtype=torch.float32, device="cuda")
+    ctx = ap.Context(16, max_nbr=8, skin=0.5)
+    runs = []
+    for _ in range(2):
+        p = _ptensor(mlp_init(3))
+        hist = ctx.mlp_train(qd, td, p, batch=250, epochs=30, lr=3e-3)
+        runs.append((hist, p.cpu().numpy()))
+    hist = runs[0][0]
+    _say("  loss %.4f -> %.4f" % (hist[0], hist[-1]))
+    assert hist[-1] < 0.5 * hist[0]
+    assert np.array_equal(runs[0][1], runs[1][1]) and np.array_equal(runs[0][0], runs[1][0])
+    ctx.close()
