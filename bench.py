@@ -121,6 +121,101 @@ def cpu_baseline(s, steps):
                        "workload, FP64 oracle in S-skip mode, %.1f s" % (steps, len(s["pos"]), dt))
 
 
+def train_indicator(eam, ace, sw, n_cells=200, epochs=150):
+    """The learned indicator, trained by the library's kernels on per-atom |E^ACE - E^EAM| that the
+    library computes on seeded strained and defected bcc cells."""
+    import torch
+    from paper_2512_07693_amd import ap
+    from synth.learned import mlp_init, training_cells
+    cells = training_cells(n_cells)
+    nmax = max(len(p) for p, _ in cells)
+    c_ace = ap.Context(nmax, max_nbr=128, skin=0.0)
+    c_ace.set_potential(eam, ace, sw, lambda_mode=ap.AP_LAMBDA_PRECISE)
+    c_eam = ap.Context(nmax, max_nbr=128, skin=0.0)
+    c_eam.set_potential(eam, ace, sw, lambda_mode=ap.AP_LAMBDA_FAST)
+    Q, Y = [], []
+    for p, b in cells:
+        P = torch.tensor(np.ascontiguousarray(p.T), device="cuda")
+        Y.append((c_ace.ace_eval(P, b)["E_atom"] - c_eam.eam_eval(P, b)["E_atom"]).abs())
+        Q.append(c_ace.mlp_features(P, b))
+    perm = torch.tensor(np.random.default_rng(0).permutation(sum(len(q) for q in Q)), device="cuda")
+    Q = torch.cat(Q)[perm].contiguous()
+    T = torch.log(torch.cat(Y)[perm] + 1e-4).float().contiguous()
+    params = torch.tensor(mlp_init(1, b3=float(T.mean())), dtype=torch.float32, device="cuda")
+    t = time.time()
+    hist = c_ace.mlp_train(Q, T, params, batch=4096, epochs=epochs, lr=2e-3)
+    torch.cuda.synchronize()
+    return params, dict(samples=int(len(Q)), epochs=epochs, train_s=time.time() - t, loss_first=float(hist[0]),
+                        loss_last=float(hist[-1]), target_var=float(T.var()))
+
+
+def learned_comparison(steps, warmup):
+    """Vacancy-cluster workload (1M atoms): CSP against the trained network at the same precise
+    fraction x, on drift, force error near the clusters (against pure ACE) and atom-steps/s."""
+    import torch
+    import synth
+    from synth import structures as st
+    from paper_2512_07693_amd import ap
+    s = synth.build_system(4)
+    n, box = len(s["pos"]), s["box"]
+    log("learned indicator: training ...")
+    params, train = train_indicator(s["eam"], s["ace"], s["sw"])
+    pos0 = torch.tensor(np.ascontiguousarray(s["pos"].T), device="cuda")
+    vel0 = torch.tensor(np.ascontiguousarray(s["vel"].T), device="cuda")
+    # atoms within 8 A of a removed lattice site
+    full, _ = st.bcc(3.16, 80)
+    key = lambda a: set(map(tuple, np.round(a / 0.79).astype(np.int64).tolist()))
+    removed = np.array(sorted(key(full) - key(s["pos_ref"]))) * 0.79
+    near = np.zeros(n, dtype=bool)
+    for r in removed:
+        d = s["pos"] - r
+        d -= box * np.rint(d / box)
+        near |= (d * d).sum(1) < 64.0
+    c_ref = ap.Context(n, max_nbr=128, skin=s["run"]["skin"])
+    c_ref.set_potential(s["eam"], s["ace"], s["sw"], lambda_mode=ap.AP_LAMBDA_PRECISE)
+    Fref = c_ref.mixed_energy_forces(pos0, box)["F"].cpu().numpy().T
+    c_ref.close()
+    del c_ref
+
+    def ctx_for(indicator, sw):
+        c = ap.Context(n, max_nbr=128, skin=s["run"]["skin"])
+        c.set_potential(s["eam"], s["ace"], sw, indicator=indicator)
+        if indicator == ap.AP_IND_MLP:
+            c.set_mlp(params, 5.5)
+        else:
+            c.csp_pairs_build(torch.tensor(np.ascontiguousarray(s["pos_ref"].T), device="cuda"), box, 8)
+        return c
+
+    out = dict(workload=s["name"], n_atoms=n, removed_sites=int(len(removed)), atoms_near=int(near.sum()),
+               training=train)
+    c = ctx_for(ap.AP_IND_CSP, s["sw"])
+    x_csp = float((c.switch_eval(pos0, box)["lam"] < 1).double().mean())
+    lo, hi = 1e-4, 10.0
+    cm = ctx_for(ap.AP_IND_MLP, dict(s["sw"], d_lo=1.0, d_hi=2.0))
+    for _ in range(40):  # thresholds of the network (eV; d_hi = 2 d_lo) bisected to CSP's x
+        mid = np.sqrt(lo * hi)
+        cm.set_potential(s["eam"], s["ace"], dict(s["sw"], d_lo=mid, d_hi=2 * mid), indicator=ap.AP_IND_MLP)
+        x = float((cm.switch_eval(pos0, box)["lam"] < 1).double().mean())
+        lo, hi = (mid, hi) if x > x_csp else (lo, mid)
+    cm.set_potential(s["eam"], s["ace"], dict(s["sw"], d_lo=hi, d_hi=2 * hi), indicator=ap.AP_IND_MLP)
+    for name, ctx in (("csp", c), ("learned", cm)):
+        F = ctx.mixed_energy_forces(pos0, box)["F"].cpu().numpy().T
+        log("learned indicator: %s run, %d + %d steps ..." % (name, warmup, steps))
+        ms, thermo, prof, th_w = run_md(ctx, s, pos0, vel0, steps, warmup, 0)
+        nve = drift_fit(thermo, n, s["run"]["dt"])
+        out[name] = dict(x0=float((ctx.switch_eval(pos0, box)["lam"] < 1).double().mean()),
+                         value=n * steps / (ms / 1e3), ms_per_step=ms / steps,
+                         force_rmse_near=float(np.sqrt(((F - Fref)[near] ** 2).sum(1).mean())),
+                         force_rmse_all=float(np.sqrt(((F - Fref) ** 2).sum(1).mean())),
+                         drift_eV_per_atom_per_ps=nve["drift_eV_per_atom_per_ps"],
+                         max_abs_dE_per_atom=nve["max_abs_dE_per_atom"], x_mean=nve["x_mean"],
+                         kernels={k: round(v[0], 5) for k, v in prof.items()})
+        if name == "learned":
+            out[name]["d_lo"] = float(hi)
+        ctx.close()
+    return out
+
+
 def main():
     ap_ = argparse.ArgumentParser()
     ap_.add_argument("--gpus", type=int, default=1)
@@ -129,6 +224,8 @@ def main():
     ap_.add_argument("--pure-steps", type=int, default=20)
     ap_.add_argument("--cpu-steps", type=int, default=2)
     ap_.add_argument("--no-cpu", action="store_true")
+    ap_.add_argument("--learned-steps", type=int, default=500,
+                     help="NVE steps of the learned-indicator comparison on the 1M-atom workload (0: skip)")
     ap_.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                      help="only copy a MIB-sized buffer 5 times (calibrates the HBM byte counters)")
     args = ap_.parse_args()
@@ -223,6 +320,13 @@ def main():
             tf = per * ns / (pr[0] * 1e-3) / 1e12
             ace_roof[tag] = dict(TFLOPs=tf, frac=tf / FP32_PEAK_TFLOPS, avg_ms=pr[0])
 
+    learned = None
+    if args.learned_steps > 0:
+        try:
+            learned = learned_comparison(args.learned_steps, 50)
+        except Exception as e:  # reported, not fatal to the headline line
+            learned = dict(error=repr(e))
+
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle, %d steps) ..." % args.cpu_steps)
@@ -246,6 +350,7 @@ def main():
         "hbm_kernels": hbm,
         "kernels": kernels,
         "cpu_baseline": cpu,
+        "learned_indicator": learned,
     }
     print(json.dumps(out), flush=True)
 
