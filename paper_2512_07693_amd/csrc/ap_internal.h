@@ -14,6 +14,10 @@ namespace ap {
 
 constexpr int kBlock = 256;      // threads per workgroup of the per-atom kernels (4 wavefronts)
 constexpr int kAceMaxValid = 128; // neighbours within the ACE cutoff held per site in LDS
+constexpr int kLanesPerAtom = 8;  // lanes that share one atom's neighbour loop in the per-atom passes
+constexpr int kForceLanes = 4;    // the same for the force assembly
+// workgroups of the force kernel, each writing one row of the per-block partial sums
+inline int force_blocks(int n) { return (int)(((long long)n * kForceLanes + kBlock - 1) / kBlock); }
 constexpr double kConv = 9648.533212;  // eV / (A u) in A / ps^2
 constexpr double kPi = 3.14159265358979323846;
 

@@ -138,7 +138,7 @@ static int evaluate(ap_ctx *c, int n, const double *box, const EvalFlags &f, con
     }
     {
         ProfScope p(c, "reduce");
-        launch_reduce(c, nblocks(n), E_tot, virial);
+        launch_reduce(c, force_blocks(n), E_tot, virial);
     }
     return hip_check(c, hipGetLastError(), "evaluate");
 }
@@ -301,7 +301,7 @@ int ap_ctx_create(ap_ctx **out, int n_max_atoms, int max_nbr, double skin, void 
     alloc(&c->mark, n, 4);
     alloc(&c->sid, n, 4);
     alloc(&c->blk_cnt, 2 * nb + 2, 4);
-    alloc(&c->partials, nb * 16, 8);
+    alloc(&c->partials, (size_t)std::max<long long>((long long)nb, force_blocks((int)n)) * 16, 8);
     alloc(&c->scalars, 16, 8);
     if (rc) {
         g_create_error = c->err;

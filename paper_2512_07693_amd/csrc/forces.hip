@@ -40,6 +40,17 @@ struct SwP {
     double d_lo, d_hi, r_w, r_w2, d0;
 };
 
+// SUB lanes per atom: lane `sub` takes slots sub, sub + SUB, ...; the lane partials are combined by
+// a fixed xor butterfly inside the group (the same pairs on every lane, so the sums are identical
+// and the result does not depend on scheduling).
+template <int SUB>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+    for (int m = 1; m < SUB; m <<= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+template <int SUB>
 __global__ __launch_bounds__(kBlock) void k_dens_desc(const double *__restrict__ pos, int n, double Lx, double Ly,
                                                       double Lz, EamP ep, SwP sp, int switching, double lam_const,
                                                       const double *__restrict__ lam_in,
@@ -49,28 +60,37 @@ __global__ __launch_bounds__(kBlock) void k_dens_desc(const double *__restrict__
                                                       double *__restrict__ wbar, double *__restrict__ dd,
                                                       double *__restrict__ lam, double *__restrict__ dlam,
                                                       double *__restrict__ Ep, double *__restrict__ Et, int *flags) {
-    const int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
-    const int cnt = ncount[i];
-    double z = 0.0, pair = 0.0, ws = 1.0, gs = switching ? g[i] : 0.0;  // self term of Eq. (6): w(0) = 1
-    for (int k = 0; k < cnt; k++) {
-        const int j = nidx[(size_t)k * n + i];
-        const double ux = min_image(pos[j] - xi, Lx), uy = min_image(pos[n + j] - yi, Ly),
-                     uz = min_image(pos[2 * n + j] - zi, Lz);
-        const double r2 = ux * ux + uy * uy + uz * uz;
-        if (r2 < ep.rc2) {
-            double zz, dz, ph, dph;
-            eam_pair(ep, sqrt(r2), zz, dz, ph, dph);
-            z += zz;
-            pair += ph;
-        }
-        if (switching && r2 < sp.r_w2) {
-            const double w = ftrans(sqrt(r2), sp.r_w - 1.0, sp.r_w);
-            ws += w;
-            gs += g[j] * w;
+    const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int i = t / SUB, sub = t - i * SUB;
+    double z = 0.0, pair = 0.0, ws = 0.0, gs = 0.0;
+    if (i < n) {
+        const double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
+        const int cnt = ncount[i];
+        for (int k = sub; k < cnt; k += SUB) {
+            const int j = nidx[(size_t)k * n + i];
+            const double ux = min_image(pos[j] - xi, Lx), uy = min_image(pos[n + j] - yi, Ly),
+                         uz = min_image(pos[2 * n + j] - zi, Lz);
+            const double r2 = ux * ux + uy * uy + uz * uz;
+            if (r2 < ep.rc2) {
+                double zz, dz, ph, dph;
+                eam_pair(ep, sqrt(r2), zz, dz, ph, dph);
+                z += zz;
+                pair += ph;
+            }
+            if (switching && r2 < sp.r_w2) {
+                const double w = ftrans(sqrt(r2), sp.r_w - 1.0, sp.r_w);
+                ws += w;
+                gs += g[j] * w;
+            }
         }
     }
+    z = group_sum<SUB>(z);
+    pair = group_sum<SUB>(pair);
+    ws = group_sum<SUB>(ws);
+    gs = group_sum<SUB>(gs);
+    if (i >= n || sub != 0) return;
+    ws += 1.0;  // self term of Eq. (6): w(0) = 1
+    if (switching) gs += g[i];
     double emb = 0.0, demb = 0.0;
     if (z > 0.0) {
         const double s = sqrt(z);
@@ -98,7 +118,8 @@ __global__ __launch_bounds__(kBlock) void k_dens_desc(const double *__restrict__
 
 void launch_dens_desc(ap_ctx *c, int n, const double *box, const EvalFlags &f, const double *lam_in) {
     const SwP sp{c->sw.d_lo, c->sw.d_hi, c->sw.r_w, c->sw.r_w * c->sw.r_w, c->sw.d0};
-    k_dens_desc<<<(n + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(
+    constexpr int SUB = kLanesPerAtom;
+    k_dens_desc<SUB><<<((size_t)n * SUB + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(
         c->pos, n, box[0], box[1], box[2], eamp(c->eam), sp, f.switching ? 1 : 0, f.lam_const, lam_in, c->nbr_cnt,
         c->nbr_idx, c->g, c->Ef, c->xip, c->wbar, c->d, c->lam, c->dlam, c->Ep, c->Et, c->d_flags);
 }
@@ -177,31 +198,36 @@ void launch_compact(ap_ctx *c, int n, const int32_t *subset, int n_subset) {
 // ------------------------------------------------------------------------------------------
 // W_j = sum_k E~_k w(r_kj), including k = j (w(0) = 1).
 // ------------------------------------------------------------------------------------------
+template <int SUB>
 __global__ __launch_bounds__(kBlock) void k_W(const double *__restrict__ pos, int n, double Lx, double Ly, double Lz,
                                               double r_w, const int32_t *__restrict__ ncount,
                                               const int32_t *__restrict__ nidx, const double *__restrict__ Et,
                                               double *__restrict__ W) {
-    const int j = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (j >= n) return;
-    const double xj = pos[j], yj = pos[n + j], zj = pos[2 * n + j];
-    double s = Et[j];
-    const double r_w2 = r_w * r_w;
-    const int cnt = ncount[j];
-    for (int q = 0; q < cnt; q++) {
-        const int k = nidx[(size_t)q * n + j];
-        const double e = Et[k];
-        if (e == 0.0) continue;
-        const double ux = min_image(pos[k] - xj, Lx), uy = min_image(pos[n + k] - yj, Ly),
-                     uz = min_image(pos[2 * n + k] - zj, Lz);
-        const double r2 = ux * ux + uy * uy + uz * uz;
-        if (r2 < r_w2) s += e * ftrans(sqrt(r2), r_w - 1.0, r_w);
+    const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int j = t / SUB, sub = t - j * SUB;
+    double s = 0.0;
+    if (j < n) {
+        const double xj = pos[j], yj = pos[n + j], zj = pos[2 * n + j];
+        const double r_w2 = r_w * r_w;
+        const int cnt = ncount[j];
+        for (int q = sub; q < cnt; q += SUB) {
+            const int k = nidx[(size_t)q * n + j];
+            const double e = Et[k];
+            if (e == 0.0) continue;
+            const double ux = min_image(pos[k] - xj, Lx), uy = min_image(pos[n + k] - yj, Ly),
+                         uz = min_image(pos[2 * n + k] - zj, Lz);
+            const double r2 = ux * ux + uy * uy + uz * uz;
+            if (r2 < r_w2) s += e * ftrans(sqrt(r2), r_w - 1.0, r_w);
+        }
     }
-    W[j] = s;
+    s = group_sum<SUB>(s);
+    if (j < n && sub == 0) W[j] = Et[j] + s;
 }
 
 void launch_W(ap_ctx *c, int n, const double *box) {
-    k_W<<<(n + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(c->pos, n, box[0], box[1], box[2], c->sw.r_w, c->nbr_cnt,
-                                                             c->nbr_idx, c->Et, c->W);
+    constexpr int SUB = kLanesPerAtom;
+    k_W<SUB><<<((size_t)n * SUB + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(
+        c->pos, n, box[0], box[1], box[2], c->sw.r_w, c->nbr_cnt, c->nbr_idx, c->Et, c->W);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -249,14 +275,16 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
     return s;
 }
 
-template <typename TF>
+template <typename TF, int SUB>
 __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
     __shared__ double sh[kBlock / 64];
     const int blk = xcd_block(blockIdx.x, gridDim.x);
-    const int i = blk * blockDim.x + threadIdx.x;
+    const int t = blk * blockDim.x + threadIdx.x;
+    const int i = t / SUB, sub = t - i * SUB;  // SUB lanes per atom, slots sub, sub + SUB, ...
     const int n = a.n;
     double F0 = 0, F1 = 0, F2 = 0, Ei = 0;
     double v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const bool gl = a.switching && a.grad_lambda;
     if (i < n) {
         const double xi = a.pos[i], yi = a.pos[n + i], zi = a.pos[2 * n + i];
         const double li = a.lam[i], xpi = a.xip[i];
@@ -264,11 +292,10 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
         const int si = a.sidx[i];
         const TF *fp = reinterpret_cast<const TF *>(a.fpair);
         const int cnt = a.ncount[i];
-        const bool gl = a.switching && a.grad_lambda;
         const int wi = (gl && a.ind_mlp) ? a.widx[i] : -1;
         const double *Lb = a.sbox ? a.sbox + 3 * a.sid[i] : a.L;  // own cell in a batch of cells
         const double Lx = Lb[0], Ly = Lb[1], Lz = Lb[2];
-        for (int k = 0; k < cnt; k++) {
+        for (int k = sub; k < cnt; k += SUB) {
             const int j = a.nidx[(size_t)k * n + i];
             const double ux = min_image(a.pos[j] - xi, Lx), uy = min_image(a.pos[n + j] - yi, Ly),
                          uz = min_image(a.pos[2 * n + j] - zi, Lz);
@@ -348,6 +375,13 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
                 }
             }
         }
+    }
+    F0 = group_sum<SUB>(F0);
+    F1 = group_sum<SUB>(F1);
+    F2 = group_sum<SUB>(F2);
+    if (i < n && sub == 0) {
+        const double xi = a.pos[i], yi = a.pos[n + i], zi = a.pos[2 * n + i];
+        const double li = a.lam[i];
         if (gl && !a.ind_mlp) {
             // CSP part (S24)-(S27): own list 2 W_i sum_l (r_il + r_i,opp(l)); reverse entries
             // -2 W_j (r_ji + r_j,opp(i)).
@@ -443,30 +477,33 @@ void launch_force(ap_ctx *c, int n, const double *box, const EvalFlags &f, doubl
     a.hpair = c->hpair;
     a.hrev = c->hrev;
     a.widx = c->widx;
-    const int nb = (n + kBlock - 1) / kBlock;
+    const int nb = force_blocks(n);
     if (a.fp32)
-        k_force<float><<<nb, kBlock, 0, c->stream>>>(a);
+        k_force<float, kForceLanes><<<nb, kBlock, 0, c->stream>>>(a);
     else
-        k_force<double><<<nb, kBlock, 0, c->stream>>>(a);
+        k_force<double, kForceLanes><<<nb, kBlock, 0, c->stream>>>(a);
 }
 
-// Sums the per-block partials [nb][16] (energy, virial) in a fixed order.
-__global__ __launch_bounds__(kBlock) void k_reduce_partials(const double *__restrict__ part, int nb, int ncol,
-                                                            double *__restrict__ out, int *flags) {
-    __shared__ double sh[kBlock / 64];
-    for (int col = 0; col < ncol; col++) {
-        double s = 0.0;
-        for (int b = threadIdx.x; b < nb; b += kBlock) s += part[(size_t)b * 16 + col];
-        s = block_sum(s, sh);
-        if (threadIdx.x == 0) {
-            out[col] = s;
-            if (!isfinite(s)) atomicOr(&flags[1], kErrNonFinite);
-        }
+// Sums the per-block partials [nb][16] (energy, virial) in a fixed order, one workgroup per column.
+__global__ __launch_bounds__(1024) void k_reduce_partials(const double *__restrict__ part, int nb,
+                                                          double *__restrict__ out, int *flags) {
+    __shared__ double sh[1024 / 64];
+    const int col = blockIdx.x;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[(size_t)b * 16 + col];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int q = 0; q < (int)(blockDim.x >> 6); q++) t += sh[q];
+        out[col] = t;
+        if (!isfinite(t)) atomicOr(&flags[1], kErrNonFinite);
     }
 }
 
 void launch_reduce(ap_ctx *c, int nblocks, double *E_tot, double *virial9) {
-    k_reduce_partials<<<1, kBlock, 0, c->stream>>>(c->partials, nblocks, 10, c->scalars, c->d_flags);
+    k_reduce_partials<<<10, 1024, 0, c->stream>>>(c->partials, nblocks, c->scalars, c->d_flags);
     if (E_tot) hipMemcpyAsync(E_tot, c->scalars, sizeof(double), hipMemcpyDeviceToDevice, c->stream);
     if (virial9) hipMemcpyAsync(virial9, c->scalars + 1, 9 * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
 }
