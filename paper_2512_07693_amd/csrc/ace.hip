@@ -79,6 +79,48 @@ __device__ __forceinline__ double block_sum_d(double v, double *sh) {
 // Couplings of one (l1, l2, L) block in its three orderings, staged in LDS per block.
 constexpr int kKapStage = 672;
 
+// Stages one block's couplings (three orderings, at most kKapStage entries) and its dense
+// coefficient block (NCE elements) in LDS: every load is issued before the first store, the block
+// with 16-byte vector loads, so the whole stage costs about one memory latency.
+template <typename T, int NCE>
+__device__ __forceinline__ void stage_block(int *kc, T *kv, T *Cs, const int *__restrict__ kidx,
+                                            const T *__restrict__ kval, const T *__restrict__ C, int k0, int k1) {
+    constexpr int VW = 16 / sizeof(T);
+    static_assert(NCE % VW == 0, "coefficient block size");
+    typedef T vec __attribute__((ext_vector_type(VW)));
+    constexpr int NV = NCE / VW, PER = (NV + kBlock - 1) / kBlock, KP = (kKapStage + kBlock - 1) / kBlock;
+    const int tid = threadIdx.x;
+    int ci[KP];
+    T cv[KP];
+    vec cc[PER];
+#pragma unroll
+    for (int u = 0; u < KP; u++) {
+        const int q = k0 + tid + u * kBlock;
+        if (q < k1) {
+            ci[u] = kidx[q];
+            cv[u] = kval[q];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+        const int q = tid + u * kBlock;
+        if (q < NV) cc[u] = reinterpret_cast<const vec *>(C)[q];
+    }
+#pragma unroll
+    for (int u = 0; u < KP; u++) {
+        const int q = k0 + tid + u * kBlock;
+        if (q < k1) {
+            kc[q - k0] = ci[u];
+            kv[q - k0] = cv[u];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+        const int q = tid + u * kBlock;
+        if (q < NV) reinterpret_cast<vec *>(Cs)[q] = cc[u];
+    }
+}
+
 template <typename T, int NMAX, int LMAX>
 __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
     constexpr int NLM = (LMAX + 1) * (LMAX + 1), NA = NMAX * NLM, NN = NMAX * NMAX, MM = 2 * LMAX + 1;
@@ -91,7 +133,7 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
     };
     struct BlkBuf {
         T P[MM * NN], Q[MM * NN];
-        T C[NN * NMAX];
+        alignas(16) T C[NN * NMAX];
         T kv[kKapStage];
         int kc[kKapStage];
     };
@@ -257,14 +299,7 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
             const int k0 = bk[4], k1 = bk[32 + n2m];
             // stage the block's couplings (host checks k1 - k0 <= kKapStage) and coefficients
             __syncthreads();
-            for (int q = k0 + tid; q < k1; q += kBlock) {
-                W.bb.kc[q - k0] = a.kidx[q];
-                W.bb.kv[q - k0] = kval[q];
-            }
-            {
-                const T *C = c3 + bk[3];
-                for (int q = tid; q < NN * NMAX; q += kBlock) W.bb.C[q] = C[q];
-            }
+            stage_block<T, NN * NMAX>(W.bb.kc, W.bb.kv, W.bb.C, a.kidx, kval, c3 + bk[3], k0, k1);
             __syncthreads();
             // P_M[n1][n2] = sum kappa A[n1][l1 m1] A[n2][l2 m2]; Q_M[n1][n2] = sum_n3 C A[n3][L M];
             // one thread per (M, n1) holds the twelve n2 in registers
