@@ -36,6 +36,8 @@ struct AceArgs {
     void *gbuf;   // [S][n_max * nlm] G = dE/dA
     void *fpair;  // [S][max_nbr][3]
     void *frev;   // [3][max_nbr][n]: f of pair (i, j) stored at slot k of i in j's list
+    const Rec4 *xl;  // [n] {x, y, z, lambda}
+    Rec4 *eb;        // [n] {xi', g, d + d0, E~}: E~ written here
     const void *c1, *bd, *c2, *c3, *kval;
     const int *kidx, *blk;
     int nblk;
@@ -176,9 +178,10 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
             double ux = 0, uy = 0, uz = 0, r2 = 0;
             if (slot < cnt) {
                 const int j = a.nidx[(size_t)slot * n + i];
-                ux = min_image(a.pos[j] - xi, Lx);
-                uy = min_image(a.pos[n + j] - yi, Ly);
-                uz = min_image(a.pos[2 * n + j] - zi, Lz);
+                const Rec4 pj = a.xl[j];
+                ux = min_image(pj.x - xi, Lx);
+                uy = min_image(pj.y - yi, Ly);
+                uz = min_image(pj.z - zi, Lz);
                 r2 = ux * ux + uy * uy + uz * uz;
                 valid = r2 < rc2;
             }
@@ -401,7 +404,9 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
         for (int o = tid; o < NA; o += kBlock) gout[o] = sG[o];
         if (tid == 0) {
             a.Ep[i] = E;
-            a.Et[i] = (E - a.Ef[i]) * a.dlam[i] / a.wbar[i];
+            const double et = (E - a.Ef[i]) * a.dlam[i] / a.wbar[i];
+            a.Et[i] = et;
+            a.eb[i].w = et;
             if (!isfinite(E)) atomicOr(&a.flags[1], kErrNonFinite);
         }
         __syncthreads();
@@ -428,8 +433,8 @@ __global__ __launch_bounds__(128) void k_ace_pairforce(AceArgs a) {
         T *fo = (T *)a.fpair + (size_t)s * a.max_nbr * 3;
         for (int slot = threadIdx.x; slot < cnt; slot += blockDim.x) {
             const int j = a.nidx[(size_t)slot * n + i];
-            const double ux = min_image(a.pos[j] - xi, Lx), uy = min_image(a.pos[n + j] - yi, Ly),
-                         uz = min_image(a.pos[2 * n + j] - zi, Lz);
+            const Rec4 pj = a.xl[j];
+            const double ux = min_image(pj.x - xi, Lx), uy = min_image(pj.y - yi, Ly), uz = min_image(pj.z - zi, Lz);
             const double r2 = ux * ux + uy * uy + uz * uz;
             T f0 = T(0), f1 = T(0), f2 = T(0);
             if (r2 < rc2) {
@@ -799,6 +804,8 @@ int launch_ace(ap_ctx *c, int n, const double *box, int grid_cap, const double *
     a.gbuf = c->gbuf;
     a.fpair = c->fpair;
     a.frev = c->frev;
+    a.xl = c->xl;
+    a.eb = c->eb;
     a.c1 = t.c1;
     a.bd = t.bd;
     a.c2 = t.c2;

@@ -90,6 +90,12 @@ struct AceTables {
 // L, l1, l2, c3 offset, 3 x 14 coupling start offsets (by M, m1, m2), order-3 gradient list range
 constexpr int kBlkInts = 48;
 
+// Per-atom record read by the neighbour loops: four doubles in one 32-byte aligned slot, so that a
+// gather of a neighbour's data is one pair of 16-byte loads instead of one load per quantity.
+struct alignas(32) Rec4 {
+    double x, y, z, w;
+};
+
 struct Geometry {
     double L[3];
     int nc[3];
@@ -132,6 +138,8 @@ struct ap_ctx {
     // neighbour list (slot-major)
     int32_t *nbr_cnt = nullptr, *nbr_idx = nullptr;
 
+    // gathered records: xg = {x, y, z, g}, xl = {x, y, z, lambda}, eb = {xi', g, d + d0, E~}
+    ap::Rec4 *xg = nullptr, *xl = nullptr, *eb = nullptr;
     // per-atom intermediates
     double *g = nullptr, *d = nullptr, *wbar = nullptr, *lam = nullptr, *dlam = nullptr;
     double *Ef = nullptr, *Ep = nullptr, *Et = nullptr, *W = nullptr, *xip = nullptr;

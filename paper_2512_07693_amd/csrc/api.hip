@@ -265,7 +265,7 @@ void ap_ctx_destroy(ap_ctx *c) {
     void *bufs[] = {c->csp_t, c->rev_start, c->rev_code, c->pos, c->pos_build, c->d_flags, c->cell_of, c->cell_cnt,
                     c->cell_start, c->cell_fill, c->cell_atoms, c->nbr_cnt, c->nbr_idx, c->g, c->d,
                     c->wbar, c->lam, c->dlam, c->Ef, c->Ep, c->Et, c->W, c->xip, c->sidx, c->slist, c->blk_cnt,
-                    c->mark, c->fpair, c->frev, c->gbuf, c->partials, c->scalars, c->sid, c->b_off, c->b_box, c->bval};
+                    c->mark, c->fpair, c->frev, c->xg, c->xl, c->eb, c->gbuf, c->partials, c->scalars, c->sid, c->b_off, c->b_box, c->bval};
     for (void *p : bufs) hipFree(p);
     delete c;
 }
@@ -296,6 +296,9 @@ int ap_ctx_create(ap_ctx **out, int n_max_atoms, int max_nbr, double skin, void 
     alloc(&c->nbr_idx, n * max_nbr, 4);
     double **per_atom[] = {&c->g, &c->d, &c->wbar, &c->lam, &c->dlam, &c->Ef, &c->Ep, &c->Et, &c->W, &c->xip};
     for (double **p : per_atom) alloc(p, n, 8);
+    alloc(&c->xg, n, sizeof(ap::Rec4));
+    alloc(&c->xl, n, sizeof(ap::Rec4));
+    alloc(&c->eb, n, sizeof(ap::Rec4));
     alloc(&c->sidx, n, 4);
     alloc(&c->slist, n, 4);
     alloc(&c->mark, n, 4);
@@ -492,11 +495,14 @@ int ap_mixed_energy_forces(ap_ctx *c, int n, const double *pos, const int32_t *s
     return rc;
 }
 
-__global__ void k_batch_fill(int n, const double *weight, double *lam, double *dlam, double *wbar, double *Ef,
-                             double *xip, double *Et) {
+__global__ void k_batch_fill(int n, const double *weight, const double *pos, double *lam, double *dlam, double *wbar,
+                             double *Ef, double *xip, double *Et, Rec4 *xl, Rec4 *eb) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    lam[i] = weight ? 1.0 - weight[i] : 0.0;  // the ACE weight of Eq. (4) is 1 - lambda
+    const double l = weight ? 1.0 - weight[i] : 0.0;  // the ACE weight of Eq. (4) is 1 - lambda
+    lam[i] = l;
+    xl[i] = Rec4{pos[i], pos[n + i], pos[2 * n + i], l};
+    eb[i] = Rec4{0.0, 0.0, 0.0, 0.0};
     dlam[i] = 0.0;
     wbar[i] = 1.0;
     Ef[i] = 0.0;
@@ -550,7 +556,8 @@ int ap_ace_batch_eval(ap_ctx *c, int n_struct, const int32_t *offsets, const dou
         rc = batch_lists(c, n, n_struct, c->b_off, c->b_box, pos, c->ace.rc);
     }
     if (rc) return rc;
-    k_batch_fill<<<nblocks(n), kBlock, 0, c->stream>>>(n, weight, c->lam, c->dlam, c->wbar, c->Ef, c->xip, c->Et);
+    k_batch_fill<<<nblocks(n), kBlock, 0, c->stream>>>(n, weight, c->pos, c->lam, c->dlam, c->wbar, c->Ef, c->xip,
+                                                       c->Et, c->xl, c->eb);
     {
         ProfScope p(c, "compact");
         launch_compact(c, n, nullptr, 0);

@@ -56,7 +56,9 @@ __global__ __launch_bounds__(kBlock) void k_dens_desc(const double *__restrict__
                                                       const double *__restrict__ lam_in,
                                                       const int32_t *__restrict__ ncount,
                                                       const int32_t *__restrict__ nidx, const double *__restrict__ g,
-                                                      double *__restrict__ Ef, double *__restrict__ xip,
+                                                      const Rec4 *__restrict__ xg, Rec4 *__restrict__ xl,
+                                                      Rec4 *__restrict__ eb, double *__restrict__ Ef,
+                                                      double *__restrict__ xip,
                                                       double *__restrict__ wbar, double *__restrict__ dd,
                                                       double *__restrict__ lam, double *__restrict__ dlam,
                                                       double *__restrict__ Ep, double *__restrict__ Et, int *flags) {
@@ -68,8 +70,19 @@ __global__ __launch_bounds__(kBlock) void k_dens_desc(const double *__restrict__
         const int cnt = ncount[i];
         for (int k = sub; k < cnt; k += SUB) {
             const int j = nidx[(size_t)k * n + i];
-            const double ux = min_image(pos[j] - xi, Lx), uy = min_image(pos[n + j] - yi, Ly),
-                         uz = min_image(pos[2 * n + j] - zi, Lz);
+            double px, py, pz, gj = 0.0;
+            if (switching) {  // {x, y, z, g} in one record
+                const Rec4 r = xg[j];
+                px = r.x;
+                py = r.y;
+                pz = r.z;
+                gj = r.w;
+            } else {
+                px = pos[j];
+                py = pos[n + j];
+                pz = pos[2 * n + j];
+            }
+            const double ux = min_image(px - xi, Lx), uy = min_image(py - yi, Ly), uz = min_image(pz - zi, Lz);
             const double r2 = ux * ux + uy * uy + uz * uz;
             if (r2 < ep.rc2) {
                 double zz, dz, ph, dph;
@@ -80,7 +93,7 @@ __global__ __launch_bounds__(kBlock) void k_dens_desc(const double *__restrict__
             if (switching && r2 < sp.r_w2) {
                 const double w = ftrans(sqrt(r2), sp.r_w - 1.0, sp.r_w);
                 ws += w;
-                gs += g[j] * w;
+                gs += gj * w;
             }
         }
     }
@@ -114,6 +127,8 @@ __global__ __launch_bounds__(kBlock) void k_dens_desc(const double *__restrict__
     dlam[i] = dl;
     Ep[i] = 0.0;
     Et[i] = 0.0;
+    xl[i] = Rec4{pos[i], pos[n + i], pos[2 * n + i], l};
+    eb[i] = Rec4{demb, switching ? g[i] : 0.0, d + sp.d0, 0.0};
 }
 
 void launch_dens_desc(ap_ctx *c, int n, const double *box, const EvalFlags &f, const double *lam_in) {
@@ -121,7 +136,8 @@ void launch_dens_desc(ap_ctx *c, int n, const double *box, const EvalFlags &f, c
     constexpr int SUB = kLanesPerAtom;
     k_dens_desc<SUB><<<((size_t)n * SUB + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(
         c->pos, n, box[0], box[1], box[2], eamp(c->eam), sp, f.switching ? 1 : 0, f.lam_const, lam_in, c->nbr_cnt,
-        c->nbr_idx, c->g, c->Ef, c->xip, c->wbar, c->d, c->lam, c->dlam, c->Ep, c->Et, c->d_flags);
+        c->nbr_idx, c->g, c->xg, c->xl, c->eb, c->Ef, c->xip, c->wbar, c->d, c->lam, c->dlam, c->Ep, c->Et,
+        c->d_flags);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -202,7 +218,7 @@ template <int SUB>
 __global__ __launch_bounds__(kBlock) void k_W(const double *__restrict__ pos, int n, double Lx, double Ly, double Lz,
                                               double r_w, const int32_t *__restrict__ ncount,
                                               const int32_t *__restrict__ nidx, const double *__restrict__ Et,
-                                              double *__restrict__ W) {
+                                              const Rec4 *__restrict__ xl, double *__restrict__ W) {
     const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const int j = t / SUB, sub = t - j * SUB;
     double s = 0.0;
@@ -214,8 +230,8 @@ __global__ __launch_bounds__(kBlock) void k_W(const double *__restrict__ pos, in
             const int k = nidx[(size_t)q * n + j];
             const double e = Et[k];
             if (e == 0.0) continue;
-            const double ux = min_image(pos[k] - xj, Lx), uy = min_image(pos[n + k] - yj, Ly),
-                         uz = min_image(pos[2 * n + k] - zj, Lz);
+            const Rec4 pk = xl[k];
+            const double ux = min_image(pk.x - xj, Lx), uy = min_image(pk.y - yj, Ly), uz = min_image(pk.z - zj, Lz);
             const double r2 = ux * ux + uy * uy + uz * uz;
             if (r2 < r_w2) s += e * ftrans(sqrt(r2), r_w - 1.0, r_w);
         }
@@ -227,7 +243,7 @@ __global__ __launch_bounds__(kBlock) void k_W(const double *__restrict__ pos, in
 void launch_W(ap_ctx *c, int n, const double *box) {
     constexpr int SUB = kLanesPerAtom;
     k_W<SUB><<<((size_t)n * SUB + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(
-        c->pos, n, box[0], box[1], box[2], c->sw.r_w, c->nbr_cnt, c->nbr_idx, c->Et, c->W);
+        c->pos, n, box[0], box[1], box[2], c->sw.r_w, c->nbr_cnt, c->nbr_idx, c->Et, c->xl, c->W);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -253,6 +269,7 @@ struct ForceArgs {
     int ind_mlp;                      // learned indicator: grad-g terms from hpair / hrev
     const float *hpair, *hrev;
     const int *widx;
+    const Rec4 *xl, *eb;  // neighbour records {x, y, z, lambda}, {xi', g, d + d0, E~}
 };
 
 template <typename TF>
@@ -297,18 +314,20 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
         const double Lx = Lb[0], Ly = Lb[1], Lz = Lb[2];
         for (int k = sub; k < cnt; k += SUB) {
             const int j = a.nidx[(size_t)k * n + i];
-            const double ux = min_image(a.pos[j] - xi, Lx), uy = min_image(a.pos[n + j] - yi, Ly),
-                         uz = min_image(a.pos[2 * n + j] - zi, Lz);
+            const Rec4 pj = a.xl[j];
+            Rec4 qj{0.0, 0.0, 0.0, 0.0};
+            if (a.eam_on || gl) qj = a.eb[j];
+            const double ux = min_image(pj.x - xi, Lx), uy = min_image(pj.y - yi, Ly), uz = min_image(pj.z - zi, Lz);
             const double r2 = ux * ux + uy * uy + uz * uz;
             const double r = sqrt(r2), ir = 1.0 / r;
             const double ex = ux * ir, ey = uy * ir, ez = uz * ir;
-            const double lj = a.lam[j];
+            const double lj = pj.w;
             if (a.eam_on && r2 < a.ep.rc2) {
                 double zz, dz, ph, dph;
                 eam_pair(a.ep, r, zz, dz, ph, dph);
                 // lambda_i f_ki - lambda_k f_ik, (S12), along rhat_ki = u / r
                 const double own = li * (xpi * dz + 0.5 * dph);
-                const double s = own + lj * (a.xip[j] * dz + 0.5 * dph);
+                const double s = own + lj * (qj.x * dz + 0.5 * dph);
                 F0 += s * ex;
                 F1 += s * ey;
                 F2 += s * ez;
@@ -321,8 +340,8 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
             if (gl && r2 < a.sp.r_w2) {
                 // weight part (S19)-(S21): F_i -= (s_i + s_k) u / r
                 const double dw = ftrans_d(r, a.sp.r_w - 1.0, a.sp.r_w);
-                const double s_i = Eti * (a.g[j] - di - a.sp.d0) * dw;
-                const double s_k = a.Et[j] * (gi - a.d[j] - a.sp.d0) * dw;
+                const double s_i = Eti * (qj.y - di - a.sp.d0) * dw;
+                const double s_k = qj.w * (gi - qj.z) * dw;
                 const double s = -(s_i + s_k);
                 F0 += s * ex;
                 F1 += s * ey;
@@ -477,6 +496,8 @@ void launch_force(ap_ctx *c, int n, const double *box, const EvalFlags &f, doubl
     a.hpair = c->hpair;
     a.hrev = c->hrev;
     a.widx = c->widx;
+    a.xl = c->xl;
+    a.eb = c->eb;
     const int nb = force_blocks(n);
     if (a.fp32)
         k_force<float, kForceLanes><<<nb, kBlock, 0, c->stream>>>(a);

@@ -474,7 +474,7 @@ int install_csp(ap_ctx *c, int n, int n_csp, const int32_t *list) {
 // g_i = sum over the stored pairs (a, b) of |u_ia + u_ib|^2.
 __global__ __launch_bounds__(kBlock) void k_csp_value(const double *__restrict__ pos, int n, double Lx, double Ly,
                                                       double Lz, int n_csp, const int32_t *__restrict__ lt,
-                                                      double *__restrict__ g) {
+                                                      double *__restrict__ g, Rec4 *__restrict__ xg) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
@@ -487,11 +487,12 @@ __global__ __launch_bounds__(kBlock) void k_csp_value(const double *__restrict__
         s += vx * vx + vy * vy + vz * vz;
     }
     g[i] = s;
+    xg[i] = Rec4{xi, yi, zi, s};
 }
 
 void launch_csp_value(ap_ctx *c, int n, const double *box) {
     k_csp_value<<<(n + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(c->pos, n, box[0], box[1], box[2], c->n_csp,
-                                                                     c->csp_t, c->g);
+                                                                     c->csp_t, c->g, c->xg);
 }
 
 }  // namespace ap

@@ -119,6 +119,8 @@ struct MlpArgs {
     int max_nbr;
     const float *P;
     double *g;        // [n] indicator (k_mlp_indicator)
+    Rec4 *xg;         // [n] {x, y, z, g}
+    const Rec4 *xl;   // [n] {x, y, z, lambda} (after the density pass)
     float *q;         // [n][16] features (feature mode)
     const double *W;  // [n]
     const int *wlist, *wcount;
@@ -142,6 +144,7 @@ __global__ __launch_bounds__(kBlock) void k_mlp_indicator(MlpArgs a, int feature
     const float g = softplus(o);
     if (!isfinite(g)) atomicOr(&a.flags[1], kErrNonFinite);
     a.g[i] = (double)g;
+    a.xg[i] = Rec4{a.pos[i], a.pos[a.n + i], a.pos[2 * a.n + i], (double)g};
 }
 
 // g and dg/dq of m samples (one thread per sample, the backward pass in registers)
@@ -228,8 +231,9 @@ __global__ __launch_bounds__(64) void k_mlp_gradg(MlpArgs a) {
         for (int t = 0; t < 48; t++) A[t] = 0.0f;
         for (int slot = lane; slot < cnt; slot += 64) {
             const int k = a.nidx[(size_t)slot * n + j];
-            const double ux = min_image(a.pos[k] - xj, a.L[0]), uy = min_image(a.pos[n + k] - yj, a.L[1]),
-                         uz = min_image(a.pos[2 * n + k] - zj, a.L[2]);
+            const Rec4 pk = a.xl[k];
+            const double ux = min_image(pk.x - xj, a.L[0]), uy = min_image(pk.y - yj, a.L[1]),
+                         uz = min_image(pk.z - zj, a.L[2]);
             const double r2 = ux * ux + uy * uy + uz * uz;
             if (!(r2 < rc2)) continue;
             const double rd = sqrt(r2);
@@ -300,8 +304,9 @@ __global__ __launch_bounds__(64) void k_mlp_gradg(MlpArgs a) {
         float* hp = a.hpair + (size_t)w * a.max_nbr * 3;
         for (int slot = lane; slot < cnt; slot += 64) {
             const int k = a.nidx[(size_t)slot * n + j];
-            const double ux = min_image(a.pos[k] - xj, a.L[0]), uy = min_image(a.pos[n + k] - yj, a.L[1]),
-                         uz = min_image(a.pos[2 * n + k] - zj, a.L[2]);
+            const Rec4 pk = a.xl[k];
+            const double ux = min_image(pk.x - xj, a.L[0]), uy = min_image(pk.y - yj, a.L[1]),
+                         uz = min_image(pk.z - zj, a.L[2]);
             const double r2 = ux * ux + uy * uy + uz * uz;
             float h0 = 0.0f, h1 = 0.0f, h2 = 0.0f;
             if (r2 < rc2) {
@@ -552,6 +557,8 @@ static MlpArgs mlp_args(ap_ctx *c, int n, const double *box) {
     a.max_nbr = c->max_nbr;
     a.P = c->mlp_p;
     a.g = c->g;
+    a.xg = c->xg;
+    a.xl = c->xl;
     a.q = nullptr;
     a.W = c->W;
     a.wlist = c->wlist;
