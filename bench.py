@@ -32,10 +32,10 @@ FP64_PEAK_TFLOPS = 78.6
 # same counters read for a 1 GiB device copy (fetch x2.0, write x1.0), with a digest of the kernel's source
 # file and the shared header at the time: a kernel whose source has changed reports null until re-measured.
 MEASURED_TRAFFIC = {
-    "ace_energy": (12.18e6, "ace.hip", "b59715d62fce6791"),
-    "force": (82.12e6, "forces.hip", "9173e5f4b91e6325"),
-    "dens_desc": (65.17e6, "forces.hip", "9173e5f4b91e6325"),
-    "W": (55.49e6, "forces.hip", "9173e5f4b91e6325"),
+    "ace_energy": (12.68e6, "ace.hip", "6375d9b637651ead"),
+    "force": (92.87e6, "forces.hip", "6ed845a6bd6a78b7"),
+    "dens_desc": (78.65e6, "forces.hip", "6ed845a6bd6a78b7"),
+    "W": (55.46e6, "forces.hip", "6ed845a6bd6a78b7"),
 }
 
 
