@@ -216,6 +216,46 @@ def learned_comparison(steps, warmup):
     return out
 
 
+def large_run(steps, warmup, pure_steps):
+    """The 2M-atom fcc penny-crack workload: the mixed loop against pure ACE on the same GPU, with the
+    per-kernel times and the memory-bound kernels' achieved bandwidth at a working set far above the
+    Infinity Cache."""
+    import torch
+    import synth
+    from paper_2512_07693_amd import ap
+    s = synth.build_system(5)
+    n, box = len(s["pos"]), s["box"]
+    pos0 = torch.tensor(np.ascontiguousarray(s["pos"].T), device="cuda")
+    vel0 = torch.tensor(np.ascontiguousarray(s["vel"].T), device="cuda")
+    ctx = ap.Context(n, max_nbr=160, skin=s["run"]["skin"])
+    ctx.set_potential(s["eam"], s["ace"], s["sw"])
+    ctx.csp_pairs_build(torch.tensor(np.ascontiguousarray(s["pos_ref"].T), device="cuda"), box, s["sw"]["n_csp"])
+    log("fcc penny crack: mixed %d + %d steps ..." % (warmup, steps))
+    ms, thermo, prof, _ = run_md(ctx, s, pos0, vel0, steps, warmup, 0)
+    nve = drift_fit(thermo, n, s["run"]["dt"])
+    cnt, _ = ctx.nblist_build(pos0, box, max(s["ace"]["rc"], s["sw"]["r_w"]) + s["run"]["skin"], 160)
+    nnb = float(cnt.double().mean().item())
+    ctx.close()
+    del ctx
+    hbm = {}
+    for k in ("dens_desc", "force", "W"):
+        if k in prof:
+            b = algorithmic_bytes(k, n, nnb, nve["x_mean"] * n, 54.0, s["sw"]["n_csp"])
+            hbm[k] = dict(avg_ms=prof[k][0], GBs=b / (prof[k][0] * 1e-3) / 1e9,
+                          frac=b / (prof[k][0] * 1e-3) / 1e9 / HBM_PEAK_GBS)
+    out = dict(workload=s["name"], n_atoms=n, value=n * steps / (ms / 1e3), ms_per_step=ms / steps, nve=nve,
+               kernels={k: round(v[0], 5) for k, v in prof.items()}, hbm_kernels=hbm)
+    if pure_steps > 0:
+        cp = ap.Context(n, max_nbr=160, skin=s["run"]["skin"])
+        cp.set_potential(s["eam"], s["ace"], s["sw"], lambda_mode=ap.AP_LAMBDA_PRECISE)
+        log("fcc penny crack: pure ACE %d steps ..." % pure_steps)
+        ms_p, _, _, _ = run_md(cp, s, pos0, vel0, pure_steps, 1, 0)
+        out["pure_ace"] = dict(value=n * pure_steps / (ms_p / 1e3), ms_per_step=ms_p / pure_steps)
+        out["speedup_vs_pure_ace"] = (ms_p / pure_steps) / (ms / steps)
+        cp.close()
+    return out
+
+
 def main():
     ap_ = argparse.ArgumentParser()
     ap_.add_argument("--gpus", type=int, default=1)
@@ -224,6 +264,8 @@ def main():
     ap_.add_argument("--pure-steps", type=int, default=20)
     ap_.add_argument("--cpu-steps", type=int, default=2)
     ap_.add_argument("--no-cpu", action="store_true")
+    ap_.add_argument("--large-steps", type=int, default=500,
+                     help="NVE steps of the 2M-atom fcc penny-crack run (0: skip)")
     ap_.add_argument("--learned-steps", type=int, default=500,
                      help="NVE steps of the learned-indicator comparison on the 1M-atom workload (0: skip)")
     ap_.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -320,6 +362,13 @@ def main():
             tf = per * ns / (pr[0] * 1e-3) / 1e12
             ace_roof[tag] = dict(TFLOPs=tf, frac=tf / FP32_PEAK_TFLOPS, avg_ms=pr[0])
 
+    large = None
+    if args.large_steps > 0:
+        try:
+            large = large_run(args.large_steps, 50, 3)
+        except Exception as e:  # reported, not fatal to the headline line
+            large = dict(error=repr(e))
+
     learned = None
     if args.learned_steps > 0:
         try:
@@ -351,6 +400,7 @@ def main():
         "kernels": kernels,
         "cpu_baseline": cpu,
         "learned_indicator": learned,
+        "large_fcc_penny_crack": large,
     }
     print(json.dumps(out), flush=True)
 

@@ -216,7 +216,7 @@ def size_defect(k, target_x):
     return {key: best[0]}
 
 
-TARGETS = {1: 0.05, 2: 0.01, 3: None, 4: None, 5: 0.01}
+TARGETS = {1: 0.05, 2: 0.01, 3: None, 4: None, 5: None}
 
 if __name__ == "__main__":
     O.set_threads(int(os.environ.get("ORA_THREADS", "0")))

@@ -32,10 +32,14 @@ _DATA = os.path.join(os.path.dirname(__file__), "data")
 # EAM draws: the Finnis-Sinclair form with tungsten-like nominal values (density cutoff 4.400224 A,
 # pair cutoff 3.25 A; bcc ground state at a = 3.165 A, cohesive energy 8.90 eV); A is drawn +-2 %
 # and beta in [0, 0.02], c0 is then solved for zero pressure at the workload's lattice constant.
+# fcc: a copper-like set of the same form (density cutoff between the 2nd and 3rd fcc shells, pair cutoff
+# between the 1st and 2nd), fitted by lattice sums at a = 3.61 A to E_coh 3.54 eV and positive C', C44 with
+# bcc 75 meV/atom above fcc.
 _EAM_NOMINAL = {
     "bcc": dict(A=1.896373, c1=-33.7665655, c2=6.2541999, r_rho=4.400224, r_phi=3.25),
+    "fcc": dict(A=1.27726, c1=-11.7176, c2=2.37883, r_rho=4.0, r_phi=3.4),
 }
-_EAM_RANGES = {"bcc": dict(A=(0.98, 1.02), beta=(0.0, 0.02))}
+_EAM_RANGES = {"bcc": dict(A=(0.98, 1.02), beta=(0.0, 0.02)), "fcc": dict(A=(0.98, 1.02), beta=(0.0, 0.02))}
 
 _RECIPES = {
     1: dict(lattice="bcc", a=3.16, nc=8, sigma=0.05, mass=183.84, n_max=8, l_max=4, caps={},
@@ -51,7 +55,7 @@ _RECIPES = {
             precision="fp32", r_w=6.5, skin=0.5, dt=1e-3, steps=1000, T=300.0,
             defect=dict(kind="vacancy_clusters", n=20)),
     5: dict(lattice="fcc", a=3.61, nc=80, sigma=0.05, mass=63.546, n_max=12, l_max=6, caps={},
-            precision="fp32", r_w=6.5, skin=0.15, dt=1e-3, steps=1000, T=300.0,
+            precision="fp32", r_w=6.5, skin=0.5, dt=1e-3, steps=1000, T=300.0,
             defect=dict(kind="penny_crack", radius=40.0, half_width=1.0)),
 }
 

@@ -210,3 +210,25 @@ def test_mixed_fp32_full_vacancy_clusters(oracle):
     _lt("E/N", abs(float(out["E"]) - want["E"]) / n, TOL_ENERGY)
     _lt("sum F", float(np.abs(F.sum(0)).max() / np.abs(F).max()), 1e-5)
     ctx.close()
+
+
+def test_mixed_fp32_full_fcc_penny_crack(oracle):
+    """The 2,047,229-atom fcc workload with a 4 nm penny crack (x ~ 0.39 %), FP32 ACE, 12-neighbour CSP: the CSP
+    list bit-exact and every atom's force against the oracle (S-skip mode)."""
+    import time
+    s = synth.build_system(5, with_velocities=False)
+    n = len(s["pos"])
+    _say("mixed fp32 fcc penny crack n=%d" % n)
+    ctx, csp = make_ctx(s, max_nbr=160)
+    out = ctx.mixed_energy_forces(to_dev(s["pos"]), s["box"])
+    csp_ref = oracle.csp_pairs(s["pos_ref"], s["box"], 12)
+    assert np.array_equal(csp.cpu().numpy(), csp_ref)
+    t = time.time()
+    want = oracle.evaluate(s, csp=csp_ref)
+    x = float((want["aux"]["lam"] < 1).mean())
+    _say("  oracle %.1f s, x = %.4f" % (time.time() - t, x))
+    F = soa_to_aos(out["F"])
+    _lt("F rms", force_err_rms(F, want["F"]), TOL_F32_FORCE)
+    _lt("E/N", abs(float(out["E"]) - want["E"]) / n, TOL_ENERGY)
+    _lt("sum F", float(np.abs(F.sum(0)).max() / np.abs(F).max()), 1e-5)
+    ctx.close()
