@@ -321,6 +321,36 @@ def main():
         value_p = n * args.pure_steps / (ms_p / 1e3)
         log("pure ACE: %.3f ms/step, %.3e atom-steps/s" % (ms_p / args.pure_steps, value_p))
 
+    # Eq. (1): per-atom times of the fast model, the precise model and the switching overhead, measured
+    # separately, predict the speedup of the mixed loop over pure ACE
+    eq1 = None
+    if ms_p:
+        ctx_f = ap.Context(n, max_nbr=128, skin=s["run"]["skin"])
+        ctx_f.set_potential(s["eam"], s["ace"], s["sw"], lambda_mode=ap.AP_LAMBDA_FAST)
+        log("pure EAM: 100 timed steps ...")
+        ms_f, _, prof_f, _ = run_md(ctx_f, s, pos0, vel0, 100, 5, 0)
+        ctx_f.close()
+        x = nve["x_mean"]
+        t_p, t_f, t_m = ms_p / args.pure_steps / n, ms_f / 100 / n, ms / args.steps / n
+        sw_ms = sum(prof[k][0] for k in ("csp_value", "compact", "W") if k in prof)
+        sw_ms += sum(max(0.0, prof[k][0] - prof_f.get(k, (0.0,))[0]) for k in ("dens_desc",))
+        t_d = sw_ms / n
+        # the force kernel of the mixed step also gathers the ACE pair terms and the grad-lambda terms:
+        # what it costs above the EAM-only force kernel counts with the overhead too
+        t_d += max(0.0, prof["force"][0] - prof_f["force"][0]) / n if "force" in prof and "force" in prof_f else 0.0
+        eq1 = dict(t_precise_ns=t_p * 1e6, t_fast_ns=t_f * 1e6, t_switch_ns=t_d * 1e6, x=x,
+                   s_measured=t_p / t_m,
+                   s_eq1_paper=t_p / (x * t_p + (1 - x) * t_f + t_d),
+                   s_eq1_all_eam=t_p / (x * t_p + t_f + t_d))
+        eq1["rel_err_all_eam"] = eq1["s_eq1_all_eam"] / eq1["s_measured"] - 1.0
+        # the precise model's cost per atom inside the mixed step (a few thousand atoms fill the GPU
+        # less well than the pure run's 128k): with it, Eq. (1) predicts the mixed step itself
+        t_pm = sum(prof[k][0] for k in ("ace_energy", "ace_pairforce") if k in prof) / max(1.0, x * n)
+        eq1["t_precise_in_mixed_ns"] = t_pm * 1e6
+        eq1["s_eq1_mixed_tp"] = t_p / (x * t_pm + t_f + t_d)
+        log("Eq. (1): measured %.2f, predicted %.2f (EAM on all atoms), %.2f (paper form)" %
+            (eq1["s_measured"], eq1["s_eq1_all_eam"], eq1["s_eq1_paper"]))
+
     # roofline of the dominant kernel of the mixed step
     cost = ctx.ace_cost()
     cnt_rc, _ = ctx.nblist_build(pos0, box, s["ace"]["rc"], 128)
@@ -393,6 +423,7 @@ def main():
         "pure_ace": {"value": value_p, "unit": "atom-steps/s", "steps": args.pure_steps,
                      "ms_per_step": ms_p / args.pure_steps if ms_p else None},
         "speedup_vs_pure_ace": value / value_p if value_p else None,
+        "speedup_eq1": eq1,
         "nve": nve,
         "roofline": roof,
         "ace_roofline": ace_roof,
