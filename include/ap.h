@@ -8,6 +8,7 @@
  *   lambda_i = f_trans(d_i, d_lo, d_hi)                                          Eq. (2), (S1)
  *   d_i   = sum_k g_k w(r_ik) / wbar_i - d0,  wbar_i = sum_k w(r_ik)              Eq. (6)
  *   g_i   = CSP_i^list (pairs fixed at set-up)                                   (B3)
+ *           or the learned indicator of ap_set_mlp (a network on invariant features)
  *   E^f   = EAM (B1) on every atom; E^p = ACE on the atoms with lambda_i < 1
  *   F_i   = -grad_i sum_k E_k, assembled in the pair form (A1)-(A2) with the EAM,
  *           ACE and grad-lambda contributions (S12), (S14), (S21), (S27)-(S29).
@@ -180,8 +181,9 @@ int ap_vv_step(ap_ctx *ctx, int n, double *pos, double *vel, double *F, double m
 
 /* Measurement support (not part of the method).
  * ap_set_profiling: on != 0 records HIP events on the context stream around every kernel group
- * (neighbour list, CSP value, density/descriptor, compaction, ACE energy, ACE pair gradients, W,
- * force assembly, reductions, velocity-Verlet kernels) and clears the accumulated times.
+ * (neighbour list, CSP value or learned indicator, density/descriptor, compaction, ACE energy, ACE
+ * pair gradients, W, learned-indicator gradients, force assembly, reductions, velocity-Verlet
+ * kernels) and clears the accumulated times.
  * ap_get_profile: returns the number of kernel groups m (or an error) and fills, for the first
  * max_entries of them, names [m][32] (NUL-terminated), the average duration in ms and the count of
  * timed launches (host arrays, each optional). */
