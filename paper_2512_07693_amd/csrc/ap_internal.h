@@ -137,6 +137,8 @@ struct ap_ctx {
 
     // neighbour list (slot-major)
     int32_t *nbr_cnt = nullptr, *nbr_idx = nullptr;
+    int32_t *nbr_short = nullptr;  // [n] the first nbr_short[i] slots hold the neighbours inside max(r_rho, r_phi) + skin
+    int *act = nullptr;            // [n] 1 if the atom or a neighbour has lambda < 1 (the force needs its full list)
 
     // gathered records: xg = {x, y, z, g}, xl = {x, y, z, lambda}, eb = {xi', g, d + d0, E~}
     ap::Rec4 *xg = nullptr, *xl = nullptr, *eb = nullptr;

@@ -265,7 +265,7 @@ void ap_ctx_destroy(ap_ctx *c) {
     void *bufs[] = {c->csp_t, c->rev_start, c->rev_code, c->pos, c->pos_build, c->d_flags, c->cell_of, c->cell_cnt,
                     c->cell_start, c->cell_fill, c->cell_atoms, c->nbr_cnt, c->nbr_idx, c->g, c->d,
                     c->wbar, c->lam, c->dlam, c->Ef, c->Ep, c->Et, c->W, c->xip, c->sidx, c->slist, c->blk_cnt,
-                    c->mark, c->fpair, c->frev, c->xg, c->xl, c->eb, c->gbuf, c->partials, c->scalars, c->sid, c->b_off, c->b_box, c->bval};
+                    c->mark, c->fpair, c->frev, c->xg, c->xl, c->eb, c->nbr_short, c->act, c->gbuf, c->partials, c->scalars, c->sid, c->b_off, c->b_box, c->bval};
     for (void *p : bufs) hipFree(p);
     delete c;
 }
@@ -294,6 +294,8 @@ int ap_ctx_create(ap_ctx **out, int n_max_atoms, int max_nbr, double skin, void 
     alloc(&c->cell_atoms, n, 4);
     alloc(&c->nbr_cnt, n, 4);
     alloc(&c->nbr_idx, n * max_nbr, 4);
+    alloc(&c->nbr_short, n, 4);
+    alloc(&c->act, n, 4);
     double **per_atom[] = {&c->g, &c->d, &c->wbar, &c->lam, &c->dlam, &c->Ef, &c->Ep, &c->Et, &c->W, &c->xip};
     for (double **p : per_atom) alloc(p, n, 8);
     alloc(&c->xg, n, sizeof(ap::Rec4));

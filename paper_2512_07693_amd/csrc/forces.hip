@@ -218,16 +218,19 @@ template <int SUB>
 __global__ __launch_bounds__(kBlock) void k_W(const double *__restrict__ pos, int n, double Lx, double Ly, double Lz,
                                               double r_w, const int32_t *__restrict__ ncount,
                                               const int32_t *__restrict__ nidx, const double *__restrict__ Et,
-                                              const Rec4 *__restrict__ xl, double *__restrict__ W) {
+                                              const Rec4 *__restrict__ xl, const double *__restrict__ lam,
+                                              double *__restrict__ W, int *__restrict__ act) {
     const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const int j = t / SUB, sub = t - j * SUB;
     double s = 0.0;
+    int near_s = 0;  // a neighbour with lambda < 1
     if (j < n) {
         const double xj = pos[j], yj = pos[n + j], zj = pos[2 * n + j];
         const double r_w2 = r_w * r_w;
         const int cnt = ncount[j];
         for (int q = sub; q < cnt; q += SUB) {
             const int k = nidx[(size_t)q * n + j];
+            near_s |= lam[k] < 1.0;
             const double e = Et[k];
             if (e == 0.0) continue;
             const Rec4 pk = xl[k];
@@ -237,13 +240,18 @@ __global__ __launch_bounds__(kBlock) void k_W(const double *__restrict__ pos, in
         }
     }
     s = group_sum<SUB>(s);
-    if (j < n && sub == 0) W[j] = Et[j] + s;
+#pragma unroll
+    for (int m = 1; m < SUB; m <<= 1) near_s |= __shfl_xor(near_s, m, 64);
+    if (j < n && sub == 0) {
+        W[j] = Et[j] + s;
+        act[j] = near_s | (lam[j] < 1.0);
+    }
 }
 
 void launch_W(ap_ctx *c, int n, const double *box) {
     constexpr int SUB = kLanesPerAtom;
     k_W<SUB><<<((size_t)n * SUB + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(
-        c->pos, n, box[0], box[1], box[2], c->sw.r_w, c->nbr_cnt, c->nbr_idx, c->Et, c->xl, c->W);
+        c->pos, n, box[0], box[1], box[2], c->sw.r_w, c->nbr_cnt, c->nbr_idx, c->Et, c->xl, c->lam, c->W, c->act);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -270,6 +278,10 @@ struct ForceArgs {
     const float *hpair, *hrev;
     const int *widx;
     const Rec4 *xl, *eb;  // neighbour records {x, y, z, lambda}, {xi', g, d + d0, E~}
+    // 0: every slot; 1: atoms with act == 0 stop after their nshort EAM-range slots; 2: all atoms do
+    int short_mode;
+    const int *act;
+    const int32_t *nshort;
 };
 
 template <typename TF>
@@ -308,7 +320,8 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
         const double Eti = a.Et[i], gi = a.g[i], di = a.d[i];
         const int si = a.sidx[i];
         const TF *fp = reinterpret_cast<const TF *>(a.fpair);
-        const int cnt = a.ncount[i];
+        // without a precise atom in reach only the EAM pairs contribute: those are the first nshort slots
+        const int cnt = (a.short_mode == 2 || (a.short_mode == 1 && !a.act[i])) ? a.nshort[i] : a.ncount[i];
         const int wi = (gl && a.ind_mlp) ? a.widx[i] : -1;
         const double *Lb = a.sbox ? a.sbox + 3 * a.sid[i] : a.L;  // own cell in a batch of cells
         const double Lx = Lb[0], Ly = Lb[1], Lz = Lb[2];
@@ -498,6 +511,11 @@ void launch_force(ap_ctx *c, int n, const double *box, const EvalFlags &f, doubl
     a.widx = c->widx;
     a.xl = c->xl;
     a.eb = c->eb;
+    a.act = c->act;
+    a.nshort = c->nbr_short;
+    a.short_mode = 0;
+    if (!sbox && f.switching && f.grad_lambda && c->sw.indicator == AP_IND_CSP) a.short_mode = 1;
+    if (!sbox && !f.switching && (!f.ace_forces || f.lam_const == 1.0)) a.short_mode = 2;
     const int nb = force_blocks(n);
     if (a.fp32)
         k_force<float, kForceLanes><<<nb, kBlock, 0, c->stream>>>(a);

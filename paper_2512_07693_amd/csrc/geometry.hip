@@ -125,10 +125,14 @@ __global__ void k_cell_sort(int ncell, const int *start, const int *cnt, int *at
     }
 }
 
+// One pass over the 27 cells: the neighbours inside r_short are written from the front of the slot
+// array, those between r_short and r_list from its back; the back part is then moved down behind
+// the front part (a forward copy, since it only moves to lower slots). ncount_short = the front part.
 __global__ __launch_bounds__(kBlock) void k_nbr_build(const double *__restrict__ pos, int n, Geometry g, double r2,
-                                                      const int *__restrict__ start, const int *__restrict__ cnt,
-                                                      const int *__restrict__ atoms, const int *__restrict__ cell_of,
-                                                      int max_nbr, int32_t *__restrict__ ncount,
+                                                      double rs2, const int *__restrict__ start,
+                                                      const int *__restrict__ cnt, const int *__restrict__ atoms,
+                                                      const int *__restrict__ cell_of, int max_nbr,
+                                                      int32_t *__restrict__ ncount, int32_t *__restrict__ ncount_short,
                                                       int32_t *__restrict__ nidx, double *__restrict__ pos_build,
                                                       int *flags) {
     if (flags[0] == 0) return;
@@ -137,7 +141,7 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(const double *__restrict__
     const double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
     const int cc = cell_of[i];
     const int c0 = cc / (g.nc[1] * g.nc[2]), c1 = (cc / g.nc[2]) % g.nc[1], c2 = cc % g.nc[2];
-    int k = 0;
+    int ks = 0, kl = 0;  // front (short) and back (long) counts
     const int rx = g.nc[0] > 1 ? 1 : 0, ry = g.nc[1] > 1 ? 1 : 0, rz = g.nc[2] > 1 ? 1 : 0;
     for (int dx = -rx; dx <= rx; dx++)
         for (int dy = -ry; dy <= ry; dy++)
@@ -154,12 +158,22 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(const double *__restrict__
                     double ux = min_image(pos[j] - xi, g.L[0]);
                     double uy = min_image(pos[n + j] - yi, g.L[1]);
                     double uz = min_image(pos[2 * n + j] - zi, g.L[2]);
-                    if (norm2_nofma(ux, uy, uz) < r2) {
-                        if (k < max_nbr) nidx[(size_t)k * n + i] = j;
-                        k++;
+                    const double d2 = norm2_nofma(ux, uy, uz);
+                    if (d2 < r2) {
+                        if (ks + kl < max_nbr) nidx[(size_t)(d2 < rs2 ? ks : max_nbr - 1 - kl) * n + i] = j;
+                        if (d2 < rs2)
+                            ks++;
+                        else
+                            kl++;
                     }
                 }
             }
+    int k = ks + kl;
+    if (k <= max_nbr) {
+        // the back part [max_nbr - kl, max_nbr) moves to [ks, ks + kl); ks <= max_nbr - kl
+        for (int t = 0; t < kl; t++) nidx[(size_t)(ks + t) * n + i] = nidx[(size_t)(max_nbr - kl + t) * n + i];
+    }
+    ncount_short[i] = ks < max_nbr ? ks : max_nbr;
     if (k > max_nbr) {
         atomicOr(&flags[1], kErrOverflow);
         k = max_nbr;
@@ -233,9 +247,10 @@ int ensure_list(ap_ctx *c, int n, const double *box, double r_list, bool force) 
     k_scan_excl<<<1, 1024, 0, c->stream>>>(c->cell_cnt, c->cell_start, g.ncell, nullptr, c->d_flags);
     k_cell_fill<<<nb, kBlock, 0, c->stream>>>(n, c->cell_of, c->cell_start, c->cell_fill, c->cell_atoms, c->d_flags);
     k_cell_sort<<<cb, kBlock, 0, c->stream>>>(g.ncell, c->cell_start, c->cell_cnt, c->cell_atoms, c->d_flags);
-    k_nbr_build<<<nb, kBlock, 0, c->stream>>>(c->pos, n, g, r_list * r_list, c->cell_start, c->cell_cnt,
-                                              c->cell_atoms, c->cell_of, c->max_nbr, c->nbr_cnt, c->nbr_idx,
-                                              c->pos_build, c->d_flags);
+    const double rs = std::max(c->eam.r_rho, c->eam.r_phi) + c->skin;  // the EAM pairs first
+    k_nbr_build<<<nb, kBlock, 0, c->stream>>>(c->pos, n, g, r_list * r_list, rs * rs, c->cell_start, c->cell_cnt,
+                                              c->cell_atoms, c->cell_of, c->max_nbr, c->nbr_cnt, c->nbr_short,
+                                              c->nbr_idx, c->pos_build, c->d_flags);
     k_commit<<<1, 1, 0, c->stream>>>(c->d_flags);
     c->list_r = r_list;
     c->list_n = n;
