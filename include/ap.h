@@ -181,9 +181,11 @@ int ap_vv_step(ap_ctx *ctx, int n, double *pos, double *vel, double *F, double m
 
 /* Measurement support (not part of the method).
  * ap_set_profiling: on != 0 records HIP events on the context stream around every kernel group
- * (neighbour list, CSP value or learned indicator, density/descriptor, compaction, ACE energy, ACE
- * pair gradients, W, learned-indicator gradients, force assembly, reductions, velocity-Verlet
- * kernels) and clears the accumulated times.
+ * (neighbour list, CSP value or learned indicator, density/descriptor, compaction, ACE basis, ACE
+ * energy, ACE pair gradients, W, learned-indicator gradients, force assembly, reductions,
+ * velocity-Verlet kernels) and clears the accumulated times. With on = k > 1, ap_vv_step times only
+ * the launches of every k-th step (steps 0, k, 2k, ...), so that the event records, which cost a few
+ * microseconds each, stay out of the other steps; the other entry points time every launch.
  * ap_get_profile: returns the number of kernel groups m (or an error) and fills, for the first
  * max_entries of them, names [m][32] (NUL-terminated), the average duration in ms and the count of
  * timed launches (host arrays, each optional). */

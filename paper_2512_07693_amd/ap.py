@@ -283,8 +283,9 @@ class Context:
                                      1 if fit_norm else 0, _ptr(params), hist))
         return np.array(hist[:epochs])
 
-    def set_profiling(self, on=True):
-        self._chk(lib().ap_set_profiling(self.h, 1 if on else 0))
+    def set_profiling(self, on=True, every=1):
+        """Times every kernel group (every > 1: in vv_step, only the launches of every every-th step)."""
+        self._chk(lib().ap_set_profiling(self.h, (max(1, int(every)) if on else 0)))
 
     def get_profile(self):
         """{kernel group: (average ms, launches)} from the HIP events recorded while profiling."""

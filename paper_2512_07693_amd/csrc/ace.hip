@@ -33,7 +33,8 @@ struct AceArgs {
     const double *dlam, *wbar, *Ef;
     const double *c1d, *bdd;
     double *Ep, *Et;
-    void *gbuf;   // [S][n_max * nlm] G = dE/dA
+    void *gbuf;   // [S][n_max * nlm] A, then G = dE/dA
+    double *s0buf;  // [S][n_max] FP64 sums of the radial channels over the neighbours
     void *fpair;  // [S][max_nbr][3]
     void *frev;   // [3][max_nbr][n]: f of pair (i, j) stored at slot k of i in j's list
     const Rec4 *xl;  // [n] {x, y, z, lambda}
@@ -123,37 +124,37 @@ __device__ __forceinline__ void stage_block(int *kc, T *kv, T *Cs, const int *__
     }
 }
 
+// Per S atom: the neighbours inside rc, their radial channels and harmonics, and the atomic basis
+// A[n][lm] (with the l = 0 sums also in FP64), written to the adjoint buffer and the sum buffer.
+// Four consecutive LDS elements (16-byte aligned) into registers.
+template <typename T>
+__device__ __forceinline__ void ld4(const T *p, T *o) {
+    if constexpr (sizeof(T) == 4) {
+        const float4 v = *reinterpret_cast<const float4 *>(p);
+        o[0] = v.x;
+        o[1] = v.y;
+        o[2] = v.z;
+        o[3] = v.w;
+    } else {
+        const double2 v0 = reinterpret_cast<const double2 *>(p)[0], v1 = reinterpret_cast<const double2 *>(p)[1];
+        o[0] = v0.x;
+        o[1] = v0.y;
+        o[2] = v1.x;
+        o[3] = v1.y;
+    }
+}
+
 template <typename T, int NMAX, int LMAX>
-__global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
-    constexpr int NLM = (LMAX + 1) * (LMAX + 1), NA = NMAX * NLM, NN = NMAX * NMAX, MM = 2 * LMAX + 1;
+__global__ __launch_bounds__(kBlock) void k_ace_basis(AceArgs a) {
+    constexpr int NLM = (LMAX + 1) * (LMAX + 1), NA = NMAX * NLM;
     constexpr int V = kAceMaxValid, CH = 64;  // neighbours kept per site; harmonics computed CH at a time
-    // neighbour phase and block phase share one LDS region
-    struct NbrBuf {
-        T R[CH * NMAX];
-        T Y[CH * NLM];
-        double R64[CH * NMAX];
-    };
-    struct BlkBuf {
-        T P[MM * NN], Q[MM * NN];
-        alignas(16) T C[NN * NMAX];
-        T kv[kKapStage];
-        int kc[kKapStage];
-    };
-    union Work {
-        NbrBuf nb;
-        BlkBuf bb;
-    };
-    __shared__ Work W;
-    __shared__ T sA[NA], sAt[NA], sG[NA];  // A[n][lm], its transpose At[lm][n], dE/dA[n][lm]
+    __shared__ T sR[CH * NMAX], sY[CH * NLM];
+    __shared__ double sR64[CH * NMAX];
+    __shared__ T sA[NA];
     __shared__ T sU[V * 4];
     __shared__ double sRd[V], sS[NMAX];
     __shared__ int sCnt[5];
-    __shared__ double sRed[kBlock / 64];
-    __shared__ T sEmbD;
-    __shared__ double sEmbD64;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const T *c1 = (const T *)a.c1, *bd = (const T *)a.bd, *c2 = (const T *)a.c2, *c3 = (const T *)a.c3;
-    const T *kval = (const T *)a.kval;
     const int n = a.n;
     const int S = *a.scount;
     const double rc2 = a.rc * a.rc;
@@ -166,10 +167,7 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
         const int cnt = a.ncount[i];
         if (tid == 0) sCnt[4] = 0;
         if (tid < NMAX) sS[tid] = 0.0;
-        for (int o = tid; o < NA; o += kBlock) {
-            sA[o] = T(0);
-            sG[o] = T(0);
-        }
+        for (int o = tid; o < NA; o += kBlock) sA[o] = T(0);
         __syncthreads();
         // ---- phase 0: neighbours inside rc, compacted in list order (ballot prefix) ----
         for (int base = 0; base < cnt; base += kBlock) {
@@ -210,42 +208,93 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
         // ---- phases 1-2: radial channels and harmonics, CH neighbours at a time, into A[n][lm] ----
         for (int v0 = 0; v0 < nv; v0 += CH) {
             const int nc = min(CH, nv - v0);
-            for (int v = tid; v < nc; v += kBlock) {
-                const int u = v0 + v;
+            // a lane per neighbour in each wavefront: wavefront 0 evaluates the radial channels,
+            // wavefronts 1-3 the harmonics of the orders m assigned to them (about 16 values each)
+            static_assert(kBlock == 4 * CH, "one neighbour per lane in each of four wavefronts");
+            if (lane < nc) {
+                const int v = lane, u = v0 + v;
                 const T r = sU[4 * u + 3], ir = T(1) / r;
-                T g[NMAX];
-                radial<T, NMAX>(r, rcT, g, (T *)nullptr);
+                if (wv == 0) {
+                    T g[NMAX];
+                    radial<T, NMAX>(r, rcT, g, (T *)nullptr);
 #pragma unroll
-                for (int q = 0; q < NMAX; q++) W.nb.R[v * NMAX + q] = g[q];
-                // the l = 0 radial sums feed the two-body and density terms, whose fitted
-                // coefficients cancel strongly: they are kept in FP64 whatever T is
-                double gd[NMAX];
-                radial<double, NMAX>(sRd[u], a.rc, gd, (double *)nullptr);
+                    for (int q = 0; q < NMAX; q++) sR[v * NMAX + q] = g[q];
+                    // the l = 0 radial sums feed the two-body and density terms, whose fitted
+                    // coefficients cancel strongly: they are kept in FP64 whatever T is
+                    double gd[NMAX];
+                    radial<double, NMAX>(sRd[u], a.rc, gd, (double *)nullptr);
 #pragma unroll
-                for (int q = 0; q < NMAX; q++) W.nb.R64[v * NMAX + q] = gd[q];
-                T Y[NLM];
-                ylm_real<T, LMAX>(sU[4 * u] * ir, sU[4 * u + 1] * ir, sU[4 * u + 2] * ir, Y);
+                    for (int q = 0; q < NMAX; q++) sR64[v * NMAX + q] = gd[q];
+                } else {
+                    const T x = sU[4 * u] * ir, y = sU[4 * u + 1] * ir, z = sU[4 * u + 2] * ir;
+                    T cm = T(1), sm = T(0);  // (x + iy)^m
 #pragma unroll
-                for (int q = 0; q < NLM; q++) W.nb.Y[v * NLM + q] = Y[q];
+                    for (int m = 0; m <= LMAX; m++) {
+                        if (m > 0) {
+                            const T c2 = x * cm - y * sm;
+                            sm = x * sm + y * cm;
+                            cm = c2;
+                        }
+                        // orders per wavefront: {1, 5}, {2, 4, 6}, {0, 3}
+                        const int owner = (m == 0 || m == 3) ? 3 : ((m == 1 || m == 5) ? 1 : 2);
+                        if (owner == wv) ylm_real_order<T, LMAX>(m, z, cm, sm, sY + v * NLM);
+                    }
+                }
             }
             __syncthreads();
             for (int o = tid; o < NA; o += kBlock) {
                 const int q = o / NLM, lm = o - q * NLM;
                 T acc = sA[o];
-                for (int v = 0; v < nc; v++) acc += W.nb.R[v * NMAX + q] * W.nb.Y[v * NLM + lm];
+                for (int v = 0; v < nc; v++) acc += sR[v * NMAX + q] * sY[v * NLM + lm];
                 sA[o] = acc;
             }
             if (tid < NMAX) {
                 double s0 = sS[tid];
-                for (int v = 0; v < nc; v++) s0 += W.nb.R64[v * NMAX + tid];
+                for (int v = 0; v < nc; v++) s0 += sR64[v * NMAX + tid];
                 sS[tid] = s0;
             }
             __syncthreads();
         }
+        T *aout = (T *)a.gbuf + (size_t)s * NA;
+        for (int o = tid; o < NA; o += kBlock) aout[o] = sA[o];
+        if (tid < NMAX) a.s0buf[(size_t)s * NMAX + tid] = sS[tid];
+        __syncthreads();
+    }
+}
+
+// Per S atom, from its basis A: orders 1-3 with the embedding, the site energy, and the adjoint
+// G = dE/dA (written over A in the adjoint buffer).
+template <typename T, int NMAX, int LMAX>
+__global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
+    constexpr int NLM = (LMAX + 1) * (LMAX + 1), NA = NMAX * NLM, NN = NMAX * NMAX, MM = 2 * LMAX + 1;
+    struct BlkBuf {
+        T P[MM * NN], Q[MM * NN];
+        alignas(16) T C[NN * NMAX];
+        T kv[kKapStage];
+        int kc[kKapStage];
+    };
+    __shared__ BlkBuf B;
+    __shared__ T sA[NA], sAt[NA], sG[NA];  // A[n][lm], its transpose At[lm][n], dE/dA[n][lm]
+    __shared__ double sS[NMAX];
+    __shared__ double sRed[kBlock / 64];
+    __shared__ T sEmbD;
+    __shared__ double sEmbD64;
+    const int tid = threadIdx.x;
+    const T *c1 = (const T *)a.c1, *bd = (const T *)a.bd, *c2 = (const T *)a.c2, *c3 = (const T *)a.c3;
+    const T *kval = (const T *)a.kval;
+    const int S = *a.scount;
+    for (int s = blockIdx.x; s < S; s += gridDim.x) {
+        const int i = a.slist[s];
+        const T *ain = (const T *)a.gbuf + (size_t)s * NA;
         for (int o = tid; o < NA; o += kBlock) {
             const int q = o / NLM, lm = o - q * NLM;
-            sAt[lm * NMAX + q] = sA[o];
+            const T v = ain[o];
+            sA[o] = v;
+            sAt[lm * NMAX + q] = v;
+            sG[o] = T(0);
         }
+        if (tid < NMAX) sS[tid] = a.s0buf[(size_t)s * NMAX + tid];
+        __syncthreads();
         // ---- phase 3a: orders 1 and 2, embedding ----
         double e = 0.0;
         if (tid == 0) {
@@ -302,7 +351,7 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
             const int k0 = bk[4], k1 = bk[32 + n2m];
             // stage the block's couplings (host checks k1 - k0 <= kKapStage) and coefficients
             __syncthreads();
-            stage_block<T, NN * NMAX>(W.bb.kc, W.bb.kv, W.bb.C, a.kidx, kval, c3 + bk[3], k0, k1);
+            stage_block<T, NN * NMAX>(B.kc, B.kv, B.C, a.kidx, kval, c3 + bk[3], k0, k1);
             __syncthreads();
             // P_M[n1][n2] = sum kappa A[n1][l1 m1] A[n2][l2 m2]; Q_M[n1][n2] = sum_n3 C A[n3][L M];
             // one thread per (M, n1) holds the twelve n2 in registers
@@ -313,10 +362,11 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
                 for (int q = 0; q < NMAX; q++) P[q] = T(0);
                 const int e0 = bk[4 + Mi] - k0, e1 = bk[4 + Mi + 1] - k0;
                 for (int q = e0; q < e1; q++) {
-                    const int code = W.bb.kc[q];
-                    const int m1 = (code & 255) - 8, m2 = ((code >> 8) & 255) - 8;
-                    const T a1 = W.bb.kv[q] * sA[n1 * NLM + b1 + m1];
-                    const T *a2 = sAt + (b2 + m2) * NMAX;
+                    // (l1 m1 column) | (l2 m2 row of At, in units of four) << 8: the row offset stays a
+                    // visible multiple of four, so its reads are 16-byte vector loads
+                    const int code = B.kc[q];
+                    const T a1 = B.kv[q] * sA[n1 * NLM + (code & 255)];
+                    const T *a2 = sAt + 4 * (code >> 8);
 #pragma unroll
                     for (int q2 = 0; q2 < NMAX; q2++) P[q2] += a1 * a2[q2];
                 }
@@ -324,7 +374,7 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
                 T A3[NMAX];
 #pragma unroll
                 for (int q = 0; q < NMAX; q++) A3[q] = a3[q];
-                const T *cr = W.bb.C + n1 * NN;
+                const T *cr = B.C + n1 * NN;
 #pragma unroll
                 for (int q2 = 0; q2 < NMAX; q2++) {
                     T acc = T(0);
@@ -332,13 +382,15 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
                     for (int q3 = 0; q3 < NMAX; q3++) acc += cr[q2 * NMAX + q3] * A3[q3];
                     Q[q2] = acc;
                 }
-                T *pp = W.bb.P + Mi * NN + n1 * NMAX, *qq = W.bb.Q + Mi * NN + n1 * NMAX;
+                T *pp = B.P + Mi * NN + n1 * NMAX, *qq = B.Q + Mi * NN + n1 * NMAX;
+                T ep = T(0);
 #pragma unroll
                 for (int q2 = 0; q2 < NMAX; q2++) {
-                    e += (double)(P[q2] * Q[q2]);
+                    ep += P[q2] * Q[q2];
                     pp[q2] = P[q2];
                     qq[q2] = Q[q2];
                 }
+                e += (double)ep;
             }
             __syncthreads();
             if (bout) {
@@ -347,18 +399,49 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
                     const int code = a.g3[2 * q];
                     const int rem = code & 0xffff, q3 = code >> 16;
                     T bsum = T(0);
-                    for (int Mi = 0; Mi < nM; Mi++) bsum += W.bb.P[Mi * NN + rem] * sA[q3 * NLM + bL + Mi - L];
+                    for (int Mi = 0; Mi < nM; Mi++) bsum += B.P[Mi * NN + rem] * sA[q3 * NLM + bL + Mi - L];
                     bout[a.g3[2 * q + 1]] = bsum;
                 }
             }
-            // dE/dA[n3][L M] = sum_{n1 n2} C[n1][n2][n3] P_M[n1][n2]
-            for (int w = tid; w < NMAX * nM; w += kBlock) {
-                const int q3 = w / nM, Mi = w - q3 * nM;
-                const T *pp = W.bb.P + Mi * NN;
-                T acc = T(0);
-#pragma unroll 12
-                for (int p = 0; p < NN; p++) acc += W.bb.C[p * NMAX + q3] * pp[p];
-                sG[q3 * NLM + bL + Mi - L] += acc;
+            // dE/dA[n3][L M] = sum_{n1 n2} C[n1][n2][n3] P_M[n1][n2]: a lane per (M, four n3, quarter of
+            // the (n1, n2) range) reading 16-byte rows of C; the quarters are combined by a fixed
+            // butterfly over four adjacent lanes
+            {
+                constexpr int NQ3 = NMAX / 4, PCH = NN / 4;
+                static_assert(NMAX % 4 == 0 && PCH % 4 == 0, "tile shape");
+                const int items = nM * NQ3 * 4;
+                for (int base = 0; base < items; base += kBlock) {
+                    const int w = base + tid, part = w & 3;
+                    T acc[4] = {T(0), T(0), T(0), T(0)};
+                    int col = -1, j4 = 0;
+                    if (w < items) {
+                        const int it = w >> 2, Mi = it / NQ3;
+                        j4 = (it - Mi * NQ3) * 4;
+                        col = bL + Mi - L;
+                        const T *pp = B.P + Mi * NN + part * PCH;
+                        const T *cc = B.C + part * PCH * NMAX + j4;
+                        for (int p = 0; p < PCH; p += 4) {
+                            T p4[4];
+                            ld4(pp + p, p4);
+#pragma unroll
+                            for (int u = 0; u < 4; u++) {
+                                T c4[4];
+                                ld4(cc + (p + u) * NMAX, c4);
+#pragma unroll
+                                for (int j = 0; j < 4; j++) acc[j] += c4[j] * p4[u];
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int j = 0; j < 4; j++) {
+                        acc[j] += __shfl_xor(acc[j], 1, 64);
+                        acc[j] += __shfl_xor(acc[j], 2, 64);
+                    }
+                    if (col >= 0 && part == 0) {
+#pragma unroll
+                        for (int j = 0; j < 4; j++) sG[(j4 + j) * NLM + col] += acc[j];
+                    }
+                }
             }
             __syncthreads();
             // dE/dA[n1][l1 m1] = sum kappa sum_n2 Q_M[n1][n2] A[n2][l2 m2]
@@ -367,14 +450,13 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
                 T acc = T(0);
                 const int e0 = bk[18 + i1] - k0, e1 = bk[18 + i1 + 1] - k0;
                 for (int q = e0; q < e1; q++) {
-                    const int code = W.bb.kc[q];
-                    const int m2 = ((code >> 8) & 255) - 8, Mi = ((code >> 16) & 255) - 8 + L;
-                    const T *qr = W.bb.Q + Mi * NN + q1 * NMAX;
-                    const T *a2 = sAt + (b2 + m2) * NMAX;
+                    const int code = B.kc[q];  // (Q_M offset) | (l2 m2 row of At) << 12, in units of four
+                    const T *qr = B.Q + 4 * (code & 4095) + q1 * NMAX;
+                    const T *a2 = sAt + 4 * (code >> 12);
                     T s2 = T(0);
 #pragma unroll
                     for (int q2 = 0; q2 < NMAX; q2++) s2 += qr[q2] * a2[q2];
-                    acc += W.bb.kv[q] * s2;
+                    acc += B.kv[q] * s2;
                 }
                 sG[q1 * NLM + b1 + i1 - l1] += acc;
             }
@@ -385,14 +467,13 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
                 T acc = T(0);
                 const int e0 = bk[32 + i2] - k0, e1 = bk[32 + i2 + 1] - k0;
                 for (int q = e0; q < e1; q++) {
-                    const int code = W.bb.kc[q];
-                    const int m1 = (code & 255) - 8, Mi = ((code >> 16) & 255) - 8 + L;
-                    const T *qc = W.bb.Q + Mi * NN + q2;
-                    const T *a1 = sAt + (b1 + m1) * NMAX;
+                    const int code = B.kc[q];  // (Q_M offset) | (l1 m1 row of At) << 12, in units of four
+                    const T *qc = B.Q + 4 * (code & 4095) + q2;
+                    const T *a1 = sAt + 4 * (code >> 12);
                     T s1 = T(0);
 #pragma unroll
                     for (int q1 = 0; q1 < NMAX; q1++) s1 += qc[q1 * NMAX] * a1[q1];
-                    acc += W.bb.kv[q] * s1;
+                    acc += B.kv[q] * s1;
                 }
                 sG[q2 * NLM + b2 + i2 - l2] += acc;
             }
@@ -416,7 +497,7 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
 template <typename T, int NMAX, int LMAX>
 __global__ __launch_bounds__(128) void k_ace_pairforce(AceArgs a) {
     constexpr int NLM = (LMAX + 1) * (LMAX + 1), NA = NMAX * NLM;
-    __shared__ T sG[NA];
+    __shared__ alignas(16) T sGt[NA];  // G transposed: [lm][n]
     const int n = a.n;
     const int S = *a.scount;
     const double rc2 = a.rc * a.rc;
@@ -424,7 +505,10 @@ __global__ __launch_bounds__(128) void k_ace_pairforce(AceArgs a) {
     for (int s = blockIdx.x; s < S; s += gridDim.x) {
         const int i = a.slist[s];
         const T *gin = (const T *)a.gbuf + (size_t)s * NA;
-        for (int o = threadIdx.x; o < NA; o += blockDim.x) sG[o] = gin[o];
+        for (int o = threadIdx.x; o < NA; o += blockDim.x) {
+            const int q = o / NLM, lm = o - q * NLM;
+            sGt[lm * NMAX + q] = gin[o];
+        }
         __syncthreads();
         double Lx, Ly, Lz;
         atom_box(a, i, Lx, Ly, Lz);
@@ -442,21 +526,69 @@ __global__ __launch_bounds__(128) void k_ace_pairforce(AceArgs a) {
                 const T x = (T)ux * ir, y = (T)uy * ir, z = (T)uz * ir;
                 T g[NMAX], dg[NMAX];
                 radial<T, NMAX>(r, rcT, g, dg);
-                T Y[NLM], dY[3 * NLM];
-                ylm_real_grad<T, LMAX>(x, y, z, ir, Y, dY);
-#pragma unroll
-                for (int lm = 0; lm < NLM; lm++) {
+                // f = sum_{n, lm} G_{n lm} [g_n'(r) Y_lm uhat + g_n(r) grad_u Y_lm], the harmonics and
+                // their gradients generated order by order (the recurrences of ylm_real_grad), so that
+                // only the current column of the Legendre recursion is held in registers
+                auto term = [&](int lm, T val, T px, T py, T pz) {
                     T sg = T(0), sdg = T(0);
 #pragma unroll
-                    for (int q = 0; q < NMAX; q++) {
-                        const T G = sG[q * NLM + lm];
-                        sg += G * g[q];
-                        sdg += G * dg[q];
+                    for (int q = 0; q < NMAX; q += 4) {
+                        T G4[4];
+                        ld4(sGt + lm * NMAX + q, G4);
+#pragma unroll
+                        for (int u = 0; u < 4; u++) {
+                            sg += G4[u] * g[q + u];
+                            sdg += G4[u] * dg[q + u];
+                        }
                     }
-                    const T t = sdg * Y[lm];
-                    f0 += t * x + sg * dY[3 * lm];
-                    f1 += t * y + sg * dY[3 * lm + 1];
-                    f2 += t * z + sg * dY[3 * lm + 2];
+                    const T rad = px * x + py * y + pz * z, t = sdg * val;
+                    f0 += t * x + sg * ((px - rad * x) * ir);
+                    f1 += t * y + sg * ((py - rad * y) * ir);
+                    f2 += t * z + sg * ((pz - rad * z) * ir);
+                    // keeps the scheduler from hoisting every coefficient load to the top
+                    __builtin_amdgcn_sched_barrier(0);
+                };
+                const T r2c = T(1.4142135623730951);
+                T cp = T(1), sp = T(0), cm = T(1), sm = T(0), dfm = T(1);  // (x + iy)^(m-1), (x + iy)^m
+#pragma unroll
+                for (int m = 0; m <= LMAX; m++) {
+                    if (m > 0) {
+                        cp = cm;
+                        sp = sm;
+                        const T c2 = x * cm - y * sm;
+                        sm = x * sm + y * cm;
+                        cm = c2;
+                        dfm *= T(2 * m - 1);
+                    }
+                    T q1 = T(0), q2 = T(0), d1 = T(0), d2 = T(0);  // Q_{l-1}^m, Q_{l-2}^m and their z-derivatives
+#pragma unroll
+                    for (int l = 0; l <= LMAX; l++) {
+                        if (l < m) continue;
+                        T q, dq;
+                        if (l == m) {
+                            q = dfm;
+                            dq = T(0);
+                        } else if (l == m + 1) {
+                            q = T(2 * m + 1) * z * q1;
+                            dq = T(2 * m + 1) * q1;
+                        } else {
+                            const T inv = T(1) / T(l - m);
+                            q = (T(2 * l - 1) * z * q1 - T(l + m - 1) * q2) * inv;
+                            dq = (T(2 * l - 1) * (q1 + z * d1) - T(l + m - 1) * d2) * inv;
+                        }
+                        q2 = q1;
+                        q1 = q;
+                        d2 = d1;
+                        d1 = dq;
+                        if (m == 0) {
+                            const T k = klm<T>(l, 0);
+                            term(l * l + l, k * q, T(0), T(0), k * dq);
+                        } else {
+                            const T k = r2c * klm<T>(l, m), kq = k * q, kd = k * dq, mm = T(m);
+                            term(l * l + l + m, kq * cm, kq * mm * cp, -kq * mm * sp, kd * cm);
+                            term(l * l + l - m, kq * sm, kq * mm * sp, kq * mm * cp, kd * sm);
+                        }
+                    }
                 }
             }
             fo[3 * slot] = f0;
@@ -695,7 +827,12 @@ int ace_setup(ap_ctx *c, const ap_ace_params *p) {
                 for (const Kap &e : k) {
                     const int kv = which == 0 ? e.M : (which == 1 ? e.m1 : e.m2);
                     if (kv != key) continue;
-                    kidx.push_back((e.m1 + 8) | ((e.m2 + 8) << 8) | ((e.M + 8) << 16));
+                    // LDS offsets the kernel uses directly: by M, the column l1 m1 of A and the row
+                    // l2 m2 of its transpose; by m1 (m2), the matrix Q_M and the row l2 m2 (l1 m1)
+                    const int c1 = B.l1 * B.l1 + B.l1 + e.m1, c2 = B.l2 * B.l2 + B.l2 + e.m2;
+                    // (offsets of rows and matrices in units of four elements; n_max is a multiple of 4)
+                    const int qm = (e.M + B.L) * N * N / 4, r1 = c1 * N / 4, r2 = c2 * N / 4;
+                    kidx.push_back(which == 0 ? c1 | (r2 << 8) : (which == 1 ? qm | (r2 << 12) : qm | (r1 << 12)));
                     kval.push_back(e.v);
                 }
             }
@@ -754,6 +891,10 @@ int ace_setup(ap_ctx *c, const ap_ace_params *p) {
 template <typename T, int NMAX, int LMAX>
 static void launch_t(ap_ctx *c, const AceArgs &a, int grid) {
     {
+        ProfScope p(c, "ace_basis");
+        k_ace_basis<T, NMAX, LMAX><<<grid, kBlock, 0, c->stream>>>(a);
+    }
+    {
         ProfScope p(c, "ace_energy");
         k_ace_energy<T, NMAX, LMAX><<<grid, kBlock, 0, c->stream>>>(a);
     }
@@ -802,6 +943,8 @@ int launch_ace(ap_ctx *c, int n, const double *box, int grid_cap, const double *
     a.Ep = c->Ep;
     a.Et = c->Et;
     a.gbuf = c->gbuf;
+    a.s0buf = (double *)((char *)c->gbuf + (size_t)c->n_cap * t.n_max * (t.l_max + 1) * (t.l_max + 1) *
+                                             (t.precision == AP_FP32 ? 4 : 8));
     a.fpair = c->fpair;
     a.frev = c->frev;
     a.xl = c->xl;

@@ -154,7 +154,7 @@ struct ap_ctx {
     size_t bval_bytes = 0;
     void *fpair = nullptr;       // [n_cap][max_nbr][3] ACE pair gradients (double or float)
     void *frev = nullptr;        // [3][max_nbr][n] the same pair terms at the neighbour's slot (k, j)
-    void *gbuf = nullptr;        // [n_cap][n_max * (l_max+1)^2] dE/dA of the S atoms
+    void *gbuf = nullptr;        // [n_cap][n_max * (l_max+1)^2] A, then dE/dA, of the S atoms; then [n_cap][n_max] FP64 sums
     size_t fpair_bytes = 0, gbuf_bytes = 0;
     // learned indicator
     bool have_mlp = false;
@@ -172,6 +172,8 @@ struct ap_ctx {
 
     // kernel timing with HIP events on the context stream (ap_set_profiling)
     bool prof_on = false;
+    int prof_every = 1;      // ap_vv_step times the launches of every prof_every-th step
+    bool prof_skip = false;  // set by ap_vv_step on the steps it does not time
     struct Pending {
         int label;
         hipEvent_t a, b;

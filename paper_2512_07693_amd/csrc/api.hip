@@ -33,7 +33,7 @@ static hipEvent_t take_event(ap_ctx *c) {
 }
 
 ProfScope::ProfScope(ap_ctx *ctx, const char *name) : c(ctx) {
-    if (!c->prof_on) return;
+    if (!c->prof_on || c->prof_skip) return;
     for (size_t q = 0; q < c->prof_names.size(); q++)
         if (c->prof_names[q] == name) label = (int)q;
     if (label < 0) {
@@ -341,7 +341,9 @@ int ap_set_potential(ap_ctx *c, const ap_eam_params *eam, const ap_ace_params *a
     if (rc) return rc;
     const int NA = ace->n_max * (ace->l_max + 1) * (ace->l_max + 1);
     const size_t es = ace->precision == AP_FP32 ? 4 : 8;
-    const size_t fb = (size_t)c->n_cap * c->max_nbr * 3 * es, gb = (size_t)c->n_cap * NA * es;
+    // adjoint buffer: A then dE/dA per S atom, followed by the FP64 radial sums per S atom
+    const size_t fb = (size_t)c->n_cap * c->max_nbr * 3 * es,
+                 gb = (size_t)c->n_cap * NA * es + (size_t)c->n_cap * ace->n_max * sizeof(double);
     if (fb != c->fpair_bytes) {
         (void)hipFree(c->fpair);
         c->fpair = nullptr;
@@ -585,6 +587,8 @@ int ap_set_profiling(ap_ctx *c, int on) {
     int rc = hip_check(c, hipStreamSynchronize(c->stream), "stream synchronize");
     prof_resolve(c);
     c->prof_on = on != 0;
+    c->prof_every = on > 1 ? on : 1;
+    c->prof_skip = false;
     c->prof_names.clear();
     c->prof_ms.clear();
     c->prof_cnt.clear();
@@ -637,18 +641,23 @@ int ap_vv_step(ap_ctx *c, int n, double *pos, double *vel, double *F, double mas
     // the list must describe these positions: rebuild on the first step of every call
     bool force = true;
     for (int s = 0; s < n_steps; s++) {
+        c->prof_skip = c->prof_every > 1 && s % c->prof_every != 0;
         {
             ProfScope p(c, "vv_first");
             k_vv_first<<<nb, kBlock, 0, c->stream>>>(pos, vel, F, c->pos, n, hdtm, dt, box->L[0], box->L[1],
                                                      box->L[2]);
         }
         rc = evaluate(c, n, box->L, f, nullptr, nullptr, 0, run_ace, nullptr, nullptr, F, nullptr, force);
-        if (rc) return rc;
+        if (rc) {
+            c->prof_skip = false;
+            return rc;
+        }
         force = false;
         ProfScope p(c, "vv_second");
         k_vv_second<<<nb, kBlock, 0, c->stream>>>(vel, F, n, hdtm, mass, c->partials);
         k_thermo<<<1, kBlock, 0, c->stream>>>(c->partials, nb, c->scalars, c->d_flags, thermo + (size_t)8 * s);
     }
+    c->prof_skip = false;
     rc = hip_check(c, hipGetLastError(), "vv");
     if (!rc) rc = sync_and_check(c);
     return rc;

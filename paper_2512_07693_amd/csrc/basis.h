@@ -51,6 +51,38 @@ __host__ __device__ __forceinline__ void ylm_real(T x, T y, T z, T *Y) {
     }
 }
 
+// The harmonics of one order m >= 0 at the unit vector (x, y, z), by the same recurrences as ylm_real:
+// Y_lm and Y_l,-m for l = m..LMAX, stored at index l*l + l +- m of Y; cm, sm = Re, Im (x + iy)^m.
+template <typename T, int LMAX>
+__device__ __forceinline__ void ylm_real_order(int m, T z, T cm, T sm, T *Y) {
+    T dfm = T(1);
+#pragma unroll
+    for (int k = 1; k <= LMAX; k++)
+        if (k <= m) dfm *= T(2 * k - 1);
+    const T r2 = T(1.4142135623730951);
+    T qm2 = T(0), qm1 = T(0);
+#pragma unroll
+    for (int l = 0; l <= LMAX; l++) {
+        if (l < m) continue;
+        T q;
+        if (l == m)
+            q = dfm;
+        else if (l == m + 1)
+            q = T(2 * m + 1) * z * qm1;
+        else
+            q = (T(2 * l - 1) * z * qm1 - T(l + m - 1) * qm2) / T(l - m);
+        qm2 = qm1;
+        qm1 = q;
+        if (m == 0) {
+            Y[l * l + l] = klm<T>(l, 0) * q;
+        } else {
+            const T k = r2 * klm<T>(l, m) * q;
+            Y[l * l + l + m] = k * cm;
+            Y[l * l + l - m] = k * sm;
+        }
+    }
+}
+
 // Same harmonics and their gradient with respect to the unnormalised vector u (|u| = r):
 // grad_u Y = (grad_p - (uhat . grad_p) uhat) / r for the polynomial p(x, y, z).
 template <typename T, int LMAX>
