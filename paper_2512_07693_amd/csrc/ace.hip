@@ -314,6 +314,9 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
             sEmbD64 = demb;
             e = a.E0 + e1 + emb;
         }
+        // the order-2 coefficients C2_l[n1][n2] staged in the (still unused) coefficient-block space
+        static_assert(LMAX + 1 <= NMAX, "order-2 table fits the block buffer");
+        for (int o = tid; o < (LMAX + 1) * NN; o += kBlock) B.C[o] = c2[o];
         __syncthreads();
         T *bout = a.bval ? (T *)a.bval + (size_t)s * a.bstride : nullptr;
         if (bout) {
@@ -333,7 +336,7 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
             const int q = o / NLM, lm = o - q * NLM;
             int l = 0;
             while ((l + 1) * (l + 1) <= lm) l++;
-            const T *row = c2 + ((size_t)l * NMAX + q) * NMAX;
+            const T *row = B.C + (l * NMAX + q) * NMAX;
             const T *acol = sAt + lm * NMAX;
             T g2 = T(0);
 #pragma unroll
@@ -460,6 +463,11 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
                 }
                 sG[q1 * NLM + b1 + i1 - l1] += acc;
             }
+            // Q_M transposed into the space of P (no longer read), for the row reads below
+            for (int o = tid; o < nM * NN; o += kBlock) {
+                const int Mi = o / NN, r = o - Mi * NN, n1 = r / NMAX, n2 = r - n1 * NMAX;
+                B.P[Mi * NN + n2 * NMAX + n1] = B.Q[o];
+            }
             __syncthreads();
             // dE/dA[n2][l2 m2] = sum kappa sum_n1 Q_M[n1][n2] A[n1][l1 m1]
             for (int w = tid; w < NMAX * n2m; w += kBlock) {
@@ -468,11 +476,11 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
                 const int e0 = bk[32 + i2] - k0, e1 = bk[32 + i2 + 1] - k0;
                 for (int q = e0; q < e1; q++) {
                     const int code = B.kc[q];  // (Q_M offset) | (l1 m1 row of At) << 12, in units of four
-                    const T *qc = B.Q + 4 * (code & 4095) + q2;
+                    const T *qt = B.P + 4 * (code & 4095) + q2 * NMAX;  // row n2 of Q_M transposed
                     const T *a1 = sAt + 4 * (code >> 12);
                     T s1 = T(0);
 #pragma unroll
-                    for (int q1 = 0; q1 < NMAX; q1++) s1 += qc[q1 * NMAX] * a1[q1];
+                    for (int q1 = 0; q1 < NMAX; q1++) s1 += qt[q1] * a1[q1];
                     acc += B.kv[q] * s1;
                 }
                 sG[q2 * NLM + b2 + i2 - l2] += acc;
