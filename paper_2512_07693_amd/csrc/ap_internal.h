@@ -142,6 +142,7 @@ struct ap_ctx {
 
     // gathered records: xg = {x, y, z, g}, xl = {x, y, z, lambda}, eb = {xi', g, d + d0, E~}
     ap::Rec4 *xg = nullptr, *xl = nullptr, *eb = nullptr;
+    ap::Rec4 *xe = nullptr;  // [n] {x, y, z, xi'}: the EAM-only force gather
     // per-atom intermediates
     double *g = nullptr, *d = nullptr, *wbar = nullptr, *lam = nullptr, *dlam = nullptr;
     double *Ef = nullptr, *Ep = nullptr, *Et = nullptr, *W = nullptr, *xip = nullptr;
@@ -233,8 +234,9 @@ struct EvalFlags {
 void launch_dens_desc(ap_ctx *c, int n, const double *box, const EvalFlags &f, const double *lam_in);
 void launch_compact(ap_ctx *c, int n, const int32_t *subset, int n_subset);
 void launch_W(ap_ctx *c, int n, const double *box);
+// uniform_lambda: lambda is the constant of f on every atom (no per-atom lambda from the caller)
 void launch_force(ap_ctx *c, int n, const double *box, const EvalFlags &f, double *E_atom, double *F,
-                  const double *sbox = nullptr);
+                  const double *sbox = nullptr, bool uniform_lambda = true);
 // per-structure sums of weight_i x (E^p_i, dE_i/dc, dE_i/db) over a batch (deterministic order)
 void launch_struct_reduce(ap_ctx *c, int n, int n_struct, const int *d_off, const double *weight, double *E_struct,
                           double *dEdc, double *dEdb);

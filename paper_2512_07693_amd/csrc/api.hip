@@ -134,7 +134,7 @@ static int evaluate(ap_ctx *c, int n, const double *box, const EvalFlags &f, con
     }
     {
         ProfScope p(c, "force");
-        launch_force(c, n, box, f, E_atom, F);
+        launch_force(c, n, box, f, E_atom, F, nullptr, lam_in == nullptr);
     }
     {
         ProfScope p(c, "reduce");
@@ -265,7 +265,7 @@ void ap_ctx_destroy(ap_ctx *c) {
     void *bufs[] = {c->csp_t, c->rev_start, c->rev_code, c->pos, c->pos_build, c->d_flags, c->cell_of, c->cell_cnt,
                     c->cell_start, c->cell_fill, c->cell_atoms, c->nbr_cnt, c->nbr_idx, c->g, c->d,
                     c->wbar, c->lam, c->dlam, c->Ef, c->Ep, c->Et, c->W, c->xip, c->sidx, c->slist, c->blk_cnt,
-                    c->mark, c->fpair, c->frev, c->xg, c->xl, c->eb, c->nbr_short, c->act, c->gbuf, c->partials, c->scalars, c->sid, c->b_off, c->b_box, c->bval};
+                    c->mark, c->fpair, c->frev, c->xg, c->xl, c->eb, c->xe, c->nbr_short, c->act, c->gbuf, c->partials, c->scalars, c->sid, c->b_off, c->b_box, c->bval};
     for (void *p : bufs) hipFree(p);
     delete c;
 }
@@ -301,6 +301,7 @@ int ap_ctx_create(ap_ctx **out, int n_max_atoms, int max_nbr, double skin, void 
     alloc(&c->xg, n, sizeof(ap::Rec4));
     alloc(&c->xl, n, sizeof(ap::Rec4));
     alloc(&c->eb, n, sizeof(ap::Rec4));
+    alloc(&c->xe, n, sizeof(ap::Rec4));
     alloc(&c->sidx, n, 4);
     alloc(&c->slist, n, 4);
     alloc(&c->mark, n, 4);

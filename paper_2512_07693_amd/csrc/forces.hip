@@ -57,7 +57,8 @@ __global__ __launch_bounds__(kBlock) void k_dens_desc(const double *__restrict__
                                                       const int32_t *__restrict__ ncount,
                                                       const int32_t *__restrict__ nidx, const double *__restrict__ g,
                                                       const Rec4 *__restrict__ xg, Rec4 *__restrict__ xl,
-                                                      Rec4 *__restrict__ eb, double *__restrict__ Ef,
+                                                      Rec4 *__restrict__ eb, Rec4 *__restrict__ xe,
+                                                      double *__restrict__ Ef,
                                                       double *__restrict__ xip,
                                                       double *__restrict__ wbar, double *__restrict__ dd,
                                                       double *__restrict__ lam, double *__restrict__ dlam,
@@ -129,6 +130,7 @@ __global__ __launch_bounds__(kBlock) void k_dens_desc(const double *__restrict__
     Et[i] = 0.0;
     xl[i] = Rec4{pos[i], pos[n + i], pos[2 * n + i], l};
     eb[i] = Rec4{demb, switching ? g[i] : 0.0, d + sp.d0, 0.0};
+    xe[i] = Rec4{pos[i], pos[n + i], pos[2 * n + i], demb};
 }
 
 void launch_dens_desc(ap_ctx *c, int n, const double *box, const EvalFlags &f, const double *lam_in) {
@@ -136,7 +138,7 @@ void launch_dens_desc(ap_ctx *c, int n, const double *box, const EvalFlags &f, c
     constexpr int SUB = kLanesPerAtom;
     k_dens_desc<SUB><<<((size_t)n * SUB + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(
         c->pos, n, box[0], box[1], box[2], eamp(c->eam), sp, f.switching ? 1 : 0, f.lam_const, lam_in, c->nbr_cnt,
-        c->nbr_idx, c->g, c->xg, c->xl, c->eb, c->Ef, c->xip, c->wbar, c->d, c->lam, c->dlam, c->Ep, c->Et,
+        c->nbr_idx, c->g, c->xg, c->xl, c->eb, c->xe, c->Ef, c->xip, c->wbar, c->d, c->lam, c->dlam, c->Ep, c->Et,
         c->d_flags);
 }
 
@@ -278,7 +280,9 @@ struct ForceArgs {
     const float *hpair, *hrev;
     const int *widx;
     const Rec4 *xl, *eb;  // neighbour records {x, y, z, lambda}, {xi', g, d + d0, E~}
-    // 0: every slot; 1: atoms with act == 0 stop after their nshort EAM-range slots; 2: all atoms do
+    const Rec4 *xe;       // {x, y, z, xi'} for the EAM-only gather
+    // 0: every slot; 1: atoms with act == 0 take the EAM-only gather over their nshort EAM-range
+    // slots; 2: all atoms do; 3: all atoms stop after nshort slots (per-atom lambda)
     int short_mode;
     const int *act;
     const int32_t *nshort;
@@ -320,11 +324,37 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
         const double Eti = a.Et[i], gi = a.g[i], di = a.d[i];
         const int si = a.sidx[i];
         const TF *fp = reinterpret_cast<const TF *>(a.fpair);
-        // without a precise atom in reach only the EAM pairs contribute: those are the first nshort slots
-        const int cnt = (a.short_mode == 2 || (a.short_mode == 1 && !a.act[i])) ? a.nshort[i] : a.ncount[i];
+        // without a precise atom in reach only the EAM pairs contribute: those are the first nshort
+        // slots, and every lambda in reach equals lambda_i (no switching, or lambda = 1 all around)
+        const bool eam_only = a.short_mode == 2 || (a.short_mode == 1 && !a.act[i]);
+        const int cnt = eam_only ? 0 : (a.short_mode == 3 ? a.nshort[i] : a.ncount[i]);
         const int wi = (gl && a.ind_mlp) ? a.widx[i] : -1;
         const double *Lb = a.sbox ? a.sbox + 3 * a.sid[i] : a.L;  // own cell in a batch of cells
         const double Lx = Lb[0], Ly = Lb[1], Lz = Lb[2];
+        if (eam_only && a.eam_on) {
+            // (S12) with lambda_k = lambda_i, from one {x, y, z, xi'} record per neighbour
+            const int cs = a.nshort[i];
+            for (int k = sub; k < cs; k += SUB) {
+                const Rec4 pj = a.xe[a.nidx[(size_t)k * n + i]];
+                const double ux = min_image(pj.x - xi, Lx), uy = min_image(pj.y - yi, Ly),
+                             uz = min_image(pj.z - zi, Lz);
+                const double r2 = ux * ux + uy * uy + uz * uz;
+                if (r2 < a.ep.rc2) {
+                    const double r = sqrt(r2), ir = 1.0 / r;
+                    double zz, dz, ph, dph;
+                    eam_pair(a.ep, r, zz, dz, ph, dph);
+                    const double own = li * (xpi * dz + 0.5 * dph);
+                    const double s = (own + li * (pj.w * dz + 0.5 * dph)) * ir;
+                    F0 += s * ux;
+                    F1 += s * uy;
+                    F2 += s * uz;
+                    const double t = -own * ir;
+                    v[0] += t * ux * ux; v[1] += t * ux * uy; v[2] += t * ux * uz;
+                    v[3] += t * uy * ux; v[4] += t * uy * uy; v[5] += t * uy * uz;
+                    v[6] += t * uz * ux; v[7] += t * uz * uy; v[8] += t * uz * uz;
+                }
+            }
+        }
         for (int k = sub; k < cnt; k += SUB) {
             const int j = a.nidx[(size_t)k * n + i];
             const Rec4 pj = a.xl[j];
@@ -469,7 +499,7 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
 }
 
 void launch_force(ap_ctx *c, int n, const double *box, const EvalFlags &f, double *E_atom, double *F,
-                  const double *sbox) {
+                  const double *sbox, bool uniform_lambda) {
     ForceArgs a;
     a.sbox = sbox;
     a.sid = c->sid;
@@ -511,11 +541,14 @@ void launch_force(ap_ctx *c, int n, const double *box, const EvalFlags &f, doubl
     a.widx = c->widx;
     a.xl = c->xl;
     a.eb = c->eb;
+    a.xe = c->xe;
     a.act = c->act;
     a.nshort = c->nbr_short;
+    // 0: full lists; 1: EAM-only gather for the atoms with no lambda < 1 in reach; 2: EAM-only gather
+    // for every atom; 3: EAM pairs only (short lists) with a per-atom lambda
     a.short_mode = 0;
     if (!sbox && f.switching && f.grad_lambda && c->sw.indicator == AP_IND_CSP) a.short_mode = 1;
-    if (!sbox && !f.switching && (!f.ace_forces || f.lam_const == 1.0)) a.short_mode = 2;
+    if (!sbox && !f.switching && (!f.ace_forces || f.lam_const == 1.0)) a.short_mode = uniform_lambda ? 2 : 3;
     const int nb = force_blocks(n);
     if (a.fp32)
         k_force<float, kForceLanes><<<nb, kBlock, 0, c->stream>>>(a);

@@ -86,6 +86,20 @@ def test_eam_matches_oracle(oracle, cfg1):
     ctx.close()
 
 
+def test_eam_per_atom_lambda_matches_oracle(cfg1, cfg1_oracle):
+    # ap_eam_eval with a per-atom lambda: E = sum_i lambda_i E^f_i and F = -grad E, which is the
+    # oracle's EAM-weighted force family (S12) of the mixed evaluation at the same lambda
+    _say("eam_eval cfg1 with per-atom lambda")
+    want = cfg1_oracle[1]
+    lam = want["aux"]["lam"]
+    assert ((lam > 0) & (lam < 1)).sum() > 0 and (lam == 1).sum() > 0
+    ctx, _ = make_ctx(cfg1, lambda_mode=1)
+    out = ctx.eam_eval(to_dev(cfg1["pos"]), cfg1["box"], lam=to_dev(lam))
+    _lt("F", force_err_max(soa_to_aos(out["F"]), want["fam"][0]), TOL_F64_FORCE)
+    _lt("E/N", abs(out["E"].item() - float((lam * want["aux"]["Ef"]).sum())) / len(lam), TOL_ENERGY)
+    ctx.close()
+
+
 def test_ace_fp64_matches_oracle(oracle, cfg1):
     _say("ace_eval cfg1 fp64 all atoms")
     ctx, _ = make_ctx(cfg1, lambda_mode=0)
