@@ -125,9 +125,13 @@ __global__ void k_cell_sort(int ncell, const int *start, const int *cnt, int *at
     }
 }
 
-// One pass over the 27 cells: the neighbours inside r_short are written from the front of the slot
-// array, those between r_short and r_list from its back; the back part is then moved down behind
-// the front part (a forward copy, since it only moves to lower slots). ncount_short = the front part.
+// One pass over the 27 cells per atom, SUB lanes per atom: in each round the SUB lanes test SUB
+// consecutive candidates of a cell, and a ballot gives every hit its rank among the group's hits, so
+// the slots come out in the order of a sequential scan (cells in a fixed order, atoms of a cell by
+// index). The neighbours inside r_short are written from the front of the slot array, those between
+// r_short and r_list from its back; the back part is then moved down behind the front part (a forward
+// copy: it only moves to lower slots). ncount_short = the front part.
+template <int SUB>
 __global__ __launch_bounds__(kBlock) void k_nbr_build(const double *__restrict__ pos, int n, Geometry g, double r2,
                                                       double rs2, const int *__restrict__ start,
                                                       const int *__restrict__ cnt, const int *__restrict__ atoms,
@@ -135,44 +139,76 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(const double *__restrict__
                                                       int32_t *__restrict__ ncount, int32_t *__restrict__ ncount_short,
                                                       int32_t *__restrict__ nidx, double *__restrict__ pos_build,
                                                       int *flags) {
+    static_assert(SUB > 0 && 64 % SUB == 0, "lane groups inside a wavefront");
     if (flags[0] == 0) return;
-    int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
-    const int cc = cell_of[i];
-    const int c0 = cc / (g.nc[1] * g.nc[2]), c1 = (cc / g.nc[2]) % g.nc[1], c2 = cc % g.nc[2];
-    int ks = 0, kl = 0;  // front (short) and back (long) counts
+    const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int i = t / SUB, sub = t - i * SUB;
+    const int gbase = (threadIdx.x & 63) - sub;  // first lane of this atom's group in the wavefront
+    const bool live = i < n;
+    double xi = 0.0, yi = 0.0, zi = 0.0;
+    int c0 = 0, c1 = 0, c2 = 0;
+    if (live) {
+        xi = pos[i];
+        yi = pos[n + i];
+        zi = pos[2 * n + i];
+        const int cc = cell_of[i];
+        c0 = cc / (g.nc[1] * g.nc[2]);
+        c1 = (cc / g.nc[2]) % g.nc[1];
+        c2 = cc % g.nc[2];
+    }
+    int ks = 0, kl = 0;  // front (short) and back (long) counts, the same on every lane of the group
     const int rx = g.nc[0] > 1 ? 1 : 0, ry = g.nc[1] > 1 ? 1 : 0, rz = g.nc[2] > 1 ? 1 : 0;
     for (int dx = -rx; dx <= rx; dx++)
         for (int dy = -ry; dy <= ry; dy++)
             for (int dz = -rz; dz <= rz; dz++) {
-                int x = c0 + dx, y = c1 + dy, z = c2 + dz;
-                x += x < 0 ? g.nc[0] : (x >= g.nc[0] ? -g.nc[0] : 0);
-                y += y < 0 ? g.nc[1] : (y >= g.nc[1] ? -g.nc[1] : 0);
-                z += z < 0 ? g.nc[2] : (z >= g.nc[2] ? -g.nc[2] : 0);
-                const int q = (x * g.nc[1] + y) * g.nc[2] + z;
-                const int b = start[q], e = b + cnt[q];
-                for (int p = b; p < e; p++) {
-                    const int j = atoms[p];
-                    if (j == i) continue;
-                    double ux = min_image(pos[j] - xi, g.L[0]);
-                    double uy = min_image(pos[n + j] - yi, g.L[1]);
-                    double uz = min_image(pos[2 * n + j] - zi, g.L[2]);
-                    const double d2 = norm2_nofma(ux, uy, uz);
-                    if (d2 < r2) {
-                        if (ks + kl < max_nbr) nidx[(size_t)(d2 < rs2 ? ks : max_nbr - 1 - kl) * n + i] = j;
-                        if (d2 < rs2)
-                            ks++;
-                        else
-                            kl++;
+                int b = 0, e = 0;
+                if (live) {
+                    int x = c0 + dx, y = c1 + dy, z = c2 + dz;
+                    x += x < 0 ? g.nc[0] : (x >= g.nc[0] ? -g.nc[0] : 0);
+                    y += y < 0 ? g.nc[1] : (y >= g.nc[1] ? -g.nc[1] : 0);
+                    z += z < 0 ? g.nc[2] : (z >= g.nc[2] ? -g.nc[2] : 0);
+                    const int q = (x * g.nc[1] + y) * g.nc[2] + z;
+                    b = start[q];
+                    e = b + cnt[q];
+                }
+                // every lane of a group runs the same rounds (b and e are the group's)
+                for (int p0 = b; p0 < e; p0 += SUB) {
+                    const int p = p0 + sub;
+                    bool hs = false, hl = false;
+                    int j = -1;
+                    if (p < e) {
+                        j = atoms[p];
+                        if (j != i) {
+                            const double ux = min_image(pos[j] - xi, g.L[0]);
+                            const double uy = min_image(pos[n + j] - yi, g.L[1]);
+                            const double uz = min_image(pos[2 * n + j] - zi, g.L[2]);
+                            const double d2 = norm2_nofma(ux, uy, uz);
+                            hs = d2 < r2 && d2 < rs2;
+                            hl = d2 < r2 && !(d2 < rs2);
+                        }
                     }
+                    const unsigned long long ms = __ballot(hs), ml = __ballot(hl);
+                    const unsigned long long grp = (SUB == 64 ? ~0ull : ((1ull << SUB) - 1ull)) << gbase;
+                    const unsigned long long below = ((1ull << (threadIdx.x & 63)) - 1ull) & grp;
+                    // hits before this one in scan order: the front and back parts never meet
+                    const bool room = ks + kl + __popcll((ms | ml) & below) < max_nbr;
+                    if (hs && room) nidx[(size_t)(ks + __popcll(ms & below)) * n + i] = j;
+                    if (hl && room) nidx[(size_t)(max_nbr - 1 - kl - __popcll(ml & below)) * n + i] = j;
+                    ks += __popcll(ms & grp);
+                    kl += __popcll(ml & grp);
                 }
             }
+    if (!live) return;
     int k = ks + kl;
     if (k <= max_nbr) {
-        // the back part [max_nbr - kl, max_nbr) moves to [ks, ks + kl); ks <= max_nbr - kl
-        for (int t = 0; t < kl; t++) nidx[(size_t)(ks + t) * n + i] = nidx[(size_t)(max_nbr - kl + t) * n + i];
+        // the back part [max_nbr - kl, max_nbr) moves down to [ks, ks + kl), ks <= max_nbr - kl, in
+        // increasing slot order: a store only hits a slot read in the same round or an earlier one
+        for (int t = sub; t < kl; t += SUB) {
+            const int v = nidx[(size_t)(max_nbr - kl + t) * n + i];
+            nidx[(size_t)(ks + t) * n + i] = v;
+        }
     }
+    if (sub != 0) return;
     ncount_short[i] = ks < max_nbr ? ks : max_nbr;
     if (k > max_nbr) {
         atomicOr(&flags[1], kErrOverflow);
@@ -248,7 +284,9 @@ int ensure_list(ap_ctx *c, int n, const double *box, double r_list, bool force) 
     k_cell_fill<<<nb, kBlock, 0, c->stream>>>(n, c->cell_of, c->cell_start, c->cell_fill, c->cell_atoms, c->d_flags);
     k_cell_sort<<<cb, kBlock, 0, c->stream>>>(g.ncell, c->cell_start, c->cell_cnt, c->cell_atoms, c->d_flags);
     const double rs = std::max(c->eam.r_rho, c->eam.r_phi) + c->skin;  // the EAM pairs first
-    k_nbr_build<<<nb, kBlock, 0, c->stream>>>(c->pos, n, g, r_list * r_list, rs * rs, c->cell_start, c->cell_cnt,
+    constexpr int SUB = 8;  // lanes per atom in the list build
+    k_nbr_build<SUB><<<(int)(((size_t)n * SUB + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(
+        c->pos, n, g, r_list * r_list, rs * rs, c->cell_start, c->cell_cnt,
                                               c->cell_atoms, c->cell_of, c->max_nbr, c->nbr_cnt, c->nbr_short,
                                               c->nbr_idx, c->pos_build, c->d_flags);
     k_commit<<<1, 1, 0, c->stream>>>(c->d_flags);
