@@ -132,6 +132,7 @@ struct ap_ctx {
 
     // cell list
     int ncell_cap = 0;
+    int ncell_cur = 0;  // cells of the geometry of the last list build
     int *cell_of = nullptr, *cell_cnt = nullptr, *cell_start = nullptr, *cell_fill = nullptr, *cell_atoms = nullptr;
     int *scan_tmp = nullptr;
 
@@ -203,7 +204,11 @@ struct ProfScope {
 void prof_resolve(ap_ctx *c);
 
 // geometry.hip
-int ensure_list(ap_ctx *c, int n, const double *box, double r_list, bool force);
+// skin_checked: the caller's kernel already ran the skin check on these positions and cleared the
+// cell counts; commit = false: the caller's next kernel commits the rebuild flag (flags[3] = flags[0],
+// flags[0] = 0) instead of a kernel of its own
+int ensure_list(ap_ctx *c, int n, const double *box, double r_list, bool force, bool skin_checked = false,
+                bool commit = true);
 int prepare_positions(ap_ctx *c, int n, const double *pos_in, const double *box);
 void launch_csp_value(ap_ctx *c, int n, const double *box);
 int build_csp_pairs(ap_ctx *c, int n, const double *box, int n_csp, int32_t *out);

@@ -95,11 +95,12 @@ static int nblocks(int n) { return (n + kBlock - 1) / kBlock; }
 // The force evaluation on the positions already in c->pos.
 static int evaluate(ap_ctx *c, int n, const double *box, const EvalFlags &f, const double *lam_in,
                     const int32_t *subset, int n_subset, bool run_ace, double *E_tot, double *E_atom, double *F,
-                    double *virial, bool force_list) {
+                    double *virial, bool force_list, bool skin_checked = false) {
     int rc;
     {
         ProfScope p(c, "nbr_list");
-        rc = ensure_list(c, n, box, list_radius(c, f.switching), force_list);
+        // the rebuild flag is committed by the density pass below
+        rc = ensure_list(c, n, box, list_radius(c, f.switching), force_list, skin_checked, false);
     }
     if (rc) return rc;
     if (f.switching && c->sw.indicator == AP_IND_MLP) {
@@ -175,11 +176,20 @@ static EvalFlags mixed_flags(const ap_ctx *c) {
 // ------------------------------------------------------------------------------------------
 // Velocity Verlet kernels
 // ------------------------------------------------------------------------------------------
+// First half kick and drift. Also the neighbour-list work of the step's start: the skin check of the
+// new positions (flags[0] |= 1 when an atom moved more than skin/2 since the last build) and zeroed
+// cell counts for a rebuild (the geometry is that of the last build; a new one is cleared anew).
 __global__ void k_vv_first(double *pos, double *vel, const double *F, double *ipos, int n, double hdtm, double dt,
-                           double Lx, double Ly, double Lz) {
+                           double Lx, double Ly, double Lz, const double *__restrict__ pos_build, double half_skin2,
+                           int *flags, int *cell_cnt, int *cell_fill, int ncell) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int q = i; q < ncell; q += gridDim.x * blockDim.x) {
+        cell_cnt[q] = 0;
+        cell_fill[q] = 0;
+    }
     if (i >= n) return;
     const double L[3] = {Lx, Ly, Lz};
+    double u[3];
     for (int a = 0; a < 3; a++) {
         const size_t o = (size_t)a * n + i;
         const double v = vel[o] + hdtm * F[o];
@@ -187,7 +197,9 @@ __global__ void k_vv_first(double *pos, double *vel, const double *F, double *ip
         const double x = wrap_coord(pos[o] + dt * v, L[a]);
         pos[o] = x;
         ipos[o] = x;
+        u[a] = min_image(x - pos_build[o], L[a]);
     }
+    if (u[0] * u[0] + u[1] * u[1] + u[2] * u[2] > half_skin2) atomicOr(&flags[0], 1);
 }
 
 __global__ __launch_bounds__(kBlock) void k_vv_second(double *vel, const double *F, int n, double hdtm, double mass,
@@ -645,10 +657,12 @@ int ap_vv_step(ap_ctx *c, int n, double *pos, double *vel, double *F, double mas
         c->prof_skip = c->prof_every > 1 && s % c->prof_every != 0;
         {
             ProfScope p(c, "vv_first");
+            // (the first step rebuilds the list anyway: its check and clearing are redone there)
             k_vv_first<<<nb, kBlock, 0, c->stream>>>(pos, vel, F, c->pos, n, hdtm, dt, box->L[0], box->L[1],
-                                                     box->L[2]);
+                                                     box->L[2], c->pos_build, 0.25 * c->skin * c->skin, c->d_flags,
+                                                     c->cell_cnt, c->cell_fill, force ? 0 : c->ncell_cur);
         }
-        rc = evaluate(c, n, box->L, f, nullptr, nullptr, 0, run_ace, nullptr, nullptr, F, nullptr, force);
+        rc = evaluate(c, n, box->L, f, nullptr, nullptr, 0, run_ace, nullptr, nullptr, F, nullptr, force, !force);
         if (rc) {
             c->prof_skip = false;
             return rc;

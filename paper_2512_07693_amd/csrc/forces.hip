@@ -63,6 +63,11 @@ __global__ __launch_bounds__(kBlock) void k_dens_desc(const double *__restrict__
                                                       double *__restrict__ wbar, double *__restrict__ dd,
                                                       double *__restrict__ lam, double *__restrict__ dlam,
                                                       double *__restrict__ Ep, double *__restrict__ Et, int *flags) {
+    // commit of the neighbour-list rebuild flag, after every list kernel of this evaluation
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        flags[3] = flags[0];
+        flags[0] = 0;
+    }
     const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const int i = t / SUB, sub = t - i * SUB;
     double z = 0.0, pair = 0.0, ws = 0.0, gs = 0.0;

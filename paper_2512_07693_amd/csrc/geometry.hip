@@ -262,7 +262,7 @@ static int grow_cells(ap_ctx *c, int ncell) {
 
 // (Re)builds the neighbour list of the positions in c->pos at radius r_list when forced, when the
 // list parameters changed, or when the device-side skin check flagged it.
-int ensure_list(ap_ctx *c, int n, const double *box, double r_list, bool force) {
+int ensure_list(ap_ctx *c, int n, const double *box, double r_list, bool force, bool skin_checked, bool commit) {
     Geometry g;
     int rc = make_geometry(c, box, r_list, g);
     if (rc) return rc;
@@ -271,14 +271,16 @@ int ensure_list(ap_ctx *c, int n, const double *box, double r_list, bool force) 
     bool changed = force || r_list != c->list_r || n != c->list_n || box[0] != c->list_box[0] ||
                    box[1] != c->list_box[1] || box[2] != c->list_box[2];
     const int nb = (n + kBlock - 1) / kBlock;
+    const int cb = (g.ncell + kBlock - 1) / kBlock;
     if (changed) {
         launch_fill_int(c, c->d_flags, 1, 1);
-    } else {
+        k_cell_clear<<<cb, kBlock, 0, c->stream>>>(c->cell_cnt, c->cell_fill, g.ncell, c->d_flags);
+    } else if (!skin_checked) {
         k_skin_check<<<nb, kBlock, 0, c->stream>>>(c->pos, c->pos_build, n, box[0], box[1], box[2],
                                                    0.25 * c->skin * c->skin, c->d_flags);
+        k_cell_clear<<<cb, kBlock, 0, c->stream>>>(c->cell_cnt, c->cell_fill, g.ncell, c->d_flags);
     }
-    const int cb = (g.ncell + kBlock - 1) / kBlock;
-    k_cell_clear<<<cb, kBlock, 0, c->stream>>>(c->cell_cnt, c->cell_fill, g.ncell, c->d_flags);
+    c->ncell_cur = g.ncell;
     k_cell_assign<<<nb, kBlock, 0, c->stream>>>(c->pos, n, g, c->cell_of, c->cell_cnt, c->d_flags);
     k_scan_excl<<<1, 1024, 0, c->stream>>>(c->cell_cnt, c->cell_start, g.ncell, nullptr, c->d_flags);
     k_cell_fill<<<nb, kBlock, 0, c->stream>>>(n, c->cell_of, c->cell_start, c->cell_fill, c->cell_atoms, c->d_flags);
@@ -289,7 +291,7 @@ int ensure_list(ap_ctx *c, int n, const double *box, double r_list, bool force) 
         c->pos, n, g, r_list * r_list, rs * rs, c->cell_start, c->cell_cnt,
                                               c->cell_atoms, c->cell_of, c->max_nbr, c->nbr_cnt, c->nbr_short,
                                               c->nbr_idx, c->pos_build, c->d_flags);
-    k_commit<<<1, 1, 0, c->stream>>>(c->d_flags);
+    if (commit) k_commit<<<1, 1, 0, c->stream>>>(c->d_flags);
     c->list_r = r_list;
     c->list_n = n;
     for (int a = 0; a < 3; a++) c->list_box[a] = box[a];
