@@ -35,10 +35,12 @@ FP64_PEAK_TFLOPS = 78.6
 # same counters read for a 1 GiB device copy (fetch x2.0, write x1.0), with a digest of the kernel's source
 # file and the shared header at the time: a kernel whose source has changed reports null until re-measured.
 MEASURED_TRAFFIC = {
-    "ace_energy": (12.68e6, "ace.hip", "6375d9b637651ead"),
-    "force": (92.87e6, "forces.hip", "6ed845a6bd6a78b7"),
-    "dens_desc": (78.65e6, "forces.hip", "6ed845a6bd6a78b7"),
-    "W": (55.46e6, "forces.hip", "6ed845a6bd6a78b7"),
+    "ace_energy": (9.40e6, "ace.hip", "bbb1f06cb4e1e055"),
+    "ace_basis": (10.11e6, "ace.hip", "bbb1f06cb4e1e055"),
+    "ace_pairforce": (30.28e6, "ace.hip", "bbb1f06cb4e1e055"),
+    "force": (48.35e6, "forces.hip", "71f0a02d05938612"),
+    "dens_desc": (83.15e6, "forces.hip", "71f0a02d05938612"),
+    "W": (57.85e6, "forces.hip", "71f0a02d05938612"),
 }
 
 
