@@ -33,8 +33,13 @@ struct AceArgs {
     const double *dlam, *wbar, *Ef;
     const double *c1d, *bdd;
     double *Ep, *Et;
-    void *gbuf;   // [S][n_max * nlm] A, then G = dE/dA
+    void *gbuf;     // [S][n_max * nlm] the atomic basis A
     double *s0buf;  // [S][n_max] FP64 sums of the radial channels over the neighbours
+    void *gpart;    // [2][gstride][n_max * nlm] dE/dA, whole or in two halves of the coupling blocks
+    double *epart;  // [S][2] the site energy, whole or in two halves
+    int gstride;    // capacity in atoms
+    int nsplit;     // first coupling block of the second half
+    int slots;      // energy-kernel workgroups resident at once on the device
     void *fpair;  // [S][max_nbr][3]
     void *frev;   // [3][max_nbr][n]: f of pair (i, j) stored at slot k of i in j's list
     const Rec4 *xl;  // [n] {x, y, z, lambda}
@@ -143,6 +148,14 @@ __device__ __forceinline__ void ld4(const T *p, T *o) {
         o[3] = v1.y;
     }
 }
+
+// Whether each S atom's coupling blocks go to two workgroups. The per-atom time is a chain of
+// dependent block steps, about as long with one workgroup on a CU as with four (0.20 against 0.23 ms at
+// n_max 12, l_max 6), and a half chain takes about 0.62 of it: splitting pays when all 2 S halves fit in
+// one round of resident workgroups, and not when it only trades rounds of whole chains for more rounds
+// of halves. Decided from the device-side S alone, the same way by the energy kernel and by the pair
+// kernel that adds the parts.
+__device__ __forceinline__ int ace_parts(int S, int slots) { return 2LL * S <= slots ? 2 : 1; }
 
 template <typename T, int NMAX, int LMAX>
 __global__ __launch_bounds__(kBlock) void k_ace_basis(AceArgs a) {
@@ -283,8 +296,11 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
     const T *c1 = (const T *)a.c1, *bd = (const T *)a.bd, *c2 = (const T *)a.c2, *c3 = (const T *)a.c3;
     const T *kval = (const T *)a.kval;
     const int S = *a.scount;
-    for (int s = blockIdx.x; s < S; s += gridDim.x) {
-        const int i = a.slist[s];
+    const int K = ace_parts(S, a.slots);
+    // K workgroups per S atom: with K = 2, part 0 takes orders 1-2 and the blocks before nsplit, part 1
+    // the others; each writes its own dE/dA and energy, added by the pair kernel in a fixed order
+    for (int w = blockIdx.x; w < K * S; w += gridDim.x) {
+        const int s = K == 2 ? w >> 1 : w, h = K == 2 ? w & 1 : 0;
         const T *ain = (const T *)a.gbuf + (size_t)s * NA;
         for (int o = tid; o < NA; o += kBlock) {
             const int q = o / NLM, lm = o - q * NLM;
@@ -297,6 +313,8 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
         __syncthreads();
         // ---- phase 3a: orders 1 and 2, embedding ----
         double e = 0.0;
+        T *bout = a.bval ? (T *)a.bval + (size_t)s * a.bstride : nullptr;
+        if (h == 0) {
         if (tid == 0) {
             const double y00 = 0.28209479177387814;  // 1 / sqrt(4 pi)
             double phi2 = 0.0, e1 = 0.0;
@@ -318,7 +336,6 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
         static_assert(LMAX + 1 <= NMAX, "order-2 table fits the block buffer");
         for (int o = tid; o < (LMAX + 1) * NN; o += kBlock) B.C[o] = c2[o];
         __syncthreads();
-        T *bout = a.bval ? (T *)a.bval + (size_t)s * a.bstride : nullptr;
         if (bout) {
             // dE/dc for orders 1 and 2 (B values) and dE/db_n = xi'(phi2) s_n
             const double y00 = 0.28209479177387814;
@@ -345,8 +362,10 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
             e += 0.5 * (double)(sA[o] * g2);
             sG[o] += g2 + (lm == 0 ? c1[q] + sEmbD * bd[q] : T(0));  // order-1 and density parts of dE/dA
         }
+        }
         // ---- phase 3b: order-3 blocks ----
-        for (int b = 0; b < a.nblk; b++) {
+        const int b_lo = K == 2 && h == 1 ? a.nsplit : 0, b_hi = K == 2 && h == 0 ? a.nsplit : a.nblk;
+        for (int b = b_lo; b < b_hi; b++) {
             const int *bk = a.blk + b * kBlkInts;
             const int L = bk[0], l1 = bk[1], l2 = bk[2];
             const int nM = 2 * L + 1, n1m = 2 * l1 + 1, n2m = 2 * l2 + 1;
@@ -487,17 +506,11 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
             }
         }
         __syncthreads();
-        // ---- outputs ----
+        // ---- outputs: this part's energy and dE/dA ----
         const double E = block_sum_d(e, sRed);
-        T *gout = (T *)a.gbuf + (size_t)s * NA;
+        T *gout = (T *)a.gpart + ((size_t)h * a.gstride + s) * NA;
         for (int o = tid; o < NA; o += kBlock) gout[o] = sG[o];
-        if (tid == 0) {
-            a.Ep[i] = E;
-            const double et = (E - a.Ef[i]) * a.dlam[i] / a.wbar[i];
-            a.Et[i] = et;
-            a.eb[i].w = et;
-            if (!isfinite(E)) atomicOr(&a.flags[1], kErrNonFinite);
-        }
+        if (tid == 0) a.epart[2 * s + h] = E;
         __syncthreads();
     }
 }
@@ -512,10 +525,20 @@ __global__ __launch_bounds__(128) void k_ace_pairforce(AceArgs a) {
     const T rcT = (T)a.rc;
     for (int s = blockIdx.x; s < S; s += gridDim.x) {
         const int i = a.slist[s];
-        const T *gin = (const T *)a.gbuf + (size_t)s * NA;
+        // G = dE/dA and the site energy from the energy kernel's one or two parts, added in a fixed order
+        const bool two = ace_parts(S, a.slots) == 2;
+        const T *g0 = (const T *)a.gpart + (size_t)s * NA, *g1 = g0 + (size_t)a.gstride * NA;
         for (int o = threadIdx.x; o < NA; o += blockDim.x) {
             const int q = o / NLM, lm = o - q * NLM;
-            sGt[lm * NMAX + q] = gin[o];
+            sGt[lm * NMAX + q] = two ? g0[o] + g1[o] : g0[o];
+        }
+        if (threadIdx.x == 0) {
+            const double E = two ? a.epart[2 * s] + a.epart[2 * s + 1] : a.epart[2 * s];
+            a.Ep[i] = E;
+            const double et = (E - a.Ef[i]) * a.dlam[i] / a.wbar[i];
+            a.Et[i] = et;
+            a.eb[i].w = et;
+            if (!isfinite(E)) atomicOr(&a.flags[1], kErrNonFinite);
         }
         __syncthreads();
         double Lx, Ly, Lz;
@@ -858,6 +881,9 @@ int ace_setup(ap_ctx *c, const ap_ace_params *p) {
     }
     t.nblk = nb;
     t.h_blk = hblk;
+    // the two parts of a split atom get equal numbers of blocks (each block is about one step of the
+    // per-atom chain, whatever its size); the first part also takes orders 1-2
+    t.nsplit = nb / 2;
     t.ng1 = (int)g1.size() / 2;
     t.ng2 = (int)g2.size() / 2;
     int rc;
@@ -897,14 +923,29 @@ int ace_setup(ap_ctx *c, const ap_ace_params *p) {
 }
 
 template <typename T, int NMAX, int LMAX>
-static void launch_t(ap_ctx *c, const AceArgs &a, int grid) {
+static void launch_t(ap_ctx *c, AceArgs a, int grid) {
+    {
+        // workgroups of the energy kernel resident at once: the rounds the split decision counts (taken
+        // once per device for each instantiation)
+        static int dev = -1, slots = 0;
+        if (dev != c->device) {
+            int per_cu = 0, cus = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ace_energy<T, NMAX, LMAX>, kBlock, 0) !=
+                    hipSuccess ||
+                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess)
+                per_cu = cus = 0;
+            slots = per_cu > 0 && cus > 0 ? per_cu * cus : 1 << 30;
+            dev = c->device;
+        }
+        a.slots = slots;
+    }
     {
         ProfScope p(c, "ace_basis");
         k_ace_basis<T, NMAX, LMAX><<<grid, kBlock, 0, c->stream>>>(a);
     }
     {
         ProfScope p(c, "ace_energy");
-        k_ace_energy<T, NMAX, LMAX><<<grid, kBlock, 0, c->stream>>>(a);
+        k_ace_energy<T, NMAX, LMAX><<<2 * grid, kBlock, 0, c->stream>>>(a);
     }
     ProfScope p(c, "ace_pairforce");
     k_ace_pairforce<T, NMAX, LMAX><<<grid, 128, 0, c->stream>>>(a);
@@ -951,8 +992,19 @@ int launch_ace(ap_ctx *c, int n, const double *box, int grid_cap, const double *
     a.Ep = c->Ep;
     a.Et = c->Et;
     a.gbuf = c->gbuf;
-    a.s0buf = (double *)((char *)c->gbuf + (size_t)c->n_cap * t.n_max * (t.l_max + 1) * (t.l_max + 1) *
-                                             (t.precision == AP_FP32 ? 4 : 8));
+    {
+        // scratch layout: A [n_cap][NA], radial sums [n_cap][n_max], dE/dA parts [2][n_cap][NA], energy parts
+        // [n_cap][2]
+        const size_t abytes = (size_t)c->n_cap * t.n_max * (t.l_max + 1) * (t.l_max + 1) *
+                              (t.precision == AP_FP32 ? 4 : 8);
+        char *base = (char *)c->gbuf;
+        a.s0buf = (double *)(base + abytes);
+        a.gpart = base + abytes + (size_t)c->n_cap * t.n_max * sizeof(double);
+        a.epart = (double *)(base + 3 * abytes + (size_t)c->n_cap * t.n_max * sizeof(double));
+        a.gstride = c->n_cap;
+        a.nsplit = t.nsplit;
+    }
+
     a.fpair = c->fpair;
     a.frev = c->frev;
     a.xl = c->xl;

@@ -83,6 +83,7 @@ struct AceTables {
     void *kval = nullptr; // coupling values, three orderings (by M, by m1, by m2)
     int *kidx = nullptr;  // packed (m1 + 8) | (m2 + 8) << 8 | (M + 8) << 16, same three orderings
     int *blk = nullptr;   // [nblk][kBlkInts] block descriptors
+    int nsplit = 0;       // first block of the second part when an atom is split over two workgroups
     int *g1 = nullptr, *g2 = nullptr, *g3 = nullptr;  // coefficient-gradient lists (see ace_setup)
     int ng1 = 0, ng2 = 0;
     std::vector<int> h_blk;
@@ -156,7 +157,7 @@ struct ap_ctx {
     size_t bval_bytes = 0;
     void *fpair = nullptr;       // [n_cap][max_nbr][3] ACE pair gradients (double or float)
     void *frev = nullptr;        // [3][max_nbr][n] the same pair terms at the neighbour's slot (k, j)
-    void *gbuf = nullptr;        // [n_cap][n_max * (l_max+1)^2] A, then dE/dA, of the S atoms; then [n_cap][n_max] FP64 sums
+    void *gbuf = nullptr;        // ACE scratch of the S atoms: A, FP64 radial sums, two dE/dA parts, two energy parts
     size_t fpair_bytes = 0, gbuf_bytes = 0;
     // learned indicator
     bool have_mlp = false;
