@@ -40,6 +40,7 @@ struct AceArgs {
     int gstride;    // capacity in atoms
     int nsplit;     // first coupling block of the second half
     int slots;      // energy-kernel workgroups resident at once on the device
+    int *queue;     // work-item counter of the energy kernel
     void *fpair;  // [S][max_nbr][3]
     void *frev;   // [3][max_nbr][n]: f of pair (i, j) stored at slot k of i in j's list
     const Rec4 *xl;  // [n] {x, y, z, lambda}
@@ -149,13 +150,23 @@ __device__ __forceinline__ void ld4(const T *p, T *o) {
     }
 }
 
-// Whether each S atom's coupling blocks go to two workgroups. The per-atom time is a chain of
-// dependent block steps, about as long with one workgroup on a CU as with four (0.20 against 0.23 ms at
-// n_max 12, l_max 6), and a half chain takes about 0.62 of it: splitting pays when all 2 S halves fit in
-// one round of resident workgroups, and not when it only trades rounds of whole chains for more rounds
-// of halves. Decided from the device-side S alone, the same way by the energy kernel and by the pair
-// kernel that adds the parts.
-__device__ __forceinline__ int ace_parts(int S, int slots) { return 2LL * S <= slots ? 2 : 1; }
+// Work plan of the energy kernel. The per-atom time is a chain of dependent block steps, about as long
+// with one workgroup on a CU as with four (0.20 against 0.23 ms at n_max 12, l_max 6), and a half chain
+// takes about 0.62 of it. So the atoms that fill whole rounds of the resident workgroups (slots) are
+// taken whole, and the remaining R atoms of a last, partial round are split into two halves of their
+// coupling blocks when the 2 R halves fit one round: atoms s < whole are one work item each, atoms
+// s >= whole two (items whole + 2 (s - whole) and the next). Computed from the device-side S alone,
+// the same way by the energy kernel and by the pair kernel that adds the halves.
+__device__ __forceinline__ void ace_plan(int S, int slots, int &whole, int &items) {
+    const int R = S % slots;
+    if (R > 0 && 2LL * R <= slots) {
+        whole = S - R;
+        items = whole + 2 * R;
+    } else {
+        whole = S;
+        items = S;
+    }
+}
 
 template <typename T, int NMAX, int LMAX>
 __global__ __launch_bounds__(kBlock) void k_ace_basis(AceArgs a) {
@@ -172,6 +183,7 @@ __global__ __launch_bounds__(kBlock) void k_ace_basis(AceArgs a) {
     const int S = *a.scount;
     const double rc2 = a.rc * a.rc;
     const T rcT = (T)a.rc;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *a.queue = 0;  // the energy kernel's work counter
     for (int s = blockIdx.x; s < S; s += gridDim.x) {
         const int i = a.slist[s];
         const double xi = a.pos[i], yi = a.pos[n + i], zi = a.pos[2 * n + i];
@@ -296,11 +308,16 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
     const T *c1 = (const T *)a.c1, *bd = (const T *)a.bd, *c2 = (const T *)a.c2, *c3 = (const T *)a.c3;
     const T *kval = (const T *)a.kval;
     const int S = *a.scount;
-    const int K = ace_parts(S, a.slots);
-    // K workgroups per S atom: with K = 2, part 0 takes orders 1-2 and the blocks before nsplit, part 1
-    // the others; each writes its own dE/dA and energy, added by the pair kernel in a fixed order
-    for (int w = blockIdx.x; w < K * S; w += gridDim.x) {
-        const int s = K == 2 ? w >> 1 : w, h = K == 2 ? w & 1 : 0;
+    int whole, items;
+    ace_plan(S, a.slots, whole, items);
+    // a persistent grid: workgroup b takes item b, then the next items in order from a device counter
+    // (zeroed by the basis kernel): whole atoms first, then the halves. Half 0 takes orders 1-2 and the
+    // blocks before nsplit, half 1 the others; each item writes its own dE/dA and energy, added by the
+    // pair kernel in a fixed order.
+    __shared__ int sItem;
+    for (int w = blockIdx.x; w < items;) {
+        const bool K2 = w >= whole;
+        const int s = K2 ? whole + ((w - whole) >> 1) : w, h = K2 ? (w - whole) & 1 : 0;
         const T *ain = (const T *)a.gbuf + (size_t)s * NA;
         for (int o = tid; o < NA; o += kBlock) {
             const int q = o / NLM, lm = o - q * NLM;
@@ -364,7 +381,7 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
         }
         }
         // ---- phase 3b: order-3 blocks ----
-        const int b_lo = K == 2 && h == 1 ? a.nsplit : 0, b_hi = K == 2 && h == 0 ? a.nsplit : a.nblk;
+        const int b_lo = K2 && h == 1 ? a.nsplit : 0, b_hi = K2 && h == 0 ? a.nsplit : a.nblk;
         for (int b = b_lo; b < b_hi; b++) {
             const int *bk = a.blk + b * kBlkInts;
             const int L = bk[0], l1 = bk[1], l2 = bk[2];
@@ -510,8 +527,12 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
         const double E = block_sum_d(e, sRed);
         T *gout = (T *)a.gpart + ((size_t)h * a.gstride + s) * NA;
         for (int o = tid; o < NA; o += kBlock) gout[o] = sG[o];
-        if (tid == 0) a.epart[2 * s + h] = E;
+        if (tid == 0) {
+            a.epart[2 * s + h] = E;
+            sItem = (int)gridDim.x + atomicAdd(a.queue, 1);
+        }
         __syncthreads();
+        w = sItem;
     }
 }
 
@@ -526,7 +547,9 @@ __global__ __launch_bounds__(128) void k_ace_pairforce(AceArgs a) {
     for (int s = blockIdx.x; s < S; s += gridDim.x) {
         const int i = a.slist[s];
         // G = dE/dA and the site energy from the energy kernel's one or two parts, added in a fixed order
-        const bool two = ace_parts(S, a.slots) == 2;
+        int whole, items;
+        ace_plan(S, a.slots, whole, items);
+        const bool two = s >= whole;
         const T *g0 = (const T *)a.gpart + (size_t)s * NA, *g1 = g0 + (size_t)a.gstride * NA;
         for (int o = threadIdx.x; o < NA; o += blockDim.x) {
             const int q = o / NLM, lm = o - q * NLM;
@@ -945,7 +968,9 @@ static void launch_t(ap_ctx *c, AceArgs a, int grid) {
     }
     {
         ProfScope p(c, "ace_energy");
-        k_ace_energy<T, NMAX, LMAX><<<2 * grid, kBlock, 0, c->stream>>>(a);
+        // a persistent grid: the resident workgroups, which take the work items from the counter
+        const int eg = a.slots < (1 << 30) ? a.slots : 2 * grid;
+        k_ace_energy<T, NMAX, LMAX><<<eg, kBlock, 0, c->stream>>>(a);
     }
     ProfScope p(c, "ace_pairforce");
     k_ace_pairforce<T, NMAX, LMAX><<<grid, 128, 0, c->stream>>>(a);
@@ -1003,6 +1028,7 @@ int launch_ace(ap_ctx *c, int n, const double *box, int grid_cap, const double *
         a.epart = (double *)(base + 3 * abytes + (size_t)c->n_cap * t.n_max * sizeof(double));
         a.gstride = c->n_cap;
         a.nsplit = t.nsplit;
+        a.queue = c->d_flags + 6;
     }
 
     a.fpair = c->fpair;
