@@ -41,6 +41,8 @@ struct AceArgs {
     int nsplit;     // first coupling block of the second half
     int slots;      // energy-kernel workgroups resident at once on the device
     int *queue;     // work-item counter of the energy kernel
+    int *stamp;     // [n] set to gen for every precise atom and every atom in its list (null: not kept)
+    int gen;
     void *fpair;  // [S][max_nbr][3]
     void *frev;   // [3][max_nbr][n]: f of pair (i, j) stored at slot k of i in j's list
     const Rec4 *xl;  // [n] {x, y, z, lambda}
@@ -569,8 +571,10 @@ __global__ __launch_bounds__(128) void k_ace_pairforce(AceArgs a) {
         const double xi = a.pos[i], yi = a.pos[n + i], zi = a.pos[2 * n + i];
         const int cnt = a.ncount[i];
         T *fo = (T *)a.fpair + (size_t)s * a.max_nbr * 3;
+        if (a.stamp && threadIdx.x == 0) a.stamp[i] = a.gen;
         for (int slot = threadIdx.x; slot < cnt; slot += blockDim.x) {
             const int j = a.nidx[(size_t)slot * n + i];
+            if (a.stamp) a.stamp[j] = a.gen;
             const Rec4 pj = a.xl[j];
             const double ux = min_image(pj.x - xi, Lx), uy = min_image(pj.y - yi, Ly), uz = min_image(pj.z - zi, Lz);
             const double r2 = ux * ux + uy * uy + uz * uz;
@@ -1029,6 +1033,8 @@ int launch_ace(ap_ctx *c, int n, const double *box, int grid_cap, const double *
         a.gstride = c->n_cap;
         a.nsplit = t.nsplit;
         a.queue = c->d_flags + 6;
+        a.stamp = sbox ? nullptr : c->stamp;
+        a.gen = c->stamp_gen;
     }
 
     a.fpair = c->fpair;

@@ -141,6 +141,8 @@ struct ap_ctx {
     int32_t *nbr_cnt = nullptr, *nbr_idx = nullptr;
     int32_t *nbr_short = nullptr;  // [n] the first nbr_short[i] slots hold the neighbours inside max(r_rho, r_phi) + skin
     int *act = nullptr;            // [n] 1 if the atom or a neighbour has lambda < 1 (the force needs its full list)
+    int *stamp = nullptr;          // [n] = stamp_gen when the atom is precise or in a precise atom's list
+    int stamp_gen = 0;             // evaluation counter of the stamps
 
     // gathered records: xg = {x, y, z, g}, xl = {x, y, z, lambda}, eb = {xi', g, d + d0, E~}
     ap::Rec4 *xg = nullptr, *xl = nullptr, *eb = nullptr;
@@ -239,7 +241,7 @@ struct EvalFlags {
 };
 void launch_dens_desc(ap_ctx *c, int n, const double *box, const EvalFlags &f, const double *lam_in);
 void launch_compact(ap_ctx *c, int n, const int32_t *subset, int n_subset);
-void launch_W(ap_ctx *c, int n, const double *box);
+void launch_W(ap_ctx *c, int n, const double *box, bool stamped);
 // uniform_lambda: lambda is the constant of f on every atom (no per-atom lambda from the caller)
 void launch_force(ap_ctx *c, int n, const double *box, const EvalFlags &f, double *E_atom, double *F,
                   const double *sbox = nullptr, bool uniform_lambda = true);

@@ -114,6 +114,8 @@ static int evaluate(ap_ctx *c, int n, const double *box, const EvalFlags &f, con
         ProfScope p(c, "dens_desc");
         launch_dens_desc(c, n, box, f, lam_in);
     }
+    // the precise atoms stamp themselves and their list neighbours (ACE pair kernel) for the W pass
+    c->stamp_gen = c->stamp_gen == 0x7fffffff ? 1 : c->stamp_gen + 1;
     if (run_ace) {
         {
             ProfScope p(c, "compact");
@@ -127,7 +129,7 @@ static int evaluate(ap_ctx *c, int n, const double *box, const EvalFlags &f, con
     }
     if (f.switching && f.grad_lambda) {
         ProfScope p(c, "W");
-        launch_W(c, n, box);
+        launch_W(c, n, box, run_ace && !subset);
     }
     if (f.switching && f.grad_lambda && c->sw.indicator == AP_IND_MLP) {
         ProfScope p(c, "mlp_gradg");
@@ -277,7 +279,7 @@ void ap_ctx_destroy(ap_ctx *c) {
     void *bufs[] = {c->csp_t, c->rev_start, c->rev_code, c->pos, c->pos_build, c->d_flags, c->cell_of, c->cell_cnt,
                     c->cell_start, c->cell_fill, c->cell_atoms, c->nbr_cnt, c->nbr_idx, c->g, c->d,
                     c->wbar, c->lam, c->dlam, c->Ef, c->Ep, c->Et, c->W, c->xip, c->sidx, c->slist, c->blk_cnt,
-                    c->mark, c->fpair, c->frev, c->xg, c->xl, c->eb, c->xe, c->nbr_short, c->act, c->gbuf, c->partials, c->scalars, c->sid, c->b_off, c->b_box, c->bval};
+                    c->mark, c->fpair, c->frev, c->xg, c->xl, c->eb, c->xe, c->nbr_short, c->act, c->stamp, c->gbuf, c->partials, c->scalars, c->sid, c->b_off, c->b_box, c->bval};
     for (void *p : bufs) hipFree(p);
     delete c;
 }
@@ -308,6 +310,7 @@ int ap_ctx_create(ap_ctx **out, int n_max_atoms, int max_nbr, double skin, void 
     alloc(&c->nbr_idx, n * max_nbr, 4);
     alloc(&c->nbr_short, n, 4);
     alloc(&c->act, n, 4);
+    alloc(&c->stamp, n, 4);
     double **per_atom[] = {&c->g, &c->d, &c->wbar, &c->lam, &c->dlam, &c->Ef, &c->Ep, &c->Et, &c->W, &c->xip};
     for (double **p : per_atom) alloc(p, n, 8);
     alloc(&c->xg, n, sizeof(ap::Rec4));
@@ -327,6 +330,7 @@ int ap_ctx_create(ap_ctx **out, int n_max_atoms, int max_nbr, double skin, void 
         return rc;
     }
     launch_fill_int(c, c->d_flags, 0, 8);
+    launch_fill_int(c, c->stamp, 0, (int)n);
     launch_fill_double(c, c->g, 0.0, (int)n);
     launch_fill_double(c, c->W, 0.0, (int)n);
     launch_fill_double(c, c->d, 0.0, (int)n);

@@ -226,12 +226,15 @@ __global__ __launch_bounds__(kBlock) void k_W(const double *__restrict__ pos, in
                                               double r_w, const int32_t *__restrict__ ncount,
                                               const int32_t *__restrict__ nidx, const double *__restrict__ Et,
                                               const Rec4 *__restrict__ xl, const double *__restrict__ lam,
-                                              double *__restrict__ W, int *__restrict__ act) {
+                                              double *__restrict__ W, int *__restrict__ act,
+                                              const int *__restrict__ stamp, int gen, int use_stamp) {
     const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const int j = t / SUB, sub = t - j * SUB;
     double s = 0.0;
     int near_s = 0;  // a neighbour with lambda < 1
-    if (j < n) {
+    // an atom that no precise atom stamped (not precise, none in its symmetric list) has W = 0 and no
+    // lambda < 1 in reach: only the stamped ones gather
+    if (j < n && (!use_stamp || stamp[j] == gen)) {
         const double xj = pos[j], yj = pos[n + j], zj = pos[2 * n + j];
         const double r_w2 = r_w * r_w;
         const int cnt = ncount[j];
@@ -250,15 +253,18 @@ __global__ __launch_bounds__(kBlock) void k_W(const double *__restrict__ pos, in
 #pragma unroll
     for (int m = 1; m < SUB; m <<= 1) near_s |= __shfl_xor(near_s, m, 64);
     if (j < n && sub == 0) {
-        W[j] = Et[j] + s;
-        act[j] = near_s | (lam[j] < 1.0);
+        const bool stamped = !use_stamp || stamp[j] == gen;
+        W[j] = stamped ? Et[j] + s : 0.0;
+        act[j] = stamped ? (near_s | (lam[j] < 1.0)) : 0;
     }
 }
 
-void launch_W(ap_ctx *c, int n, const double *box) {
+// stamped: the ACE pair kernel of this evaluation stamped the precise atoms' neighbourhoods
+void launch_W(ap_ctx *c, int n, const double *box, bool stamped) {
     constexpr int SUB = kLanesPerAtom;
     k_W<SUB><<<((size_t)n * SUB + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(
-        c->pos, n, box[0], box[1], box[2], c->sw.r_w, c->nbr_cnt, c->nbr_idx, c->Et, c->xl, c->lam, c->W, c->act);
+        c->pos, n, box[0], box[1], box[2], c->sw.r_w, c->nbr_cnt, c->nbr_idx, c->Et, c->xl, c->lam, c->W, c->act,
+        c->stamp, c->stamp_gen, stamped ? 1 : 0);
 }
 
 // ------------------------------------------------------------------------------------------
