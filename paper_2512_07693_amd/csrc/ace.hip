@@ -204,9 +204,9 @@ __global__ __launch_bounds__(kBlock) void k_ace_basis(AceArgs a) {
             if (slot < cnt) {
                 const int j = a.nidx[(size_t)slot * n + i];
                 const Rec4 pj = a.xl[j];
-                ux = min_image(pj.x - xi, Lx);
-                uy = min_image(pj.y - yi, Ly);
-                uz = min_image(pj.z - zi, Lz);
+                ux = min_image_w(pj.x - xi, Lx);
+                uy = min_image_w(pj.y - yi, Ly);
+                uz = min_image_w(pj.z - zi, Lz);
                 r2 = ux * ux + uy * uy + uz * uz;
                 valid = r2 < rc2;
             }
@@ -576,7 +576,7 @@ __global__ __launch_bounds__(128) void k_ace_pairforce(AceArgs a) {
             const int j = a.nidx[(size_t)slot * n + i];
             if (a.stamp) a.stamp[j] = a.gen;
             const Rec4 pj = a.xl[j];
-            const double ux = min_image(pj.x - xi, Lx), uy = min_image(pj.y - yi, Ly), uz = min_image(pj.z - zi, Lz);
+            const double ux = min_image_w(pj.x - xi, Lx), uy = min_image_w(pj.y - yi, Ly), uz = min_image_w(pj.z - zi, Lz);
             const double r2 = ux * ux + uy * uy + uz * uz;
             T f0 = T(0), f1 = T(0), f2 = T(0);
             if (r2 < rc2) {

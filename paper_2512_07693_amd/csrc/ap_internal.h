@@ -46,6 +46,14 @@ __device__ __forceinline__ double min_image(double d, double L) {
     return d - L * rint(d / L);
 }
 
+// Minimum image of a difference of two wrapped coordinates (|d| < L): the value of min_image wherever
+// |d| is not within rounding of L / 2 (never inside a cutoff below L / 2), without the division. The
+// neighbour-list and CSP tests keep min_image, whose result the CPU reference reproduces bit for bit.
+__device__ __forceinline__ double min_image_w(double d, double L) {
+    const double h = 0.5 * L;
+    return d > h ? d - L : (d < -h ? d + L : d);
+}
+
 // |u|^2 as the plain left-to-right sum of products, never fused: the neighbour test must give the
 // same set as any IEEE implementation of the same expression.
 __device__ __forceinline__ double norm2_nofma(double x, double y, double z) {

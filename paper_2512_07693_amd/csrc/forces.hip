@@ -13,11 +13,11 @@
 namespace ap {
 
 struct EamP {
-    double A, beta, c0, c1, c2, r_rho, r_phi, rc2;  // rc2 = max(r_rho, r_phi)^2
+    double A, beta, c0, c1, c2, r_rho, r_phi, rc2, inv_rr;  // rc2 = max(r_rho, r_phi)^2, inv_rr = 1 / r_rho
 };
 static EamP eamp(const ap_eam_params &e) {
     const double m = e.r_rho > e.r_phi ? e.r_rho : e.r_phi;
-    return {e.A, e.beta, e.c0, e.c1, e.c2, e.r_rho, e.r_phi, m * m};
+    return {e.A, e.beta, e.c0, e.c1, e.c2, e.r_rho, e.r_phi, m * m, 1.0 / e.r_rho};
 }
 
 // zeta, zeta', Phi, Phi' of the Finnis-Sinclair form at r (each zero beyond its own cutoff)
@@ -25,8 +25,8 @@ __device__ __forceinline__ void eam_pair(const EamP &p, double r, double &z, dou
     z = dz = ph = dph = 0.0;
     if (r < p.r_rho) {
         const double x = r - p.r_rho;
-        z = x * x * (1.0 + p.beta * x / p.r_rho);
-        dz = x * (2.0 + 3.0 * p.beta * x / p.r_rho);
+        z = x * x * (1.0 + p.beta * x * p.inv_rr);
+        dz = x * (2.0 + 3.0 * p.beta * x * p.inv_rr);
     }
     if (r < p.r_phi) {
         const double y = r - p.r_phi;
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(kBlock) void k_dens_desc(const double *__restrict__
                 py = pos[n + j];
                 pz = pos[2 * n + j];
             }
-            const double ux = min_image(px - xi, Lx), uy = min_image(py - yi, Ly), uz = min_image(pz - zi, Lz);
+            const double ux = min_image_w(px - xi, Lx), uy = min_image_w(py - yi, Ly), uz = min_image_w(pz - zi, Lz);
             const double r2 = ux * ux + uy * uy + uz * uz;
             if (r2 < ep.rc2) {
                 double zz, dz, ph, dph;
@@ -244,7 +244,7 @@ __global__ __launch_bounds__(kBlock) void k_W(const double *__restrict__ pos, in
             const double e = Et[k];
             if (e == 0.0) continue;
             const Rec4 pk = xl[k];
-            const double ux = min_image(pk.x - xj, Lx), uy = min_image(pk.y - yj, Ly), uz = min_image(pk.z - zj, Lz);
+            const double ux = min_image_w(pk.x - xj, Lx), uy = min_image_w(pk.y - yj, Ly), uz = min_image_w(pk.z - zj, Lz);
             const double r2 = ux * ux + uy * uy + uz * uz;
             if (r2 < r_w2) s += e * ftrans(sqrt(r2), r_w - 1.0, r_w);
         }
@@ -347,8 +347,8 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
             const int cs = a.nshort[i];
             for (int k = sub; k < cs; k += SUB) {
                 const Rec4 pj = a.xe[a.nidx[(size_t)k * n + i]];
-                const double ux = min_image(pj.x - xi, Lx), uy = min_image(pj.y - yi, Ly),
-                             uz = min_image(pj.z - zi, Lz);
+                const double ux = min_image_w(pj.x - xi, Lx), uy = min_image_w(pj.y - yi, Ly),
+                             uz = min_image_w(pj.z - zi, Lz);
                 const double r2 = ux * ux + uy * uy + uz * uz;
                 if (r2 < a.ep.rc2) {
                     const double r = sqrt(r2), ir = 1.0 / r;
@@ -371,7 +371,7 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
             const Rec4 pj = a.xl[j];
             Rec4 qj{0.0, 0.0, 0.0, 0.0};
             if (a.eam_on || gl) qj = a.eb[j];
-            const double ux = min_image(pj.x - xi, Lx), uy = min_image(pj.y - yi, Ly), uz = min_image(pj.z - zi, Lz);
+            const double ux = min_image_w(pj.x - xi, Lx), uy = min_image_w(pj.y - yi, Ly), uz = min_image_w(pj.z - zi, Lz);
             const double r2 = ux * ux + uy * uy + uz * uz;
             const double r = sqrt(r2), ir = 1.0 / r;
             const double ex = ux * ir, ey = uy * ir, ez = uz * ir;
@@ -462,10 +462,10 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
             if (Wi != 0.0) {
                 for (int t = 0; t < a.n_csp; t++) {
                     const int l = a.csp_t[(size_t)t * n + i], o = a.csp_t[(size_t)(t ^ 1) * n + i];
-                    const double lx = min_image(a.pos[l] - xi, a.L[0]), ly = min_image(a.pos[n + l] - yi, a.L[1]),
-                                 lz = min_image(a.pos[2 * n + l] - zi, a.L[2]);
-                    const double ox = min_image(a.pos[o] - xi, a.L[0]), oy = min_image(a.pos[n + o] - yi, a.L[1]),
-                                 oz = min_image(a.pos[2 * n + o] - zi, a.L[2]);
+                    const double lx = min_image_w(a.pos[l] - xi, a.L[0]), ly = min_image_w(a.pos[n + l] - yi, a.L[1]),
+                                 lz = min_image_w(a.pos[2 * n + l] - zi, a.L[2]);
+                    const double ox = min_image_w(a.pos[o] - xi, a.L[0]), oy = min_image_w(a.pos[n + o] - yi, a.L[1]),
+                                 oz = min_image_w(a.pos[2 * n + o] - zi, a.L[2]);
                     const double sx = lx + ox, sy = ly + oy, sz = lz + oz;
                     F0 -= 2.0 * Wi * sx;
                     F1 -= 2.0 * Wi * sy;
@@ -484,9 +484,9 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
                 if (Wj == 0.0) continue;
                 const int o = a.csp_t[(size_t)(t ^ 1) * n + jj];
                 const double xj = a.pos[jj], yj = a.pos[n + jj], zj = a.pos[2 * n + jj];
-                const double sx = min_image(xi - xj, a.L[0]) + min_image(a.pos[o] - xj, a.L[0]);
-                const double sy = min_image(yi - yj, a.L[1]) + min_image(a.pos[n + o] - yj, a.L[1]);
-                const double sz = min_image(zi - zj, a.L[2]) + min_image(a.pos[2 * n + o] - zj, a.L[2]);
+                const double sx = min_image_w(xi - xj, a.L[0]) + min_image_w(a.pos[o] - xj, a.L[0]);
+                const double sy = min_image_w(yi - yj, a.L[1]) + min_image_w(a.pos[n + o] - yj, a.L[1]);
+                const double sz = min_image_w(zi - zj, a.L[2]) + min_image_w(a.pos[2 * n + o] - zj, a.L[2]);
                 F0 += 2.0 * Wj * sx;
                 F1 += 2.0 * Wj * sy;
                 F2 += 2.0 * Wj * sz;
