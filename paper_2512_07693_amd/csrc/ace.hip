@@ -42,6 +42,7 @@ struct AceArgs {
     int slots;      // energy-kernel workgroups resident at once on the device
     int *queue;     // work-item counter of the energy kernel
     int *stamp;     // [n] set to gen for every precise atom and every atom in its list (null: not kept)
+    const void *c30, *kap0;  // the L = 0 blocks folded into order 2 (null: processed as blocks)
     int gen;
     void *fpair;  // [S][max_nbr][3]
     void *frev;   // [3][max_nbr][n]: f of pair (i, j) stored at slot k of i in j's list
@@ -333,6 +334,8 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
         // ---- phase 3a: orders 1 and 2, embedding ----
         double e = 0.0;
         T *bout = a.bval ? (T *)a.bval + (size_t)s * a.bstride : nullptr;
+        // the L = 0 blocks folded into order 2, except when their own B values are asked for
+        const bool fold0 = a.c30 != nullptr && !bout;
         if (h == 0) {
         if (tid == 0) {
             const double y00 = 0.28209479177387814;  // 1 / sqrt(4 pi)
@@ -354,6 +357,54 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
         // the order-2 coefficients C2_l[n1][n2] staged in the (still unused) coefficient-block space
         static_assert(LMAX + 1 <= NMAX, "order-2 table fits the block buffer");
         for (int o = tid; o < (LMAX + 1) * NN; o += kBlock) B.C[o] = c2[o];
+        if (fold0) {
+            // The L = 0 blocks in closed form. With kappa_l their one coupling value (m1 = m2, M = 0),
+            // block (0, l, l) contributes kappa_l sum_{n1 n2} D_l[n1][n2] R_l[n1][n2], where
+            // D_l = sum_n3 C0_l[..][..][n3] A[n3][00] and R_l[n1][n2] = sum_m A[n1][l m] A[n2][l m]: an
+            // order-2 term with matrix kappa_l (D_l + D_l^T) / 2, added to C2_l, plus the gradient through
+            // D_l, dE/dA[n3][00] += kappa_l sum_{n1 n2} C0_l[n1][n2][n3] R_l[n1][n2]. One thread per
+            // (l, n1, n2) reads the row C0_l[n1][n2][:] once for both.
+            const T *c30 = (const T *)a.c30, *kap0 = (const T *)a.kap0;
+            T acc[NMAX];
+#pragma unroll
+            for (int q = 0; q < NMAX; q++) acc[q] = T(0);
+            for (int w = tid; w < (LMAX + 1) * NN; w += kBlock) {
+                const int l = w / NN, r = w - l * NN, n1 = r / NMAX, n2 = r - n1 * NMAX;
+                const T kap = kap0[l];
+                T D = T(0);
+                if (kap != T(0)) {
+                    T R = T(0);
+                    for (int m = l * l; m <= l * l + 2 * l; m++) R += sAt[m * NMAX + n1] * sAt[m * NMAX + n2];
+                    const T kr = kap * R;
+                    const T *crow = c30 + (size_t)w * NMAX;
+#pragma unroll
+                    for (int q = 0; q < NMAX; q++) {
+                        const T cv = crow[q];
+                        D += cv * sAt[q];  // A[q][00]
+                        acc[q] += cv * kr;
+                    }
+                }
+                B.P[w] = D;
+            }
+            // the A[n3][00] gradient: a fixed butterfly per wavefront, then the wavefronts in order
+#pragma unroll
+            for (int q = 0; q < NMAX; q++) {
+                T v = acc[q];
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+                if ((tid & 63) == 0) B.Q[(tid >> 6) * NMAX + q] = v;
+            }
+            __syncthreads();
+            if (tid < NMAX) {
+                T v = T(0);
+                for (int wv = 0; wv < kBlock / 64; wv++) v += B.Q[wv * NMAX + tid];
+                sG[tid * NLM] += v;
+            }
+            for (int o = tid; o < (LMAX + 1) * NN; o += kBlock) {
+                const int l = o / NN, r = o - l * NN, n1 = r / NMAX, n2 = r - n1 * NMAX;
+                B.C[o] += kap0[l] * T(0.5) * (B.P[o] + B.P[l * NN + n2 * NMAX + n1]);
+            }
+        }
         __syncthreads();
         if (bout) {
             // dE/dc for orders 1 and 2 (B values) and dE/db_n = xi'(phi2) s_n
@@ -387,6 +438,7 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
         for (int b = b_lo; b < b_hi; b++) {
             const int *bk = a.blk + b * kBlkInts;
             const int L = bk[0], l1 = bk[1], l2 = bk[2];
+            if (fold0 && L == 0) continue;  // done with order 2
             const int nM = 2 * L + 1, n1m = 2 * l1 + 1, n2m = 2 * l2 + 1;
             const int bL = L * L + L, b1 = l1 * l1 + l1, b2 = l2 * l2 + l2;
             const int k0 = bk[4], k1 = bk[32 + n2m];
@@ -783,6 +835,8 @@ void ace_free(ap_ctx *c) {
     (void)hipFree(t.kval);
     (void)hipFree(t.kidx);
     (void)hipFree(t.blk);
+    (void)hipFree(t.c30);
+    (void)hipFree(t.kap0);
     t = AceTables();
 }
 
@@ -867,12 +921,27 @@ int ace_setup(ap_ctx *c, const ap_ace_params *p) {
     // keep only blocks with coefficients; build coupling tables in three orderings
     std::vector<int> hblk;
     std::vector<int> kidx;
+    std::vector<double> c30((size_t)(Lm + 1) * N * N * N, 0.0), kap0(Lm + 1, 0.0);
+    bool fold0 = true;
     std::vector<double> kval, c3u;
     int nb = 0;
     for (size_t bi = 0; bi < blocks.size(); bi++) {
         if (!used[bi]) continue;
         const Blk &B = blocks[bi];
         std::vector<Kap> k = coupling(B.l1, B.l2, B.L);
+        if (B.L == 0) {
+            // (0, l, l): one coupling value on the diagonal m1 = m2 with M = 0, or no closed form
+            bool diag = (int)k.size() == 2 * B.l1 + 1;
+            for (const Kap &e : k)
+                diag = diag && e.M == 0 && e.m1 == e.m2 && std::fabs(e.v - k[0].v) <= 1e-14 * std::fabs(k[0].v);
+            if (diag) {
+                kap0[B.l1] = k[0].v;
+                std::copy(c3.begin() + bi * (size_t)N * N * N, c3.begin() + (bi + 1) * (size_t)N * N * N,
+                          c30.begin() + (size_t)B.l1 * N * N * N);
+            } else {
+                fold0 = false;
+            }
+        }
         std::vector<int> d(kBlkInts, 0);
         d[0] = B.L;
         d[1] = B.l1;
@@ -908,9 +977,14 @@ int ace_setup(ap_ctx *c, const ap_ace_params *p) {
     }
     t.nblk = nb;
     t.h_blk = hblk;
-    // the two parts of a split atom get equal numbers of blocks (each block is about one step of the
-    // per-atom chain, whatever its size); the first part also takes orders 1-2
-    t.nsplit = nb / 2;
+    // the two parts of a split atom get equal numbers of the blocks they run (each block is about one
+    // step of the per-atom chain, whatever its size; the L = 0 blocks, first in the table, are folded
+    // into order 2 unless coefficient gradients are asked for); the first part also takes orders 1-2
+    {
+        int n0 = 0;
+        while (n0 < nb && hblk[(size_t)n0 * kBlkInts] == 0) n0++;
+        t.nsplit = n0 + (nb - n0) / 2;
+    }
     t.ng1 = (int)g1.size() / 2;
     t.ng2 = (int)g2.size() / 2;
     int rc;
@@ -936,6 +1010,15 @@ int ace_setup(ap_ctx *c, const ap_ace_params *p) {
         if (!rc) rc = upload<double>(c, &t.c2, c2);
         if (!rc) rc = upload<double>(c, &t.c3, c3u);
         if (!rc) rc = upload<double>(c, &t.kval, kval);
+    }
+    if (!rc && fold0) {
+        if (p->precision == AP_FP32) {
+            rc = upload<float>(c, &t.c30, c30);
+            if (!rc) rc = upload<float>(c, &t.kap0, kap0);
+        } else {
+            rc = upload<double>(c, &t.c30, c30);
+            if (!rc) rc = upload<double>(c, &t.kap0, kap0);
+        }
     }
     if (!rc) rc = upload<double>(c, (void **)&t.c1d, c1);
     if (!rc) rc = upload<double>(c, (void **)&t.bdd, std::vector<double>(p->b_dens, p->b_dens + N));
@@ -1033,6 +1116,8 @@ int launch_ace(ap_ctx *c, int n, const double *box, int grid_cap, const double *
         a.gstride = c->n_cap;
         a.nsplit = t.nsplit;
         a.queue = c->d_flags + 6;
+        a.c30 = t.c30;
+        a.kap0 = t.kap0;
         a.stamp = sbox ? nullptr : c->stamp;
         a.gen = c->stamp_gen;
     }

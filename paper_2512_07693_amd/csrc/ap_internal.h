@@ -92,6 +92,9 @@ struct AceTables {
     int *kidx = nullptr;  // packed (m1 + 8) | (m2 + 8) << 8 | (M + 8) << 16, same three orderings
     int *blk = nullptr;   // [nblk][kBlkInts] block descriptors
     int nsplit = 0;       // first block of the second part when an atom is split over two workgroups
+    // the L = 0 blocks (0, l, l) in closed form: C0[l][n1][n2][n3] and their coupling kappa_l (null when
+    // a block does not have the single-value diagonal form)
+    void *c30 = nullptr, *kap0 = nullptr;
     int *g1 = nullptr, *g2 = nullptr, *g3 = nullptr;  // coefficient-gradient lists (see ace_setup)
     int ng1 = 0, ng2 = 0;
     std::vector<int> h_blk;
