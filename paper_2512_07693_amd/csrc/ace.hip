@@ -538,8 +538,9 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
             }
             __syncthreads();
             // dE/dA[n1][l1 m1] = sum kappa sum_n2 Q_M[n1][n2] A[n2][l2 m2]
+            // (lanes in runs of n_max share m1: the same coupling list, read as a broadcast)
             for (int w = tid; w < NMAX * n1m; w += kBlock) {
-                const int q1 = w / n1m, i1 = w - q1 * n1m;
+                const int i1 = w / NMAX, q1 = w - i1 * NMAX;
                 T acc = T(0);
                 const int e0 = bk[18 + i1] - k0, e1 = bk[18 + i1 + 1] - k0;
                 for (int q = e0; q < e1; q++) {
@@ -561,7 +562,7 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
             __syncthreads();
             // dE/dA[n2][l2 m2] = sum kappa sum_n1 Q_M[n1][n2] A[n1][l1 m1]
             for (int w = tid; w < NMAX * n2m; w += kBlock) {
-                const int q2 = w / n2m, i2 = w - q2 * n2m;
+                const int i2 = w / NMAX, q2 = w - i2 * NMAX;
                 T acc = T(0);
                 const int e0 = bk[32 + i2] - k0, e1 = bk[32 + i2 + 1] - k0;
                 for (int q = e0; q < e1; q++) {
