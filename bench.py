@@ -35,12 +35,12 @@ FP64_PEAK_TFLOPS = 78.6
 # same counters read for a 1 GiB device copy (fetch x2.0, write x1.0), with a digest of the kernel's source
 # file and the shared header at the time: a kernel whose source has changed reports null until re-measured.
 MEASURED_TRAFFIC = {
-    "ace_energy": (9.40e6, "ace.hip", "bbb1f06cb4e1e055"),
-    "ace_basis": (10.11e6, "ace.hip", "bbb1f06cb4e1e055"),
-    "ace_pairforce": (30.28e6, "ace.hip", "bbb1f06cb4e1e055"),
-    "force": (48.35e6, "forces.hip", "71f0a02d05938612"),
-    "dens_desc": (83.15e6, "forces.hip", "71f0a02d05938612"),
-    "W": (57.85e6, "forces.hip", "71f0a02d05938612"),
+    "ace_energy": (9.90e6, "ace.hip", "28d73f1120730d50"),
+    "ace_basis": (10.10e6, "ace.hip", "28d73f1120730d50"),
+    "ace_pairforce": (31.65e6, "ace.hip", "28d73f1120730d50"),
+    "force": (48.34e6, "forces.hip", "de063bf0a6b977f9"),
+    "dens_desc": (83.12e6, "forces.hip", "de063bf0a6b977f9"),
+    "W": (4.79e6, "forces.hip", "de063bf0a6b977f9"),
 }
 
 
