@@ -71,23 +71,48 @@ def drift_fit(thermo, n, dt_ps):
                 x_mean=float(thermo[:, 6].mean() / n), x_max=float(thermo[:, 6].max() / n))
 
 
-def algorithmic_bytes(kernel, n, nnb, n_s, nnb_rc, n_csp):
-    """Minimal HBM bytes per launch of the HBM-bound kernels: the slot-major lists are
-    read once (4 B per entry), every per-atom array once, outputs written once."""
-    per_atom = {
+def algorithmic_bytes(kernel, n, nnb, n_s, nnb_rc, n_csp, n_near=None, nnb_short=None):
+    """Minimal HBM bytes per launch of the HBM-bound kernels: the slot-major lists are read once (4 B
+    per entry), every per-atom array once, outputs written once. n_near atoms (the precise ones and
+    their list neighbours) need the full lists in the W and force passes; the others need only their
+    flag (W) or their nnb_short EAM-range slots (force). Without those counts every atom is charged the
+    full list."""
+    if n_near is None:
+        n_near, nnb_short = n, nnb
+    full = {
         "dens_desc": 4 * nnb + 4 + 24 + 8 + 8 * 8,        # list + count, position, g; 8 outputs
         "force": 4 * nnb + 4 + 24 + 8 * 8 + 4 + 32,      # list + count, position, 8 own scalars, sidx, F, E_i
-        "W": 4 * nnb + 4 + 24 + 8 + 8,
+        "W": 4 * nnb + 4 + 4 + 24 + 8 + 8 + 12,          # list + count, flag, position, E~, lambda; W, act
         "csp_value": 4 * n_csp + 24 + 8,
         "vv_first": 6 * 8 + 3 * 8 + 6 * 8,
         "vv_second": 6 * 8 + 3 * 8,
     }.get(kernel)
-    if per_atom is None:
+    if full is None:
         return None
-    b = per_atom * n
+    # the atoms away from every precise atom
+    far = {"W": 4 + 12,                                                   # flag; W, act
+           "force": 4 * nnb_short + 4 + 4 + 24 + 4 * 8 + 32}.get(kernel)  # short list, flag, own 4 scalars
+    if far is None:
+        b = full * n
+    else:
+        b = full * n_near + far * (n - n_near)
     if kernel == "force":
         b += n_s * nnb_rc * 3 * 4 * 2  # FP32 pair gradients of S read from both sides
     return float(b)
+
+
+def near_counts(ctx, pos, box, r_list, r_short, max_nbr):
+    """Atoms that are precise or in a precise atom's list at these positions, and the mean count of
+    neighbours inside the EAM range plus skin (the lists' short part)."""
+    lam = ctx.switch_eval(pos, box)["lam"]
+    cnt, idx = ctx.nblist_build(pos, box, r_list, max_nbr)
+    near = lam < 1.0
+    prec = near.nonzero().flatten()
+    if prec.numel():
+        nb = idx[:, prec].flatten()
+        near[nb[nb >= 0].long()] = True
+    cnt_s, _ = ctx.nblist_build(pos, box, r_short, max_nbr)
+    return int(near.sum().item()), float(cnt_s.double().mean().item())
 
 
 def run_md(ctx, s, pos0, vel0, steps, warmup, profile_steps):
@@ -238,14 +263,17 @@ def large_run(steps, warmup, pure_steps):
     log("fcc penny crack: mixed %d + %d steps ..." % (warmup, steps))
     ms, thermo, prof, _ = run_md(ctx, s, pos0, vel0, steps, warmup, 0)
     nve = drift_fit(thermo, n, s["run"]["dt"])
-    cnt, _ = ctx.nblist_build(pos0, box, max(s["ace"]["rc"], s["sw"]["r_w"]) + s["run"]["skin"], 160)
+    r_list = max(s["ace"]["rc"], s["sw"]["r_w"]) + s["run"]["skin"]
+    cnt, _ = ctx.nblist_build(pos0, box, r_list, 160)
     nnb = float(cnt.double().mean().item())
+    n_near, nnb_short = near_counts(ctx, pos0, box, r_list, max(s["eam"]["r_rho"], s["eam"]["r_phi"]) + s["run"]["skin"],
+                                    160)
     ctx.close()
     del ctx
     hbm = {}
     for k in ("dens_desc", "force", "W"):
         if k in prof:
-            b = algorithmic_bytes(k, n, nnb, nve["x_mean"] * n, 54.0, s["sw"]["n_csp"])
+            b = algorithmic_bytes(k, n, nnb, nve["x_mean"] * n, 54.0, s["sw"]["n_csp"], n_near, nnb_short)
             hbm[k] = dict(avg_ms=prof[k][0], GBs=b / (prof[k][0] * 1e-3) / 1e9,
                           frac=b / (prof[k][0] * 1e-3) / 1e9 / HBM_PEAK_GBS)
     out = dict(workload=s["name"], n_atoms=n, value=n * steps / (ms / 1e3), ms_per_step=ms / steps, nve=nve,
@@ -363,6 +391,8 @@ def main():
     nnb_rc = float(cnt_rc.double().mean().item())
     nnb = float(cnt_w.double().mean().item())
     n_s = nve["x_mean"] * n
+    n_near, nnb_short = near_counts(ctx, pos0, box, max(s["ace"]["rc"], s["sw"]["r_w"]) + s["run"]["skin"],
+                                    max(s["eam"]["r_rho"], s["eam"]["r_phi"]) + s["run"]["skin"], 128)
     tot = {k: v[0] * v[1] for k, v in prof.items()}
     dom = max(tot, key=tot.get)
     avg_ms, launches = prof[dom]
@@ -376,7 +406,7 @@ def main():
                     frac=achieved / FP32_PEAK_TFLOPS, traffic=measured_traffic(dom), kernel=dom, avg_ms=avg_ms,
                     work_per_launch="%.4g flop (%.0f precise atoms x %.4g flop)" % (flops, n_s, per))
     else:
-        b = algorithmic_bytes(dom, n, nnb, n_s, nnb_rc, s["sw"]["n_csp"])
+        b = algorithmic_bytes(dom, n, nnb, n_s, nnb_rc, s["sw"]["n_csp"], n_near, nnb_short)
         achieved = b / (avg_ms * 1e-3) / 1e9 if b else None
         roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=(achieved / HBM_PEAK_GBS) if achieved else None, traffic=measured_traffic(dom), kernel=dom,
@@ -386,7 +416,7 @@ def main():
     hbm = {}
     for k in ("dens_desc", "force", "W"):
         if k in prof:
-            b = algorithmic_bytes(k, n, nnb, n_s, nnb_rc, s["sw"]["n_csp"])
+            b = algorithmic_bytes(k, n, nnb, n_s, nnb_rc, s["sw"]["n_csp"], n_near, nnb_short)
             hbm[k] = dict(GBs=b / (prof[k][0] * 1e-3) / 1e9, frac=b / (prof[k][0] * 1e-3) / 1e9 / HBM_PEAK_GBS,
                           algorithmic_bytes=b, traffic=measured_traffic(k))
     ace_roof = {}
@@ -432,6 +462,7 @@ def main():
         "roofline": roof,
         "ace_roofline": ace_roof,
         "hbm_kernels": hbm,
+        "path_counts": {"n_near_precise": n_near, "nnb_list": nnb, "nnb_eam_short": nnb_short, "nnb_ace": nnb_rc},
         "kernels": kernels,
         "kernels_timed_every_nth_step": PROF_EVERY,
         "cpu_baseline": cpu,
