@@ -146,6 +146,7 @@ struct ap_ctx {
     int ncell_cap = 0;
     int ncell_cur = 0;  // cells of the geometry of the last list build
     int *cell_of = nullptr, *cell_cnt = nullptr, *cell_start = nullptr, *cell_fill = nullptr, *cell_atoms = nullptr;
+    ap::Rec4 *cell_rec = nullptr;  // [n] {x, y, z, index} of the atoms in cell order (the list build's candidates)
     int *scan_tmp = nullptr;
 
     // neighbour list (slot-major)

@@ -277,7 +277,7 @@ void ap_ctx_destroy(ap_ctx *c) {
     ace_free(c);
     mlp_free(c);
     void *bufs[] = {c->csp_t, c->rev_start, c->rev_code, c->pos, c->pos_build, c->d_flags, c->cell_of, c->cell_cnt,
-                    c->cell_start, c->cell_fill, c->cell_atoms, c->nbr_cnt, c->nbr_idx, c->g, c->d,
+                    c->cell_start, c->cell_fill, c->cell_atoms, c->cell_rec, c->nbr_cnt, c->nbr_idx, c->g, c->d,
                     c->wbar, c->lam, c->dlam, c->Ef, c->Ep, c->Et, c->W, c->xip, c->sidx, c->slist, c->blk_cnt,
                     c->mark, c->fpair, c->frev, c->xg, c->xl, c->eb, c->xe, c->nbr_short, c->act, c->stamp, c->gbuf, c->partials, c->scalars, c->sid, c->b_off, c->b_box, c->bval};
     for (void *p : bufs) hipFree(p);
@@ -306,6 +306,7 @@ int ap_ctx_create(ap_ctx **out, int n_max_atoms, int max_nbr, double skin, void 
     alloc(&c->d_flags, 8, 4);
     alloc(&c->cell_of, n + 1, 4);
     alloc(&c->cell_atoms, n, 4);
+    alloc(&c->cell_rec, n, sizeof(ap::Rec4));
     alloc(&c->nbr_cnt, n, 4);
     alloc(&c->nbr_idx, n * max_nbr, 4);
     alloc(&c->nbr_short, n, 4);

@@ -108,20 +108,42 @@ __global__ void k_cell_fill(int n, const int *cell_of, const int *start, int *fi
     atoms[start[cc] + atomicAdd(&fill[cc], 1)] = i;
 }
 
-// Insertion sort of every cell's atoms by index (the fill order above is not deterministic).
-__global__ void k_cell_sort(int ncell, const int *start, const int *cnt, int *atoms, const int *flags) {
+// Every cell's atoms sorted by index (the fill order above is not deterministic), a wavefront per cell:
+// each lane ranks its atom against the others of the cell. The sorted cell also gets its records
+// {x, y, z, index}, which the list build reads in cell order. A cell of more than 64 atoms is
+// insertion-sorted by its first lane.
+__global__ void k_cell_sort(int ncell, const int *start, const int *cnt, int *atoms, const double *__restrict__ pos,
+                            int n, Rec4 *__restrict__ rec, const int *flags) {
     if (flags[0] == 0) return;
-    int cc = blockIdx.x * blockDim.x + threadIdx.x;
-    if (cc >= ncell) return;
-    int *a = atoms + start[cc];
-    int m = cnt[cc];
-    for (int p = 1; p < m; p++) {
-        int v = a[p], q = p - 1;
-        while (q >= 0 && a[q] > v) {
-            a[q + 1] = a[q];
-            q--;
+    const int lane = threadIdx.x & 63;
+    const int cc = (int)(((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    if (cc >= ncell) return;  // whole wavefronts
+    const int b = start[cc], m = cnt[cc];
+    int *a = atoms + b;
+    if (m <= 64) {
+        const int v = lane < m ? a[lane] : 0;
+        int rank = 0;
+        for (int u = 0; u < m; u++) rank += __shfl(v, u, 64) < v;
+        if (lane < m) {
+            a[rank] = v;
+            rec[b + rank] = Rec4{pos[v], pos[n + v], pos[2 * n + v], (double)v};
         }
-        a[q + 1] = v;
+        return;
+    }
+    if (lane == 0) {
+        for (int p = 1; p < m; p++) {
+            int v = a[p], q = p - 1;
+            while (q >= 0 && a[q] > v) {
+                a[q + 1] = a[q];
+                q--;
+            }
+            a[q + 1] = v;
+        }
+    }
+    __threadfence_block();
+    for (int p = lane; p < m; p += 64) {
+        const int v = a[p];
+        rec[b + p] = Rec4{pos[v], pos[n + v], pos[2 * n + v], (double)v};
     }
 }
 
@@ -134,7 +156,7 @@ __global__ void k_cell_sort(int ncell, const int *start, const int *cnt, int *at
 template <int SUB>
 __global__ __launch_bounds__(kBlock) void k_nbr_build(const double *__restrict__ pos, int n, Geometry g, double r2,
                                                       double rs2, const int *__restrict__ start,
-                                                      const int *__restrict__ cnt, const int *__restrict__ atoms,
+                                                      const int *__restrict__ cnt, const Rec4 *__restrict__ rec,
                                                       const int *__restrict__ cell_of, int max_nbr,
                                                       int32_t *__restrict__ ncount, int32_t *__restrict__ ncount_short,
                                                       int32_t *__restrict__ nidx, double *__restrict__ pos_build,
@@ -177,11 +199,12 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(const double *__restrict__
                     bool hs = false, hl = false;
                     int j = -1;
                     if (p < e) {
-                        j = atoms[p];
+                        const Rec4 cr = rec[p];  // the candidate's position and index, in cell order
+                        j = (int)cr.w;
                         if (j != i) {
-                            const double ux = min_image(pos[j] - xi, g.L[0]);
-                            const double uy = min_image(pos[n + j] - yi, g.L[1]);
-                            const double uz = min_image(pos[2 * n + j] - zi, g.L[2]);
+                            const double ux = min_image(cr.x - xi, g.L[0]);
+                            const double uy = min_image(cr.y - yi, g.L[1]);
+                            const double uz = min_image(cr.z - zi, g.L[2]);
                             const double d2 = norm2_nofma(ux, uy, uz);
                             hs = d2 < r2 && d2 < rs2;
                             hl = d2 < r2 && !(d2 < rs2);
@@ -284,13 +307,13 @@ int ensure_list(ap_ctx *c, int n, const double *box, double r_list, bool force, 
     k_cell_assign<<<nb, kBlock, 0, c->stream>>>(c->pos, n, g, c->cell_of, c->cell_cnt, c->d_flags);
     k_scan_excl<<<1, 1024, 0, c->stream>>>(c->cell_cnt, c->cell_start, g.ncell, nullptr, c->d_flags);
     k_cell_fill<<<nb, kBlock, 0, c->stream>>>(n, c->cell_of, c->cell_start, c->cell_fill, c->cell_atoms, c->d_flags);
-    k_cell_sort<<<cb, kBlock, 0, c->stream>>>(g.ncell, c->cell_start, c->cell_cnt, c->cell_atoms, c->d_flags);
+    k_cell_sort<<<(int)(((size_t)g.ncell * 64 + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(
+        g.ncell, c->cell_start, c->cell_cnt, c->cell_atoms, c->pos, n, c->cell_rec, c->d_flags);
     const double rs = std::max(c->eam.r_rho, c->eam.r_phi) + c->skin;  // the EAM pairs first
     constexpr int SUB = 8;  // lanes per atom in the list build
     k_nbr_build<SUB><<<(int)(((size_t)n * SUB + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(
-        c->pos, n, g, r_list * r_list, rs * rs, c->cell_start, c->cell_cnt,
-                                              c->cell_atoms, c->cell_of, c->max_nbr, c->nbr_cnt, c->nbr_short,
-                                              c->nbr_idx, c->pos_build, c->d_flags);
+        c->pos, n, g, r_list * r_list, rs * rs, c->cell_start, c->cell_cnt, c->cell_rec, c->cell_of, c->max_nbr,
+        c->nbr_cnt, c->nbr_short, c->nbr_idx, c->pos_build, c->d_flags);
     if (commit) k_commit<<<1, 1, 0, c->stream>>>(c->d_flags);
     c->list_r = r_list;
     c->list_n = n;
