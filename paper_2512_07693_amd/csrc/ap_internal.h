@@ -70,6 +70,23 @@ __host__ __device__ __forceinline__ T ftrans(T x, T lo, T hi) {
     T y2 = y * y;
     return T(0.5) + y * (T(0.9375) + y2 * (T(-0.625) + T(0.1875) * y2));
 }
+// The same with 1 / (hi - lo) given (the pair weight w(r) evaluates it per neighbour; for its unit
+// window the product equals the quotient exactly).
+template <typename T>
+__host__ __device__ __forceinline__ T ftrans_i(T x, T lo, T hi, T inv) {
+    if (x <= lo) return T(1);
+    if (x >= hi) return T(0);
+    T y = (hi + lo - T(2) * x) * inv;
+    T y2 = y * y;
+    return T(0.5) + y * (T(0.9375) + y2 * (T(-0.625) + T(0.1875) * y2));
+}
+template <typename T>
+__host__ __device__ __forceinline__ T ftrans_d_i(T x, T lo, T hi, T inv) {
+    if (x <= lo || x >= hi) return T(0);
+    T y = (hi + lo - T(2) * x) * inv;
+    T s = T(1) - y * y;
+    return T(0.9375) * s * s * (T(-2) * inv);
+}
 template <typename T>
 __host__ __device__ __forceinline__ T ftrans_d(T x, T lo, T hi) {
     if (x <= lo || x >= hi) return T(0);

@@ -37,7 +37,7 @@ __device__ __forceinline__ void eam_pair(const EamP &p, double r, double &z, dou
 }
 
 struct SwP {
-    double d_lo, d_hi, r_w, r_w2, d0;
+    double d_lo, d_hi, r_w, r_w2, d0, inv_ww;  // inv_ww = 1 / (r_w - (r_w - 1)), the weight window
 };
 
 // SUB lanes per atom: lane `sub` takes slots sub, sub + SUB, ...; the lane partials are combined by
@@ -97,7 +97,7 @@ __global__ __launch_bounds__(kBlock) void k_dens_desc(const double *__restrict__
                 pair += ph;
             }
             if (switching && r2 < sp.r_w2) {
-                const double w = ftrans(sqrt(r2), sp.r_w - 1.0, sp.r_w);
+                const double w = ftrans_i(sqrt(r2), sp.r_w - 1.0, sp.r_w, sp.inv_ww);
                 ws += w;
                 gs += gj * w;
             }
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(kBlock) void k_dens_desc(const double *__restrict__
 }
 
 void launch_dens_desc(ap_ctx *c, int n, const double *box, const EvalFlags &f, const double *lam_in) {
-    const SwP sp{c->sw.d_lo, c->sw.d_hi, c->sw.r_w, c->sw.r_w * c->sw.r_w, c->sw.d0};
+    const SwP sp{c->sw.d_lo, c->sw.d_hi, c->sw.r_w, c->sw.r_w * c->sw.r_w, c->sw.d0, 1.0 / (c->sw.r_w - (c->sw.r_w - 1.0))};
     constexpr int SUB = kLanesPerAtom;
     k_dens_desc<SUB><<<((size_t)n * SUB + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(
         c->pos, n, box[0], box[1], box[2], eamp(c->eam), sp, f.switching ? 1 : 0, f.lam_const, lam_in, c->nbr_cnt,
@@ -246,7 +246,7 @@ __global__ __launch_bounds__(kBlock) void k_W(const double *__restrict__ pos, in
             const Rec4 pk = xl[k];
             const double ux = min_image_w(pk.x - xj, Lx), uy = min_image_w(pk.y - yj, Ly), uz = min_image_w(pk.z - zj, Lz);
             const double r2 = ux * ux + uy * uy + uz * uz;
-            if (r2 < r_w2) s += e * ftrans(sqrt(r2), r_w - 1.0, r_w);
+            if (r2 < r_w2) s += e * ftrans_i(sqrt(r2), r_w - 1.0, r_w, 1.0 / (r_w - (r_w - 1.0)));
         }
     }
     s = group_sum<SUB>(s);
@@ -393,7 +393,7 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
             }
             if (gl && r2 < a.sp.r_w2) {
                 // weight part (S19)-(S21): F_i -= (s_i + s_k) u / r
-                const double dw = ftrans_d(r, a.sp.r_w - 1.0, a.sp.r_w);
+                const double dw = ftrans_d_i(r, a.sp.r_w - 1.0, a.sp.r_w, a.sp.inv_ww);
                 const double s_i = Eti * (qj.y - di - a.sp.d0) * dw;
                 const double s_k = qj.w * (gi - qj.z) * dw;
                 const double s = -(s_i + s_k);
@@ -518,7 +518,7 @@ void launch_force(ap_ctx *c, int n, const double *box, const EvalFlags &f, doubl
     a.n = n;
     for (int q = 0; q < 3; q++) a.L[q] = box[q];
     a.ep = eamp(c->eam);
-    a.sp = SwP{c->sw.d_lo, c->sw.d_hi, c->sw.r_w, c->sw.r_w * c->sw.r_w, c->sw.d0};
+    a.sp = SwP{c->sw.d_lo, c->sw.d_hi, c->sw.r_w, c->sw.r_w * c->sw.r_w, c->sw.d0, 1.0 / (c->sw.r_w - (c->sw.r_w - 1.0))};
     a.switching = f.switching;
     a.grad_lambda = f.grad_lambda;
     a.eam_on = f.eam_forces;
