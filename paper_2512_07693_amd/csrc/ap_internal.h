@@ -17,6 +17,9 @@ constexpr int kAceMaxValid = 128; // neighbours within the ACE cutoff held per s
 constexpr int kLanesPerAtom = 8;  // lanes that share one atom's neighbour loop in the per-atom passes
 constexpr int kForceLanes = 4;    // the same for the force assembly
 // workgroups of the force kernel, each writing one row of the per-block partial sums
+// Above this many atoms the one-kernel compaction (each workgroup sums all the chunk counts before it)
+// gives way to count, scan and scatter.
+constexpr int kCountedCompactMax = 1 << 18;
 inline int force_blocks(int n) { return (int)(((long long)n * kForceLanes + kBlock - 1) / kBlock); }
 constexpr double kConv = 9648.533212;  // eV / (A u) in A / ps^2
 constexpr double kPi = 3.14159265358979323846;
@@ -180,6 +183,7 @@ struct ap_ctx {
     double *g = nullptr, *d = nullptr, *wbar = nullptr, *lam = nullptr, *dlam = nullptr;
     double *Ef = nullptr, *Ep = nullptr, *Et = nullptr, *W = nullptr, *xip = nullptr;
     int *sidx = nullptr, *slist = nullptr, *blk_cnt = nullptr, *mark = nullptr;
+    int *chunk_cnt = nullptr;  // [ceil(n / (kBlock / kLanesPerAtom))] counts of lambda < 1 from the density pass
     int *sid = nullptr;          // [n_cap] structure of each atom in a batch evaluation
     int *b_off = nullptr;        // [n_struct + 1] device copy of the batch offsets
     double *b_box = nullptr;     // [n_struct][3] device copy of the batch boxes
@@ -268,8 +272,10 @@ struct EvalFlags {
     bool eam_forces;  // EAM family included
     bool ace_forces;  // ACE family included
 };
-void launch_dens_desc(ap_ctx *c, int n, const double *box, const EvalFlags &f, const double *lam_in);
-void launch_compact(ap_ctx *c, int n, const int32_t *subset, int n_subset);
+// count: also write the per-workgroup counts of lambda < 1 (chunk_cnt) that launch_compact(counted) uses
+void launch_dens_desc(ap_ctx *c, int n, const double *box, const EvalFlags &f, const double *lam_in, bool count);
+// counted: S from the density pass's chunk counts in one kernel (no subset); otherwise count, scan, scatter
+void launch_compact(ap_ctx *c, int n, const int32_t *subset, int n_subset, bool counted);
 void launch_W(ap_ctx *c, int n, const double *box, bool stamped);
 // uniform_lambda: lambda is the constant of f on every atom (no per-atom lambda from the caller)
 void launch_force(ap_ctx *c, int n, const double *box, const EvalFlags &f, double *E_atom, double *F,

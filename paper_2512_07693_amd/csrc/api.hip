@@ -95,7 +95,7 @@ static int nblocks(int n) { return (n + kBlock - 1) / kBlock; }
 // The force evaluation on the positions already in c->pos.
 static int evaluate(ap_ctx *c, int n, const double *box, const EvalFlags &f, const double *lam_in,
                     const int32_t *subset, int n_subset, bool run_ace, double *E_tot, double *E_atom, double *F,
-                    double *virial, bool force_list, bool skin_checked = false) {
+                    double *virial, bool force_list, bool skin_checked = false, bool reduce = true) {
     int rc;
     {
         ProfScope p(c, "nbr_list");
@@ -110,16 +110,17 @@ static int evaluate(ap_ctx *c, int n, const double *box, const EvalFlags &f, con
         ProfScope p(c, "csp_value");
         launch_csp_value(c, n, box);
     }
+    const bool counted = run_ace && !subset && n <= kCountedCompactMax;
     {
         ProfScope p(c, "dens_desc");
-        launch_dens_desc(c, n, box, f, lam_in);
+        launch_dens_desc(c, n, box, f, lam_in, counted);
     }
     // the precise atoms stamp themselves and their list neighbours (ACE pair kernel) for the W pass
     c->stamp_gen = c->stamp_gen == 0x7fffffff ? 1 : c->stamp_gen + 1;
     if (run_ace) {
         {
             ProfScope p(c, "compact");
-            launch_compact(c, n, subset, n_subset);
+            launch_compact(c, n, subset, n_subset, counted);
         }
         rc = launch_ace(c, n, box, std::min(n, 8192));
         if (rc) return rc;
@@ -139,7 +140,7 @@ static int evaluate(ap_ctx *c, int n, const double *box, const EvalFlags &f, con
         ProfScope p(c, "force");
         launch_force(c, n, box, f, E_atom, F, nullptr, lam_in == nullptr);
     }
-    {
+    if (reduce) {
         ProfScope p(c, "reduce");
         launch_reduce(c, force_blocks(n), E_tot, virial);
     }
@@ -233,12 +234,17 @@ __global__ __launch_bounds__(kBlock) void k_vv_second(double *vel, const double 
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_thermo(const double *partials, int nb, const double *scalars,
-                                                   const int *flags, double *row) {
+// One thermo row: the potential energy from the force pass's partials (column 0 of nbf rows), the kinetic
+// energy and momentum from the second half-kick's (columns 10-13 of nb rows), |S| and the rebuild flag.
+__global__ __launch_bounds__(kBlock) void k_thermo(const double *partials, int nb, int nbf, int *flags, double *row) {
     __shared__ double sh[kBlock / 64];
-    for (int q = 0; q < 4; q++) {
+    double epot = 0.0;
+    for (int q = -1; q < 4; q++) {
         double s = 0;
-        for (int b = threadIdx.x; b < nb; b += kBlock) s += partials[(size_t)b * 16 + 10 + q];
+        if (q < 0)
+            for (int b = threadIdx.x; b < nbf; b += kBlock) s += partials[(size_t)b * 16];
+        else
+            for (int b = threadIdx.x; b < nb; b += kBlock) s += partials[(size_t)b * 16 + 10 + q];
         for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
         __syncthreads();
         if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
@@ -246,10 +252,13 @@ __global__ __launch_bounds__(kBlock) void k_thermo(const double *partials, int n
         if (threadIdx.x == 0) {
             double t = 0;
             for (int w = 0; w < kBlock / 64; w++) t += sh[w];
-            if (q == 0) {
-                row[0] = scalars[0];
+            if (q < 0) {
+                epot = t;
+                if (!isfinite(t)) atomicOr(&flags[1], kErrNonFinite);
+            } else if (q == 0) {
+                row[0] = epot;
                 row[1] = t;
-                row[2] = scalars[0] + t;
+                row[2] = epot + t;
             } else {
                 row[2 + q] = t;
             }
@@ -279,8 +288,8 @@ void ap_ctx_destroy(ap_ctx *c) {
     void *bufs[] = {c->csp_t, c->rev_start, c->rev_code, c->pos, c->pos_build, c->d_flags, c->cell_of, c->cell_cnt,
                     c->cell_start, c->cell_fill, c->cell_atoms, c->cell_rec, c->nbr_cnt, c->nbr_idx, c->g, c->d,
                     c->wbar, c->lam, c->dlam, c->Ef, c->Ep, c->Et, c->W, c->xip, c->sidx, c->slist, c->blk_cnt,
-                    c->mark, c->fpair, c->frev, c->xg, c->xl, c->eb, c->xe, c->nbr_short, c->act, c->stamp, c->gbuf, c->partials, c->scalars, c->sid, c->b_off, c->b_box, c->bval};
-    for (void *p : bufs) hipFree(p);
+                    c->chunk_cnt, c->mark, c->fpair, c->frev, c->xg, c->xl, c->eb, c->xe, c->nbr_short, c->act, c->stamp, c->gbuf, c->partials, c->scalars, c->sid, c->b_off, c->b_box, c->bval};
+    for (void *p : bufs) (void)hipFree(p);
     delete c;
 }
 
@@ -294,7 +303,7 @@ int ap_ctx_create(ap_ctx **out, int n_max_atoms, int max_nbr, double skin, void 
     c->n_cap = n_max_atoms;
     c->max_nbr = max_nbr;
     c->skin = skin;
-    hipGetDevice(&c->device);
+    (void)hipGetDevice(&c->device);
     const size_t n = (size_t)n_max_atoms, nb = (size_t)nblocks(n_max_atoms);
     int rc = AP_OK;
     auto alloc = [&](auto **p, size_t count, size_t elem) {
@@ -323,6 +332,7 @@ int ap_ctx_create(ap_ctx **out, int n_max_atoms, int max_nbr, double skin, void 
     alloc(&c->mark, n, 4);
     alloc(&c->sid, n, 4);
     alloc(&c->blk_cnt, 2 * nb + 2, 4);
+    alloc(&c->chunk_cnt, (n * kLanesPerAtom + kBlock - 1) / kBlock, 4);
     alloc(&c->partials, (size_t)std::max<long long>((long long)nb, force_blocks((int)n)) * 16, 8);
     alloc(&c->scalars, 16, 8);
     if (rc) {
@@ -470,15 +480,15 @@ int ap_switch_eval(ap_ctx *c, int n, const double *pos, const ap_box *box, doubl
         launch_mlp_indicator(c, n, box->L);
     else
         launch_csp_value(c, n, box->L);
-    launch_dens_desc(c, n, box->L, f, nullptr);
-    launch_compact(c, n, nullptr, 0);
+    launch_dens_desc(c, n, box->L, f, nullptr, false);
+    launch_compact(c, n, nullptr, 0, false);
     const int nb = nblocks(n);
     if (g) k_copy_d<<<nb, kBlock, 0, c->stream>>>(c->g, g, n);
     if (d) k_copy_d<<<nb, kBlock, 0, c->stream>>>(c->d, d, n);
     if (wbar) k_copy_d<<<nb, kBlock, 0, c->stream>>>(c->wbar, wbar, n);
     if (lambda) k_copy_d<<<nb, kBlock, 0, c->stream>>>(c->lam, lambda, n);
     if (dlambda) k_copy_d<<<nb, kBlock, 0, c->stream>>>(c->dlam, dlambda, n);
-    if (n_precise) hipMemcpyAsync(n_precise, c->d_flags + 2, sizeof(int32_t), hipMemcpyDeviceToDevice, c->stream);
+    if (n_precise) (void)hipMemcpyAsync(n_precise, c->d_flags + 2, sizeof(int32_t), hipMemcpyDeviceToDevice, c->stream);
     rc = hip_check(c, hipGetLastError(), "switch");
     if (!rc) rc = sync_and_check(c);
     return rc;
@@ -582,7 +592,7 @@ int ap_ace_batch_eval(ap_ctx *c, int n_struct, const int32_t *offsets, const dou
                                                        c->Et, c->xl, c->eb);
     {
         ProfScope p(c, "compact");
-        launch_compact(c, n, nullptr, 0);
+        launch_compact(c, n, nullptr, 0, false);
     }
     rc = launch_ace(c, n, boxes, std::min(n, 8192), c->b_box, want_b);
     if (rc) return rc;
@@ -667,7 +677,9 @@ int ap_vv_step(ap_ctx *c, int n, double *pos, double *vel, double *F, double mas
                                                      box->L[2], c->pos_build, 0.25 * c->skin * c->skin, c->d_flags,
                                                      c->cell_cnt, c->cell_fill, force ? 0 : c->ncell_cur);
         }
-        rc = evaluate(c, n, box->L, f, nullptr, nullptr, 0, run_ace, nullptr, nullptr, F, nullptr, force, !force);
+        // (the thermo kernel sums the force pass's energy partials itself)
+        rc = evaluate(c, n, box->L, f, nullptr, nullptr, 0, run_ace, nullptr, nullptr, F, nullptr, force, !force,
+                      false);
         if (rc) {
             c->prof_skip = false;
             return rc;
@@ -675,7 +687,7 @@ int ap_vv_step(ap_ctx *c, int n, double *pos, double *vel, double *F, double mas
         force = false;
         ProfScope p(c, "vv_second");
         k_vv_second<<<nb, kBlock, 0, c->stream>>>(vel, F, n, hdtm, mass, c->partials);
-        k_thermo<<<1, kBlock, 0, c->stream>>>(c->partials, nb, c->scalars, c->d_flags, thermo + (size_t)8 * s);
+        k_thermo<<<1, kBlock, 0, c->stream>>>(c->partials, nb, force_blocks(n), c->d_flags, thermo + (size_t)8 * s);
     }
     c->prof_skip = false;
     rc = hip_check(c, hipGetLastError(), "vv");

@@ -62,7 +62,8 @@ __global__ __launch_bounds__(kBlock) void k_dens_desc(const double *__restrict__
                                                       double *__restrict__ xip,
                                                       double *__restrict__ wbar, double *__restrict__ dd,
                                                       double *__restrict__ lam, double *__restrict__ dlam,
-                                                      double *__restrict__ Ep, double *__restrict__ Et, int *flags) {
+                                                      double *__restrict__ Ep, double *__restrict__ Et, int *flags,
+                                                      int *__restrict__ chunk_cnt) {
     // commit of the neighbour-list rebuild flag, after every list kernel of this evaluation
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         flags[3] = flags[0];
@@ -107,44 +108,59 @@ __global__ __launch_bounds__(kBlock) void k_dens_desc(const double *__restrict__
     pair = group_sum<SUB>(pair);
     ws = group_sum<SUB>(ws);
     gs = group_sum<SUB>(gs);
-    if (i >= n || sub != 0) return;
-    ws += 1.0;  // self term of Eq. (6): w(0) = 1
-    if (switching) gs += g[i];
-    double emb = 0.0, demb = 0.0;
-    if (z > 0.0) {
-        const double s = sqrt(z);
-        emb = -ep.A * s;
-        demb = -0.5 * ep.A / s;
+    bool prec = false;  // lambda_i < 1
+    if (i < n && sub == 0) {
+        ws += 1.0;  // self term of Eq. (6): w(0) = 1
+        if (switching) gs += g[i];
+        double emb = 0.0, demb = 0.0;
+        if (z > 0.0) {
+            const double s = sqrt(z);
+            emb = -ep.A * s;
+            demb = -0.5 * ep.A / s;
+        }
+        Ef[i] = emb + 0.5 * pair;
+        xip[i] = demb;
+        double l, dl = 0.0, d = 0.0;
+        if (switching) {
+            d = gs / ws - sp.d0;
+            l = ftrans(d, sp.d_lo, sp.d_hi);
+            dl = ftrans_d(d, sp.d_lo, sp.d_hi);
+        } else {
+            l = lam_in ? lam_in[i] : lam_const;
+            ws = 1.0;
+        }
+        wbar[i] = ws;
+        dd[i] = d;
+        lam[i] = l;
+        dlam[i] = dl;
+        Ep[i] = 0.0;
+        Et[i] = 0.0;
+        xl[i] = Rec4{pos[i], pos[n + i], pos[2 * n + i], l};
+        eb[i] = Rec4{demb, switching ? g[i] : 0.0, d + sp.d0, 0.0};
+        xe[i] = Rec4{pos[i], pos[n + i], pos[2 * n + i], demb};
+        prec = l < 1.0;
     }
-    Ef[i] = emb + 0.5 * pair;
-    xip[i] = demb;
-    double l, dl = 0.0, d = 0.0;
-    if (switching) {
-        d = gs / ws - sp.d0;
-        l = ftrans(d, sp.d_lo, sp.d_hi);
-        dl = ftrans_d(d, sp.d_lo, sp.d_hi);
-    } else {
-        l = lam_in ? lam_in[i] : lam_const;
-        ws = 1.0;
+    if (chunk_cnt) {
+        // the count of precise atoms among this workgroup's kBlock / SUB atoms, for the compaction
+        __shared__ int sc[kBlock / 64];
+        const unsigned long long m = __ballot(prec);
+        if ((threadIdx.x & 63) == 0) sc[threadIdx.x >> 6] = __popcll(m);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int s = 0;
+            for (int w = 0; w < kBlock / 64; w++) s += sc[w];
+            chunk_cnt[t / (int)blockDim.x] = s;
+        }
     }
-    wbar[i] = ws;
-    dd[i] = d;
-    lam[i] = l;
-    dlam[i] = dl;
-    Ep[i] = 0.0;
-    Et[i] = 0.0;
-    xl[i] = Rec4{pos[i], pos[n + i], pos[2 * n + i], l};
-    eb[i] = Rec4{demb, switching ? g[i] : 0.0, d + sp.d0, 0.0};
-    xe[i] = Rec4{pos[i], pos[n + i], pos[2 * n + i], demb};
 }
 
-void launch_dens_desc(ap_ctx *c, int n, const double *box, const EvalFlags &f, const double *lam_in) {
+void launch_dens_desc(ap_ctx *c, int n, const double *box, const EvalFlags &f, const double *lam_in, bool count) {
     const SwP sp{c->sw.d_lo, c->sw.d_hi, c->sw.r_w, c->sw.r_w * c->sw.r_w, c->sw.d0, 1.0 / (c->sw.r_w - (c->sw.r_w - 1.0))};
     constexpr int SUB = kLanesPerAtom;
     k_dens_desc<SUB><<<((size_t)n * SUB + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(
         c->pos, n, box[0], box[1], box[2], eamp(c->eam), sp, f.switching ? 1 : 0, f.lam_const, lam_in, c->nbr_cnt,
         c->nbr_idx, c->g, c->xg, c->xl, c->eb, c->xe, c->Ef, c->xip, c->wbar, c->d, c->lam, c->dlam, c->Ep, c->Et,
-        c->d_flags);
+        c->d_flags, count ? c->chunk_cnt : nullptr);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -203,8 +219,52 @@ __global__ void k_mark_subset(const int32_t *__restrict__ subset, int m, int n, 
     mark[i] = 1;
 }
 
-void launch_compact(ap_ctx *c, int n, const int32_t *subset, int n_subset) {
+// Ordered compaction from the density pass's counts of lambda < 1 per kBlock / kLanesPerAtom atoms: each
+// workgroup of kBlock atoms sums the counts before it (integers: exact in any order) and ranks its own
+// atoms by ballot; the last one writes |S|.
+__global__ __launch_bounds__(kBlock) void k_compact_chunks(int n, const double *__restrict__ lam,
+                                                           const int *__restrict__ chunk_cnt, int per_block,
+                                                           int *__restrict__ sidx, int *__restrict__ slist,
+                                                           int *__restrict__ S_out) {
+    __shared__ int sh[kBlock / 64], sb[kBlock / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int part = 0;
+    for (int q = threadIdx.x; q < (int)blockIdx.x * per_block; q += blockDim.x) part += chunk_cnt[q];
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_down(part, o, 64);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool f = i < n && lam[i] < 1.0;
+    const unsigned long long m = __ballot(f);
+    if (lane == 0) {
+        sb[w] = part;
+        sh[w] = __popcll(m);
+    }
+    __syncthreads();
+    int off = 0;
+    for (int q = 0; q < kBlock / 64; q++) off += sb[q];
+    for (int q = 0; q < w; q++) off += sh[q];
+    const int rank = __popcll(m & ((1ull << lane) - 1ull));
+    if (i < n) {
+        if (f) {
+            slist[off + rank] = i;
+            sidx[i] = off + rank;
+        } else {
+            sidx[i] = -1;
+        }
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+        int tot = 0;
+        for (int q = 0; q < kBlock / 64; q++) tot += sb[q] + sh[q];
+        *S_out = tot;
+    }
+}
+
+void launch_compact(ap_ctx *c, int n, const int32_t *subset, int n_subset, bool counted) {
     const int nb = (n + kBlock - 1) / kBlock;
+    if (counted && !subset) {
+        k_compact_chunks<<<nb, kBlock, 0, c->stream>>>(n, c->lam, c->chunk_cnt, kLanesPerAtom, c->sidx, c->slist,
+                                                       c->d_flags + 2);
+        return;
+    }
     int *mark = nullptr;
     if (subset) {
         mark = c->mark;
@@ -587,8 +647,8 @@ __global__ __launch_bounds__(1024) void k_reduce_partials(const double *__restri
 
 void launch_reduce(ap_ctx *c, int nblocks, double *E_tot, double *virial9) {
     k_reduce_partials<<<10, 1024, 0, c->stream>>>(c->partials, nblocks, c->scalars, c->d_flags);
-    if (E_tot) hipMemcpyAsync(E_tot, c->scalars, sizeof(double), hipMemcpyDeviceToDevice, c->stream);
-    if (virial9) hipMemcpyAsync(virial9, c->scalars + 1, 9 * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+    if (E_tot) (void)hipMemcpyAsync(E_tot, c->scalars, sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+    if (virial9) (void)hipMemcpyAsync(virial9, c->scalars + 1, 9 * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
 }
 
 // One thread per (structure, column): column 0 sums E^p_i, the next n_funcs columns dE_i/dc and the
