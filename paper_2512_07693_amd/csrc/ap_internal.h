@@ -175,6 +175,7 @@ struct ap_ctx {
     int *act = nullptr;            // [n] 1 if the atom or a neighbour has lambda < 1 (the force needs its full list)
     int *stamp = nullptr;          // [n] = stamp_gen when the atom is precise or in a precise atom's list
     int stamp_gen = 0;             // evaluation counter of the stamps
+    int *cmark = nullptr;          // [n] = stamp_gen when a CSP neighbour of the atom has W != 0
 
     // gathered records: xg = {x, y, z, g}, xl = {x, y, z, lambda}, eb = {xi', g, d + d0, E~}
     ap::Rec4 *xg = nullptr, *xl = nullptr, *eb = nullptr;
@@ -276,10 +277,13 @@ struct EvalFlags {
 void launch_dens_desc(ap_ctx *c, int n, const double *box, const EvalFlags &f, const double *lam_in, bool count);
 // counted: S from the density pass's chunk counts in one kernel (no subset); otherwise count, scan, scatter
 void launch_compact(ap_ctx *c, int n, const int32_t *subset, int n_subset, bool counted);
-void launch_W(ap_ctx *c, int n, const double *box, bool stamped);
-// uniform_lambda: lambda is the constant of f on every atom (no per-atom lambda from the caller)
+// stamped: only the atoms stamped by this evaluation's ACE pair kernel gather; csp_marks: also stamp (cmark)
+// the CSP neighbours of every atom with W != 0
+void launch_W(ap_ctx *c, int n, const double *box, bool stamped, bool csp_marks);
+// uniform_lambda: lambda is the constant of f on every atom (no per-atom lambda from the caller);
+// csp_marked: the W pass wrote cmark, and only marked atoms look for reverse CSP terms
 void launch_force(ap_ctx *c, int n, const double *box, const EvalFlags &f, double *E_atom, double *F,
-                  const double *sbox = nullptr, bool uniform_lambda = true);
+                  const double *sbox = nullptr, bool uniform_lambda = true, bool csp_marked = false);
 // per-structure sums of weight_i x (E^p_i, dE_i/dc, dE_i/db) over a batch (deterministic order)
 void launch_struct_reduce(ap_ctx *c, int n, int n_struct, const int *d_off, const double *weight, double *E_struct,
                           double *dEdc, double *dEdb);

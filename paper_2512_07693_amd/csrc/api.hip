@@ -128,9 +128,12 @@ static int evaluate(ap_ctx *c, int n, const double *box, const EvalFlags &f, con
         launch_fill_int(c, c->sidx, -1, n);
         launch_fill_int(c, c->d_flags + 2, 0, 1);
     }
+    // with the stamps, W != 0 only near S: the W pass marks the atoms with reverse CSP terms
+    const bool stamped = run_ace && !subset;
+    const bool csp_marks = stamped && c->sw.indicator == AP_IND_CSP && c->n_csp > 0;
     if (f.switching && f.grad_lambda) {
         ProfScope p(c, "W");
-        launch_W(c, n, box, run_ace && !subset);
+        launch_W(c, n, box, stamped, csp_marks);
     }
     if (f.switching && f.grad_lambda && c->sw.indicator == AP_IND_MLP) {
         ProfScope p(c, "mlp_gradg");
@@ -138,7 +141,7 @@ static int evaluate(ap_ctx *c, int n, const double *box, const EvalFlags &f, con
     }
     {
         ProfScope p(c, "force");
-        launch_force(c, n, box, f, E_atom, F, nullptr, lam_in == nullptr);
+        launch_force(c, n, box, f, E_atom, F, nullptr, lam_in == nullptr, csp_marks && f.switching && f.grad_lambda);
     }
     if (reduce) {
         ProfScope p(c, "reduce");
@@ -288,7 +291,7 @@ void ap_ctx_destroy(ap_ctx *c) {
     void *bufs[] = {c->csp_t, c->rev_start, c->rev_code, c->pos, c->pos_build, c->d_flags, c->cell_of, c->cell_cnt,
                     c->cell_start, c->cell_fill, c->cell_atoms, c->cell_rec, c->nbr_cnt, c->nbr_idx, c->g, c->d,
                     c->wbar, c->lam, c->dlam, c->Ef, c->Ep, c->Et, c->W, c->xip, c->sidx, c->slist, c->blk_cnt,
-                    c->chunk_cnt, c->mark, c->fpair, c->frev, c->xg, c->xl, c->eb, c->xe, c->nbr_short, c->act, c->stamp, c->gbuf, c->partials, c->scalars, c->sid, c->b_off, c->b_box, c->bval};
+                    c->chunk_cnt, c->mark, c->fpair, c->frev, c->xg, c->xl, c->eb, c->xe, c->nbr_short, c->act, c->stamp, c->cmark, c->gbuf, c->partials, c->scalars, c->sid, c->b_off, c->b_box, c->bval};
     for (void *p : bufs) (void)hipFree(p);
     delete c;
 }
@@ -321,6 +324,7 @@ int ap_ctx_create(ap_ctx **out, int n_max_atoms, int max_nbr, double skin, void 
     alloc(&c->nbr_short, n, 4);
     alloc(&c->act, n, 4);
     alloc(&c->stamp, n, 4);
+    alloc(&c->cmark, n, 4);
     double **per_atom[] = {&c->g, &c->d, &c->wbar, &c->lam, &c->dlam, &c->Ef, &c->Ep, &c->Et, &c->W, &c->xip};
     for (double **p : per_atom) alloc(p, n, 8);
     alloc(&c->xg, n, sizeof(ap::Rec4));
@@ -342,6 +346,7 @@ int ap_ctx_create(ap_ctx **out, int n_max_atoms, int max_nbr, double skin, void 
     }
     launch_fill_int(c, c->d_flags, 0, 8);
     launch_fill_int(c, c->stamp, 0, (int)n);
+    launch_fill_int(c, c->cmark, 0, (int)n);
     launch_fill_double(c, c->g, 0.0, (int)n);
     launch_fill_double(c, c->W, 0.0, (int)n);
     launch_fill_double(c, c->d, 0.0, (int)n);

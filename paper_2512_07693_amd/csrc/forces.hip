@@ -37,8 +37,15 @@ __device__ __forceinline__ void eam_pair(const EamP &p, double r, double &z, dou
 }
 
 struct SwP {
-    double d_lo, d_hi, r_w, r_w2, d0, inv_ww;  // inv_ww = 1 / (r_w - (r_w - 1)), the weight window
+    // inv_ww = 1 / (r_w - (r_w - 1)), the weight window; below lo2 (the largest double under (r_w - 1)^2)
+    // the weight is 1
+    double d_lo, d_hi, r_w, r_w2, d0, inv_ww, lo2;
 };
+static SwP swp(const ap_ctx *c) {
+    const double lo = c->sw.r_w - 1.0;
+    return {c->sw.d_lo, c->sw.d_hi, c->sw.r_w, c->sw.r_w * c->sw.r_w, c->sw.d0, 1.0 / (c->sw.r_w - lo),
+            std::nextafter(lo * lo, 0.0)};
+}
 
 // SUB lanes per atom: lane `sub` takes slots sub, sub + SUB, ...; the lane partials are combined by
 // a fixed xor butterfly inside the group (the same pairs on every lane, so the sums are identical
@@ -75,33 +82,46 @@ __global__ __launch_bounds__(kBlock) void k_dens_desc(const double *__restrict__
     if (i < n) {
         const double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
         const int cnt = ncount[i];
+        // two-deep software pipeline: the record of slot k + SUB and the index of slot k + 2 SUB are in
+        // flight while slot k is evaluated (the gathers are latency bound, not bandwidth bound)
+        // ({x, y, z, g} in one record when switching)
+        int jn = sub < cnt ? nidx[(size_t)sub * n + i] : 0;
+        Rec4 rc{0.0, 0.0, 0.0, 0.0};
+        if (sub < cnt) {
+            if (switching)
+                rc = xg[jn];
+            else
+                rc = Rec4{pos[jn], pos[n + jn], pos[2 * n + jn], 0.0};
+        }
+        jn = sub + SUB < cnt ? nidx[(size_t)(sub + SUB) * n + i] : 0;
         for (int k = sub; k < cnt; k += SUB) {
-            const int j = nidx[(size_t)k * n + i];
-            double px, py, pz, gj = 0.0;
-            if (switching) {  // {x, y, z, g} in one record
-                const Rec4 r = xg[j];
-                px = r.x;
-                py = r.y;
-                pz = r.z;
-                gj = r.w;
-            } else {
-                px = pos[j];
-                py = pos[n + j];
-                pz = pos[2 * n + j];
+            Rec4 rn = rc;
+            if (k + SUB < cnt) {
+                if (switching)
+                    rn = xg[jn];
+                else
+                    rn = Rec4{pos[jn], pos[n + jn], pos[2 * n + jn], 0.0};
             }
-            const double ux = min_image_w(px - xi, Lx), uy = min_image_w(py - yi, Ly), uz = min_image_w(pz - zi, Lz);
+            if (k + 2 * SUB < cnt) jn = nidx[(size_t)(k + 2 * SUB) * n + i];
+            const double ux = min_image_w(rc.x - xi, Lx), uy = min_image_w(rc.y - yi, Ly), uz = min_image_w(rc.z - zi, Lz);
             const double r2 = ux * ux + uy * uy + uz * uz;
-            if (r2 < ep.rc2) {
+            // one square root, taken only inside the EAM range or the weight's transition band
+            const bool in_eam = r2 < ep.rc2;
+            const bool in_band = switching && r2 > sp.lo2 && r2 < sp.r_w2;
+            double r = 0.0;
+            if (in_eam || in_band) r = sqrt(r2);
+            if (in_eam) {
                 double zz, dz, ph, dph;
-                eam_pair(ep, sqrt(r2), zz, dz, ph, dph);
+                eam_pair(ep, r, zz, dz, ph, dph);
                 z += zz;
                 pair += ph;
             }
             if (switching && r2 < sp.r_w2) {
-                const double w = ftrans_i(sqrt(r2), sp.r_w - 1.0, sp.r_w, sp.inv_ww);
+                const double w = in_band ? ftrans_i(r, sp.r_w - 1.0, sp.r_w, sp.inv_ww) : 1.0;
                 ws += w;
-                gs += gj * w;
+                gs += rc.w * w;
             }
+            rc = rn;
         }
     }
     z = group_sum<SUB>(z);
@@ -155,7 +175,7 @@ __global__ __launch_bounds__(kBlock) void k_dens_desc(const double *__restrict__
 }
 
 void launch_dens_desc(ap_ctx *c, int n, const double *box, const EvalFlags &f, const double *lam_in, bool count) {
-    const SwP sp{c->sw.d_lo, c->sw.d_hi, c->sw.r_w, c->sw.r_w * c->sw.r_w, c->sw.d0, 1.0 / (c->sw.r_w - (c->sw.r_w - 1.0))};
+    const SwP sp = swp(c);
     constexpr int SUB = kLanesPerAtom;
     k_dens_desc<SUB><<<((size_t)n * SUB + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(
         c->pos, n, box[0], box[1], box[2], eamp(c->eam), sp, f.switching ? 1 : 0, f.lam_const, lam_in, c->nbr_cnt,
@@ -287,8 +307,11 @@ __global__ __launch_bounds__(kBlock) void k_W(const double *__restrict__ pos, in
                                               const int32_t *__restrict__ nidx, const double *__restrict__ Et,
                                               const Rec4 *__restrict__ xl, const double *__restrict__ lam,
                                               double *__restrict__ W, int *__restrict__ act,
-                                              const int *__restrict__ stamp, int gen, int use_stamp) {
-    const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+                                              const int *__restrict__ stamp, int gen, int use_stamp,
+                                              const int32_t *__restrict__ csp_t, int n_csp, int *__restrict__ cmark) {
+    // plain block order: the stamped atoms are a few contiguous index ranges, and an XCD-contiguous
+    // mapping would put them all on one or two XCDs
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = t / SUB, sub = t - j * SUB;
     double s = 0.0;
     int near_s = 0;  // a neighbour with lambda < 1
@@ -298,12 +321,25 @@ __global__ __launch_bounds__(kBlock) void k_W(const double *__restrict__ pos, in
         const double xj = pos[j], yj = pos[n + j], zj = pos[2 * n + j];
         const double r_w2 = r_w * r_w;
         const int cnt = ncount[j];
+        // {x, y, z, lambda} and E~ of slot q + SUB and the index of slot q + 2 SUB in flight during slot q
+        int kn = sub + SUB < cnt ? nidx[(size_t)(sub + SUB) * n + j] : 0;
+        Rec4 pc{0.0, 0.0, 0.0, 1.0};
+        double ec = 0.0;
+        if (sub < cnt) {
+            const int k0 = nidx[(size_t)sub * n + j];
+            pc = xl[k0];
+            ec = Et[k0];
+        }
         for (int q = sub; q < cnt; q += SUB) {
-            const int k = nidx[(size_t)q * n + j];
-            near_s |= lam[k] < 1.0;
-            const double e = Et[k];
+            const Rec4 pk = pc;
+            const double e = ec;
+            if (q + SUB < cnt) {
+                pc = xl[kn];
+                ec = Et[kn];
+            }
+            if (q + 2 * SUB < cnt) kn = nidx[(size_t)(q + 2 * SUB) * n + j];
+            near_s |= pk.w < 1.0;
             if (e == 0.0) continue;
-            const Rec4 pk = xl[k];
             const double ux = min_image_w(pk.x - xj, Lx), uy = min_image_w(pk.y - yj, Ly), uz = min_image_w(pk.z - zj, Lz);
             const double r2 = ux * ux + uy * uy + uz * uz;
             if (r2 < r_w2) s += e * ftrans_i(sqrt(r2), r_w - 1.0, r_w, 1.0 / (r_w - (r_w - 1.0)));
@@ -312,19 +348,25 @@ __global__ __launch_bounds__(kBlock) void k_W(const double *__restrict__ pos, in
     s = group_sum<SUB>(s);
 #pragma unroll
     for (int m = 1; m < SUB; m <<= 1) near_s |= __shfl_xor(near_s, m, 64);
-    if (j < n && sub == 0) {
+    if (j < n) {
         const bool stamped = !use_stamp || stamp[j] == gen;
-        W[j] = stamped ? Et[j] + s : 0.0;
-        act[j] = stamped ? (near_s | (lam[j] < 1.0)) : 0;
+        const double Wj = stamped ? Et[j] + s : 0.0;
+        if (sub == 0) {
+            W[j] = Wj;
+            act[j] = stamped ? (near_s | (lam[j] < 1.0)) : 0;
+        }
+        // the atoms in j's CSP list receive a reverse term of (S27) from W_j (all writers store gen)
+        if (cmark && Wj != 0.0)
+            for (int t = sub; t < n_csp; t += SUB) cmark[csp_t[(size_t)t * n + j]] = gen;
     }
 }
 
 // stamped: the ACE pair kernel of this evaluation stamped the precise atoms' neighbourhoods
-void launch_W(ap_ctx *c, int n, const double *box, bool stamped) {
+void launch_W(ap_ctx *c, int n, const double *box, bool stamped, bool csp_marks) {
     constexpr int SUB = kLanesPerAtom;
     k_W<SUB><<<((size_t)n * SUB + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(
         c->pos, n, box[0], box[1], box[2], c->sw.r_w, c->nbr_cnt, c->nbr_idx, c->Et, c->xl, c->lam, c->W, c->act,
-        c->stamp, c->stamp_gen, stamped ? 1 : 0);
+        c->stamp, c->stamp_gen, stamped ? 1 : 0, c->csp_t, c->n_csp, csp_marks ? c->cmark : nullptr);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -357,6 +399,8 @@ struct ForceArgs {
     int short_mode;
     const int *act;
     const int32_t *nshort;
+    const int *cmark;  // null: every atom scans its reverse CSP entries; else only those with cmark == cgen
+    int cgen;
 };
 
 template <typename TF>
@@ -379,10 +423,14 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
     return s;
 }
 
-template <typename TF, int SUB>
+// FULL = false: only the EAM-only gather (every atom in that mode), compiled without the full-list loop
+// and the CSP part so that it keeps its own, lower register count
+template <typename TF, int SUB, bool FULL>
 __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
     __shared__ double sh[kBlock / 64];
-    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    // plain block order (as in the W pass): the atoms with a precise atom in reach are contiguous index
+    // ranges, spread this way over every XCD
+    const int blk = blockIdx.x;
     const int t = blk * blockDim.x + threadIdx.x;
     const int i = t / SUB, sub = t - i * SUB;  // SUB lanes per atom, slots sub, sub + SUB, ...
     const int n = a.n;
@@ -398,15 +446,22 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
         // without a precise atom in reach only the EAM pairs contribute: those are the first nshort
         // slots, and every lambda in reach equals lambda_i (no switching, or lambda = 1 all around)
         const bool eam_only = a.short_mode == 2 || (a.short_mode == 1 && !a.act[i]);
-        const int cnt = eam_only ? 0 : (a.short_mode == 3 ? a.nshort[i] : a.ncount[i]);
+        const int cnt = (!FULL || eam_only) ? 0 : (a.short_mode == 3 ? a.nshort[i] : a.ncount[i]);
         const int wi = (gl && a.ind_mlp) ? a.widx[i] : -1;
         const double *Lb = a.sbox ? a.sbox + 3 * a.sid[i] : a.L;  // own cell in a batch of cells
         const double Lx = Lb[0], Ly = Lb[1], Lz = Lb[2];
         if (eam_only && a.eam_on) {
             // (S12) with lambda_k = lambda_i, from one {x, y, z, xi'} record per neighbour
+            // (two-deep pipeline of the gathers, as in the density pass)
             const int cs = a.nshort[i];
+            int jn = sub + SUB < cs ? a.nidx[(size_t)(sub + SUB) * n + i] : 0;
+            Rec4 pc = sub < cs ? a.xe[a.nidx[(size_t)sub * n + i]] : Rec4{0.0, 0.0, 0.0, 0.0};
             for (int k = sub; k < cs; k += SUB) {
-                const Rec4 pj = a.xe[a.nidx[(size_t)k * n + i]];
+                Rec4 pn = pc;
+                if (k + SUB < cs) pn = a.xe[jn];
+                if (k + 2 * SUB < cs) jn = a.nidx[(size_t)(k + 2 * SUB) * n + i];
+                const Rec4 pj = pc;
+                pc = pn;
                 const double ux = min_image_w(pj.x - xi, Lx), uy = min_image_w(pj.y - yi, Ly),
                              uz = min_image_w(pj.z - zi, Lz);
                 const double r2 = ux * ux + uy * uy + uz * uz;
@@ -426,101 +481,113 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
                 }
             }
         }
-        for (int k = sub; k < cnt; k += SUB) {
-            const int j = a.nidx[(size_t)k * n + i];
-            const Rec4 pj = a.xl[j];
-            Rec4 qj{0.0, 0.0, 0.0, 0.0};
-            if (a.eam_on || gl) qj = a.eb[j];
-            const double ux = min_image_w(pj.x - xi, Lx), uy = min_image_w(pj.y - yi, Ly), uz = min_image_w(pj.z - zi, Lz);
-            const double r2 = ux * ux + uy * uy + uz * uz;
-            const double r = sqrt(r2), ir = 1.0 / r;
-            const double ex = ux * ir, ey = uy * ir, ez = uz * ir;
-            const double lj = pj.w;
-            if (a.eam_on && r2 < a.ep.rc2) {
-                double zz, dz, ph, dph;
-                eam_pair(a.ep, r, zz, dz, ph, dph);
-                // lambda_i f_ki - lambda_k f_ik, (S12), along rhat_ki = u / r
-                const double own = li * (xpi * dz + 0.5 * dph);
-                const double s = own + lj * (qj.x * dz + 0.5 * dph);
-                F0 += s * ex;
-                F1 += s * ey;
-                F2 += s * ez;
-                // virial of the edge owned by i: -(d(lambda_i E_i)/du)_a u_b
-                const double t = -own * ir;
-                v[0] += t * ux * ux; v[1] += t * ux * uy; v[2] += t * ux * uz;
-                v[3] += t * uy * ux; v[4] += t * uy * uy; v[5] += t * uy * uz;
-                v[6] += t * uz * ux; v[7] += t * uz * uy; v[8] += t * uz * uz;
+        if (cnt > 0) {  // the full-list loop; its gathers run one slot ahead (indices two)
+            const bool need_q = a.eam_on || gl;
+            int jc = sub < cnt ? a.nidx[(size_t)sub * n + i] : 0;
+            Rec4 pc{0.0, 0.0, 0.0, 0.0}, qc{0.0, 0.0, 0.0, 0.0};
+            int sc = -1;
+            if (sub < cnt) {
+                pc = a.xl[jc];
+                if (need_q) qc = a.eb[jc];
+                sc = a.sidx[jc];
             }
-            if (gl && r2 < a.sp.r_w2) {
-                // weight part (S19)-(S21): F_i -= (s_i + s_k) u / r
-                const double dw = ftrans_d_i(r, a.sp.r_w - 1.0, a.sp.r_w, a.sp.inv_ww);
-                const double s_i = Eti * (qj.y - di - a.sp.d0) * dw;
-                const double s_k = qj.w * (gi - qj.z) * dw;
-                const double s = -(s_i + s_k);
-                F0 += s * ex;
-                F1 += s * ey;
-                F2 += s * ez;
-                const double t = s_i * ir;
-                v[0] += t * ux * ux; v[1] += t * ux * uy; v[2] += t * ux * uz;
-                v[3] += t * uy * ux; v[4] += t * uy * uy; v[5] += t * uy * uz;
-                v[6] += t * uz * ux; v[7] += t * uz * uy; v[8] += t * uz * uz;
-            }
-            if (gl && a.ind_mlp) {
-                // learned indicator, (S16): F_i -= W_i dg_i/du_ik (own), F_i += W_j dg_j/du_ji (j's)
-                if (wi >= 0) {
-                    const float *h = a.hpair + ((size_t)wi * a.max_nbr + k) * 3;
-                    const double hx = (double)h[0], hy = (double)h[1], hz = (double)h[2];
-                    F0 -= hx;
-                    F1 -= hy;
-                    F2 -= hz;
-                    v[0] += hx * ux; v[1] += hx * uy; v[2] += hx * uz;
-                    v[3] += hy * ux; v[4] += hy * uy; v[5] += hy * uz;
-                    v[6] += hz * ux; v[7] += hz * uy; v[8] += hz * uz;
+            int jn = sub + SUB < cnt ? a.nidx[(size_t)(sub + SUB) * n + i] : 0;
+            for (int k = sub; k < cnt; k += SUB) {
+                const int j = jc;
+                const Rec4 pj = pc, qj = qc;
+                const int sj = sc;
+                if (k + SUB < cnt) {
+                    jc = jn;
+                    pc = a.xl[jn];
+                    if (need_q) qc = a.eb[jn];
+                    sc = a.sidx[jn];
                 }
-                if (a.widx[j] >= 0) {
-                    const size_t st = (size_t)a.max_nbr * n, o = (size_t)k * n + i;
-                    F0 += (double)a.hrev[o];
-                    F1 += (double)a.hrev[st + o];
-                    F2 += (double)a.hrev[2 * st + o];
+                if (k + 2 * SUB < cnt) jn = a.nidx[(size_t)(k + 2 * SUB) * n + i];
+                const double ux = min_image_w(pj.x - xi, Lx), uy = min_image_w(pj.y - yi, Ly), uz = min_image_w(pj.z - zi, Lz);
+                const double r2 = ux * ux + uy * uy + uz * uz;
+                const double r = sqrt(r2), ir = 1.0 / r;
+                const double ex = ux * ir, ey = uy * ir, ez = uz * ir;
+                const double lj = pj.w;
+                if (a.eam_on && r2 < a.ep.rc2) {
+                    double zz, dz, ph, dph;
+                    eam_pair(a.ep, r, zz, dz, ph, dph);
+                    // lambda_i f_ki - lambda_k f_ik, (S12), along rhat_ki = u / r
+                    const double own = li * (xpi * dz + 0.5 * dph);
+                    const double s = own + lj * (qj.x * dz + 0.5 * dph);
+                    F0 += s * ex;
+                    F1 += s * ey;
+                    F2 += s * ez;
+                    // virial of the edge owned by i: -(d(lambda_i E_i)/du)_a u_b
+                    const double t = -own * ir;
+                    v[0] += t * ux * ux; v[1] += t * ux * uy; v[2] += t * ux * uz;
+                    v[3] += t * uy * ux; v[4] += t * uy * uy; v[5] += t * uy * uz;
+                    v[6] += t * uz * ux; v[7] += t * uz * uy; v[8] += t * uz * uz;
                 }
-            }
-            if (a.ace_on) {
-                // (S14): (1 - lambda_i) f_ki from i's own site, minus (1 - lambda_k) f_ik from k's site
-                if (si >= 0) {
-                    double fx, fy, fz;
-                    load_f(fp, ((size_t)si * a.max_nbr + k) * 3, fx, fy, fz);
-                    const double wgt = 1.0 - li;
-                    F0 += wgt * fx;
-                    F1 += wgt * fy;
-                    F2 += wgt * fz;
-                    v[0] -= wgt * fx * ux; v[1] -= wgt * fx * uy; v[2] -= wgt * fx * uz;
-                    v[3] -= wgt * fy * ux; v[4] -= wgt * fy * uy; v[5] -= wgt * fy * uz;
-                    v[6] -= wgt * fz * ux; v[7] -= wgt * fz * uy; v[8] -= wgt * fz * uz;
+                if (gl && r2 < a.sp.r_w2) {
+                    // weight part (S19)-(S21): F_i -= (s_i + s_k) u / r
+                    const double dw = ftrans_d_i(r, a.sp.r_w - 1.0, a.sp.r_w, a.sp.inv_ww);
+                    const double s_i = Eti * (qj.y - di - a.sp.d0) * dw;
+                    const double s_k = qj.w * (gi - qj.z) * dw;
+                    const double s = -(s_i + s_k);
+                    F0 += s * ex;
+                    F1 += s * ey;
+                    F2 += s * ez;
+                    const double t = s_i * ir;
+                    v[0] += t * ux * ux; v[1] += t * ux * uy; v[2] += t * ux * uz;
+                    v[3] += t * uy * ux; v[4] += t * uy * uy; v[5] += t * uy * uz;
+                    v[6] += t * uz * ux; v[7] += t * uz * uy; v[8] += t * uz * uz;
                 }
-                if (a.sidx[j] >= 0) {  // precise j: its term for this pair, stored at (k, i)
-                    const TF *fr = reinterpret_cast<const TF *>(a.frev);
-                    const size_t st = (size_t)a.max_nbr * n, o = (size_t)k * n + i;
-                    const double fx = (double)fr[o], fy = (double)fr[st + o], fz = (double)fr[2 * st + o];
-                    const double wgt = 1.0 - lj;
-                    F0 -= wgt * fx;
-                    F1 -= wgt * fy;
-                    F2 -= wgt * fz;
+                if (gl && a.ind_mlp) {
+                    // learned indicator, (S16): F_i -= W_i dg_i/du_ik (own), F_i += W_j dg_j/du_ji (j's)
+                    if (wi >= 0) {
+                        const float *h = a.hpair + ((size_t)wi * a.max_nbr + k) * 3;
+                        const double hx = (double)h[0], hy = (double)h[1], hz = (double)h[2];
+                        F0 -= hx;
+                        F1 -= hy;
+                        F2 -= hz;
+                        v[0] += hx * ux; v[1] += hx * uy; v[2] += hx * uz;
+                        v[3] += hy * ux; v[4] += hy * uy; v[5] += hy * uz;
+                        v[6] += hz * ux; v[7] += hz * uy; v[8] += hz * uz;
+                    }
+                    if (a.widx[j] >= 0) {
+                        const size_t st = (size_t)a.max_nbr * n, o = (size_t)k * n + i;
+                        F0 += (double)a.hrev[o];
+                        F1 += (double)a.hrev[st + o];
+                        F2 += (double)a.hrev[2 * st + o];
+                    }
+                }
+                if (a.ace_on) {
+                    // (S14): (1 - lambda_i) f_ki from i's own site, minus (1 - lambda_k) f_ik from k's site
+                    if (si >= 0) {
+                        double fx, fy, fz;
+                        load_f(fp, ((size_t)si * a.max_nbr + k) * 3, fx, fy, fz);
+                        const double wgt = 1.0 - li;
+                        F0 += wgt * fx;
+                        F1 += wgt * fy;
+                        F2 += wgt * fz;
+                        v[0] -= wgt * fx * ux; v[1] -= wgt * fx * uy; v[2] -= wgt * fx * uz;
+                        v[3] -= wgt * fy * ux; v[4] -= wgt * fy * uy; v[5] -= wgt * fy * uz;
+                        v[6] -= wgt * fz * ux; v[7] -= wgt * fz * uy; v[8] -= wgt * fz * uz;
+                    }
+                    if (sj >= 0) {  // precise j: its term for this pair, stored at (k, i)
+                        const TF *fr = reinterpret_cast<const TF *>(a.frev);
+                        const size_t st = (size_t)a.max_nbr * n, o = (size_t)k * n + i;
+                        const double fx = (double)fr[o], fy = (double)fr[st + o], fz = (double)fr[2 * st + o];
+                        const double wgt = 1.0 - lj;
+                        F0 -= wgt * fx;
+                        F1 -= wgt * fy;
+                        F2 -= wgt * fz;
+                    }
                 }
             }
         }
-    }
-    F0 = group_sum<SUB>(F0);
-    F1 = group_sum<SUB>(F1);
-    F2 = group_sum<SUB>(F2);
-    if (i < n && sub == 0) {
-        const double xi = a.pos[i], yi = a.pos[n + i], zi = a.pos[2 * n + i];
-        const double li = a.lam[i];
-        if (gl && !a.ind_mlp) {
-            // CSP part (S24)-(S27): own list 2 W_i sum_l (r_il + r_i,opp(l)); reverse entries
-            // -2 W_j (r_ji + r_j,opp(i)).
+        if (FULL && gl && !a.ind_mlp) {
+            // CSP part (S24)-(S27), its terms spread over the atom's SUB lanes: own list 2 W_i sum_l (r_il +
+            // r_i,opp(l)); reverse entries -2 W_j (r_ji + r_j,opp(i)), looked for only where the W pass marked
+            // a CSP neighbour with W_j != 0
             const double Wi = a.W[i];
             if (Wi != 0.0) {
-                for (int t = 0; t < a.n_csp; t++) {
+                for (int t = sub; t < a.n_csp; t += SUB) {
                     const int l = a.csp_t[(size_t)t * n + i], o = a.csp_t[(size_t)(t ^ 1) * n + i];
                     const double lx = min_image_w(a.pos[l] - xi, a.L[0]), ly = min_image_w(a.pos[n + l] - yi, a.L[1]),
                                  lz = min_image_w(a.pos[2 * n + l] - zi, a.L[2]);
@@ -536,22 +603,30 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
                     v[6] += t2 * sz * lx; v[7] += t2 * sz * ly; v[8] += t2 * sz * lz;
                 }
             }
-            const int rb = a.rev_start[i], re = a.rev_start[i + 1];
-            for (int q = rb; q < re; q++) {
-                const int code = a.rev_code[q];
-                const int jj = code >> 4, t = code & 15;
-                const double Wj = a.W[jj];
-                if (Wj == 0.0) continue;
-                const int o = a.csp_t[(size_t)(t ^ 1) * n + jj];
-                const double xj = a.pos[jj], yj = a.pos[n + jj], zj = a.pos[2 * n + jj];
-                const double sx = min_image_w(xi - xj, a.L[0]) + min_image_w(a.pos[o] - xj, a.L[0]);
-                const double sy = min_image_w(yi - yj, a.L[1]) + min_image_w(a.pos[n + o] - yj, a.L[1]);
-                const double sz = min_image_w(zi - zj, a.L[2]) + min_image_w(a.pos[2 * n + o] - zj, a.L[2]);
-                F0 += 2.0 * Wj * sx;
-                F1 += 2.0 * Wj * sy;
-                F2 += 2.0 * Wj * sz;
+            if (!a.cmark || a.cmark[i] == a.cgen) {
+                const int rb = a.rev_start[i], re = a.rev_start[i + 1];
+                for (int q = rb + sub; q < re; q += SUB) {
+                    const int code = a.rev_code[q];
+                    const int jj = code >> 4, t = code & 15;
+                    const double Wj = a.W[jj];
+                    if (Wj == 0.0) continue;
+                    const int o = a.csp_t[(size_t)(t ^ 1) * n + jj];
+                    const double xj = a.pos[jj], yj = a.pos[n + jj], zj = a.pos[2 * n + jj];
+                    const double sx = min_image_w(xi - xj, a.L[0]) + min_image_w(a.pos[o] - xj, a.L[0]);
+                    const double sy = min_image_w(yi - yj, a.L[1]) + min_image_w(a.pos[n + o] - yj, a.L[1]);
+                    const double sz = min_image_w(zi - zj, a.L[2]) + min_image_w(a.pos[2 * n + o] - zj, a.L[2]);
+                    F0 += 2.0 * Wj * sx;
+                    F1 += 2.0 * Wj * sy;
+                    F2 += 2.0 * Wj * sz;
+                }
             }
         }
+    }
+    F0 = group_sum<SUB>(F0);
+    F1 = group_sum<SUB>(F1);
+    F2 = group_sum<SUB>(F2);
+    if (i < n && sub == 0) {
+        const double li = a.lam[i];
         Ei = li * a.Ef[i] + (1.0 - li) * a.Ep[i];
         if (a.E_atom) a.E_atom[i] = Ei;
         if (a.F) {
@@ -570,15 +645,17 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
 }
 
 void launch_force(ap_ctx *c, int n, const double *box, const EvalFlags &f, double *E_atom, double *F,
-                  const double *sbox, bool uniform_lambda) {
+                  const double *sbox, bool uniform_lambda, bool csp_marked) {
     ForceArgs a;
+    a.cmark = csp_marked ? c->cmark : nullptr;
+    a.cgen = c->stamp_gen;
     a.sbox = sbox;
     a.sid = c->sid;
     a.pos = c->pos;
     a.n = n;
     for (int q = 0; q < 3; q++) a.L[q] = box[q];
     a.ep = eamp(c->eam);
-    a.sp = SwP{c->sw.d_lo, c->sw.d_hi, c->sw.r_w, c->sw.r_w * c->sw.r_w, c->sw.d0, 1.0 / (c->sw.r_w - (c->sw.r_w - 1.0))};
+    a.sp = swp(c);
     a.switching = f.switching;
     a.grad_lambda = f.grad_lambda;
     a.eam_on = f.eam_forces;
@@ -621,10 +698,12 @@ void launch_force(ap_ctx *c, int n, const double *box, const EvalFlags &f, doubl
     if (!sbox && f.switching && f.grad_lambda && c->sw.indicator == AP_IND_CSP) a.short_mode = 1;
     if (!sbox && !f.switching && (!f.ace_forces || f.lam_const == 1.0)) a.short_mode = uniform_lambda ? 2 : 3;
     const int nb = force_blocks(n);
-    if (a.fp32)
-        k_force<float, kForceLanes><<<nb, kBlock, 0, c->stream>>>(a);
+    if (a.short_mode == 2)
+        k_force<double, kForceLanes, false><<<nb, kBlock, 0, c->stream>>>(a);
+    else if (a.fp32)
+        k_force<float, kForceLanes, true><<<nb, kBlock, 0, c->stream>>>(a);
     else
-        k_force<double, kForceLanes><<<nb, kBlock, 0, c->stream>>>(a);
+        k_force<double, kForceLanes, true><<<nb, kBlock, 0, c->stream>>>(a);
 }
 
 // Sums the per-block partials [nb][16] (energy, virial) in a fixed order, one workgroup per column.
