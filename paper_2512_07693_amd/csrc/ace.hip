@@ -35,10 +35,12 @@ struct AceArgs {
     double *Ep, *Et;
     void *gbuf;     // [S][n_max * nlm] the atomic basis A
     double *s0buf;  // [S][n_max] FP64 sums of the radial channels over the neighbours
-    void *gpart;    // [2][gstride][n_max * nlm] dE/dA, whole or in two halves of the coupling blocks
-    double *epart;  // [S][2] the site energy, whole or in two halves
+    // dE/dA [2][gstride][n_max * nlm]: row s of the first region holds atom s whole or its part 0; part
+    // p >= 1 of split atom whole + r is row (p - 1) R + r of the second (R atoms split)
+    void *gpart;
+    double *epart;  // [kMaxParts][gstride] the site energy of each part
     int gstride;    // capacity in atoms
-    int nsplit;     // first coupling block of the second half
+    int n0;         // leading L = 0 blocks (the parts share out the blocks after them)
     int slots;      // energy-kernel workgroups resident at once on the device
     int *queue;     // work-item counter of the energy kernel
     int *stamp;     // [n] set to gen for every precise atom and every atom in its list (null: not kept)
@@ -154,21 +156,32 @@ __device__ __forceinline__ void ld4(const T *p, T *o) {
 }
 
 // Work plan of the energy kernel. The per-atom time is a chain of dependent block steps, about as long
-// with one workgroup on a CU as with four (0.20 against 0.23 ms at n_max 12, l_max 6), and a half chain
-// takes about 0.62 of it. So the atoms that fill whole rounds of the resident workgroups (slots) are
-// taken whole, and the remaining R atoms of a last, partial round are split into two halves of their
-// coupling blocks when the 2 R halves fit one round: atoms s < whole are one work item each, atoms
-// s >= whole two (items whole + 2 (s - whole) and the next). Computed from the device-side S alone,
-// the same way by the energy kernel and by the pair kernel that adds the halves.
-__device__ __forceinline__ void ace_plan(int S, int slots, int &whole, int &items) {
+// with one workgroup on a CU as with four (0.20 against 0.23 ms at n_max 12, l_max 6). So the atoms
+// that fill whole rounds of the resident workgroups (slots) are taken whole, and the remaining R atoms
+// of a last, partial round are split into P = min(kMaxParts, slots / R) parts of their coupling blocks,
+// so that the P R parts fill that round: atoms s < whole are one work item each, atom whole + r is the
+// P items whole + P r + p. (P is also capped so that the extra parts' rows fit the scratch rows.)
+// Computed from the device-side S alone, the same way by the energy kernel and by the pair kernel that
+// adds the parts.
+constexpr int kMaxParts = 4;
+__device__ __forceinline__ void ace_plan(int S, int slots, int cap, int &whole, int &items, int &parts) {
     const int R = S % slots;
-    if (R > 0 && 2LL * R <= slots) {
+    int P = R > 0 ? slots / R : 1;
+    if (P > kMaxParts) P = kMaxParts;
+    if (P > 1 && (long long)(P - 1) * R > cap) P = 1 + cap / R;
+    if (P >= 2) {
         whole = S - R;
-        items = whole + 2 * R;
+        items = whole + P * R;
+        parts = P;
     } else {
         whole = S;
         items = S;
+        parts = 1;
     }
+}
+// first coupling block of part p of P: equal shares of the blocks after the n0 leading L = 0 ones
+__device__ __forceinline__ int ace_part_block(int p, int P, int n0, int nblk) {
+    return p == 0 ? 0 : n0 + (nblk - n0) * p / P;
 }
 
 template <typename T, int NMAX, int LMAX>
@@ -311,16 +324,18 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
     const T *c1 = (const T *)a.c1, *bd = (const T *)a.bd, *c2 = (const T *)a.c2, *c3 = (const T *)a.c3;
     const T *kval = (const T *)a.kval;
     const int S = *a.scount;
-    int whole, items;
-    ace_plan(S, a.slots, whole, items);
+    int whole, items, parts;
+    ace_plan(S, a.slots, a.gstride, whole, items, parts);
+    const int R = S - whole;
     // a persistent grid: workgroup b takes item b, then the next items in order from a device counter
-    // (zeroed by the basis kernel): whole atoms first, then the halves. Half 0 takes orders 1-2 and the
-    // blocks before nsplit, half 1 the others; each item writes its own dE/dA and energy, added by the
-    // pair kernel in a fixed order.
+    // (zeroed by the basis kernel): whole atoms first, then the parts. Part 0 takes orders 1-2 and its
+    // share of the blocks, the other parts theirs; each item writes its own dE/dA and energy, added by
+    // the pair kernel in a fixed order.
     __shared__ int sItem;
     for (int w = blockIdx.x; w < items;) {
         const bool K2 = w >= whole;
-        const int s = K2 ? whole + ((w - whole) >> 1) : w, h = K2 ? (w - whole) & 1 : 0;
+        const int r = K2 ? (w - whole) / parts : 0, h = K2 ? (w - whole) - r * parts : 0;
+        const int s = K2 ? whole + r : w;
         const T *ain = (const T *)a.gbuf + (size_t)s * NA;
         for (int o = tid; o < NA; o += kBlock) {
             const int q = o / NLM, lm = o - q * NLM;
@@ -434,7 +449,8 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
         }
         }
         // ---- phase 3b: order-3 blocks ----
-        const int b_lo = K2 && h == 1 ? a.nsplit : 0, b_hi = K2 && h == 0 ? a.nsplit : a.nblk;
+        const int b_lo = K2 ? ace_part_block(h, parts, a.n0, a.nblk) : 0;
+        const int b_hi = K2 && h + 1 < parts ? ace_part_block(h + 1, parts, a.n0, a.nblk) : a.nblk;
         for (int b = b_lo; b < b_hi; b++) {
             const int *bk = a.blk + b * kBlkInts;
             const int L = bk[0], l1 = bk[1], l2 = bk[2];
@@ -580,10 +596,10 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
         __syncthreads();
         // ---- outputs: this part's energy and dE/dA ----
         const double E = block_sum_d(e, sRed);
-        T *gout = (T *)a.gpart + ((size_t)h * a.gstride + s) * NA;
+        T *gout = (T *)a.gpart + (h == 0 ? (size_t)s : (size_t)a.gstride + (size_t)(h - 1) * R + r) * NA;
         for (int o = tid; o < NA; o += kBlock) gout[o] = sG[o];
         if (tid == 0) {
-            a.epart[2 * s + h] = E;
+            a.epart[(size_t)h * a.gstride + s] = E;
             sItem = (int)gridDim.x + atomicAdd(a.queue, 1);
         }
         __syncthreads();
@@ -601,17 +617,20 @@ __global__ __launch_bounds__(128) void k_ace_pairforce(AceArgs a) {
     const T rcT = (T)a.rc;
     for (int s = blockIdx.x; s < S; s += gridDim.x) {
         const int i = a.slist[s];
-        // G = dE/dA and the site energy from the energy kernel's one or two parts, added in a fixed order
-        int whole, items;
-        ace_plan(S, a.slots, whole, items);
-        const bool two = s >= whole;
-        const T *g0 = (const T *)a.gpart + (size_t)s * NA, *g1 = g0 + (size_t)a.gstride * NA;
+        // G = dE/dA and the site energy from the energy kernel's parts, added in part order
+        int whole, items, parts;
+        ace_plan(S, a.slots, a.gstride, whole, items, parts);
+        const int P = s >= whole ? parts : 1, R = S - whole, r = s - whole;
+        const T *g0 = (const T *)a.gpart + (size_t)s * NA;
         for (int o = threadIdx.x; o < NA; o += blockDim.x) {
             const int q = o / NLM, lm = o - q * NLM;
-            sGt[lm * NMAX + q] = two ? g0[o] + g1[o] : g0[o];
+            T g = g0[o];
+            for (int p = 1; p < P; p++) g += ((const T *)a.gpart)[((size_t)a.gstride + (size_t)(p - 1) * R + r) * NA + o];
+            sGt[lm * NMAX + q] = g;
         }
         if (threadIdx.x == 0) {
-            const double E = two ? a.epart[2 * s] + a.epart[2 * s + 1] : a.epart[2 * s];
+            double E = a.epart[s];
+            for (int p = 1; p < P; p++) E += a.epart[(size_t)p * a.gstride + s];
             a.Ep[i] = E;
             const double et = (E - a.Ef[i]) * a.dlam[i] / a.wbar[i];
             a.Et[i] = et;
@@ -978,13 +997,13 @@ int ace_setup(ap_ctx *c, const ap_ace_params *p) {
     }
     t.nblk = nb;
     t.h_blk = hblk;
-    // the two parts of a split atom get equal numbers of the blocks they run (each block is about one
-    // step of the per-atom chain, whatever its size; the L = 0 blocks, first in the table, are folded
-    // into order 2 unless coefficient gradients are asked for); the first part also takes orders 1-2
+    // the parts of a split atom get equal numbers of the blocks they run (each block is about one step
+    // of the per-atom chain, whatever its size; the L = 0 blocks, first in the table, are folded into
+    // order 2 unless coefficient gradients are asked for); the first part also takes orders 1-2
     {
         int n0 = 0;
         while (n0 < nb && hblk[(size_t)n0 * kBlkInts] == 0) n0++;
-        t.nsplit = n0 + (nb - n0) / 2;
+        t.n0 = n0;
     }
     t.ng1 = (int)g1.size() / 2;
     t.ng2 = (int)g2.size() / 2;
@@ -1107,7 +1126,7 @@ int launch_ace(ap_ctx *c, int n, const double *box, int grid_cap, const double *
     a.gbuf = c->gbuf;
     {
         // scratch layout: A [n_cap][NA], radial sums [n_cap][n_max], dE/dA parts [2][n_cap][NA], energy parts
-        // [n_cap][2]
+        // [kMaxParts][n_cap]
         const size_t abytes = (size_t)c->n_cap * t.n_max * (t.l_max + 1) * (t.l_max + 1) *
                               (t.precision == AP_FP32 ? 4 : 8);
         char *base = (char *)c->gbuf;
@@ -1115,7 +1134,7 @@ int launch_ace(ap_ctx *c, int n, const double *box, int grid_cap, const double *
         a.gpart = base + abytes + (size_t)c->n_cap * t.n_max * sizeof(double);
         a.epart = (double *)(base + 3 * abytes + (size_t)c->n_cap * t.n_max * sizeof(double));
         a.gstride = c->n_cap;
-        a.nsplit = t.nsplit;
+        a.n0 = t.n0;
         a.queue = c->d_flags + 6;
         a.c30 = t.c30;
         a.kap0 = t.kap0;

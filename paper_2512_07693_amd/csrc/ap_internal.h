@@ -111,7 +111,7 @@ struct AceTables {
     void *kval = nullptr; // coupling values, three orderings (by M, by m1, by m2)
     int *kidx = nullptr;  // packed (m1 + 8) | (m2 + 8) << 8 | (M + 8) << 16, same three orderings
     int *blk = nullptr;   // [nblk][kBlkInts] block descriptors
-    int nsplit = 0;       // first block of the second part when an atom is split over two workgroups
+    int n0 = 0;           // leading L = 0 blocks; the parts of a split atom share out the blocks after them
     // the L = 0 blocks (0, l, l) in closed form: C0[l][n1][n2][n3] and their coupling kappa_l (null when
     // a block does not have the single-value diagonal form)
     void *c30 = nullptr, *kap0 = nullptr;

@@ -374,9 +374,9 @@ int ap_set_potential(ap_ctx *c, const ap_eam_params *eam, const ap_ace_params *a
     if (rc) return rc;
     const int NA = ace->n_max * (ace->l_max + 1) * (ace->l_max + 1);
     const size_t es = ace->precision == AP_FP32 ? 4 : 8;
-    // ACE scratch per S atom: A, the FP64 radial sums, two parts of dE/dA and of the site energy
+    // ACE scratch per S atom: A, the FP64 radial sums, two rows of dE/dA parts and four site-energy parts
     const size_t fb = (size_t)c->n_cap * c->max_nbr * 3 * es,
-                 gb = (size_t)c->n_cap * (3 * NA * es + ace->n_max * sizeof(double) + 2 * sizeof(double));
+                 gb = (size_t)c->n_cap * (3 * NA * es + ace->n_max * sizeof(double) + 4 * sizeof(double));
     if (fb != c->fpair_bytes) {
         (void)hipFree(c->fpair);
         c->fpair = nullptr;
