@@ -81,17 +81,18 @@ def algorithmic_bytes(kernel, n, nnb, n_s, nnb_rc, n_csp, n_near=None, nnb_short
         n_near, nnb_short = n, nnb
     full = {
         "dens_desc": 4 * nnb + 4 + 24 + 8 + 8 * 8,        # list + count, position, g; 8 outputs
-        "force": 4 * nnb + 4 + 24 + 8 * 8 + 4 + 32,      # list + count, position, 8 own scalars, sidx, F, E_i
+        "force": 4 * nnb + 4 + 24 + 8 * 8 + 4 + 32 + 48,  # list + count, position, 8 own scalars, sidx, F, E_i,
+                                                          # the half-kick's velocity in and out
         "W": 4 * nnb + 4 + 4 + 24 + 8 + 8 + 12,          # list + count, flag, position, E~, lambda; W, act
         "csp_value": 4 * n_csp + 24 + 8,
         "vv_first": 6 * 8 + 3 * 8 + 6 * 8,
-        "vv_second": 6 * 8 + 3 * 8,
     }.get(kernel)
     if full is None:
         return None
     # the atoms away from every precise atom
     far = {"W": 4 + 12,                                                   # flag; W, act
-           "force": 4 * nnb_short + 4 + 4 + 24 + 4 * 8 + 32}.get(kernel)  # short list, flag, own 4 scalars
+           "force": 4 * nnb_short + 4 + 4 + 24 + 4 * 8 + 32 + 48}.get(kernel)  # short list, flag, 4 scalars,
+                                                                                   # F, E_i, velocity
     if far is None:
         b = full * n
     else:

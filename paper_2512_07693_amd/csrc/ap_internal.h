@@ -176,6 +176,10 @@ struct ap_ctx {
     int *stamp = nullptr;          // [n] = stamp_gen when the atom is precise or in a precise atom's list
     int stamp_gen = 0;             // evaluation counter of the stamps
     int *cmark = nullptr;          // [n] = stamp_gen when a CSP neighbour of the atom has W != 0
+    // set by the velocity-Verlet loop around its force evaluations: the force pass then applies the
+    // second half-kick v += kick_hdtm F (null: no kick)
+    double *kick_vel = nullptr;
+    double kick_hdtm = 0.0, kick_mass = 0.0;
 
     // gathered records: xg = {x, y, z, g}, xl = {x, y, z, lambda}, eb = {xi', g, d + d0, E~}
     ap::Rec4 *xg = nullptr, *xl = nullptr, *eb = nullptr;

@@ -185,10 +185,13 @@ static EvalFlags mixed_flags(const ap_ctx *c) {
 // First half kick and drift. Also the neighbour-list work of the step's start: the skin check of the
 // new positions (flags[0] |= 1 when an atom moved more than skin/2 since the last build) and zeroed
 // cell counts for a rebuild (the geometry is that of the last build; a new one is cleared anew).
-__global__ void k_vv_first(double *pos, double *vel, const double *F, double *ipos, int n, double hdtm, double dt,
-                           double Lx, double Ly, double Lz, const double *__restrict__ pos_build, double half_skin2,
-                           int *flags, int *cell_cnt, int *cell_fill, int ncell) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+// First half-kick, drift and wrap, the skin check against the list's build positions, and the clearing
+// of the cell counters for a possible rebuild.
+__global__ __launch_bounds__(kBlock) void k_vv_first(double *pos, double *vel, const double *F, double *ipos, int n,
+                                                     double hdtm, double dt, double Lx, double Ly, double Lz,
+                                                     const double *__restrict__ pos_build, double half_skin2,
+                                                     int *flags, int *cell_cnt, int *cell_fill, int ncell) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     for (int q = i; q < ncell; q += gridDim.x * blockDim.x) {
         cell_cnt[q] = 0;
         cell_fill[q] = 0;
@@ -208,66 +211,34 @@ __global__ void k_vv_first(double *pos, double *vel, const double *F, double *ip
     if (u[0] * u[0] + u[1] * u[1] + u[2] * u[2] > half_skin2) atomicOr(&flags[0], 1);
 }
 
-__global__ __launch_bounds__(kBlock) void k_vv_second(double *vel, const double *F, int n, double hdtm, double mass,
-                                                      double *partials) {
-    __shared__ double sh[kBlock / 64];
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    double ek = 0, p[3] = {0, 0, 0};
-    if (i < n) {
-        for (int a = 0; a < 3; a++) {
-            const size_t o = (size_t)a * n + i;
-            const double v = vel[o] + hdtm * F[o];
-            vel[o] = v;
-            ek += 0.5 * mass * v * v / kConv;
-            p[a] = mass * v;
-        }
+// One thermo row from the force pass's partial rows (nbf of them): the potential energy (column 0), the
+// kinetic energy and momentum after the second half-kick (columns 10-13), |S| and the rebuild flag.
+constexpr int kThermoThreads = 1024;
+__global__ __launch_bounds__(kThermoThreads) void k_thermo(const double *partials, int nbf, int *flags,
+                                                           double *row) {
+    __shared__ double sh[kThermoThreads / 64][5];
+    double t5[5] = {0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nbf; b += kThermoThreads) {
+        const double *p = partials + (size_t)b * 16;
+        t5[0] += p[0];
+        for (int q = 1; q < 5; q++) t5[q] += p[9 + q];
     }
-    double vals[4] = {ek, p[0], p[1], p[2]};
-    for (int q = 0; q < 4; q++) {
-        double v = vals[q];
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-        __syncthreads();
-        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double s = 0;
-            for (int w = 0; w < kBlock / 64; w++) s += sh[w];
-            partials[(size_t)blockIdx.x * 16 + 10 + q] = s;
-        }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int q = 0; q < 5; q++) {
+        double x = t5[q];
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+        if (lane == 0) sh[w][q] = x;
     }
-}
-
-// One thermo row: the potential energy from the force pass's partials (column 0 of nbf rows), the kinetic
-// energy and momentum from the second half-kick's (columns 10-13 of nb rows), |S| and the rebuild flag.
-__global__ __launch_bounds__(kBlock) void k_thermo(const double *partials, int nb, int nbf, int *flags, double *row) {
-    __shared__ double sh[kBlock / 64];
-    double epot = 0.0;
-    for (int q = -1; q < 4; q++) {
-        double s = 0;
-        if (q < 0)
-            for (int b = threadIdx.x; b < nbf; b += kBlock) s += partials[(size_t)b * 16];
-        else
-            for (int b = threadIdx.x; b < nb; b += kBlock) s += partials[(size_t)b * 16 + 10 + q];
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-        __syncthreads();
-        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double t = 0;
-            for (int w = 0; w < kBlock / 64; w++) t += sh[w];
-            if (q < 0) {
-                epot = t;
-                if (!isfinite(t)) atomicOr(&flags[1], kErrNonFinite);
-            } else if (q == 0) {
-                row[0] = epot;
-                row[1] = t;
-                row[2] = epot + t;
-            } else {
-                row[2 + q] = t;
-            }
-        }
-    }
+    __syncthreads();
     if (threadIdx.x == 0) {
+        double s[5] = {0, 0, 0, 0, 0};
+        for (int k = 0; k < kThermoThreads / 64; k++)
+            for (int q = 0; q < 5; q++) s[q] += sh[k][q];
+        if (!isfinite(s[0])) atomicOr(&flags[1], kErrNonFinite);
+        row[0] = s[0];
+        row[1] = s[1];
+        row[2] = s[0] + s[1];
+        for (int q = 0; q < 3; q++) row[3 + q] = s[2 + q];
         row[6] = (double)flags[2];
         row[7] = (double)flags[3];
     }
@@ -669,7 +640,7 @@ int ap_vv_step(ap_ctx *c, int n, double *pos, double *vel, double *F, double mas
     }
     const bool run_ace = !(c->sw.lambda_mode == AP_LAMBDA_FAST);
     const double hdtm = 0.5 * dt / mass * kConv;
-    const int nb = nblocks(n);
+    const int nb = nblocks(n), nbf = force_blocks(n);
     launch_fill_int(c, c->d_flags + 1, 0, 1);
     // the list must describe these positions: rebuild on the first step of every call
     bool force = true;
@@ -682,17 +653,20 @@ int ap_vv_step(ap_ctx *c, int n, double *pos, double *vel, double *F, double mas
                                                      box->L[2], c->pos_build, 0.25 * c->skin * c->skin, c->d_flags,
                                                      c->cell_cnt, c->cell_fill, force ? 0 : c->ncell_cur);
         }
-        // (the thermo kernel sums the force pass's energy partials itself)
+        // the force pass applies the second half-kick and sums E_kin and P with the energy
+        c->kick_vel = vel;
+        c->kick_hdtm = hdtm;
+        c->kick_mass = mass;
         rc = evaluate(c, n, box->L, f, nullptr, nullptr, 0, run_ace, nullptr, nullptr, F, nullptr, force, !force,
                       false);
+        c->kick_vel = nullptr;
         if (rc) {
             c->prof_skip = false;
             return rc;
         }
         force = false;
-        ProfScope p(c, "vv_second");
-        k_vv_second<<<nb, kBlock, 0, c->stream>>>(vel, F, n, hdtm, mass, c->partials);
-        k_thermo<<<1, kBlock, 0, c->stream>>>(c->partials, nb, force_blocks(n), c->d_flags, thermo + (size_t)8 * s);
+        ProfScope p(c, "thermo");
+        k_thermo<<<1, kThermoThreads, 0, c->stream>>>(c->partials, nbf, c->d_flags, thermo + (size_t)8 * s);
     }
     c->prof_skip = false;
     rc = hip_check(c, hipGetLastError(), "vv");

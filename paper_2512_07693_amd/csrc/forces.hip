@@ -401,6 +401,10 @@ struct ForceArgs {
     const int32_t *nshort;
     const int *cmark;  // null: every atom scans its reverse CSP entries; else only those with cmark == cgen
     int cgen;
+    // velocity Verlet's second half-kick v += hdtm F on the new forces, with the block sums of the
+    // kinetic energy and momentum in partial columns 10-13 (null: no kick)
+    double *vel;
+    double hdtm, mass;
 };
 
 template <typename TF>
@@ -410,24 +414,30 @@ __device__ __forceinline__ void load_f(const TF *fp, size_t o, double &a, double
     c = (double)fp[o + 2];
 }
 
-__device__ __forceinline__ double block_sum(double v, double *sh) {
-    // deterministic block reduction (fixed tree)
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+// Deterministic workgroup sums of NV values at once (a fixed shuffle tree per wavefront, then the
+// wavefronts in order); thread q < NV of the workgroup writes sum q to out[q].
+template <int NV>
+__device__ __forceinline__ void block_sums(const double *v, double *sh, double *out) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; q++) {
+        double x = v[q];
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+        if (lane == 0) sh[w * NV + q] = x;
+    }
     __syncthreads();
-    if (lane == 0) sh[w] = v;
-    __syncthreads();
-    double s = 0.0;
-    if (threadIdx.x == 0)
-        for (int q = 0; q < kBlock / 64; q++) s += sh[q];
-    return s;
+    if (threadIdx.x < NV) {
+        double s = 0.0;
+        for (int k = 0; k < kBlock / 64; k++) s += sh[k * NV + threadIdx.x];
+        out[threadIdx.x] = s;
+    }
 }
 
 // FULL = false: only the EAM-only gather (every atom in that mode), compiled without the full-list loop
 // and the CSP part so that it keeps its own, lower register count
 template <typename TF, int SUB, bool FULL>
 __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
-    __shared__ double sh[kBlock / 64];
+    __shared__ double sh[kBlock / 64 * 14];
     // plain block order (as in the W pass): the atoms with a precise atom in reach are contiguous index
     // ranges, spread this way over every XCD
     const int blk = blockIdx.x;
@@ -625,9 +635,20 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
     F0 = group_sum<SUB>(F0);
     F1 = group_sum<SUB>(F1);
     F2 = group_sum<SUB>(F2);
+    double kin[4] = {0.0, 0.0, 0.0, 0.0};  // kinetic energy and momentum after the half-kick
     if (i < n && sub == 0) {
         const double li = a.lam[i];
         Ei = li * a.Ef[i] + (1.0 - li) * a.Ep[i];
+        if (a.vel) {
+            const double Fa[3] = {F0, F1, F2};
+            for (int q = 0; q < 3; q++) {
+                const size_t o = (size_t)q * n + i;
+                const double vq = a.vel[o] + a.hdtm * Fa[q];
+                a.vel[o] = vq;
+                kin[0] += 0.5 * a.mass * vq * vq / kConv;
+                kin[1 + q] = a.mass * vq;
+            }
+        }
         if (a.E_atom) a.E_atom[i] = Ei;
         if (a.F) {
             a.F[i] = F0;
@@ -636,12 +657,13 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
         }
         if (!(isfinite(F0) && isfinite(F1) && isfinite(F2) && isfinite(Ei))) atomicOr(&a.flags[1], kErrNonFinite);
     }
-    double s = block_sum(Ei, sh);
-    if (threadIdx.x == 0) a.partials[(size_t)blk * 16] = s;
-    for (int q = 0; q < 9; q++) {
-        s = block_sum(v[q], sh);
-        if (threadIdx.x == 0) a.partials[(size_t)blk * 16 + 1 + q] = s;
-    }
+    // partial row: E, the virial (9) and, with the half-kick, E_kin and P (4)
+    const double vals[14] = {Ei, v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], v[8],
+                             kin[0], kin[1], kin[2], kin[3]};
+    if (a.vel)
+        block_sums<14>(vals, sh, a.partials + (size_t)blk * 16);
+    else
+        block_sums<10>(vals, sh, a.partials + (size_t)blk * 16);
 }
 
 void launch_force(ap_ctx *c, int n, const double *box, const EvalFlags &f, double *E_atom, double *F,
@@ -649,6 +671,9 @@ void launch_force(ap_ctx *c, int n, const double *box, const EvalFlags &f, doubl
     ForceArgs a;
     a.cmark = csp_marked ? c->cmark : nullptr;
     a.cgen = c->stamp_gen;
+    a.vel = sbox ? nullptr : c->kick_vel;
+    a.hdtm = c->kick_hdtm;
+    a.mass = c->kick_mass;
     a.sbox = sbox;
     a.sid = c->sid;
     a.pos = c->pos;
