@@ -184,12 +184,13 @@ __device__ __forceinline__ int ace_part_block(int p, int P, int n0, int nblk) {
     return p == 0 ? 0 : n0 + (nblk - n0) * p / P;
 }
 
+// (in FP32 the second bound keeps it at 6 workgroups per CU: with 1,536 resident slots the S atoms of a
+// mixed step take one round)
 template <typename T, int NMAX, int LMAX>
-__global__ __launch_bounds__(kBlock) void k_ace_basis(AceArgs a) {
+__global__ __launch_bounds__(kBlock, sizeof(T) == 4 ? 6 : 1) void k_ace_basis(AceArgs a) {
     constexpr int NLM = (LMAX + 1) * (LMAX + 1), NA = NMAX * NLM;
     constexpr int V = kAceMaxValid, CH = 64;  // neighbours kept per site; harmonics computed CH at a time
     __shared__ T sR[CH * NMAX], sY[CH * NLM];
-    __shared__ double sR64[CH * NMAX];
     __shared__ T sA[NA];
     __shared__ T sU[V * 4];
     __shared__ double sRd[V], sS[NMAX];
@@ -252,21 +253,32 @@ __global__ __launch_bounds__(kBlock) void k_ace_basis(AceArgs a) {
             // a lane per neighbour in each wavefront: wavefront 0 evaluates the radial channels,
             // wavefronts 1-3 the harmonics of the orders m assigned to them (about 16 values each)
             static_assert(kBlock == 4 * CH, "one neighbour per lane in each of four wavefronts");
-            if (lane < nc) {
-                const int v = lane, u = v0 + v;
-                const T r = sU[4 * u + 3], ir = T(1) / r;
-                if (wv == 0) {
+            if (wv == 0) {
+                // the l = 0 radial sums feed the two-body and density terms, whose fitted coefficients
+                // cancel strongly: they are kept in FP64 whatever T is, summed over the chunk's
+                // neighbours by a fixed shuffle tree and added to s_n by lane 0
+                double gd[NMAX];
+#pragma unroll
+                for (int q = 0; q < NMAX; q++) gd[q] = 0.0;
+                if (lane < nc) {
+                    const int v = lane, u = v0 + v;
+                    const T r = sU[4 * u + 3];
                     T g[NMAX];
                     radial<T, NMAX>(r, rcT, g, (T *)nullptr);
 #pragma unroll
                     for (int q = 0; q < NMAX; q++) sR[v * NMAX + q] = g[q];
-                    // the l = 0 radial sums feed the two-body and density terms, whose fitted
-                    // coefficients cancel strongly: they are kept in FP64 whatever T is
-                    double gd[NMAX];
                     radial<double, NMAX>(sRd[u], a.rc, gd, (double *)nullptr);
+                }
 #pragma unroll
-                    for (int q = 0; q < NMAX; q++) sR64[v * NMAX + q] = gd[q];
-                } else {
+                for (int q = 0; q < NMAX; q++) {
+                    double x = gd[q];
+                    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+                    if (lane == 0) sS[q] += x;
+                }
+            } else if (lane < nc) {
+                const int v = lane, u = v0 + v;
+                const T r = sU[4 * u + 3], ir = T(1) / r;
+                {
                     const T x = sU[4 * u] * ir, y = sU[4 * u + 1] * ir, z = sU[4 * u + 2] * ir;
                     T cm = T(1), sm = T(0);  // (x + iy)^m
 #pragma unroll
@@ -288,11 +300,6 @@ __global__ __launch_bounds__(kBlock) void k_ace_basis(AceArgs a) {
                 T acc = sA[o];
                 for (int v = 0; v < nc; v++) acc += sR[v * NMAX + q] * sY[v * NLM + lm];
                 sA[o] = acc;
-            }
-            if (tid < NMAX) {
-                double s0 = sS[tid];
-                for (int v = 0; v < nc; v++) s0 += sR64[v * NMAX + tid];
-                sS[tid] = s0;
             }
             __syncthreads();
         }
