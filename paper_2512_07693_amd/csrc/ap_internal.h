@@ -210,7 +210,8 @@ struct ap_ctx {
     int mlp_T_cap = 0;
     float *mlp_grad = nullptr, *mlp_m1 = nullptr, *mlp_m2 = nullptr;
     double *mlp_loss = nullptr;
-    double *partials = nullptr;  // per-block partial sums [nblk][16]
+    double *partials = nullptr;  // per-block partial sums, column-major [16][pstride]
+    int pstride = 0;             // rows per column: the most blocks a per-atom or force launch has
     double *scalars = nullptr;   // [0] E_tot, [1..9] virial, [10] E_kin, [11..13] P
 
     // kernel timing with HIP events on the context stream (ap_set_profiling)

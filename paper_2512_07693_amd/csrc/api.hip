@@ -214,14 +214,13 @@ __global__ __launch_bounds__(kBlock) void k_vv_first(double *pos, double *vel, c
 // One thermo row from the force pass's partial rows (nbf of them): the potential energy (column 0), the
 // kinetic energy and momentum after the second half-kick (columns 10-13), |S| and the rebuild flag.
 constexpr int kThermoThreads = 1024;
-__global__ __launch_bounds__(kThermoThreads) void k_thermo(const double *partials, int nbf, int *flags,
+__global__ __launch_bounds__(kThermoThreads) void k_thermo(const double *partials, int nbf, int pstride, int *flags,
                                                            double *row) {
     __shared__ double sh[kThermoThreads / 64][5];
     double t5[5] = {0, 0, 0, 0, 0};
     for (int b = threadIdx.x; b < nbf; b += kThermoThreads) {
-        const double *p = partials + (size_t)b * 16;
-        t5[0] += p[0];
-        for (int q = 1; q < 5; q++) t5[q] += p[9 + q];
+        t5[0] += partials[b];
+        for (int q = 1; q < 5; q++) t5[q] += partials[(size_t)(9 + q) * pstride + b];
     }
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     for (int q = 0; q < 5; q++) {
@@ -308,7 +307,8 @@ int ap_ctx_create(ap_ctx **out, int n_max_atoms, int max_nbr, double skin, void 
     alloc(&c->sid, n, 4);
     alloc(&c->blk_cnt, 2 * nb + 2, 4);
     alloc(&c->chunk_cnt, (n * kLanesPerAtom + kBlock - 1) / kBlock, 4);
-    alloc(&c->partials, (size_t)std::max<long long>((long long)nb, force_blocks((int)n)) * 16, 8);
+    c->pstride = (int)std::max<long long>((long long)nb, force_blocks((int)n));
+    alloc(&c->partials, (size_t)c->pstride * 16, 8);
     alloc(&c->scalars, 16, 8);
     if (rc) {
         g_create_error = c->err;
@@ -666,7 +666,8 @@ int ap_vv_step(ap_ctx *c, int n, double *pos, double *vel, double *F, double mas
         }
         force = false;
         ProfScope p(c, "thermo");
-        k_thermo<<<1, kThermoThreads, 0, c->stream>>>(c->partials, nbf, c->d_flags, thermo + (size_t)8 * s);
+        k_thermo<<<1, kThermoThreads, 0, c->stream>>>(c->partials, nbf, c->pstride, c->d_flags,
+                                                      thermo + (size_t)8 * s);
     }
     c->prof_skip = false;
     rc = hip_check(c, hipGetLastError(), "vv");

@@ -385,7 +385,8 @@ struct ForceArgs {
     const void *fpair, *frev;
     int fp32, max_nbr, n_csp;
     const int32_t *csp_t, *rev_start, *rev_code;
-    double *E_atom, *F, *partials;
+    double *E_atom, *F, *partials;  // partials: [16][pstride] per-block sums, column-major
+    int pstride;
     int *flags;
     const double *sbox;  // per-structure boxes of a batch (null: L)
     const int *sid;
@@ -415,9 +416,9 @@ __device__ __forceinline__ void load_f(const TF *fp, size_t o, double &a, double
 }
 
 // Deterministic workgroup sums of NV values at once (a fixed shuffle tree per wavefront, then the
-// wavefronts in order); thread q < NV of the workgroup writes sum q to out[q].
+// wavefronts in order); thread q < NV of the workgroup writes sum q to out[q * stride].
 template <int NV>
-__device__ __forceinline__ void block_sums(const double *v, double *sh, double *out) {
+__device__ __forceinline__ void block_sums(const double *v, double *sh, double *out, int stride) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int q = 0; q < NV; q++) {
@@ -429,7 +430,7 @@ __device__ __forceinline__ void block_sums(const double *v, double *sh, double *
     if (threadIdx.x < NV) {
         double s = 0.0;
         for (int k = 0; k < kBlock / 64; k++) s += sh[k * NV + threadIdx.x];
-        out[threadIdx.x] = s;
+        out[(size_t)threadIdx.x * stride] = s;
     }
 }
 
@@ -657,13 +658,14 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
         }
         if (!(isfinite(F0) && isfinite(F1) && isfinite(F2) && isfinite(Ei))) atomicOr(&a.flags[1], kErrNonFinite);
     }
-    // partial row: E, the virial (9) and, with the half-kick, E_kin and P (4)
+    // this block's partials, column-major (column q at q * pstride): E, the virial (9) and, with the
+    // half-kick, E_kin and P (4)
     const double vals[14] = {Ei, v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], v[8],
                              kin[0], kin[1], kin[2], kin[3]};
     if (a.vel)
-        block_sums<14>(vals, sh, a.partials + (size_t)blk * 16);
+        block_sums<14>(vals, sh, a.partials + blk, a.pstride);
     else
-        block_sums<10>(vals, sh, a.partials + (size_t)blk * 16);
+        block_sums<10>(vals, sh, a.partials + blk, a.pstride);
 }
 
 void launch_force(ap_ctx *c, int n, const double *box, const EvalFlags &f, double *E_atom, double *F,
@@ -707,6 +709,7 @@ void launch_force(ap_ctx *c, int n, const double *box, const EvalFlags &f, doubl
     a.E_atom = E_atom;
     a.F = F;
     a.partials = c->partials;
+    a.pstride = c->pstride;
     a.flags = c->d_flags;
     a.ind_mlp = f.switching && c->sw.indicator == AP_IND_MLP;
     a.hpair = c->hpair;
@@ -731,13 +734,14 @@ void launch_force(ap_ctx *c, int n, const double *box, const EvalFlags &f, doubl
         k_force<double, kForceLanes, true><<<nb, kBlock, 0, c->stream>>>(a);
 }
 
-// Sums the per-block partials [nb][16] (energy, virial) in a fixed order, one workgroup per column.
-__global__ __launch_bounds__(1024) void k_reduce_partials(const double *__restrict__ part, int nb,
+// Sums the per-block partials (energy, virial; column-major [16][pstride]) in a fixed order, one workgroup
+// per column.
+__global__ __launch_bounds__(1024) void k_reduce_partials(const double *__restrict__ part, int nb, int pstride,
                                                           double *__restrict__ out, int *flags) {
     __shared__ double sh[1024 / 64];
     const int col = blockIdx.x;
     double s = 0.0;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[(size_t)b * 16 + col];
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[(size_t)col * pstride + b];
     for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
     __syncthreads();
@@ -750,7 +754,7 @@ __global__ __launch_bounds__(1024) void k_reduce_partials(const double *__restri
 }
 
 void launch_reduce(ap_ctx *c, int nblocks, double *E_tot, double *virial9) {
-    k_reduce_partials<<<10, 1024, 0, c->stream>>>(c->partials, nblocks, c->scalars, c->d_flags);
+    k_reduce_partials<<<10, 1024, 0, c->stream>>>(c->partials, nblocks, c->pstride, c->scalars, c->d_flags);
     if (E_tot) (void)hipMemcpyAsync(E_tot, c->scalars, sizeof(double), hipMemcpyDeviceToDevice, c->stream);
     if (virial9) (void)hipMemcpyAsync(virial9, c->scalars + 1, 9 * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
 }
