@@ -268,3 +268,31 @@ def test_nve_drift_bounded_128k():
     _lt("|P|/N", float(np.abs(th[:, 3:6]).max()) / n, 1e-8)
     torch.cuda.synchronize()
     ctx.close()
+
+
+def test_ace_work_split_consistent():
+    """The energy kernel takes an atom whole or splits it into two to four parts of its coupling blocks,
+    by the size of S against the resident workgroups. The same atoms must get the same site energies
+    whatever the split, and the forces of disjoint subsets must add up (FP32 ACE, 1,024-atom cell)."""
+    import torch
+    s = synth.build_system(2, nc=8)
+    n = len(s["pos"])
+    _say("ace work split n=%d" % n)
+    ctx, _ = make_ctx(s, lambda_mode=0, precision="fp32")
+    pos = to_dev(s["pos"])
+    perm = np.random.default_rng(7).permutation(n).astype(np.int32)
+    A, BC = perm[:96], perm[96:608]
+
+    def run(idx):
+        out = ctx.ace_eval(pos, s["box"], subset=torch.tensor(np.sort(idx), device="cuda"))
+        return out["E_atom"].cpu().numpy(), soa_to_aos(out["F"])
+
+    E_a, F_a = run(A)                      # 96 atoms: four parts each
+    E_ab, _ = run(perm[:416])              # 416 atoms: halves
+    E_bc, F_bc = run(BC)                   # 512 atoms: halves
+    E_all, F_all = run(perm[:608])         # 608 atoms: whole, or one round of more than half the slots
+    for name, E in (("E_atom 416", E_ab), ("E_atom 608", E_all)):
+        _lt(name, float(np.abs(E[A] - E_a[A]).max() / np.abs(E_a[A]).max()), 1e-12)
+    _lt("E_atom BC", float(np.abs(E_all[BC] - E_bc[BC]).max() / np.abs(E_bc[BC]).max()), 1e-12)
+    _lt("F additive", force_err_rms(F_a + F_bc, F_all), 2e-6)
+    ctx.close()
