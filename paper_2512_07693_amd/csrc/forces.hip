@@ -435,9 +435,10 @@ __device__ __forceinline__ void block_sums(const double *v, double *sh, double *
 }
 
 // FULL = false: only the EAM-only gather (every atom in that mode), compiled without the full-list loop
-// and the CSP part so that it keeps its own, lower register count
+// and the CSP part so that it keeps its own, lower register count. With FP32 pair terms the full kernel
+// is bounded to four workgroups per CU (128 VGPRs, no spills).
 template <typename TF, int SUB, bool FULL>
-__global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
+__global__ __launch_bounds__(kBlock, (FULL && sizeof(TF) == 4) ? 4 : 1) void k_force(ForceArgs a) {
     __shared__ double sh[kBlock / 64 * 14];
     // plain block order (as in the W pass): the atoms with a precise atom in reach are contiguous index
     // ranges, spread this way over every XCD
