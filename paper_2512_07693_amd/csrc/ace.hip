@@ -44,6 +44,10 @@ struct AceArgs {
     int slots;      // energy-kernel workgroups resident at once on the device
     int *queue;     // work-item counter of the energy kernel
     int *stamp;     // [n] set to gen for every precise atom and every atom in its list (null: not kept)
+    // reverse slots kept per list build: rslot[i][slot] is the slot of i in the list of its slot-th
+    // neighbour, valid while rstamp[i] == *list_gen (null rslot: searched every time)
+    int *rslot, *rstamp;
+    const int *list_gen;
     const void *c30, *kap0;  // the L = 0 blocks folded into order 2 (null: processed as blocks)
     int gen;
     void *fpair;  // [S][max_nbr][3]
@@ -644,6 +648,10 @@ __global__ __launch_bounds__(128) void k_ace_pairforce(AceArgs a) {
             a.eb[i].w = et;
             if (!isfinite(E)) atomicOr(&a.flags[1], kErrNonFinite);
         }
+        // this atom's reverse slots come from the cache when they were searched on the current list
+        // (read by every thread before the barrier; rewritten only after the closing one)
+        const int lgen = a.rslot ? *a.list_gen : 0;
+        const bool cached = a.rslot && a.rstamp[i] == lgen;
         __syncthreads();
         double Lx, Ly, Lz;
         atom_box(a, i, Lx, Ly, Lz);
@@ -733,15 +741,20 @@ __global__ __launch_bounds__(128) void k_ace_pairforce(AceArgs a) {
             fo[3 * slot + 2] = f2;
             // the slot k of i in j's list (lists are symmetric): j's gather reads the term at (k, j),
             // coalesced over j. Loads go out eight at a time so the search is not one long chain.
-            const int cj = a.ncount[j];
             int kk = -1;
-            for (int b0 = 0; b0 < cj && kk < 0; b0 += 8) {
-                int v[8];
+            if (cached) {
+                kk = a.rslot[(size_t)i * a.max_nbr + slot];
+            } else {
+                const int cj = a.ncount[j];
+                for (int b0 = 0; b0 < cj && kk < 0; b0 += 8) {
+                    int v[8];
 #pragma unroll
-                for (int u = 0; u < 8; u++) v[u] = b0 + u < cj ? a.nidx[(size_t)(b0 + u) * n + j] : -1;
+                    for (int u = 0; u < 8; u++) v[u] = b0 + u < cj ? a.nidx[(size_t)(b0 + u) * n + j] : -1;
 #pragma unroll
-                for (int u = 0; u < 8; u++)
-                    if (v[u] == i && kk < 0) kk = b0 + u;
+                    for (int u = 0; u < 8; u++)
+                        if (v[u] == i && kk < 0) kk = b0 + u;
+                }
+                if (a.rslot) a.rslot[(size_t)i * a.max_nbr + slot] = kk;
             }
             if (kk < 0) {
                 atomicOr(&a.flags[1], kErrAsym);
@@ -754,6 +767,7 @@ __global__ __launch_bounds__(128) void k_ace_pairforce(AceArgs a) {
             }
         }
         __syncthreads();
+        if (a.rslot && !cached && threadIdx.x == 0) a.rstamp[i] = lgen;
     }
 }
 
@@ -1147,6 +1161,9 @@ int launch_ace(ap_ctx *c, int n, const double *box, int grid_cap, const double *
         a.kap0 = t.kap0;
         a.stamp = sbox ? nullptr : c->stamp;
         a.gen = c->stamp_gen;
+        a.rslot = sbox ? nullptr : c->rslot;
+        a.rstamp = c->rstamp;
+        a.list_gen = c->list_gen;
     }
 
     a.fpair = c->fpair;

@@ -174,6 +174,10 @@ struct ap_ctx {
     int32_t *nbr_short = nullptr;  // [n] the first nbr_short[i] slots hold the neighbours inside max(r_rho, r_phi) + skin
     int *act = nullptr;            // [n] 1 if the atom or a neighbour has lambda < 1 (the force needs its full list)
     int *stamp = nullptr;          // [n] = stamp_gen when the atom is precise or in a precise atom's list
+    // device counter of neighbour-list builds (raised where a build is committed), and per atom the slot
+    // in each neighbour's list that holds it ([n][max_nbr], atom-major), valid while rstamp[i] equals the
+    // counter: the ACE pair kernel searches a precise atom's reverse slots once per list
+    int *list_gen = nullptr, *rslot = nullptr, *rstamp = nullptr;
     int stamp_gen = 0;             // evaluation counter of the stamps
     int *cmark = nullptr;          // [n] = stamp_gen when a CSP neighbour of the atom has W != 0
     // set by the velocity-Verlet loop around its force evaluations: the force pass then applies the

@@ -261,7 +261,7 @@ void ap_ctx_destroy(ap_ctx *c) {
     void *bufs[] = {c->csp_t, c->rev_start, c->rev_code, c->pos, c->pos_build, c->d_flags, c->cell_of, c->cell_cnt,
                     c->cell_start, c->cell_fill, c->cell_atoms, c->cell_rec, c->nbr_cnt, c->nbr_idx, c->g, c->d,
                     c->wbar, c->lam, c->dlam, c->Ef, c->Ep, c->Et, c->W, c->xip, c->sidx, c->slist, c->blk_cnt,
-                    c->chunk_cnt, c->mark, c->fpair, c->frev, c->xg, c->xl, c->eb, c->xe, c->nbr_short, c->act, c->stamp, c->cmark, c->gbuf, c->partials, c->scalars, c->sid, c->b_off, c->b_box, c->bval};
+                    c->chunk_cnt, c->mark, c->fpair, c->frev, c->xg, c->xl, c->eb, c->xe, c->nbr_short, c->act, c->stamp, c->cmark, c->rslot, c->rstamp, c->list_gen, c->gbuf, c->partials, c->scalars, c->sid, c->b_off, c->b_box, c->bval};
     for (void *p : bufs) (void)hipFree(p);
     delete c;
 }
@@ -291,6 +291,9 @@ int ap_ctx_create(ap_ctx **out, int n_max_atoms, int max_nbr, double skin, void 
     alloc(&c->cell_rec, n, sizeof(ap::Rec4));
     alloc(&c->nbr_cnt, n, 4);
     alloc(&c->nbr_idx, n * max_nbr, 4);
+    alloc(&c->rslot, n * max_nbr, 4);
+    alloc(&c->rstamp, n, 4);
+    alloc(&c->list_gen, 1, 4);
     alloc(&c->nbr_short, n, 4);
     alloc(&c->act, n, 4);
     alloc(&c->stamp, n, 4);
@@ -318,6 +321,8 @@ int ap_ctx_create(ap_ctx **out, int n_max_atoms, int max_nbr, double skin, void 
     launch_fill_int(c, c->d_flags, 0, 8);
     launch_fill_int(c, c->stamp, 0, (int)n);
     launch_fill_int(c, c->cmark, 0, (int)n);
+    launch_fill_int(c, c->rstamp, -1, (int)n);
+    launch_fill_int(c, c->list_gen, 0, 1);
     launch_fill_double(c, c->g, 0.0, (int)n);
     launch_fill_double(c, c->W, 0.0, (int)n);
     launch_fill_double(c, c->d, 0.0, (int)n);

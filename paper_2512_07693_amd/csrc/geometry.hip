@@ -243,10 +243,12 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(const double *__restrict__
     pos_build[2 * n + i] = zi;
 }
 
-__global__ void k_commit(int *flags) {
+__global__ void k_commit(int *flags, int *list_gen) {
+    if (flags[0]) list_gen[0]++;
     flags[3] = flags[0];
     flags[0] = 0;
 }
+__global__ void k_bump(int *list_gen) { list_gen[0]++; }
 
 // Marks a rebuild when any atom moved more than skin/2 from its position at the last build.
 __global__ void k_skin_check(const double *__restrict__ pos, const double *__restrict__ pos_build, int n,
@@ -314,7 +316,7 @@ int ensure_list(ap_ctx *c, int n, const double *box, double r_list, bool force, 
     k_nbr_build<SUB><<<(int)(((size_t)n * SUB + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(
         c->pos, n, g, r_list * r_list, rs * rs, c->cell_start, c->cell_cnt, c->cell_rec, c->cell_of, c->max_nbr,
         c->nbr_cnt, c->nbr_short, c->nbr_idx, c->pos_build, c->d_flags);
-    if (commit) k_commit<<<1, 1, 0, c->stream>>>(c->d_flags);
+    if (commit) k_commit<<<1, 1, 0, c->stream>>>(c->d_flags, c->list_gen);
     c->list_r = r_list;
     c->list_n = n;
     for (int a = 0; a < 3; a++) c->list_box[a] = box[a];
@@ -374,6 +376,7 @@ int batch_lists(ap_ctx *c, int n, int n_struct, const int *d_off, const double *
     k_batch_prepare<<<nb, kBlock, 0, c->stream>>>(pos_in, n, n_struct, d_off, d_box, c->sid, c->pos);
     k_batch_nbr<<<nb, kBlock, 0, c->stream>>>(c->pos, n, d_off, d_box, c->sid, r_list * r_list, c->max_nbr, c->nbr_cnt,
                                               c->nbr_idx, c->d_flags);
+    k_bump<<<1, 1, 0, c->stream>>>(c->list_gen);  // the lists changed outside a committed build
     c->list_r = -1;  // not a list of the single-box evaluation
     return hip_check(c, hipGetLastError(), "batch lists");
 }

@@ -150,6 +150,27 @@ def test_velocity_verlet_10_steps(oracle, cfg1, cfg1_oracle):
     ctx.close()
 
 
+def test_velocity_verlet_across_rebuilds(oracle, cfg1, cfg1_oracle):
+    """200 steps at 300 K: the list is rebuilt on the way (skin check), and every cache keyed on the list
+    (the ACE pair kernel's reverse slots) must follow; positions, velocities and thermo rows against the
+    oracle's velocity Verlet, which builds exact neighbour sets every step."""
+    _say("vv 200 steps cfg1")
+    ctx, _ = make_ctx(cfg1)
+    pos, vel = to_dev(cfg1["pos"]), to_dev(cfg1["vel"])
+    F = ctx.mixed_energy_forces(pos, cfg1["box"])["F"]
+    th = ctx.vv_step(pos, vel, F, cfg1["mass"], 1e-3, 200, cfg1["box"]).cpu().numpy()
+    rebuilds = int(th[1:, 7].sum())
+    _say("  rebuilds after the first step: %d" % rebuilds)
+    assert rebuilds >= 1
+    p_ref, v_ref, F_ref, th_ref = oracle.velocity_verlet(cfg1, 200, csp=cfg1_oracle[0])
+    d = soa_to_aos(pos) - p_ref
+    d -= cfg1["box"] * np.rint(d / cfg1["box"])
+    _lt("pos", float(np.abs(d).max()), 1e-9)
+    _lt("vel", float(np.abs(soa_to_aos(vel) - v_ref).max()), 1e-7)
+    _lt("thermo", float(np.abs(th[:, :6] - th_ref).max()), 1e-6)
+    ctx.close()
+
+
 def test_ace_fp32_large_basis(oracle):
     """Pure ACE with the n_max 12 / l_max 6 basis (32,686 functions) in FP32 on a 250-atom cell."""
     s = synth.build_system(2, nc=5)
