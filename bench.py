@@ -35,12 +35,12 @@ FP64_PEAK_TFLOPS = 78.6
 # same counters read for a 1 GiB device copy (fetch x2.0, write x1.0), with a digest of the kernel's source
 # file and the shared header at the time: a kernel whose source has changed reports null until re-measured.
 MEASURED_TRAFFIC = {
-    "ace_energy": (10.96e6, "ace.hip", "46c42150b0073236"),
-    "ace_basis": (10.15e6, "ace.hip", "46c42150b0073236"),
-    "ace_pairforce": (32.58e6, "ace.hip", "46c42150b0073236"),
-    "force": (78.27e6, "forces.hip", "0acd3620b11b201e"),
-    "dens_desc": (82.62e6, "forces.hip", "0acd3620b11b201e"),
-    "W": (7.55e6, "forces.hip", "0acd3620b11b201e"),
+    "ace_energy": (10.94e6, "ace.hip", "1c2c302110aa69ea"),
+    "ace_basis": (10.15e6, "ace.hip", "1c2c302110aa69ea"),
+    "ace_pairforce": (25.53e6, "ace.hip", "1c2c302110aa69ea"),
+    "force": (79.47e6, "forces.hip", "9b3a3d045a4cb6ca"),
+    "dens_desc": (82.28e6, "forces.hip", "9b3a3d045a4cb6ca"),
+    "W": (7.55e6, "forces.hip", "9b3a3d045a4cb6ca"),
 }
 
 
