@@ -153,7 +153,10 @@ __global__ void k_cell_sort(int ncell, const int *start, const int *cnt, int *at
 // index). The neighbours inside r_short are written from the front of the slot array, those between
 // r_short and r_list from its back; the back part is then moved down behind the front part (a forward
 // copy: it only moves to lower slots). ncount_short = the front part.
-template <int SUB>
+// STAGE: the workgroup's lists are assembled in LDS ([max_nbr][kBlock / SUB] ints, dynamic shared memory)
+// and written out row by row, each row of its atoms one contiguous run, instead of as scattered 4-byte
+// stores into the slot-major array.
+template <int SUB, bool STAGE>
 __global__ __launch_bounds__(kBlock) void k_nbr_build(const double *__restrict__ pos, int n, Geometry g, double r2,
                                                       double rs2, const int *__restrict__ start,
                                                       const int *__restrict__ cnt, const Rec4 *__restrict__ rec,
@@ -162,9 +165,21 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(const double *__restrict__
                                                       int32_t *__restrict__ nidx, double *__restrict__ pos_build,
                                                       int *flags) {
     static_assert(SUB > 0 && 64 % SUB == 0, "lane groups inside a wavefront");
-    if (flags[0] == 0) return;
-    const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    constexpr int APB = kBlock / SUB;  // atoms per workgroup
+    extern __shared__ int tile[];      // STAGE: slot s of local atom a at tile[s * APB + a]
+    __shared__ int scnt[APB];
+    if (flags[0] == 0) return;         // the same for every workgroup
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    const int t = lb * blockDim.x + threadIdx.x;
     const int i = t / SUB, sub = t - i * SUB;
+    const int al = (int)threadIdx.x / SUB;
+    auto put = [&](int slot, int v) {
+        if (STAGE)
+            tile[slot * APB + al] = v;
+        else
+            nidx[(size_t)slot * n + i] = v;
+    };
+    auto get = [&](int slot) { return STAGE ? tile[slot * APB + al] : nidx[(size_t)slot * n + i]; };
     const int gbase = (threadIdx.x & 63) - sub;  // first lane of this atom's group in the wavefront
     const bool live = i < n;
     double xi = 0.0, yi = 0.0, zi = 0.0;
@@ -215,23 +230,33 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(const double *__restrict__
                     const unsigned long long below = ((1ull << (threadIdx.x & 63)) - 1ull) & grp;
                     // hits before this one in scan order: the front and back parts never meet
                     const bool room = ks + kl + __popcll((ms | ml) & below) < max_nbr;
-                    if (hs && room) nidx[(size_t)(ks + __popcll(ms & below)) * n + i] = j;
-                    if (hl && room) nidx[(size_t)(max_nbr - 1 - kl - __popcll(ml & below)) * n + i] = j;
+                    if (hs && room) put(ks + __popcll(ms & below), j);
+                    if (hl && room) put(max_nbr - 1 - kl - __popcll(ml & below), j);
                     ks += __popcll(ms & grp);
                     kl += __popcll(ml & grp);
                 }
             }
-    if (!live) return;
     int k = ks + kl;
-    if (k <= max_nbr) {
+    if (live && k <= max_nbr) {
         // the back part [max_nbr - kl, max_nbr) moves down to [ks, ks + kl), ks <= max_nbr - kl, in
         // increasing slot order: a store only hits a slot read in the same round or an earlier one
-        for (int t = sub; t < kl; t += SUB) {
-            const int v = nidx[(size_t)(max_nbr - kl + t) * n + i];
-            nidx[(size_t)(ks + t) * n + i] = v;
+        for (int q = sub; q < kl; q += SUB) {
+            const int v = get(max_nbr - kl + q);
+            put(ks + q, v);
         }
     }
-    if (sub != 0) return;
+    if (STAGE) {
+        if (sub == 0) scnt[al] = live ? min(k, max_nbr) : 0;
+        __syncthreads();
+        int kmax = 0;
+        for (int q = 0; q < APB; q++) kmax = max(kmax, scnt[q]);
+        const int i0 = lb * APB;
+        for (int e = threadIdx.x; e < kmax * APB; e += blockDim.x) {
+            const int sl = e / APB, aa = e - sl * APB;
+            if (i0 + aa < n && sl < scnt[aa]) nidx[(size_t)sl * n + i0 + aa] = tile[sl * APB + aa];
+        }
+    }
+    if (!live || sub != 0) return;
     ncount_short[i] = ks < max_nbr ? ks : max_nbr;
     if (k > max_nbr) {
         atomicOr(&flags[1], kErrOverflow);
@@ -313,9 +338,15 @@ int ensure_list(ap_ctx *c, int n, const double *box, double r_list, bool force, 
         g.ncell, c->cell_start, c->cell_cnt, c->cell_atoms, c->pos, n, c->cell_rec, c->d_flags);
     const double rs = std::max(c->eam.r_rho, c->eam.r_phi) + c->skin;  // the EAM pairs first
     constexpr int SUB = 8;  // lanes per atom in the list build
-    k_nbr_build<SUB><<<(int)(((size_t)n * SUB + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(
-        c->pos, n, g, r_list * r_list, rs * rs, c->cell_start, c->cell_cnt, c->cell_rec, c->cell_of, c->max_nbr,
-        c->nbr_cnt, c->nbr_short, c->nbr_idx, c->pos_build, c->d_flags);
+    const int lgrid = (int)(((size_t)n * SUB + kBlock - 1) / kBlock);
+    if (c->max_nbr <= 256)  // (at most 32 KB of staged lists per workgroup)
+        k_nbr_build<SUB, true><<<lgrid, kBlock, (size_t)c->max_nbr * (kBlock / SUB) * sizeof(int), c->stream>>>(
+            c->pos, n, g, r_list * r_list, rs * rs, c->cell_start, c->cell_cnt, c->cell_rec, c->cell_of, c->max_nbr,
+            c->nbr_cnt, c->nbr_short, c->nbr_idx, c->pos_build, c->d_flags);
+    else
+        k_nbr_build<SUB, false><<<lgrid, kBlock, 0, c->stream>>>(
+            c->pos, n, g, r_list * r_list, rs * rs, c->cell_start, c->cell_cnt, c->cell_rec, c->cell_of, c->max_nbr,
+            c->nbr_cnt, c->nbr_short, c->nbr_idx, c->pos_build, c->d_flags);
     if (commit) k_commit<<<1, 1, 0, c->stream>>>(c->d_flags, c->list_gen);
     c->list_r = r_list;
     c->list_n = n;
