@@ -217,9 +217,12 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(const double *__restrict__
                         const Rec4 cr = rec[p];  // the candidate's position and index, in cell order
                         j = (int)cr.w;
                         if (j != i) {
-                            const double ux = min_image(cr.x - xi, g.L[0]);
-                            const double uy = min_image(cr.y - yi, g.L[1]);
-                            const double uz = min_image(cr.z - zi, g.L[2]);
+                            // (positions are wrapped, so a difference lies in (-L, L): the select
+                            // takes the image d - L rint(d / L) takes, without its division, except
+                            // within an ulp of |d| = L / 2, where both images are farther than r_list)
+                            const double ux = min_image_w(cr.x - xi, g.L[0]);
+                            const double uy = min_image_w(cr.y - yi, g.L[1]);
+                            const double uz = min_image_w(cr.z - zi, g.L[2]);
                             const double d2 = norm2_nofma(ux, uy, uz);
                             hs = d2 < r2 && d2 < rs2;
                             hl = d2 < r2 && !(d2 < rs2);
