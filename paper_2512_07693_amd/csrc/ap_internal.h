@@ -52,7 +52,8 @@ __device__ __forceinline__ double min_image(double d, double L) {
 // Minimum image of a difference of two wrapped coordinates (|d| < L): the value of min_image wherever
 // |d| is not within rounding of L / 2 (never inside a cutoff below L / 2), without the division. The
 // list build's distance test takes it too: within a cutoff below L / 2 both give the same bits, so the
-// neighbour sets are those of min_image. The CSP tests keep min_image.
+// neighbour sets are those of min_image, and so does the per-step CSP value. The one-time CSP pair
+// detection keeps min_image.
 __device__ __forceinline__ double min_image_w(double d, double L) {
     const double h = 0.5 * L;
     return d > h ? d - L : (d < -h ? d + L : d);

@@ -206,7 +206,7 @@ __global__ __launch_bounds__(kBlock) void k_vv_first(double *pos, double *vel, c
         const double x = wrap_coord(pos[o] + dt * v, L[a]);
         pos[o] = x;
         ipos[o] = x;
-        u[a] = min_image(x - pos_build[o], L[a]);
+        u[a] = min_image_w(x - pos_build[o], L[a]);
     }
     if (u[0] * u[0] + u[1] * u[1] + u[2] * u[2] > half_skin2) atomicOr(&flags[0], 1);
 }

@@ -283,9 +283,9 @@ __global__ void k_skin_check(const double *__restrict__ pos, const double *__res
                              double Lx, double Ly, double Lz, double half_skin2, int *flags) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    double ux = min_image(pos[i] - pos_build[i], Lx);
-    double uy = min_image(pos[n + i] - pos_build[n + i], Ly);
-    double uz = min_image(pos[2 * n + i] - pos_build[2 * n + i], Lz);
+    double ux = min_image_w(pos[i] - pos_build[i], Lx);
+    double uy = min_image_w(pos[n + i] - pos_build[n + i], Ly);
+    double uz = min_image_w(pos[2 * n + i] - pos_build[2 * n + i], Lz);
     if (ux * ux + uy * uy + uz * uz > half_skin2) atomicOr(&flags[0], 1);
 }
 
@@ -586,7 +586,8 @@ int install_csp(ap_ctx *c, int n, int n_csp, const int32_t *list) {
     return AP_OK;
 }
 
-// g_i = sum over the stored pairs (a, b) of |u_ia + u_ib|^2.
+// g_i = sum over the stored pairs (a, b) of |u_ia + u_ib|^2 (division-free minimum images: the pairs are
+// nearest neighbours, far from |d| = L / 2).
 __global__ __launch_bounds__(kBlock) void k_csp_value(const double *__restrict__ pos, int n, double Lx, double Ly,
                                                       double Lz, int n_csp, const int32_t *__restrict__ lt,
                                                       double *__restrict__ g, Rec4 *__restrict__ xg) {
@@ -596,9 +597,9 @@ __global__ __launch_bounds__(kBlock) void k_csp_value(const double *__restrict__
     double s = 0.0;
     for (int p = 0; p < n_csp / 2; p++) {
         const int a = lt[(size_t)(2 * p) * n + i], b = lt[(size_t)(2 * p + 1) * n + i];
-        double vx = min_image(pos[a] - xi, Lx) + min_image(pos[b] - xi, Lx);
-        double vy = min_image(pos[n + a] - yi, Ly) + min_image(pos[n + b] - yi, Ly);
-        double vz = min_image(pos[2 * n + a] - zi, Lz) + min_image(pos[2 * n + b] - zi, Lz);
+        double vx = min_image_w(pos[a] - xi, Lx) + min_image_w(pos[b] - xi, Lx);
+        double vy = min_image_w(pos[n + a] - yi, Ly) + min_image_w(pos[n + b] - yi, Ly);
+        double vz = min_image_w(pos[2 * n + a] - zi, Lz) + min_image_w(pos[2 * n + b] - zi, Lz);
         s += vx * vx + vy * vy + vz * vz;
     }
     g[i] = s;
