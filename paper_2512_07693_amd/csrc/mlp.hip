@@ -54,8 +54,8 @@ __device__ __forceinline__ void site_features(const double *__restrict__ pos, in
     const int cnt = ncount[i];
     for (int k = 0; k < cnt; k++) {
         const int j = nidx[(size_t)k * n + i];
-        const double ux = min_image(pos[j] - xi, Lx), uy = min_image(pos[n + j] - yi, Ly),
-                     uz = min_image(pos[2 * n + j] - zi, Lz);
+        const double ux = min_image_w(pos[j] - xi, Lx), uy = min_image_w(pos[n + j] - yi, Ly),
+                     uz = min_image_w(pos[2 * n + j] - zi, Lz);
         const double r2 = ux * ux + uy * uy + uz * uz;
         if (!(r2 < rc2)) continue;
         const double rd = sqrt(r2);
@@ -121,6 +121,10 @@ struct MlpArgs {
     double *g;        // [n] indicator (k_mlp_indicator)
     Rec4 *xg;         // [n] {x, y, z, g}
     const Rec4 *xl;   // [n] {x, y, z, lambda} (after the density pass)
+    // reverse slots kept per list build (shared with the ACE pair kernel): rslot[j][slot] is the slot of j
+    // in its slot-th neighbour's list, valid while rstamp[j] == *list_gen
+    int *rslot, *rstamp;
+    const int *list_gen;
     float *q;         // [n][16] features (feature mode)
     const double *W;  // [n]
     const int *wlist, *wcount;
@@ -219,8 +223,12 @@ __global__ __launch_bounds__(64) void k_mlp_gradg(MlpArgs a) {
     const double rc2 = a.rc * a.rc;
     const float rcf = (float)a.rc;
     const int nw = *a.wcount;
+    const int lgen = *a.list_gen;
     for (int w = blockIdx.x; w < nw; w += gridDim.x) {
         const int j = a.wlist[w];
+        // j's reverse slots from the cache when searched on the current list (read before the barriers
+        // below; rewritten only after the closing one)
+        const bool cached = a.rstamp[j] == lgen;
         const double xj = a.pos[j], yj = a.pos[n + j], zj = a.pos[2 * n + j];
         const int cnt = a.ncount[j];
         // 1. features: per-lane partial sums over its slots, then a butterfly over the wavefront
@@ -232,8 +240,8 @@ __global__ __launch_bounds__(64) void k_mlp_gradg(MlpArgs a) {
         for (int slot = lane; slot < cnt; slot += 64) {
             const int k = a.nidx[(size_t)slot * n + j];
             const Rec4 pk = a.xl[k];
-            const double ux = min_image(pk.x - xj, a.L[0]), uy = min_image(pk.y - yj, a.L[1]),
-                         uz = min_image(pk.z - zj, a.L[2]);
+            const double ux = min_image_w(pk.x - xj, a.L[0]), uy = min_image_w(pk.y - yj, a.L[1]),
+                         uz = min_image_w(pk.z - zj, a.L[2]);
             const double r2 = ux * ux + uy * uy + uz * uz;
             if (!(r2 < rc2)) continue;
             const double rd = sqrt(r2);
@@ -305,8 +313,8 @@ __global__ __launch_bounds__(64) void k_mlp_gradg(MlpArgs a) {
         for (int slot = lane; slot < cnt; slot += 64) {
             const int k = a.nidx[(size_t)slot * n + j];
             const Rec4 pk = a.xl[k];
-            const double ux = min_image(pk.x - xj, a.L[0]), uy = min_image(pk.y - yj, a.L[1]),
-                         uz = min_image(pk.z - zj, a.L[2]);
+            const double ux = min_image_w(pk.x - xj, a.L[0]), uy = min_image_w(pk.y - yj, a.L[1]),
+                         uz = min_image_w(pk.z - zj, a.L[2]);
             const double r2 = ux * ux + uy * uy + uz * uz;
             float h0 = 0.0f, h1 = 0.0f, h2 = 0.0f;
             if (r2 < rc2) {
@@ -342,15 +350,20 @@ __global__ __launch_bounds__(64) void k_mlp_gradg(MlpArgs a) {
             hp[3 * slot] = h0;
             hp[3 * slot + 1] = h1;
             hp[3 * slot + 2] = h2;
-            const int ck = a.ncount[k];
             int kk = -1;
-            for (int b0 = 0; b0 < ck && kk < 0; b0 += 8) {
-                int v[8];
+            if (cached) {
+                kk = a.rslot[(size_t)j * a.max_nbr + slot];
+            } else {
+                const int ck = a.ncount[k];
+                for (int b0 = 0; b0 < ck && kk < 0; b0 += 8) {
+                    int v[8];
 #pragma unroll
-                for (int u = 0; u < 8; u++) v[u] = b0 + u < ck ? a.nidx[(size_t)(b0 + u) * n + k] : -1;
+                    for (int u = 0; u < 8; u++) v[u] = b0 + u < ck ? a.nidx[(size_t)(b0 + u) * n + k] : -1;
 #pragma unroll
-                for (int u = 0; u < 8; u++)
-                    if (v[u] == j && kk < 0) kk = b0 + u;
+                    for (int u = 0; u < 8; u++)
+                        if (v[u] == j && kk < 0) kk = b0 + u;
+                }
+                a.rslot[(size_t)j * a.max_nbr + slot] = kk;
             }
             if (kk < 0) {
                 atomicOr(&a.flags[1], kErrAsym);
@@ -362,6 +375,7 @@ __global__ __launch_bounds__(64) void k_mlp_gradg(MlpArgs a) {
             }
         }
         __syncthreads();
+        if (!cached && threadIdx.x == 0) a.rstamp[j] = lgen;
     }
 }
 
@@ -559,6 +573,9 @@ static MlpArgs mlp_args(ap_ctx *c, int n, const double *box) {
     a.g = c->g;
     a.xg = c->xg;
     a.xl = c->xl;
+    a.rslot = c->rslot;
+    a.rstamp = c->rstamp;
+    a.list_gen = c->list_gen;
     a.q = nullptr;
     a.W = c->W;
     a.wlist = c->wlist;

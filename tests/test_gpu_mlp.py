@@ -145,3 +145,21 @@ def test_training_decreases_loss_and_is_deterministic(mlp_case):
     assert hist[-1] < 0.5 * hist[0]
     assert np.array_equal(runs[0][1], runs[1][1]) and np.array_equal(runs[0][0], runs[1][0])
     ctx.close()
+
+
+def test_learned_indicator_forces_after_steps_match_oracle(oracle, mlp_case):
+    """20 velocity-Verlet steps with the learned indicator: the later steps reuse the reverse slots kept
+    for the list (no rebuild since the first step), and the forces left at the final positions must
+    still match the oracle's evaluation there."""
+    s, _, p = mlp_case
+    vel = synth.build_system(1)["vel"]
+    ctx = _ctx(s, p)
+    pos, v = to_dev(s["pos"]), to_dev(vel)
+    F = ctx.mixed_energy_forces(pos, s["box"])["F"]
+    th = ctx.vv_step(pos, v, F, s["mass"], 1e-3, 20, s["box"]).cpu().numpy()
+    _say("vv with the learned indicator: rebuilds %d" % int(th[:, 7].sum()))
+    assert int(th[1:, 7].sum()) == 0  # the cached reverse slots are in use after the first step
+    pf = soa_to_aos(pos)
+    want = oracle.evaluate(s, pos=pf, mlp=(p, 5.5))
+    _lt("F rms", force_err_rms(soa_to_aos(F), want["F"]), TOL_F32_FORCE)
+    ctx.close()
