@@ -289,10 +289,12 @@ void launch_dens_desc(ap_ctx *c, int n, const double *box, const EvalFlags &f, c
 // counted: S from the density pass's chunk counts in one kernel (no subset); otherwise count, scan, scatter
 void launch_compact(ap_ctx *c, int n, const int32_t *subset, int n_subset, bool counted);
 // stamped: only the atoms stamped by this evaluation's ACE pair kernel gather; csp_marks: also stamp (cmark)
-// the CSP neighbours of every atom with W != 0
+// the atoms that receive terms from an atom with W != 0: its CSP neighbours, or with the learned
+// indicator its list neighbours
 void launch_W(ap_ctx *c, int n, const double *box, bool stamped, bool csp_marks);
 // uniform_lambda: lambda is the constant of f on every atom (no per-atom lambda from the caller);
-// csp_marked: the W pass wrote cmark, and only marked atoms look for reverse CSP terms
+// csp_marked: the W pass wrote cmark: only marked atoms look for reverse CSP terms, and with the learned
+// indicator an atom neither marked nor flagged active takes the EAM-only gather
 void launch_force(ap_ctx *c, int n, const double *box, const EvalFlags &f, double *E_atom, double *F,
                   const double *sbox = nullptr, bool uniform_lambda = true, bool csp_marked = false);
 // per-structure sums of weight_i x (E^p_i, dE_i/dc, dE_i/db) over a batch (deterministic order)

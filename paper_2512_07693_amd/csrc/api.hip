@@ -130,7 +130,9 @@ static int evaluate(ap_ctx *c, int n, const double *box, const EvalFlags &f, con
     }
     // with the stamps, W != 0 only near S: the W pass marks the atoms with reverse CSP terms
     const bool stamped = run_ace && !subset;
-    const bool csp_marks = stamped && c->sw.indicator == AP_IND_CSP && c->n_csp > 0;
+    // (with the learned indicator, the list neighbours of each atom with W != 0, which receive its
+    // grad-g terms)
+    const bool csp_marks = stamped && (c->sw.indicator == AP_IND_MLP || c->n_csp > 0);
     if (f.switching && f.grad_lambda) {
         ProfScope p(c, "W");
         launch_W(c, n, box, stamped, csp_marks);

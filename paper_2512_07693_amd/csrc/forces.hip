@@ -309,7 +309,8 @@ __global__ __launch_bounds__(kBlock) void k_W(const double *__restrict__ pos, in
                                               const Rec4 *__restrict__ xl, const double *__restrict__ lam,
                                               double *__restrict__ W, int *__restrict__ act,
                                               const int *__restrict__ stamp, int gen, int use_stamp,
-                                              const int32_t *__restrict__ csp_t, int n_csp, int *__restrict__ cmark) {
+                                              const int32_t *__restrict__ csp_t, int n_csp, int *__restrict__ cmark,
+                                              int mark_list) {
     // plain block order: the stamped atoms are a few contiguous index ranges, and an XCD-contiguous
     // mapping would put them all on one or two XCDs
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -356,9 +357,16 @@ __global__ __launch_bounds__(kBlock) void k_W(const double *__restrict__ pos, in
             W[j] = Wj;
             act[j] = stamped ? (near_s | (lam[j] < 1.0)) : 0;
         }
-        // the atoms in j's CSP list receive a reverse term of (S27) from W_j (all writers store gen)
-        if (cmark && Wj != 0.0)
-            for (int t = sub; t < n_csp; t += SUB) cmark[csp_t[(size_t)t * n + j]] = gen;
+        // the atoms in j's CSP list receive a reverse term of (S27) from W_j; with the learned indicator,
+        // the atoms of j's neighbour list receive its grad-g term (S16) (all writers store gen)
+        if (cmark && Wj != 0.0) {
+            if (mark_list) {
+                const int cnt = ncount[j];
+                for (int q = sub; q < cnt; q += SUB) cmark[nidx[(size_t)q * n + j]] = gen;
+            } else {
+                for (int t = sub; t < n_csp; t += SUB) cmark[csp_t[(size_t)t * n + j]] = gen;
+            }
+        }
     }
 }
 
@@ -367,7 +375,8 @@ void launch_W(ap_ctx *c, int n, const double *box, bool stamped, bool csp_marks)
     constexpr int SUB = kLanesPerAtom;
     k_W<SUB><<<((size_t)n * SUB + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(
         c->pos, n, box[0], box[1], box[2], c->sw.r_w, c->nbr_cnt, c->nbr_idx, c->Et, c->xl, c->lam, c->W, c->act,
-        c->stamp, c->stamp_gen, stamped ? 1 : 0, c->csp_t, c->n_csp, csp_marks ? c->cmark : nullptr);
+        c->stamp, c->stamp_gen, stamped ? 1 : 0, c->csp_t, c->n_csp, csp_marks ? c->cmark : nullptr,
+        c->sw.indicator == AP_IND_MLP ? 1 : 0);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -458,7 +467,9 @@ __global__ __launch_bounds__(kBlock, (FULL && sizeof(TF) == 4) ? 4 : 1) void k_f
         const TF *fp = reinterpret_cast<const TF *>(a.fpair);
         // without a precise atom in reach only the EAM pairs contribute: those are the first nshort
         // slots, and every lambda in reach equals lambda_i (no switching, or lambda = 1 all around)
-        const bool eam_only = a.short_mode == 2 || (a.short_mode == 1 && !a.act[i]);
+        // (with the learned indicator an atom that a W != 0 neighbour marked gathers its grad-g terms)
+        const bool eam_only = a.short_mode == 2 ||
+                              (a.short_mode == 1 && !a.act[i] && !(a.ind_mlp && a.cmark[i] == a.cgen));
         const int cnt = (!FULL || eam_only) ? 0 : (a.short_mode == 3 ? a.nshort[i] : a.ncount[i]);
         const int wi = (gl && a.ind_mlp) ? a.widx[i] : -1;
         const double *Lb = a.sbox ? a.sbox + 3 * a.sid[i] : a.L;  // own cell in a batch of cells
@@ -726,6 +737,8 @@ void launch_force(ap_ctx *c, int n, const double *box, const EvalFlags &f, doubl
     // for every atom; 3: EAM pairs only (short lists) with a per-atom lambda
     a.short_mode = 0;
     if (!sbox && f.switching && f.grad_lambda && c->sw.indicator == AP_IND_CSP) a.short_mode = 1;
+    // the learned indicator needs the marks of the W pass to know who receives grad-g terms
+    if (!sbox && f.switching && f.grad_lambda && c->sw.indicator == AP_IND_MLP && csp_marked) a.short_mode = 1;
     if (!sbox && !f.switching && (!f.ace_forces || f.lam_const == 1.0)) a.short_mode = uniform_lambda ? 2 : 3;
     const int nb = force_blocks(n);
     if (a.short_mode == 2)
