@@ -49,6 +49,39 @@ __device__ __forceinline__ double min_image(double d, double L) {
     return d - L * rint(d / L);
 }
 
+// One thermo row of velocity Verlet from the force pass's per-block partial sums (column-major, nbf
+// blocks): the potential energy (column 0), the kinetic energy and momentum after the second half-kick
+// (columns 10-13), then |S| and the rebuild flag given by the caller. Run by one whole workgroup of kBlock
+// threads, so that every row is summed in the same order.
+__device__ inline void thermo_row_block(const double *__restrict__ partials, int nbf, int pstride, int S,
+                                        int rebuild, int *flags, double *row) {
+    __shared__ double sh[kBlock / 64][5];
+    double t5[5] = {0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nbf; b += kBlock) {
+        t5[0] += partials[b];
+        for (int q = 1; q < 5; q++) t5[q] += partials[(size_t)(9 + q) * pstride + b];
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int q = 0; q < 5; q++) {
+        double x = t5[q];
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+        if (lane == 0) sh[w][q] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s[5] = {0, 0, 0, 0, 0};
+        for (int k = 0; k < kBlock / 64; k++)
+            for (int q = 0; q < 5; q++) s[q] += sh[k][q];
+        if (!isfinite(s[0])) atomicOr(&flags[1], kErrNonFinite);
+        row[0] = s[0];
+        row[1] = s[1];
+        row[2] = s[0] + s[1];
+        for (int q = 0; q < 3; q++) row[3 + q] = s[2 + q];
+        row[6] = (double)S;
+        row[7] = (double)rebuild;
+    }
+}
+
 // Minimum image of a difference of two wrapped coordinates (|d| < L): the value of min_image wherever
 // |d| is not within rounding of L / 2 (never inside a cutoff below L / 2), without the division. The
 // list build's distance test takes it too: within a cutoff below L / 2 both give the same bits, so the
@@ -186,6 +219,7 @@ struct ap_ctx {
     // second half-kick v += kick_hdtm F (null: no kick)
     double *kick_vel = nullptr;
     double kick_hdtm = 0.0, kick_mass = 0.0;
+    double *thermo_prev = nullptr;  // set by the same loop: the row the density pass fills for the last step
 
     // gathered records: xg = {x, y, z, g}, xl = {x, y, z, lambda}, eb = {xi', g, d + d0, E~}
     ap::Rec4 *xg = nullptr, *xl = nullptr, *eb = nullptr;

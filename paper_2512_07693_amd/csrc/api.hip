@@ -213,36 +213,11 @@ __global__ __launch_bounds__(kBlock) void k_vv_first(double *pos, double *vel, c
     if (u[0] * u[0] + u[1] * u[1] + u[2] * u[2] > half_skin2) atomicOr(&flags[0], 1);
 }
 
-// One thermo row from the force pass's partial rows (nbf of them): the potential energy (column 0), the
-// kinetic energy and momentum after the second half-kick (columns 10-13), |S| and the rebuild flag.
-constexpr int kThermoThreads = 1024;
-__global__ __launch_bounds__(kThermoThreads) void k_thermo(const double *partials, int nbf, int pstride, int *flags,
-                                                           double *row) {
-    __shared__ double sh[kThermoThreads / 64][5];
-    double t5[5] = {0, 0, 0, 0, 0};
-    for (int b = threadIdx.x; b < nbf; b += kThermoThreads) {
-        t5[0] += partials[b];
-        for (int q = 1; q < 5; q++) t5[q] += partials[(size_t)(9 + q) * pstride + b];
-    }
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int q = 0; q < 5; q++) {
-        double x = t5[q];
-        for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
-        if (lane == 0) sh[w][q] = x;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double s[5] = {0, 0, 0, 0, 0};
-        for (int k = 0; k < kThermoThreads / 64; k++)
-            for (int q = 0; q < 5; q++) s[q] += sh[k][q];
-        if (!isfinite(s[0])) atomicOr(&flags[1], kErrNonFinite);
-        row[0] = s[0];
-        row[1] = s[1];
-        row[2] = s[0] + s[1];
-        for (int q = 0; q < 3; q++) row[3 + q] = s[2 + q];
-        row[6] = (double)flags[2];
-        row[7] = (double)flags[3];
-    }
+// The thermo row of the last step of a velocity-Verlet call (the earlier ones are taken by the density
+// pass of the step after them).
+__global__ __launch_bounds__(kBlock) void k_thermo(const double *partials, int nbf, int pstride, int *flags,
+                                                   double *row) {
+    thermo_row_block(partials, nbf, pstride, flags[2], flags[3], flags, row);
 }
 
 }  // namespace ap
@@ -660,7 +635,9 @@ int ap_vv_step(ap_ctx *c, int n, double *pos, double *vel, double *F, double mas
                                                      box->L[2], c->pos_build, 0.25 * c->skin * c->skin, c->d_flags,
                                                      c->cell_cnt, c->cell_fill, force ? 0 : c->ncell_cur);
         }
-        // the force pass applies the second half-kick and sums E_kin and P with the energy
+        // the force pass applies the second half-kick and sums E_kin and P with the energy; the density
+        // pass of this step takes the thermo row of the previous one from the partials it left
+        c->thermo_prev = s > 0 ? thermo + (size_t)8 * (s - 1) : nullptr;
         c->kick_vel = vel;
         c->kick_hdtm = hdtm;
         c->kick_mass = mass;
@@ -669,14 +646,18 @@ int ap_vv_step(ap_ctx *c, int n, double *pos, double *vel, double *F, double mas
         c->kick_vel = nullptr;
         if (rc) {
             c->prof_skip = false;
+            c->thermo_prev = nullptr;
             return rc;
         }
         force = false;
-        ProfScope p(c, "thermo");
-        k_thermo<<<1, kThermoThreads, 0, c->stream>>>(c->partials, nbf, c->pstride, c->d_flags,
-                                                      thermo + (size_t)8 * s);
     }
     c->prof_skip = false;
+    c->thermo_prev = nullptr;
+    if (n_steps > 0) {
+        ProfScope p(c, "thermo");
+        k_thermo<<<1, kBlock, 0, c->stream>>>(c->partials, nbf, c->pstride, c->d_flags,
+                                              thermo + (size_t)8 * (n_steps - 1));
+    }
     rc = hip_check(c, hipGetLastError(), "vv");
     if (!rc) rc = sync_and_check(c);
     return rc;

@@ -70,9 +70,15 @@ __global__ __launch_bounds__(kBlock) void k_dens_desc(const double *__restrict__
                                                       double *__restrict__ wbar, double *__restrict__ dd,
                                                       double *__restrict__ lam, double *__restrict__ dlam,
                                                       double *__restrict__ Ep, double *__restrict__ Et, int *flags,
-                                                      int *__restrict__ chunk_cnt, int *list_gen) {
-    // commit of the neighbour-list rebuild flag, after every list kernel of this evaluation
+                                                      int *__restrict__ chunk_cnt, int *list_gen,
+                                                      const double *__restrict__ partials, int nbf, int pstride,
+                                                      double *row_prev) {
+    // commit of the neighbour-list rebuild flag, after every list kernel of this evaluation (workgroup 0
+    // keeps the previous value for the thermo row below)
+    __shared__ int s_prev_rebuild, s_prev_S;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
+        s_prev_rebuild = flags[3];
+        s_prev_S = flags[2];
         if (flags[0]) list_gen[0]++;
         flags[3] = flags[0];
         flags[0] = 0;
@@ -173,6 +179,12 @@ __global__ __launch_bounds__(kBlock) void k_dens_desc(const double *__restrict__
             chunk_cnt[t / (int)blockDim.x] = s;
         }
     }
+    // inside velocity Verlet: the previous step's thermo row, from the partials its force pass left
+    // (|S| and the rebuild flag as they were before this evaluation)
+    if (row_prev && blockIdx.x == 0) {
+        __syncthreads();
+        thermo_row_block(partials, nbf, pstride, s_prev_S, s_prev_rebuild, flags, row_prev);
+    }
 }
 
 void launch_dens_desc(ap_ctx *c, int n, const double *box, const EvalFlags &f, const double *lam_in, bool count) {
@@ -181,7 +193,8 @@ void launch_dens_desc(ap_ctx *c, int n, const double *box, const EvalFlags &f, c
     k_dens_desc<SUB><<<((size_t)n * SUB + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(
         c->pos, n, box[0], box[1], box[2], eamp(c->eam), sp, f.switching ? 1 : 0, f.lam_const, lam_in, c->nbr_cnt,
         c->nbr_idx, c->g, c->xg, c->xl, c->eb, c->xe, c->Ef, c->xip, c->wbar, c->d, c->lam, c->dlam, c->Ep, c->Et,
-        c->d_flags, count ? c->chunk_cnt : nullptr, c->list_gen);
+        c->d_flags, count ? c->chunk_cnt : nullptr, c->list_gen, c->partials, force_blocks(n), c->pstride,
+        c->thermo_prev);
 }
 
 // ------------------------------------------------------------------------------------------
