@@ -220,6 +220,8 @@ struct ap_ctx {
     double *kick_vel = nullptr;
     double kick_hdtm = 0.0, kick_mass = 0.0;
     double *thermo_prev = nullptr;  // set by the same loop: the row the density pass fills for the last step
+    double *drift_pos = nullptr;    // and the caller's positions, which the force pass drifts for the next step
+    double drift_dt = 0.0;
 
     // gathered records: xg = {x, y, z, g}, xl = {x, y, z, lambda}, eb = {xi', g, d + d0, E~}
     ap::Rec4 *xg = nullptr, *xl = nullptr, *eb = nullptr;

@@ -628,22 +628,26 @@ int ap_vv_step(ap_ctx *c, int n, double *pos, double *vel, double *F, double mas
     bool force = true;
     for (int s = 0; s < n_steps; s++) {
         c->prof_skip = c->prof_every > 1 && s % c->prof_every != 0;
-        {
+        if (s == 0) {
             ProfScope p(c, "vv_first");
             // (the first step rebuilds the list anyway: its check and clearing are redone there)
             k_vv_first<<<nb, kBlock, 0, c->stream>>>(pos, vel, F, c->pos, n, hdtm, dt, box->L[0], box->L[1],
                                                      box->L[2], c->pos_build, 0.25 * c->skin * c->skin, c->d_flags,
-                                                     c->cell_cnt, c->cell_fill, force ? 0 : c->ncell_cur);
+                                                     c->cell_cnt, c->cell_fill, 0);
         }
-        // the force pass applies the second half-kick and sums E_kin and P with the energy; the density
-        // pass of this step takes the thermo row of the previous one from the partials it left
+        // the force pass applies the second half-kick and sums E_kin and P with the energy, then (but on
+        // the last step) the next step's first half-kick, drift and skin check; the density pass of this
+        // step takes the thermo row of the previous one from the partials it left
         c->thermo_prev = s > 0 ? thermo + (size_t)8 * (s - 1) : nullptr;
         c->kick_vel = vel;
         c->kick_hdtm = hdtm;
         c->kick_mass = mass;
+        c->drift_pos = s + 1 < n_steps ? pos : nullptr;
+        c->drift_dt = dt;
         rc = evaluate(c, n, box->L, f, nullptr, nullptr, 0, run_ace, nullptr, nullptr, F, nullptr, force, !force,
                       false);
         c->kick_vel = nullptr;
+        c->drift_pos = nullptr;
         if (rc) {
             c->prof_skip = false;
             c->thermo_prev = nullptr;

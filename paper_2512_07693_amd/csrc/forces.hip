@@ -429,6 +429,14 @@ struct ForceArgs {
     // kinetic energy and momentum in partial columns 10-13 (null: no kick)
     double *vel;
     double hdtm, mass;
+    // and, when drift_pos is set (not the last step), the next step's first half-kick and drift: the
+    // wrapped positions go to drift_pos (the caller's) and ipos (the context's copy), the skin check
+    // against pos_build to flags[0], and the cell counts are cleared for a possible rebuild
+    double *drift_pos, *ipos;
+    const double *pos_build;
+    double dt, half_skin2;
+    int *cell_cnt, *cell_fill;
+    int ncell;
 };
 
 template <typename TF>
@@ -467,6 +475,10 @@ __global__ __launch_bounds__(kBlock, (FULL && sizeof(TF) == 4) ? 4 : 1) void k_f
     // ranges, spread this way over every XCD
     const int blk = blockIdx.x;
     const int t = blk * blockDim.x + threadIdx.x;
+    for (int q = t; q < a.ncell; q += gridDim.x * blockDim.x) {  // (with the fused drift)
+        a.cell_cnt[q] = 0;
+        a.cell_fill[q] = 0;
+    }
     const int i = t / SUB, sub = t - i * SUB;  // SUB lanes per atom, slots sub, sub + SUB, ...
     const int n = a.n;
     double F0 = 0, F1 = 0, F2 = 0, Ei = 0;
@@ -626,10 +638,13 @@ __global__ __launch_bounds__(kBlock, (FULL && sizeof(TF) == 4) ? 4 : 1) void k_f
             if (Wi != 0.0) {
                 for (int t = sub; t < a.n_csp; t += SUB) {
                     const int l = a.csp_t[(size_t)t * n + i], o = a.csp_t[(size_t)(t ^ 1) * n + i];
-                    const double lx = min_image_w(a.pos[l] - xi, a.L[0]), ly = min_image_w(a.pos[n + l] - yi, a.L[1]),
-                                 lz = min_image_w(a.pos[2 * n + l] - zi, a.L[2]);
-                    const double ox = min_image_w(a.pos[o] - xi, a.L[0]), oy = min_image_w(a.pos[n + o] - yi, a.L[1]),
-                                 oz = min_image_w(a.pos[2 * n + o] - zi, a.L[2]);
+                    // (other atoms' positions from their records: with the fused drift an atom's own
+                    // entry of pos changes during this pass)
+                    const Rec4 pl = a.xl[l], po = a.xl[o];
+                    const double lx = min_image_w(pl.x - xi, a.L[0]), ly = min_image_w(pl.y - yi, a.L[1]),
+                                 lz = min_image_w(pl.z - zi, a.L[2]);
+                    const double ox = min_image_w(po.x - xi, a.L[0]), oy = min_image_w(po.y - yi, a.L[1]),
+                                 oz = min_image_w(po.z - zi, a.L[2]);
                     const double sx = lx + ox, sy = ly + oy, sz = lz + oz;
                     F0 -= 2.0 * Wi * sx;
                     F1 -= 2.0 * Wi * sy;
@@ -648,10 +663,11 @@ __global__ __launch_bounds__(kBlock, (FULL && sizeof(TF) == 4) ? 4 : 1) void k_f
                     const double Wj = a.W[jj];
                     if (Wj == 0.0) continue;
                     const int o = a.csp_t[(size_t)(t ^ 1) * n + jj];
-                    const double xj = a.pos[jj], yj = a.pos[n + jj], zj = a.pos[2 * n + jj];
-                    const double sx = min_image_w(xi - xj, a.L[0]) + min_image_w(a.pos[o] - xj, a.L[0]);
-                    const double sy = min_image_w(yi - yj, a.L[1]) + min_image_w(a.pos[n + o] - yj, a.L[1]);
-                    const double sz = min_image_w(zi - zj, a.L[2]) + min_image_w(a.pos[2 * n + o] - zj, a.L[2]);
+                    const Rec4 pj = a.xl[jj], po = a.xl[o];
+                    const double xj = pj.x, yj = pj.y, zj = pj.z;
+                    const double sx = min_image_w(xi - xj, a.L[0]) + min_image_w(po.x - xj, a.L[0]);
+                    const double sy = min_image_w(yi - yj, a.L[1]) + min_image_w(po.y - yj, a.L[1]);
+                    const double sz = min_image_w(zi - zj, a.L[2]) + min_image_w(po.z - zj, a.L[2]);
                     F0 += 2.0 * Wj * sx;
                     F1 += 2.0 * Wj * sy;
                     F2 += 2.0 * Wj * sz;
@@ -668,13 +684,24 @@ __global__ __launch_bounds__(kBlock, (FULL && sizeof(TF) == 4) ? 4 : 1) void k_f
         Ei = li * a.Ef[i] + (1.0 - li) * a.Ep[i];
         if (a.vel) {
             const double Fa[3] = {F0, F1, F2};
+            double u2 = 0.0;
             for (int q = 0; q < 3; q++) {
                 const size_t o = (size_t)q * n + i;
-                const double vq = a.vel[o] + a.hdtm * Fa[q];
-                a.vel[o] = vq;
+                double vq = a.vel[o] + a.hdtm * Fa[q];
                 kin[0] += 0.5 * a.mass * vq * vq / kConv;
                 kin[1 + q] = a.mass * vq;
+                if (a.drift_pos) {
+                    // the next step's first half-kick and drift, and the skin check of its list
+                    vq = vq + a.hdtm * Fa[q];
+                    const double x = wrap_coord(a.drift_pos[o] + a.dt * vq, a.L[q]);
+                    a.drift_pos[o] = x;
+                    a.ipos[o] = x;
+                    const double u = min_image_w(x - a.pos_build[o], a.L[q]);
+                    u2 += u * u;
+                }
+                a.vel[o] = vq;
             }
+            if (a.drift_pos && u2 > a.half_skin2) atomicOr(&a.flags[0], 1);
         }
         if (a.E_atom) a.E_atom[i] = Ei;
         if (a.F) {
@@ -702,6 +729,14 @@ void launch_force(ap_ctx *c, int n, const double *box, const EvalFlags &f, doubl
     a.vel = sbox ? nullptr : c->kick_vel;
     a.hdtm = c->kick_hdtm;
     a.mass = c->kick_mass;
+    a.drift_pos = a.vel ? c->drift_pos : nullptr;
+    a.ipos = c->pos;
+    a.pos_build = c->pos_build;
+    a.dt = c->drift_dt;
+    a.half_skin2 = 0.25 * c->skin * c->skin;
+    a.cell_cnt = c->cell_cnt;
+    a.cell_fill = c->cell_fill;
+    a.ncell = a.drift_pos ? c->ncell_cur : 0;
     a.sbox = sbox;
     a.sid = c->sid;
     a.pos = c->pos;
