@@ -564,23 +564,38 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
                 }
             }
             __syncthreads();
-            // dE/dA[n1][l1 m1] = sum kappa sum_n2 Q_M[n1][n2] A[n2][l2 m2]
+            // dE/dA[n1][l1 m1] = sum kappa sum_n2 Q_M[n1][n2] A[n2][l2 m2] with the Q_M rows at qbase
             // (lanes in runs of n_max share m1: the same coupling list, read as a broadcast)
-            for (int w = tid; w < NMAX * n1m; w += kBlock) {
-                const int i1 = w / NMAX, q1 = w - i1 * NMAX;
-                T acc = T(0);
-                const int e0 = bk[18 + i1] - k0, e1 = bk[18 + i1 + 1] - k0;
-                for (int q = e0; q < e1; q++) {
-                    const int code = B.kc[q];  // (Q_M offset) | (l2 m2 row of At) << 12, in units of four
-                    const T *qr = B.Q + 4 * (code & 4095) + q1 * NMAX;
-                    const T *a2 = sAt + 4 * (code >> 12);
-                    T s2 = T(0);
+            auto adj1 = [&](const T *qbase) {
+                for (int w = tid; w < NMAX * n1m; w += kBlock) {
+                    const int i1 = w / NMAX, q1 = w - i1 * NMAX;
+                    T acc = T(0);
+                    const int e0 = bk[18 + i1] - k0, e1 = bk[18 + i1 + 1] - k0;
+                    for (int q = e0; q < e1; q++) {
+                        const int code = B.kc[q];  // (Q_M offset) | (l2 m2 row of At) << 12, in units of four
+                        const T *qr = qbase + 4 * (code & 4095) + q1 * NMAX;
+                        const T *a2 = sAt + 4 * (code >> 12);
+                        T s2 = T(0);
 #pragma unroll
-                    for (int q2 = 0; q2 < NMAX; q2++) s2 += qr[q2] * a2[q2];
-                    acc += B.kv[q] * s2;
+                        for (int q2 = 0; q2 < NMAX; q2++) s2 += qr[q2] * a2[q2];
+                        acc += B.kv[q] * s2;
+                    }
+                    sG[q1 * NLM + b1 + i1 - l1] += acc;
                 }
-                sG[q1 * NLM + b1 + i1 - l1] += acc;
+            };
+            if (l1 == l2) {
+                // l1 = l2: the couplings are symmetric in (m1, m2), so the l2 adjoint is the l1 one taken
+                // with Q_M transposed, and both together are the l1 adjoint of Q_M + Q_M^T (written into
+                // the space of P, no longer read)
+                for (int o = tid; o < nM * NN; o += kBlock) {
+                    const int Mi = o / NN, r = o - Mi * NN, n1 = r / NMAX, n2 = r - n1 * NMAX;
+                    B.P[o] = B.Q[o] + B.Q[Mi * NN + n2 * NMAX + n1];
+                }
+                __syncthreads();
+                adj1(B.P);
+                continue;
             }
+            adj1(B.Q);
             // Q_M transposed into the space of P (no longer read), for the row reads below
             for (int o = tid; o < nM * NN; o += kBlock) {
                 const int Mi = o / NN, r = o - Mi * NN, n1 = r / NMAX, n2 = r - n1 * NMAX;
