@@ -564,38 +564,34 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
                 }
             }
             __syncthreads();
-            // dE/dA[n1][l1 m1] = sum kappa sum_n2 Q_M[n1][n2] A[n2][l2 m2] with the Q_M rows at qbase
+            // dE/dA[n1][l1 m1] = scale sum kappa sum_n2 Q_M[n1][n2] A[n2][l2 m2]
             // (lanes in runs of n_max share m1: the same coupling list, read as a broadcast)
-            auto adj1 = [&](const T *qbase) {
+            auto adj1 = [&](T scale) {
                 for (int w = tid; w < NMAX * n1m; w += kBlock) {
                     const int i1 = w / NMAX, q1 = w - i1 * NMAX;
                     T acc = T(0);
                     const int e0 = bk[18 + i1] - k0, e1 = bk[18 + i1 + 1] - k0;
                     for (int q = e0; q < e1; q++) {
                         const int code = B.kc[q];  // (Q_M offset) | (l2 m2 row of At) << 12, in units of four
-                        const T *qr = qbase + 4 * (code & 4095) + q1 * NMAX;
+                        const T *qr = B.Q + 4 * (code & 4095) + q1 * NMAX;
                         const T *a2 = sAt + 4 * (code >> 12);
                         T s2 = T(0);
 #pragma unroll
                         for (int q2 = 0; q2 < NMAX; q2++) s2 += qr[q2] * a2[q2];
                         acc += B.kv[q] * s2;
                     }
-                    sG[q1 * NLM + b1 + i1 - l1] += acc;
+                    sG[q1 * NLM + b1 + i1 - l1] += scale * acc;
                 }
             };
             if (l1 == l2) {
                 // l1 = l2: the couplings are symmetric in (m1, m2), so the l2 adjoint is the l1 one taken
-                // with Q_M transposed, and both together are the l1 adjoint of Q_M + Q_M^T (written into
-                // the space of P, no longer read)
-                for (int o = tid; o < nM * NN; o += kBlock) {
-                    const int Mi = o / NN, r = o - Mi * NN, n1 = r / NMAX, n2 = r - n1 * NMAX;
-                    B.P[o] = B.Q[o] + B.Q[Mi * NN + n2 * NMAX + n1];
-                }
-                __syncthreads();
-                adj1(B.P);
+                // with Q_M transposed; the coefficient blocks of these (L, l, l) are stored symmetrised in
+                // (n1, n2) (the same energy, as P_M is symmetric), so Q_M is symmetric and both adjoints
+                // together are twice the l1 one
+                adj1(T(2));
                 continue;
             }
-            adj1(B.Q);
+            adj1(T(1));
             // Q_M transposed into the space of P (no longer read), for the row reads below
             for (int o = tid; o < nM * NN; o += kBlock) {
                 const int Mi = o / NN, r = o - Mi * NN, n1 = r / NMAX, n2 = r - n1 * NMAX;
@@ -973,6 +969,21 @@ int ace_setup(ap_ctx *c, const ap_ace_params *p) {
             g3[bi].push_back(f);
         }
     }
+    // (L, l, l) blocks: the coefficients symmetrised in (n1, n2), which leaves every energy unchanged (P_M
+    // is symmetric there) and makes Q_M symmetric, so that the energy kernel takes both coupling adjoints
+    // in one pass
+    for (size_t bi = 0; bi < blocks.size(); bi++) {
+        if (blocks[bi].l1 != blocks[bi].l2) continue;
+        double *cb = c3.data() + bi * (size_t)N * N * N;
+        for (int n1 = 0; n1 < N; n1++)
+            for (int n2 = n1 + 1; n2 < N; n2++)
+                for (int n3 = 0; n3 < N; n3++) {
+                    double &u = cb[((size_t)n1 * N + n2) * N + n3], &v = cb[((size_t)n2 * N + n1) * N + n3];
+                    const double m = 0.5 * (u + v);
+                    u = m;
+                    v = m;
+                }
+    }
     std::vector<int> g3flat;
     // keep only blocks with coefficients; build coupling tables in three orderings
     std::vector<int> hblk;
@@ -1133,9 +1144,9 @@ void ace_cost(const ap_ctx *c, double *fixed, double *per_nbr_energy, double *pe
         f += NN * nkap * 3.0;                          // P
         f += (2 * L + 1) * NN * (2.0 * N + 2.0);       // Q and the energy P.Q
         f += N * (2 * L + 1) * NN * 2.0;               // adjoint into A_{n3 L M}
-        f += N * nkap * (2.0 * N + 2.0) * 2.0;         // adjoints into A_{n1 l1} and A_{n2 l2}
-        (void)l1;
-        (void)l2;
+        // adjoints into A_{n1 l1} and A_{n2 l2}: one pass when l1 = l2 (symmetric couplings and
+        // coefficients make the two equal)
+        f += N * nkap * (2.0 * N + 2.0) * (l1 == l2 ? 1.0 : 2.0);
     }
     *fixed = f;
     *per_nbr_energy = 2.0 * NA + 8.0 * N + 10.0 * NLM;
