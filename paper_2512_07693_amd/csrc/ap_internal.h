@@ -15,6 +15,7 @@ namespace ap {
 constexpr int kBlock = 256;      // threads per workgroup of the per-atom kernels (4 wavefronts)
 constexpr int kAceMaxValid = 128; // neighbours within the ACE cutoff held per site in LDS
 constexpr int kLanesPerAtom = 8;  // lanes that share one atom's neighbour loop in the per-atom passes
+constexpr int kDensLanes = 4;     // the same in the density pass (its per-workgroup counts cover kBlock / 4 atoms)
 constexpr int kForceLanes = 4;    // the same for the force assembly
 // workgroups of the force kernel, each writing one row of the per-block partial sums
 // Above this many atoms the one-kernel compaction (each workgroup sums all the chunk counts before it)
@@ -230,7 +231,7 @@ struct ap_ctx {
     double *g = nullptr, *d = nullptr, *wbar = nullptr, *lam = nullptr, *dlam = nullptr;
     double *Ef = nullptr, *Ep = nullptr, *Et = nullptr, *W = nullptr, *xip = nullptr;
     int *sidx = nullptr, *slist = nullptr, *blk_cnt = nullptr, *mark = nullptr;
-    int *chunk_cnt = nullptr;  // [ceil(n / (kBlock / kLanesPerAtom))] counts of lambda < 1 from the density pass
+    int *chunk_cnt = nullptr;  // [ceil(n / (kBlock / kDensLanes))] counts of lambda < 1 from the density pass
     int *sid = nullptr;          // [n_cap] structure of each atom in a batch evaluation
     int *b_off = nullptr;        // [n_struct + 1] device copy of the batch offsets
     double *b_box = nullptr;     // [n_struct][3] device copy of the batch boxes

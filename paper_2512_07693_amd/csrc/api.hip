@@ -286,7 +286,7 @@ int ap_ctx_create(ap_ctx **out, int n_max_atoms, int max_nbr, double skin, void 
     alloc(&c->mark, n, 4);
     alloc(&c->sid, n, 4);
     alloc(&c->blk_cnt, 2 * nb + 2, 4);
-    alloc(&c->chunk_cnt, (n * kLanesPerAtom + kBlock - 1) / kBlock, 4);
+    alloc(&c->chunk_cnt, (n * kDensLanes + kBlock - 1) / kBlock, 4);
     c->pstride = (int)std::max<long long>((long long)nb, force_blocks((int)n));
     alloc(&c->partials, (size_t)c->pstride * 16, 8);
     alloc(&c->scalars, 16, 8);

@@ -189,7 +189,7 @@ __global__ __launch_bounds__(kBlock) void k_dens_desc(const double *__restrict__
 
 void launch_dens_desc(ap_ctx *c, int n, const double *box, const EvalFlags &f, const double *lam_in, bool count) {
     const SwP sp = swp(c);
-    constexpr int SUB = kLanesPerAtom;
+    constexpr int SUB = kDensLanes;
     k_dens_desc<SUB><<<((size_t)n * SUB + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(
         c->pos, n, box[0], box[1], box[2], eamp(c->eam), sp, f.switching ? 1 : 0, f.lam_const, lam_in, c->nbr_cnt,
         c->nbr_idx, c->g, c->xg, c->xl, c->eb, c->xe, c->Ef, c->xip, c->wbar, c->d, c->lam, c->dlam, c->Ep, c->Et,
@@ -253,7 +253,7 @@ __global__ void k_mark_subset(const int32_t *__restrict__ subset, int m, int n, 
     mark[i] = 1;
 }
 
-// Ordered compaction from the density pass's counts of lambda < 1 per kBlock / kLanesPerAtom atoms: each
+// Ordered compaction from the density pass's counts of lambda < 1 per kBlock / kDensLanes atoms: each
 // workgroup of kBlock atoms sums the counts before it (integers: exact in any order) and ranks its own
 // atoms by ballot; the last one writes |S|.
 __global__ __launch_bounds__(kBlock) void k_compact_chunks(int n, const double *__restrict__ lam,
@@ -295,7 +295,7 @@ __global__ __launch_bounds__(kBlock) void k_compact_chunks(int n, const double *
 void launch_compact(ap_ctx *c, int n, const int32_t *subset, int n_subset, bool counted) {
     const int nb = (n + kBlock - 1) / kBlock;
     if (counted && !subset) {
-        k_compact_chunks<<<nb, kBlock, 0, c->stream>>>(n, c->lam, c->chunk_cnt, kLanesPerAtom, c->sidx, c->slist,
+        k_compact_chunks<<<nb, kBlock, 0, c->stream>>>(n, c->lam, c->chunk_cnt, kDensLanes, c->sidx, c->slist,
                                                        c->d_flags + 2);
         return;
     }
