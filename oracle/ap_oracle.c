@@ -9,8 +9,10 @@
  *   transition function f_trans ............ Eq. (2) and Eq. (S1)
  *   descriptor d_i, weight w, normalisation  Eq. (6) / (S2), weighting function of App. B
  *   switching parameter lambda_i ........... Eq. (2) / (S3)
+ *   constant lambda on chosen atoms ........ App. B, the paragraph after (B4)
  *   AP energy E_i = l E^f + (1-l) E^p ...... Eq. (4)
  *   AP force (pair form) ................... Eq. (5), (A1)-(A2), (S5)-(S6)
+ *   force mixing (non-conservative) ........ Eq. (3)
  *   EAM energy and pair force .............. (B1), (B2), (S7)-(S13)
  *   ACE pair force weighting ............... (S14)
  *   grad-lambda forces ..................... (S15)-(S21) (weight part), (S22)-(S27) (CSP part),
@@ -868,6 +870,47 @@ double ora_mlp_loss_grad(int m, const double *q, const double *t, const double *
 }
 
 /* ------------------------------------------------------------------------------------------ */
+/* Descriptor, Eq. (6): d_i = sum_k g_k w(r_ik) / wbar_i - d0 with wbar_i = sum_k w(r_ik) and    */
+/* the weighting function w(r) = f_trans(r, r_w - 1 A, r_w) of App. B. Both sums run over every */
+/* atom k within r_w of i, the atom itself included (k = i, w(0) = 1).                           */
+/* ------------------------------------------------------------------------------------------ */
+static void descriptor_site(const double *pos, const double *L, const csr_t *nb, int i, const double *g, int gs,
+                            double r_w, double d0, double *wbar, double *d) {
+    double wsum = 1.0, gsum = g[(size_t)i * gs]; /* the term k = i */
+    for (int q = nb->start[i]; q < nb->start[i + 1]; q++) {
+        int k = nb->idx[q];
+        double u[3];
+        mic(pos, L, i, k, u);
+        double r = sqrt(sq3(u));
+        if (r >= r_w) continue;
+        double w = ora_ftrans(r, r_w - 1.0, r_w);
+        wsum += w;
+        gsum += g[(size_t)k * gs] * w;
+    }
+    *wbar = wsum;
+    *d = gsum / wsum - d0;
+}
+
+/* Eq. (6) for a given per-atom g[n] (any indicator) on one periodic cell: wbar[n] and d[n]. */
+int ora_descriptor(int n, const double *pos_in, const double *L, const double *g, double r_w, double d0,
+                   double *wbar, double *d) {
+    if (n <= 0 || !pos_in || !L || !g || !wbar || !d || !(r_w > 0.0)) return ORA_E_ARG;
+    int rc = check_box(L, r_w);
+    if (rc) return rc;
+    double *pos = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    memcpy(pos, pos_in, sizeof(double) * 3 * (size_t)n);
+    ora_wrap(n, pos, L);
+    csr_t nb;
+    rc = build_csr(n, pos, L, r_w, &nb);
+    if (!rc) {
+        for (int i = 0; i < n; i++) descriptor_site(pos, L, &nb, i, g, 1, r_w, d0, wbar + i, d + i);
+        csr_free(&nb);
+    }
+    free(pos);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------------------------ */
 /* Full AP evaluation                                                                            */
 /* ------------------------------------------------------------------------------------------ */
 /* aux columns per atom */
@@ -898,13 +941,24 @@ enum { AX_G, AX_D, AX_WBAR, AX_LAM, AX_DLAM, AX_EF, AX_EP, AX_ET, AX_W, AX_XIP, 
  *          aux[n][AUX_W] (may be NULL), Ffam[4][n][3] (may be NULL).
  */
 /* indicator: 0 = CSP^list with the list csp; 1 = the learned indicator with parameters mlp_P
- * (MLP_NP doubles) on features inside mlp_rc (csp unused). */
-int ora_eval_ind(int n, const double *pos_in, const double *L, const double *eam_p, int n_max, int l_max,
-                 double ace_rc, int n_funcs, const int *func, const double *c, const double *b_dens, double emb_A,
-                 double E0, const double *sw_p, int n_csp, const int *csp, int lam_mode, int skip, int no_gradlam,
-                 double *E_tot, double *E_atom, double *F, double *virial, double *aux, double *Ffam, int indicator,
-                 const double *mlp_P, double mlp_rc) {
+ * (MLP_NP doubles) on features inside mlp_rc (csp unused).
+ * lam_fix: NULL, or per atom -1 (lambda from Eq. (2)) or 0 / 1: a constant switching parameter with
+ *          dlambda/dd = 0 (App. B, the paragraph after (B4)); used only when lambda is computed.
+ * force_mix: 1 replaces the conservative force by force mixing, Eq. (3):
+ *          F_i = lambda_i F^f_i + (1 - lambda_i) F^p_i with the complete EAM and ACE forces
+ *          F^f_i = -grad_i sum_k E^f_k and F^p_i = -grad_i sum_k E^p_k; E_atom stays Eq. (4), there
+ *          are no grad-lambda terms, and the virial is not defined (returned as zeros). With skip = 1
+ *          ACE runs on the atoms with lambda < 1 and every atom within the ACE cutoff of one. */
+int ora_eval_full(int n, const double *pos_in, const double *L, const double *eam_p, int n_max, int l_max,
+                  double ace_rc, int n_funcs, const int *func, const double *c, const double *b_dens, double emb_A,
+                  double E0, const double *sw_p, int n_csp, const int *csp, int lam_mode, int skip, int no_gradlam,
+                  double *E_tot, double *E_atom, double *F, double *virial, double *aux, double *Ffam, int indicator,
+                  const double *mlp_P, double mlp_rc, int force_mix, const int *lam_fix) {
     if (n <= 0 || !pos_in || !L || !eam_p || !sw_p || !E_tot || !E_atom || !F || !virial) return ORA_E_ARG;
+    if (lam_fix)
+        for (int i = 0; i < n; i++)
+            if (lam_fix[i] < -1 || lam_fix[i] > 1) return ORA_E_ARG;
+    if (force_mix) no_gradlam = 1;
     if (n_max > 32 || l_max > 12) return ORA_E_ARG;
     if (indicator != 0 && (indicator != 1 || !mlp_P || !(mlp_rc > 0.0))) return ORA_E_ARG;
     double rc_eam = eam_p[5] > eam_p[6] ? eam_p[5] : eam_p[6];
@@ -962,21 +1016,16 @@ int ora_eval_ind(int n, const double *pos_in, const double *L, const double *eam
     if (need_sw) {
 #pragma omp parallel for schedule(static)
         for (int i = 0; i < n; i++) {
-            double wsum = 1.0, gsum = AX(i, AX_G); /* self term, w(0) = 1 */
-            for (int q = nb.start[i]; q < nb.start[i + 1]; q++) {
-                int k = nb.idx[q];
-                double u[3];
-                mic(pos, L, i, k, u);
-                double r = sqrt(sq3(u));
-                if (r >= r_w) continue;
-                double w = ora_ftrans(r, r_w - 1.0, r_w);
-                wsum += w;
-                gsum += AX(k, AX_G) * w;
+            descriptor_site(pos, L, &nb, i, ax + AX_G, AUX_W, r_w, d0, &AX(i, AX_WBAR), &AX(i, AX_D));
+            if (lam_fix && lam_fix[i] >= 0) {
+                /* an atom with a constant switching parameter (App. B, after (B4)): lambda is 0 or 1
+                 * for the whole run and not a function of d_i, so dlambda/dd = 0 */
+                AX(i, AX_LAM) = (double)lam_fix[i];
+                AX(i, AX_DLAM) = 0.0;
+            } else {
+                AX(i, AX_LAM) = ora_ftrans(AX(i, AX_D), d_lo, d_hi);
+                AX(i, AX_DLAM) = ora_ftrans_d(AX(i, AX_D), d_lo, d_hi);
             }
-            AX(i, AX_WBAR) = wsum;
-            AX(i, AX_D) = gsum / wsum - d0;
-            AX(i, AX_LAM) = ora_ftrans(AX(i, AX_D), d_lo, d_hi);
-            AX(i, AX_DLAM) = ora_ftrans_d(AX(i, AX_D), d_lo, d_hi);
         }
     } else {
         for (int i = 0; i < n; i++) {
@@ -1014,6 +1063,18 @@ int ora_eval_ind(int n, const double *pos_in, const double *L, const double *eam
     double *face = (double *)calloc((size_t)total_slots * 3 + 3, sizeof(double));
     char *do_ace = (char *)calloc((size_t)n, 1);
     for (int i = 0; i < n; i++) do_ace[i] = skip == 2 ? 0 : (skip ? (AX(i, AX_LAM) < 1.0) : 1);
+    if (force_mix && skip == 1) {
+        /* Eq. (3) takes the complete F^p_i of each atom with lambda_i < 1, which needs E^p_k of every
+         * atom k within the ACE cutoff of i as well */
+        for (int i = 0; i < n; i++) {
+            if (!(AX(i, AX_LAM) < 1.0)) continue;
+            for (int q = nb.start[i]; q < nb.start[i + 1]; q++) {
+                double u[3];
+                mic(pos, L, i, nb.idx[q], u);
+                if (sqrt(sq3(u)) < ace_rc) do_ace[nb.idx[q]] = 1;
+            }
+        }
+    }
     for (int i = 0; i < n; i++)
         if (nb.start[i + 1] - nb.start[i] > 4096) rc = ORA_E_NBR;
 #pragma omp parallel if (!rc)
@@ -1058,7 +1119,44 @@ int ora_eval_ind(int n, const double *pos_in, const double *L, const double *eam
 
     /* 5. forces, family by family, in scatter form over ordered pairs (i, k) */
     double *fE = fam, *fA = fam + 3 * (size_t)n, *fW = fam + 6 * (size_t)n, *fC = fam + 9 * (size_t)n;
-    for (int i = 0; i < n; i++) {
+    if (force_mix) {
+        /* Eq. (3): the complete force of each model, F^f_i = sum_k (f^EAM_ki - f^EAM_ik) and
+         * F^p_i = sum_k (f^ACE_ki - f^ACE_ik), then weighted by lambda_i and 1 - lambda_i per atom */
+        double *Ff = (double *)calloc((size_t)3 * n, sizeof(double));
+        double *Fp = (double *)calloc((size_t)3 * n, sizeof(double));
+        for (int i = 0; i < n; i++) {
+            for (int q = nb.start[i]; q < nb.start[i + 1]; q++) {
+                int k = nb.idx[q];
+                double u[3];
+                mic(pos, L, i, k, u);
+                double r = sqrt(sq3(u));
+                if (r < rc_eam) {
+                    double zz, dz, ph, dph;
+                    eam_pair(eam_p, r, &zz, &dz, &ph, &dph);
+                    double s = AX(i, AX_XIP) * dz + 0.5 * dph;
+                    for (int a = 0; a < 3; a++) {
+                        Ff[3 * i + a] += s * u[a] / r;
+                        Ff[3 * k + a] -= s * u[a] / r;
+                    }
+                }
+                if (do_ace[i] && r < ace_rc) {
+                    const double *f = face + 3 * (size_t)q;
+                    for (int a = 0; a < 3; a++) {
+                        Fp[3 * i + a] += f[a];
+                        Fp[3 * k + a] -= f[a];
+                    }
+                }
+            }
+        }
+        for (int i = 0; i < n; i++)
+            for (int a = 0; a < 3; a++) {
+                fE[3 * i + a] = AX(i, AX_LAM) * Ff[3 * i + a];
+                fA[3 * i + a] = (1.0 - AX(i, AX_LAM)) * Fp[3 * i + a];
+            }
+        free(Ff);
+        free(Fp);
+    }
+    for (int i = 0; i < n && !force_mix; i++) {
         double lam_i = AX(i, AX_LAM);
         for (int q = nb.start[i]; q < nb.start[i + 1]; q++) {
             int k = nb.idx[q];
@@ -1176,6 +1274,16 @@ int ora_eval_ind(int n, const double *pos_in, const double *L, const double *eam
     return rc;
 }
 
+int ora_eval_ind(int n, const double *pos_in, const double *L, const double *eam_p, int n_max, int l_max,
+                 double ace_rc, int n_funcs, const int *func, const double *c, const double *b_dens, double emb_A,
+                 double E0, const double *sw_p, int n_csp, const int *csp, int lam_mode, int skip, int no_gradlam,
+                 double *E_tot, double *E_atom, double *F, double *virial, double *aux, double *Ffam, int indicator,
+                 const double *mlp_P, double mlp_rc) {
+    return ora_eval_full(n, pos_in, L, eam_p, n_max, l_max, ace_rc, n_funcs, func, c, b_dens, emb_A, E0, sw_p, n_csp,
+                         csp, lam_mode, skip, no_gradlam, E_tot, E_atom, F, virial, aux, Ffam, indicator, mlp_P,
+                         mlp_rc, 0, NULL);
+}
+
 int ora_eval(int n, const double *pos_in, const double *L, const double *eam_p, int n_max, int l_max, double ace_rc,
              int n_funcs, const int *func, const double *c, const double *b_dens, double emb_A, double E0,
              const double *sw_p, int n_csp, const int *csp, int lam_mode, int skip, int no_gradlam, double *E_tot,
@@ -1241,10 +1349,11 @@ int ora_ace_coeff_grad(int n, const double *pos_in, const double *L, int n_max, 
 /* Velocity Verlet, NVE, in FP64 (metal units; F/m converted with 9648.533212):
  *   v += dt/2 F/m;  x += dt v;  wrap;  F = F(x);  v += dt/2 F/m.
  * thermo[s] = {E_pot, E_kin, E_tot, P_x, P_y, P_z} after step s. F must hold F(x) on entry. */
-int ora_vv(int n, double *pos, double *vel, double *F, double mass, double dt, int n_steps, const double *L,
-           const double *eam_p, int n_max, int l_max, double ace_rc, int n_funcs, const int *func, const double *c,
-           const double *b_dens, double emb_A, double E0, const double *sw_p, int n_csp, const int *csp,
-           int lam_mode, double *thermo) {
+/* force_mix and lam_fix as in ora_eval_full. */
+int ora_vv_full(int n, double *pos, double *vel, double *F, double mass, double dt, int n_steps, const double *L,
+                const double *eam_p, int n_max, int l_max, double ace_rc, int n_funcs, const int *func, const double *c,
+                const double *b_dens, double emb_A, double E0, const double *sw_p, int n_csp, const int *csp,
+                int lam_mode, double *thermo, int force_mix, const int *lam_fix) {
     double *Ea = (double *)malloc(sizeof(double) * (size_t)n);
     double vir[9], etot = 0.0;
     int rc = ORA_OK;
@@ -1252,8 +1361,8 @@ int ora_vv(int n, double *pos, double *vel, double *F, double mass, double dt, i
         for (int i = 0; i < 3 * n; i++) vel[i] += 0.5 * dt * F[i] / mass * CONV;
         for (int i = 0; i < 3 * n; i++) pos[i] += dt * vel[i];
         ora_wrap(n, pos, L);
-        rc = ora_eval(n, pos, L, eam_p, n_max, l_max, ace_rc, n_funcs, func, c, b_dens, emb_A, E0, sw_p, n_csp, csp,
-                      lam_mode, 1, 0, &etot, Ea, F, vir, NULL, NULL);
+        rc = ora_eval_full(n, pos, L, eam_p, n_max, l_max, ace_rc, n_funcs, func, c, b_dens, emb_A, E0, sw_p, n_csp,
+                           csp, lam_mode, 1, 0, &etot, Ea, F, vir, NULL, NULL, 0, NULL, 0.0, force_mix, lam_fix);
         for (int i = 0; i < 3 * n; i++) vel[i] += 0.5 * dt * F[i] / mass * CONV;
         double ek = 0.0, P[3] = {0, 0, 0};
         for (int i = 0; i < n; i++)
@@ -1271,4 +1380,12 @@ int ora_vv(int n, double *pos, double *vel, double *F, double mass, double dt, i
     }
     free(Ea);
     return rc;
+}
+
+int ora_vv(int n, double *pos, double *vel, double *F, double mass, double dt, int n_steps, const double *L,
+           const double *eam_p, int n_max, int l_max, double ace_rc, int n_funcs, const int *func, const double *c,
+           const double *b_dens, double emb_A, double E0, const double *sw_p, int n_csp, const int *csp,
+           int lam_mode, double *thermo) {
+    return ora_vv_full(n, pos, vel, F, mass, dt, n_steps, L, eam_p, n_max, l_max, ace_rc, n_funcs, func, c, b_dens,
+                       emb_A, E0, sw_p, n_csp, csp, lam_mode, thermo, 0, NULL);
 }

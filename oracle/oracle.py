@@ -35,45 +35,57 @@ def lib():
     global _lib
     if _lib is None:
         build()
-        L = C.CDLL(_LIB)
-        d, i = C.c_double, C.c_int
-        L.ora_set_threads.argtypes = [i]
-        L.ora_set_threads.restype = i
-        L.ora_ftrans.argtypes = [d, d, d]
-        L.ora_ftrans.restype = d
-        L.ora_ftrans_d.argtypes = [d, d, d]
-        L.ora_ftrans_d.restype = d
-        L.ora_wigner3j.argtypes = [i] * 6
-        L.ora_wigner3j.restype = d
-        L.ora_radial.argtypes = [i, d, d, _dp, _dp]
-        L.ora_radial.restype = None
-        L.ora_ylm.argtypes = [i, _dp, _dp, _dp, _dp, _dp]
-        L.ora_ylm.restype = None
-        L.ora_nblist.argtypes = [i, _dp, _dp, d, i, _ip, _ip]
-        L.ora_nblist.restype = i
-        L.ora_csp_pairs.argtypes = [i, _dp, _dp, d, i, _ip]
-        L.ora_csp_pairs.restype = i
-        L.ora_ace_env.argtypes = [i, _dp, i, i, d, i, _ip, _dp, _dp, d, d, _dp, _dp, _dp, _dp, _dp, _dp]
-        L.ora_ace_env.restype = i
-        L.ora_eval.argtypes = [i, _dp, _dp, _dp, i, i, d, i, _ip, _dp, _dp, d, d, _dp, i, _ip, i, i, i,
-                               _dp, _dp, _dp, _dp, _dp, _dp]
-        L.ora_eval.restype = i
-        L.ora_eval_ind.argtypes = L.ora_eval.argtypes + [i, C.c_void_p, d]
-        L.ora_eval_ind.restype = i
-        L.ora_mlp_nparams.restype = i
-        L.ora_mlp_features.argtypes = [i, _dp, _dp, d, _dp]
-        L.ora_mlp_features.restype = i
-        L.ora_mlp_forward.argtypes = [i, _dp, _dp, _dp, _dp, C.c_void_p]
-        L.ora_mlp_forward.restype = None
-        L.ora_mlp_loss_grad.argtypes = [i, _dp, _dp, _dp, _dp]
-        L.ora_mlp_loss_grad.restype = d
-        L.ora_ace_coeff_grad.argtypes = [i, _dp, _dp, i, i, d, i, _ip, _dp, _dp, d, C.c_void_p, _dp, _dp, _dp]
-        L.ora_ace_coeff_grad.restype = i
-        L.ora_vv.argtypes = [i, _dp, _dp, _dp, d, d, i, _dp, _dp, i, i, d, i, _ip, _dp, _dp, d, d, _dp, i, _ip,
-                             i, _dp]
-        L.ora_vv.restype = i
-        _lib = L
+        _lib = bind(_LIB)
     return _lib
+
+
+def bind(path):
+    """Load an oracle shared library and declare its entry points (the tests also bind copies of the
+    oracle built with a deliberate mistake, to show that the pins catch it)."""
+    L = C.CDLL(path)
+    d, i = C.c_double, C.c_int
+    L.ora_set_threads.argtypes = [i]
+    L.ora_set_threads.restype = i
+    L.ora_ftrans.argtypes = [d, d, d]
+    L.ora_ftrans.restype = d
+    L.ora_ftrans_d.argtypes = [d, d, d]
+    L.ora_ftrans_d.restype = d
+    L.ora_wigner3j.argtypes = [i] * 6
+    L.ora_wigner3j.restype = d
+    L.ora_radial.argtypes = [i, d, d, _dp, _dp]
+    L.ora_radial.restype = None
+    L.ora_ylm.argtypes = [i, _dp, _dp, _dp, _dp, _dp]
+    L.ora_ylm.restype = None
+    L.ora_nblist.argtypes = [i, _dp, _dp, d, i, _ip, _ip]
+    L.ora_nblist.restype = i
+    L.ora_csp_pairs.argtypes = [i, _dp, _dp, d, i, _ip]
+    L.ora_csp_pairs.restype = i
+    L.ora_ace_env.argtypes = [i, _dp, i, i, d, i, _ip, _dp, _dp, d, d, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.ora_ace_env.restype = i
+    L.ora_eval.argtypes = [i, _dp, _dp, _dp, i, i, d, i, _ip, _dp, _dp, d, d, _dp, i, _ip, i, i, i,
+                           _dp, _dp, _dp, _dp, _dp, _dp]
+    L.ora_eval.restype = i
+    L.ora_eval_ind.argtypes = L.ora_eval.argtypes + [i, C.c_void_p, d]
+    L.ora_eval_ind.restype = i
+    L.ora_eval_full.argtypes = L.ora_eval_ind.argtypes + [i, C.c_void_p]
+    L.ora_eval_full.restype = i
+    L.ora_descriptor.argtypes = [i, _dp, _dp, _dp, d, d, _dp, _dp]
+    L.ora_descriptor.restype = i
+    L.ora_mlp_nparams.restype = i
+    L.ora_mlp_features.argtypes = [i, _dp, _dp, d, _dp]
+    L.ora_mlp_features.restype = i
+    L.ora_mlp_forward.argtypes = [i, _dp, _dp, _dp, _dp, C.c_void_p]
+    L.ora_mlp_forward.restype = None
+    L.ora_mlp_loss_grad.argtypes = [i, _dp, _dp, _dp, _dp]
+    L.ora_mlp_loss_grad.restype = d
+    L.ora_ace_coeff_grad.argtypes = [i, _dp, _dp, i, i, d, i, _ip, _dp, _dp, d, C.c_void_p, _dp, _dp, _dp]
+    L.ora_ace_coeff_grad.restype = i
+    L.ora_vv.argtypes = [i, _dp, _dp, _dp, d, d, i, _dp, _dp, i, i, d, i, _ip, _dp, _dp, d, d, _dp, i, _ip,
+                         i, _dp]
+    L.ora_vv.restype = i
+    L.ora_vv_full.argtypes = L.ora_vv.argtypes + [i, C.c_void_p]
+    L.ora_vv_full.restype = i
+    return L
 
 
 def set_threads(t=0):
@@ -171,11 +183,30 @@ def _sw_vec(sw):
     return _f64([sw["d_lo"], sw["d_hi"], sw["r_w"], sw.get("d0", 0.0)])
 
 
-def evaluate(sys, pos=None, csp=None, lam_mode=-1, skip=1, no_gradlam=0, mlp=None):
+def descriptor(pos, box, g, r_w, d0=0.0, _lib=None):
+    """Eq. (6) for a given per-atom g: returns (wbar, d)."""
+    pos = _f64(pos)
+    n = len(pos)
+    wbar, d = np.zeros(n), np.zeros(n)
+    _chk((_lib or lib()).ora_descriptor(n, pos, _f64(box), _f64(g), float(r_w), float(d0), wbar, d),
+         "ora_descriptor")
+    return wbar, d
+
+
+def _fix_ptr(lam_fix, n):
+    if lam_fix is None:
+        return None, None
+    a = _i32(lam_fix)
+    assert a.shape == (n,)
+    return a, a.ctypes.data
+
+
+def evaluate(sys, pos=None, csp=None, lam_mode=-1, skip=1, no_gradlam=0, mlp=None, force_mix=0, lam_fix=None):
     """Full AP evaluation of a system dict (synth.build_system). Returns a dict with E, E_atom,
     F (n,3), virial (3,3), aux (dict of per-atom arrays) and fam (4, n, 3): EAM-weighted,
     ACE-weighted, grad-w and grad-indicator force families. mlp = (params, rc) selects the
-    learned indicator instead of CSP."""
+    learned indicator instead of CSP. force_mix = 1: the force of Eq. (3) instead of Eq. (5).
+    lam_fix: per-atom -1 (lambda from Eq. (2)) or a constant 0 / 1 (App. B)."""
     pos = _f64(sys["pos"] if pos is None else pos)
     n = len(pos)
     box = _f64(sys["box"])
@@ -193,10 +224,11 @@ def evaluate(sys, pos=None, csp=None, lam_mode=-1, skip=1, no_gradlam=0, mlp=Non
     aux = np.zeros(n * len(AUX_COLS))
     fam = np.zeros(12 * n)
     P = None if mlp is None else _f64(mlp[0])
-    rc = lib().ora_eval_ind(n, pos, box, _eam_vec(sys["eam"]), *_ace_args(sys["ace"]), _sw_vec(sw),
-                            int(sw["n_csp"]), _i32(csp), int(lam_mode), int(skip), int(no_gradlam), E, Ea, F, vir,
-                            aux, fam, 0 if mlp is None else 1, None if P is None else P.ctypes.data,
-                            0.0 if mlp is None else float(mlp[1]))
+    fix, fix_p = _fix_ptr(lam_fix, n)
+    rc = lib().ora_eval_full(n, pos, box, _eam_vec(sys["eam"]), *_ace_args(sys["ace"]), _sw_vec(sw),
+                             int(sw["n_csp"]), _i32(csp), int(lam_mode), int(skip), int(no_gradlam), E, Ea, F, vir,
+                             aux, fam, 0 if mlp is None else 1, None if P is None else P.ctypes.data,
+                             0.0 if mlp is None else float(mlp[1]), int(force_mix), fix_p)
     _chk(rc, "ora_eval")
     aux = aux.reshape(n, len(AUX_COLS))
     return dict(E=E[0], E_atom=Ea, F=F.reshape(n, 3), virial=vir.reshape(3, 3),
@@ -216,7 +248,7 @@ def ace_coeff_grad(pos, box, ace, weight=None):
     return dEdc, dEdb, Ea
 
 
-def velocity_verlet(sys, n_steps, pos=None, vel=None, csp=None, lam_mode=-1, dt=None):
+def velocity_verlet(sys, n_steps, pos=None, vel=None, csp=None, lam_mode=-1, dt=None, force_mix=0, lam_fix=None):
     """n_steps of FP64 velocity Verlet; returns (pos, vel, F, thermo[n_steps][6])."""
     pos = _f64(sys["pos"] if pos is None else pos).copy()
     vel = _f64(sys["vel"] if vel is None else vel).copy()
@@ -226,15 +258,16 @@ def velocity_verlet(sys, n_steps, pos=None, vel=None, csp=None, lam_mode=-1, dt=
         csp = sys.get("csp")
     if csp is None:
         csp = csp_pairs(_f64(sys.get("pos_ref", pos)), box, sw["n_csp"])
-    r0 = evaluate(sys, pos=pos, csp=csp, lam_mode=lam_mode)
+    r0 = evaluate(sys, pos=pos, csp=csp, lam_mode=lam_mode, force_mix=force_mix, lam_fix=lam_fix)
     F = _f64(r0["F"]).reshape(-1).copy()
     th = np.zeros(6 * n_steps)
     dt = float(sys["run"]["dt"] if dt is None else dt)
     flat_pos = pos.reshape(-1).copy()
     flat_vel = vel.reshape(-1).copy()
-    rc = lib().ora_vv(len(pos), flat_pos, flat_vel, F, float(sys["mass"]), dt, int(n_steps), box,
-                      _eam_vec(sys["eam"]), *_ace_args(sys["ace"]), _sw_vec(sw), int(sw["n_csp"]), _i32(csp),
-                      int(lam_mode), th)
+    fix, fix_p = _fix_ptr(lam_fix, len(pos))
+    rc = lib().ora_vv_full(len(pos), flat_pos, flat_vel, F, float(sys["mass"]), dt, int(n_steps), box,
+                           _eam_vec(sys["eam"]), *_ace_args(sys["ace"]), _sw_vec(sw), int(sw["n_csp"]), _i32(csp),
+                           int(lam_mode), th, int(force_mix), fix_p)
     _chk(rc, "ora_vv")
     n = len(pos)
     return flat_pos.reshape(n, 3), flat_vel.reshape(n, 3), F.reshape(n, 3), th.reshape(n_steps, 6)
@@ -255,13 +288,13 @@ def mlp_features(pos, box, rc=5.5):
     return q.reshape(-1, MLP_NQ)
 
 
-def mlp_forward(q, params, grad=True):
+def mlp_forward(q, params, grad=True, _lib=None):
     """Network output o, indicator g = softplus(o) and dg/dq (m, 16) for features q (m, 16)."""
     q = _f64(np.asarray(q).reshape(-1, MLP_NQ))
     m = len(q)
     o, g = np.zeros(m), np.zeros(m)
     dg = np.zeros(m * MLP_NQ) if grad else None
-    lib().ora_mlp_forward(m, q, _f64(params), o, g, dg.ctypes.data if grad else None)
+    (_lib or lib()).ora_mlp_forward(m, q, _f64(params), o, g, dg.ctypes.data if grad else None)
     return o, g, (dg.reshape(m, MLP_NQ) if grad else None)
 
 

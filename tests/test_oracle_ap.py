@@ -128,3 +128,111 @@ def test_coefficient_gradient_closed_form_and_fd(oracle, sysd):
     e1 = oracle.evaluate(dict(sysd, ace=dict(sysd["ace"], b_dens=b1)))["E"]
     e2 = oracle.evaluate(dict(sysd, ace=dict(sysd["ace"], b_dens=b2)))["E"]
     assert dEdb[n] == pytest.approx((e1 - e2) / (2 * h), rel=1e-6)
+
+
+# ---------------------------------------------------------------------------------------------------
+# Force mixing, Eq. (3): the non-conservative comparison force
+# ---------------------------------------------------------------------------------------------------
+def test_force_mixing_is_lambda_weighted_pure_forces(oracle, sysd):
+    """F_i = lambda_i F^f_i + (1 - lambda_i) F^p_i with the complete EAM and ACE forces, each pinned on its
+    own by finite differences (the lambda == 1 / 0 limits of the AP evaluation)."""
+    mix = oracle.evaluate(sysd, force_mix=1)
+    lam = mix["aux"]["lam"][:, None]
+    want = lam * oracle.evaluate(sysd, lam_mode=1)["F"] + (1 - lam) * oracle.evaluate(sysd, lam_mode=0)["F"]
+    assert np.abs(mix["F"] - want).max() < 1e-12 * np.abs(want).max()
+    ap = oracle.evaluate(sysd)
+    assert mix["E"] == ap["E"] and np.array_equal(mix["E_atom"], ap["E_atom"])  # Eq. (4) energies
+
+
+def test_force_mixing_breaks_newtons_third_law(oracle, sysd):
+    """With lambda varying between atoms the mixed forces do not sum to zero (the paper's momentum
+    violation); the conservative AP forces do."""
+    mix = oracle.evaluate(sysd, force_mix=1)
+    ap = oracle.evaluate(sysd)
+    scale = np.abs(ap["F"]).max()
+    assert np.abs(mix["F"].sum(0)).max() > 1e-3 * scale
+    assert np.abs(ap["F"].sum(0)).max() < 1e-12 * scale * len(ap["F"])
+
+
+def test_force_mixing_skip_mode_is_bit_identical(oracle, sysd):
+    """ACE only on the atoms with lambda < 1 and the atoms within the ACE cutoff of one gives the same bits
+    as ACE on every atom."""
+    s = dict(sysd, sw=dict(sysd["sw"], d_lo=1.0, d_hi=1.4))
+    a, b = oracle.evaluate(s, skip=0, force_mix=1), oracle.evaluate(s, skip=1, force_mix=1)
+    assert (a["aux"]["lam"] == 1.0).sum() > 5
+    assert np.array_equal(a["F"], b["F"]) and a["E"] == b["E"]
+
+
+def test_force_mixing_momentum_drifts_in_nve(oracle):
+    """Velocity Verlet with force mixing changes the total momentum; with the AP force it stays."""
+    import synth
+    s = synth.build_system(1)
+    P0 = (s["mass"] * s["vel"]).sum(0)
+    _, _, _, th_mix = oracle.velocity_verlet(s, 10, force_mix=1)
+    _, _, _, th_ap = oracle.velocity_verlet(s, 10)
+    assert np.abs(th_mix[-1, 3:6] - P0).max() > 1e-4
+    assert np.abs(th_ap[:, 3:6] - P0).max() < 1e-9
+
+
+# ---------------------------------------------------------------------------------------------------
+# Constant switching parameters on chosen atoms (App. B, after (B4))
+# ---------------------------------------------------------------------------------------------------
+def _mask(lam, seed=3):
+    """Some atoms of the transition region fixed to 0, some to 1, the rest computed."""
+    rng = np.random.default_rng(seed)
+    fix = np.full(len(lam), -1, np.int32)
+    mid = np.nonzero((lam > 0) & (lam < 1))[0]
+    pick = rng.choice(mid, 12, replace=False)
+    fix[pick[:6]] = 0
+    fix[pick[6:]] = 1
+    return fix
+
+
+def test_constant_lambda_forces_are_minus_energy_gradient(oracle, sysd):
+    """With lambda fixed on a subset (dlambda/dd = 0 there) the energy stays conservative: (B4) with the
+    fixed atoms' terms removed is still -grad E (central differences)."""
+    fix = _mask(oracle.evaluate(sysd)["aux"]["lam"])
+    r = oracle.evaluate(sysd, skip=0, lam_fix=fix)
+    assert np.array_equal(r["aux"]["lam"][fix >= 0], fix[fix >= 0].astype(float))
+    assert np.all(r["aux"]["dlam"][fix >= 0] == 0.0)
+    h = 1e-5
+    near = np.nonzero(fix >= 0)[0][:2].tolist() + [9]
+    for i in near:
+        for a in range(3):
+            p1, p2 = sysd["pos"].copy(), sysd["pos"].copy()
+            p1[i, a] += h
+            p2[i, a] -= h
+            fd = -(oracle.evaluate(sysd, pos=p1, lam_fix=fix)["E"] -
+                   oracle.evaluate(sysd, pos=p2, lam_fix=fix)["E"]) / (2 * h)
+            assert r["F"][i, a] == pytest.approx(fd, abs=3e-7 * max(1.0, abs(fd)))
+
+
+def test_constant_lambda_conserves_momentum_per_family(oracle, sysd):
+    fix = _mask(oracle.evaluate(sysd)["aux"]["lam"])
+    fam = oracle.evaluate(sysd, lam_fix=fix)["fam"]
+    scale = np.abs(fam).max()
+    for f in fam:
+        assert np.abs(f.sum(0)).max() < 1e-12 * scale * len(f)
+
+
+def test_constant_lambda_on_saturated_atoms_changes_nothing(oracle, sysd):
+    """Fixing lambda on atoms whose computed lambda is already 0 or 1 (with dlambda/dd = 0) gives the same
+    bits as no mask."""
+    s = dict(sysd, sw=dict(sysd["sw"], d_lo=1.0, d_hi=1.15))
+    r = oracle.evaluate(s)
+    lam, dlam = r["aux"]["lam"], r["aux"]["dlam"]
+    fix = np.full(len(lam), -1, np.int32)
+    fix[(lam == 1.0) & (dlam == 0.0)] = 1
+    fix[(lam == 0.0) & (dlam == 0.0)] = 0
+    assert (fix == 1).sum() > 5 and (fix == 0).sum() > 5
+    q = oracle.evaluate(s, lam_fix=fix)
+    assert np.array_equal(q["F"], r["F"]) and q["E"] == r["E"] and np.array_equal(q["virial"], r["virial"])
+
+
+def test_constant_lambda_everywhere_is_a_pure_model(oracle, sysd):
+    n = len(sysd["pos"])
+    eam = oracle.evaluate(sysd, lam_fix=np.ones(n, np.int32))
+    ace = oracle.evaluate(sysd, lam_fix=np.zeros(n, np.int32))
+    assert np.array_equal(eam["F"], oracle.evaluate(sysd, lam_mode=1)["F"])
+    assert np.array_equal(ace["F"], oracle.evaluate(sysd, lam_mode=0)["F"])
+    assert np.abs(eam["fam"][2:]).max() == 0 and np.abs(ace["fam"][2:]).max() == 0
