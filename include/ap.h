@@ -135,6 +135,20 @@ int ap_set_csp_list(ap_ctx *ctx, int n, int n_csp, const int32_t *csp_list);
 int ap_nblist_build(ap_ctx *ctx, int n, const double *pos, const ap_box *box, double r_list, int max_nbr,
                     int32_t *nbr_count, int32_t *nbr_idx);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the neighbour sets of ap_nblist_build without a context. The
+ * library's scratch for it (wrapped positions, cell arrays and records, flags; 13.5 MiB) is one static
+ * device array per GPU, held until the process ends; the call allocates nothing. Limits: n <= 131072
+ * atoms and at most 131072 cells (cells of edge >= r_list, floor(L / r_list) per axis); larger inputs
+ * return AP_E_ARG before anything is launched. Same arguments and output layout as ap_nblist_build
+ * (pos, nbr_count, nbr_idx device; box host; strict |u|^2 < r_list^2 after wrapping); the slots of an
+ * atom hold its neighbours in the order of a scan of the 27 cells. hip_stream: a hipStream_t (NULL =
+ * default stream); the call synchronises it to report overflow (AP_E_NBR_OVERFLOW). Calls that overlap
+ * on one GPU (other threads or streams) share the scratch and race: serialise them. Errors are read
+ * with ap_last_error(NULL). */
+int ap_nblist_build_noalloc(int n, const double *pos, const ap_box *box, double r_list, int max_nbr,
+                            int32_t *nbr_count, int32_t *nbr_idx, void *hip_stream);
+
 /* EAM, (B1) and (S12): E_atom[i] = E^EAM_i, F = sum_k (lambda_i f_ki - lambda_k f_ik) with
  * lambda = the device array lambda [n] (NULL: lambda == 1, i.e. the plain EAM force (S13)).
  * E_tot: device [1]; virial9: device [9] row-major W_ab = -sum_e (dE/du_e)_a (u_e)_b over the

@@ -22,7 +22,7 @@ SYMBOLS = ["ap_ctx_create", "ap_ctx_destroy", "ap_last_error", "ap_set_potential
            "ap_set_csp_list", "ap_nblist_build", "ap_eam_eval", "ap_switch_eval", "ap_ace_eval",
            "ap_mixed_energy_forces", "ap_vv_step", "ap_set_profiling", "ap_get_profile", "ap_ace_cost",
            "ap_ace_batch_eval", "ap_set_mlp", "ap_mlp_features", "ap_mlp_eval", "ap_mlp_loss_grad",
-           "ap_mlp_train"]
+           "ap_mlp_train", "ap_nblist_build_noalloc"]
 MLP_NQ, MLP_NPARAMS = 16, 5345
 
 
@@ -88,6 +88,7 @@ def lib():
         L.ap_mlp_eval.argtypes = [vp, i, vp, vp, vp, vp]
         L.ap_mlp_loss_grad.argtypes = [vp, i, vp, vp, vp, vp, C.POINTER(C.c_double)]
         L.ap_mlp_train.argtypes = [vp, i, vp, vp, i, i, d, i, vp, C.POINTER(C.c_double)]
+        L.ap_nblist_build_noalloc.argtypes = [i, vp, C.POINTER(Box), d, i, vp, vp, vp]
         for s in SYMBOLS:
             if s not in ("ap_ctx_destroy", "ap_last_error"):
                 getattr(L, s).restype = i
@@ -112,6 +113,22 @@ def _dev(t, dtype, shape=None):
     if shape is not None and tuple(t.shape) != tuple(shape):
         raise ValueError("expected shape %s, got %s" % (shape, tuple(t.shape)))
     return t
+
+
+def nblist_build_noalloc(pos, box, r_list, nbr_count, nbr_idx, stream=None):
+    """ap_nblist_build_noalloc: neighbour sets without a context; the outputs nbr_count (int32, (n,)) and
+    nbr_idx (int32, (max_nbr, n)) are the caller's CUDA tensors, written in place."""
+    n = pos.shape[1]
+    _dev(pos, torch.float64, (3, n))
+    _dev(nbr_count, torch.int32, (n,))
+    _dev(nbr_idx, torch.int32)
+    if nbr_idx.dim() != 2 or nbr_idx.shape[1] != n:
+        raise ValueError("nbr_idx must be (max_nbr, n)")
+    s = torch.cuda.current_stream(pos.device) if stream is None else stream
+    rc = lib().ap_nblist_build_noalloc(n, _ptr(pos), C.byref(_box(box)), float(r_list), int(nbr_idx.shape[0]),
+                                       _ptr(nbr_count), _ptr(nbr_idx), C.c_void_p(s.cuda_stream))
+    if rc != 0:
+        raise APError(rc, lib().ap_last_error(None).decode())
 
 
 class Context:

@@ -275,6 +275,8 @@ struct ap_ctx {
 namespace ap {
 
 int set_error(ap_ctx *c, int code, const std::string &msg);
+// the error text of a call without a context (what ap_last_error(NULL) returns); returns code
+int set_error_text(int code, const char *msg);
 int hip_check(ap_ctx *c, hipError_t e, const char *what);
 
 // Records HIP events around the launches made during its lifetime when profiling is on; the
@@ -289,6 +291,22 @@ struct ProfScope {
 void prof_resolve(ap_ctx *c);
 
 // geometry.hip
+// Buffers of one neighbour-list build: wrapped positions in, build-time positions, flags ([0] gates the
+// build, [1] error bits), the cell arrays, and the list out (counts, short counts, slot-major indices).
+struct ListBufs {
+    const double *pos;
+    double *pos_build;
+    int *flags;
+    int *cell_of, *cell_cnt, *cell_start, *cell_fill, *cell_atoms;
+    Rec4 *cell_rec;
+    int32_t *ncount, *nshort, *nidx;
+};
+// cells of edge >= r_list (one cell per axis below three); false when r_list >= half a box length
+bool list_geometry(const double *box, double r_list, Geometry &g);
+void launch_list_kernels(hipStream_t s, int n, const Geometry &g, double r_list, double r_short, int max_nbr,
+                         const ListBufs &b);
+void launch_wrap(hipStream_t s, const double *in, double *out, int n, const double *box);
+void launch_fill_int_on(hipStream_t s, int *p, int v, int count);
 // skin_checked: the caller's kernel already ran the skin check on these positions and cleared the
 // cell counts; commit = false: the caller's next kernel commits the rebuild flag (flags[3] = flags[0],
 // flags[0] = 0) instead of a kernel of its own

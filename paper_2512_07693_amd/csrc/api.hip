@@ -4,15 +4,22 @@
 
 #include "ap_internal.h"
 
-static thread_local std::string g_create_error;
+// text of the last error of a call without a context (a fixed buffer: setting it allocates nothing)
+static thread_local char g_create_error[256];
 
 namespace ap {
+
+int set_error_text(int code, const char *msg) {
+    std::strncpy(g_create_error, msg, sizeof(g_create_error) - 1);
+    g_create_error[sizeof(g_create_error) - 1] = 0;
+    return code;
+}
 
 int set_error(ap_ctx *c, int code, const std::string &msg) {
     if (c)
         c->err = msg;
     else
-        g_create_error = msg;
+        set_error_text(code, msg.c_str());
     return code;
 }
 
@@ -226,7 +233,7 @@ using namespace ap;
 
 extern "C" {
 
-const char *ap_last_error(const ap_ctx *ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
+const char *ap_last_error(const ap_ctx *ctx) { return ctx ? ctx->err.c_str() : g_create_error; }
 
 void ap_ctx_destroy(ap_ctx *c) {
     if (!c) return;
@@ -291,7 +298,7 @@ int ap_ctx_create(ap_ctx **out, int n_max_atoms, int max_nbr, double skin, void 
     alloc(&c->partials, (size_t)c->pstride * 16, 8);
     alloc(&c->scalars, 16, 8);
     if (rc) {
-        g_create_error = c->err;
+        set_error_text(rc, c->err.c_str());
         ap_ctx_destroy(c);
         return rc;
     }
@@ -305,7 +312,7 @@ int ap_ctx_create(ap_ctx **out, int n_max_atoms, int max_nbr, double skin, void 
     launch_fill_double(c, c->d, 0.0, (int)n);
     rc = hip_check(c, hipStreamSynchronize(c->stream), "context init");
     if (rc) {
-        g_create_error = c->err;
+        set_error_text(rc, c->err.c_str());
         ap_ctx_destroy(c);
         return rc;
     }

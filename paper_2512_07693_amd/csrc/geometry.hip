@@ -289,16 +289,52 @@ __global__ void k_skin_check(const double *__restrict__ pos, const double *__res
     if (ux * ux + uy * uy + uz * uz > half_skin2) atomicOr(&flags[0], 1);
 }
 
-static int make_geometry(ap_ctx *c, const double *box, double r_list, Geometry &g) {
+bool list_geometry(const double *box, double r_list, Geometry &g) {
     for (int a = 0; a < 3; a++) {
         g.L[a] = box[a];
-        if (!(r_list < 0.5 * box[a]))
-            return set_error(c, AP_E_BOX, "list radius (cutoff + skin) must be below half the box");
+        if (!(r_list < 0.5 * box[a])) return false;
         g.nc[a] = (int)floor(box[a] / r_list);
         if (g.nc[a] < 3) g.nc[a] = 1;  // one cell spans the box: every atom is a candidate
     }
     g.ncell = g.nc[0] * g.nc[1] * g.nc[2];
+    return true;
+}
+
+static int make_geometry(ap_ctx *c, const double *box, double r_list, Geometry &g) {
+    if (!list_geometry(box, r_list, g))
+        return set_error(c, AP_E_BOX, "list radius (cutoff + skin) must be below half the box");
     return AP_OK;
+}
+
+// The cell binning and list kernels of one build of the wrapped positions b.pos, gated by b.flags[0]
+// (nothing happens unless it is set; the caller has cleared the cell counts and fills): cell ids and
+// counts, their exclusive scan, the cells' atoms sorted by index with their records, then the lists.
+void launch_list_kernels(hipStream_t s, int n, const Geometry &g, double r_list, double r_short, int max_nbr,
+                         const ListBufs &b) {
+    const int nb = (n + kBlock - 1) / kBlock;
+    k_cell_assign<<<nb, kBlock, 0, s>>>(b.pos, n, g, b.cell_of, b.cell_cnt, b.flags);
+    k_scan_excl<<<1, 1024, 0, s>>>(b.cell_cnt, b.cell_start, g.ncell, nullptr, b.flags);
+    k_cell_fill<<<nb, kBlock, 0, s>>>(n, b.cell_of, b.cell_start, b.cell_fill, b.cell_atoms, b.flags);
+    k_cell_sort<<<(int)(((size_t)g.ncell * 64 + kBlock - 1) / kBlock), kBlock, 0, s>>>(
+        g.ncell, b.cell_start, b.cell_cnt, b.cell_atoms, b.pos, n, b.cell_rec, b.flags);
+    constexpr int SUB = 8;  // lanes per atom in the list build
+    const int lgrid = (int)(((size_t)n * SUB + kBlock - 1) / kBlock);
+    if (max_nbr <= 256)  // (at most 32 KB of staged lists per workgroup)
+        k_nbr_build<SUB, true><<<lgrid, kBlock, (size_t)max_nbr * (kBlock / SUB) * sizeof(int), s>>>(
+            b.pos, n, g, r_list * r_list, r_short * r_short, b.cell_start, b.cell_cnt, b.cell_rec, b.cell_of, max_nbr,
+            b.ncount, b.nshort, b.nidx, b.pos_build, b.flags);
+    else
+        k_nbr_build<SUB, false><<<lgrid, kBlock, 0, s>>>(b.pos, n, g, r_list * r_list, r_short * r_short,
+                                                        b.cell_start, b.cell_cnt, b.cell_rec, b.cell_of, max_nbr,
+                                                        b.ncount, b.nshort, b.nidx, b.pos_build, b.flags);
+}
+
+// The stream-ordered pieces of a context-free list build: wrapped positions and fills.
+void launch_wrap(hipStream_t s, const double *in, double *out, int n, const double *box) {
+    k_wrap_copy<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(in, out, n, box[0], box[1], box[2]);
+}
+void launch_fill_int_on(hipStream_t s, int *p, int v, int count) {
+    if (count > 0) k_fill_int<<<(count + kBlock - 1) / kBlock, kBlock, 0, s>>>(p, v, count);
 }
 
 static int grow_cells(ap_ctx *c, int ncell) {
@@ -334,22 +370,10 @@ int ensure_list(ap_ctx *c, int n, const double *box, double r_list, bool force, 
         k_cell_clear<<<cb, kBlock, 0, c->stream>>>(c->cell_cnt, c->cell_fill, g.ncell, c->d_flags);
     }
     c->ncell_cur = g.ncell;
-    k_cell_assign<<<nb, kBlock, 0, c->stream>>>(c->pos, n, g, c->cell_of, c->cell_cnt, c->d_flags);
-    k_scan_excl<<<1, 1024, 0, c->stream>>>(c->cell_cnt, c->cell_start, g.ncell, nullptr, c->d_flags);
-    k_cell_fill<<<nb, kBlock, 0, c->stream>>>(n, c->cell_of, c->cell_start, c->cell_fill, c->cell_atoms, c->d_flags);
-    k_cell_sort<<<(int)(((size_t)g.ncell * 64 + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(
-        g.ncell, c->cell_start, c->cell_cnt, c->cell_atoms, c->pos, n, c->cell_rec, c->d_flags);
     const double rs = std::max(c->eam.r_rho, c->eam.r_phi) + c->skin;  // the EAM pairs first
-    constexpr int SUB = 8;  // lanes per atom in the list build
-    const int lgrid = (int)(((size_t)n * SUB + kBlock - 1) / kBlock);
-    if (c->max_nbr <= 256)  // (at most 32 KB of staged lists per workgroup)
-        k_nbr_build<SUB, true><<<lgrid, kBlock, (size_t)c->max_nbr * (kBlock / SUB) * sizeof(int), c->stream>>>(
-            c->pos, n, g, r_list * r_list, rs * rs, c->cell_start, c->cell_cnt, c->cell_rec, c->cell_of, c->max_nbr,
-            c->nbr_cnt, c->nbr_short, c->nbr_idx, c->pos_build, c->d_flags);
-    else
-        k_nbr_build<SUB, false><<<lgrid, kBlock, 0, c->stream>>>(
-            c->pos, n, g, r_list * r_list, rs * rs, c->cell_start, c->cell_cnt, c->cell_rec, c->cell_of, c->max_nbr,
-            c->nbr_cnt, c->nbr_short, c->nbr_idx, c->pos_build, c->d_flags);
+    const ListBufs b{c->pos,        c->pos_build, c->d_flags,   c->cell_of, c->cell_cnt, c->cell_start,
+                     c->cell_fill,  c->cell_atoms, c->cell_rec, c->nbr_cnt, c->nbr_short, c->nbr_idx};
+    launch_list_kernels(c->stream, n, g, r_list, rs, c->max_nbr, b);
     if (commit) k_commit<<<1, 1, 0, c->stream>>>(c->d_flags, c->list_gen);
     c->list_r = r_list;
     c->list_n = n;
