@@ -56,6 +56,10 @@ extern "C" {
 #define AP_LAMBDA_PRECISE 0   /* lambda == 0 everywhere: pure ACE (paper orientation)    */
 #define AP_LAMBDA_FAST 1      /* lambda == 1 everywhere: pure EAM                         */
 
+#define AP_MIX_ENERGY 0 /* the conservative adaptive-precision force of Eq. (4)-(5)                */
+#define AP_MIX_FORCE 1  /* force mixing, Eq. (3): F_i = lambda_i F^f_i + (1 - lambda_i) F^p_i (the
+                           paper's non-conservative comparison; no energy behind it, no virial)     */
+
 #define AP_IND_CSP 0 /* g = CSP^list of (B3)                                                  */
 #define AP_IND_MLP 1 /* g = learned indicator: the network set by ap_set_mlp (no CSP list needed) */
 
@@ -95,13 +99,17 @@ typedef struct {
 /* Switching, Eq. (2), (6) and the weighting function of App. B:
  * w(r) = f_trans(r, r_w - 1 A, r_w); the sums of Eq. (6) include k = i (w(0) = 1).
  * lambda_mode: AP_LAMBDA_COMPUTED / _PRECISE / _FAST. grad_lambda: 1 conservative forces;
- * 0 drops the grad-lambda contributions (the non-conservative "AP without grad lambda" force). */
+ * 0 drops the grad-lambda contributions (the non-conservative "AP without grad lambda" force).
+ * mixing: AP_MIX_ENERGY (Eq. (4)-(5)) or AP_MIX_FORCE (Eq. (3): the complete EAM and ACE forces of
+ * each atom weighted by its own lambda_i; ACE then runs on the atoms with lambda < 1 and on every atom
+ * within the ACE cutoff of one; energies are still those of Eq. (4), the virial output is zero). */
 typedef struct {
     double d_lo, d_hi, r_w, d0;
     int n_csp;
     int lambda_mode;
     int indicator;
     int grad_lambda;
+    int mixing;
 } ap_switch_params;
 
 typedef struct ap_ctx ap_ctx;
@@ -128,6 +136,13 @@ int ap_csp_pairs_build(ap_ctx *ctx, int n, const double *pos_ref, const ap_box *
 
 /* Install a CSP pair list (device [n][n_csp], same layout) and build its reverse list. */
 int ap_set_csp_list(ap_ctx *ctx, int n, int n_csp, const int32_t *csp_list);
+
+/* Atoms with a constant switching parameter (App. B, the paragraph after (B4)): lam_fix device [n]
+ * int32, -1 = lambda from Eq. (2), 0 or 1 = lambda fixed at that value with dlambda/dd = 0 (the
+ * grad-lambda terms of that atom vanish and (B4) stays the exact force). The mask is copied into the
+ * context and applies to every later evaluation with a computed lambda; NULL removes it. Any other
+ * value returns AP_E_ARG (and the mask is not installed). */
+int ap_set_lambda_fixed(ap_ctx *ctx, int n, const int32_t *lam_fix);
 
 /* Neighbour sets at radius r_list (strict |u|^2 < r_list^2, minimum image, positions wrapped
  * into the box first): nbr_count device [n]; nbr_idx device [max_nbr][n] (slot-major: the k-th

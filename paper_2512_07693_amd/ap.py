@@ -16,13 +16,14 @@ LIB_PATH = os.path.join(_HERE, "libap.so")
 AP_FP64, AP_FP32 = 0, 1
 AP_LAMBDA_COMPUTED, AP_LAMBDA_PRECISE, AP_LAMBDA_FAST = -1, 0, 1
 AP_IND_CSP, AP_IND_MLP = 0, 1
+AP_MIX_ENERGY, AP_MIX_FORCE = 0, 1
 ERRORS = {-1: "AP_E_ARG", -2: "AP_E_BOX", -3: "AP_E_NBR_OVERFLOW", -4: "AP_E_NONFINITE", -5: "AP_E_HIP",
           -6: "AP_E_CSP", -7: "AP_E_STATE"}
 SYMBOLS = ["ap_ctx_create", "ap_ctx_destroy", "ap_last_error", "ap_set_potential", "ap_csp_pairs_build",
            "ap_set_csp_list", "ap_nblist_build", "ap_eam_eval", "ap_switch_eval", "ap_ace_eval",
            "ap_mixed_energy_forces", "ap_vv_step", "ap_set_profiling", "ap_get_profile", "ap_ace_cost",
            "ap_ace_batch_eval", "ap_set_mlp", "ap_mlp_features", "ap_mlp_eval", "ap_mlp_loss_grad",
-           "ap_mlp_train", "ap_nblist_build_noalloc"]
+           "ap_mlp_train", "ap_nblist_build_noalloc", "ap_set_lambda_fixed"]
 MLP_NQ, MLP_NPARAMS = 16, 5345
 
 
@@ -51,7 +52,8 @@ class AceParams(C.Structure):
 
 class SwitchParams(C.Structure):
     _fields_ = [("d_lo", C.c_double), ("d_hi", C.c_double), ("r_w", C.c_double), ("d0", C.c_double),
-                ("n_csp", C.c_int), ("lambda_mode", C.c_int), ("indicator", C.c_int), ("grad_lambda", C.c_int)]
+                ("n_csp", C.c_int), ("lambda_mode", C.c_int), ("indicator", C.c_int), ("grad_lambda", C.c_int),
+                ("mixing", C.c_int)]
 
 
 _lib = None
@@ -89,6 +91,7 @@ def lib():
         L.ap_mlp_loss_grad.argtypes = [vp, i, vp, vp, vp, vp, C.POINTER(C.c_double)]
         L.ap_mlp_train.argtypes = [vp, i, vp, vp, i, i, d, i, vp, C.POINTER(C.c_double)]
         L.ap_nblist_build_noalloc.argtypes = [i, vp, C.POINTER(Box), d, i, vp, vp, vp]
+        L.ap_set_lambda_fixed.argtypes = [vp, i, vp]
         for s in SYMBOLS:
             if s not in ("ap_ctx_destroy", "ap_last_error"):
                 getattr(L, s).restype = i
@@ -165,7 +168,7 @@ class Context:
         return torch.zeros(*shape, dtype=dtype, device=self.device)
 
     def set_potential(self, eam, ace, sw, lambda_mode=AP_LAMBDA_COMPUTED, grad_lambda=True, precision=None,
-                      indicator=AP_IND_CSP):
+                      indicator=AP_IND_CSP, mixing=AP_MIX_ENERGY):
         e = EamParams(*[float(eam[k]) for k in EAM_KEYS])
         func = np.ascontiguousarray(ace["func"], dtype=np.int32)
         c = np.ascontiguousarray(ace["c"], dtype=np.float64)
@@ -176,9 +179,17 @@ class Context:
                       b.ctypes.data_as(C.POINTER(C.c_double)), float(ace["emb_A"]), float(ace["E0"]),
                       AP_FP32 if prec in ("fp32", AP_FP32) else AP_FP64)
         s = SwitchParams(float(sw["d_lo"]), float(sw["d_hi"]), float(sw["r_w"]), float(sw.get("d0", 0.0)),
-                         int(sw["n_csp"]), int(lambda_mode), int(indicator), 1 if grad_lambda else 0)
+                         int(sw["n_csp"]), int(lambda_mode), int(indicator), 1 if grad_lambda else 0, int(mixing))
         self._chk(lib().ap_set_potential(self.h, C.byref(e), C.byref(a), C.byref(s)))
         self._nf, self._nm = len(func), int(ace["n_max"])
+
+    def set_lambda_fixed(self, lam_fix):
+        """Constant switching parameters: int32 CUDA tensor (n,) of -1 (computed), 0 or 1; None removes."""
+        if lam_fix is None:
+            self._chk(lib().ap_set_lambda_fixed(self.h, 0, None))
+            return
+        _dev(lam_fix, torch.int32)
+        self._chk(lib().ap_set_lambda_fixed(self.h, int(lam_fix.numel()), _ptr(lam_fix)))
 
     def csp_pairs_build(self, pos_ref, box, n_csp):
         n = pos_ref.shape[1]

@@ -26,7 +26,15 @@ constexpr double kConv = 9648.533212;  // eV / (A u) in A / ps^2
 constexpr double kPi = 3.14159265358979323846;
 
 // Error bits raised by kernels in ctx->d_flags[1].
-enum : int { kErrOverflow = 1, kErrNonFinite = 2, kErrCsp = 4, kErrAceNbr = 8, kErrDensity = 16, kErrAsym = 32 };
+enum : int {
+    kErrOverflow = 1,
+    kErrNonFinite = 2,
+    kErrCsp = 4,
+    kErrAceNbr = 8,
+    kErrDensity = 16,
+    kErrAsym = 32,
+    kErrLamFix = 64
+};
 
 // Block b of nb runs on XCD (b % 8); giving each XCD a contiguous range of atoms keeps the
 // neighbour gathers of one XCD inside its own L2.
@@ -184,6 +192,10 @@ struct ap_ctx {
     ap_switch_params sw{};
     ap::AceTables ace;
 
+    // constant switching parameters (ap_set_lambda_fixed): [n_cap] -1 = computed, 0 / 1 = fixed
+    int *lam_fix = nullptr;
+    bool have_fix = false;
+
     // CSP pair list and its reverse (fixed at set-up)
     int csp_n = 0, n_csp = 0;
     int32_t *csp_t = nullptr;     // [n_csp][n] slot-major
@@ -338,11 +350,16 @@ struct EvalFlags {
     double lam_const; // value of lambda when not computed
     bool eam_forces;  // EAM family included
     bool ace_forces;  // ACE family included
+    bool force_mix = false;  // force mixing, Eq. (3), instead of the conservative force
 };
 // count: also write the per-workgroup counts of lambda < 1 (chunk_cnt) that launch_compact(counted) uses
 void launch_dens_desc(ap_ctx *c, int n, const double *box, const EvalFlags &f, const double *lam_in, bool count);
 // counted: S from the density pass's chunk counts in one kernel (no subset); otherwise count, scan, scatter
 void launch_compact(ap_ctx *c, int n, const int32_t *subset, int n_subset, bool counted);
+// count, scan, scatter of the atoms with c->mark[i] != 0
+void launch_compact_marked(ap_ctx *c, int n);
+// force mixing: c->mark = the atoms that need ACE, c->act = lambda < 1
+void launch_mix_mark(ap_ctx *c, int n, const double *box);
 // stamped: only the atoms stamped by this evaluation's ACE pair kernel gather; csp_marks: also stamp (cmark)
 // the atoms that receive terms from an atom with W != 0: its CSP neighbours, or with the learned
 // indicator its list neighbours

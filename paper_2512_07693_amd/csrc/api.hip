@@ -87,6 +87,7 @@ int sync_and_check(ap_ctx *c) {
     if (e & kErrCsp) return set_error(c, AP_E_CSP, "CSP list invalid or too few neighbours for the CSP pairs");
     if (e & kErrAsym) return set_error(c, AP_E_NBR_OVERFLOW, "neighbour lists not symmetric (truncated list)");
     if (e & kErrNonFinite) return set_error(c, AP_E_NONFINITE, "non-finite energy or force");
+    if (e & kErrLamFix) return set_error(c, AP_E_ARG, "constant switching parameters must be -1, 0 or 1");
     return AP_OK;
 }
 
@@ -117,14 +118,23 @@ static int evaluate(ap_ctx *c, int n, const double *box, const EvalFlags &f, con
         ProfScope p(c, "csp_value");
         launch_csp_value(c, n, box);
     }
-    const bool counted = run_ace && !subset && n <= kCountedCompactMax;
+    const bool counted = run_ace && !subset && !f.force_mix && n <= kCountedCompactMax;
     {
         ProfScope p(c, "dens_desc");
         launch_dens_desc(c, n, box, f, lam_in, counted);
     }
     // the precise atoms stamp themselves and their list neighbours (ACE pair kernel) for the W pass
     c->stamp_gen = c->stamp_gen == 0x7fffffff ? 1 : c->stamp_gen + 1;
-    if (run_ace) {
+    if (run_ace && f.force_mix) {
+        // Eq. (3): ACE on the atoms with lambda < 1 and on every atom within the ACE cutoff of one
+        {
+            ProfScope p(c, "compact");
+            launch_mix_mark(c, n, box);
+            launch_compact_marked(c, n);
+        }
+        rc = launch_ace(c, n, box, std::min(n, 8192));
+        if (rc) return rc;
+    } else if (run_ace) {
         {
             ProfScope p(c, "compact");
             launch_compact(c, n, subset, n_subset, counted);
@@ -140,17 +150,18 @@ static int evaluate(ap_ctx *c, int n, const double *box, const EvalFlags &f, con
     // (with the learned indicator, the list neighbours of each atom with W != 0, which receive its
     // grad-g terms)
     const bool csp_marks = stamped && (c->sw.indicator == AP_IND_MLP || c->n_csp > 0);
-    if (f.switching && f.grad_lambda) {
+    if (f.switching && f.grad_lambda && !f.force_mix) {
         ProfScope p(c, "W");
         launch_W(c, n, box, stamped, csp_marks);
     }
-    if (f.switching && f.grad_lambda && c->sw.indicator == AP_IND_MLP) {
+    if (f.switching && f.grad_lambda && !f.force_mix && c->sw.indicator == AP_IND_MLP) {
         ProfScope p(c, "mlp_gradg");
         launch_mlp_gradg(c, n, box);
     }
     {
         ProfScope p(c, "force");
-        launch_force(c, n, box, f, E_atom, F, nullptr, lam_in == nullptr, csp_marks && f.switching && f.grad_lambda);
+        launch_force(c, n, box, f, E_atom, F, nullptr, lam_in == nullptr,
+                     csp_marks && f.switching && f.grad_lambda && !f.force_mix);
     }
     if (reduce) {
         ProfScope p(c, "reduce");
@@ -185,6 +196,7 @@ static EvalFlags mixed_flags(const ap_ctx *c) {
     f.lam_const = c->sw.lambda_mode == AP_LAMBDA_FAST ? 1.0 : 0.0;
     f.eam_forces = true;
     f.ace_forces = true;
+    f.force_mix = f.switching && c->sw.mixing == AP_MIX_FORCE;
     return f;
 }
 
@@ -245,7 +257,8 @@ void ap_ctx_destroy(ap_ctx *c) {
     void *bufs[] = {c->csp_t, c->rev_start, c->rev_code, c->pos, c->pos_build, c->d_flags, c->cell_of, c->cell_cnt,
                     c->cell_start, c->cell_fill, c->cell_atoms, c->cell_rec, c->nbr_cnt, c->nbr_idx, c->g, c->d,
                     c->wbar, c->lam, c->dlam, c->Ef, c->Ep, c->Et, c->W, c->xip, c->sidx, c->slist, c->blk_cnt,
-                    c->chunk_cnt, c->mark, c->fpair, c->frev, c->xg, c->xl, c->eb, c->xe, c->nbr_short, c->act, c->stamp, c->cmark, c->rslot, c->rstamp, c->list_gen, c->gbuf, c->partials, c->scalars, c->sid, c->b_off, c->b_box, c->bval};
+                    c->chunk_cnt, c->mark, c->fpair, c->frev, c->xg, c->xl, c->eb, c->xe, c->nbr_short, c->act, c->stamp, c->cmark, c->rslot, c->rstamp, c->list_gen, c->gbuf, c->partials, c->scalars, c->sid, c->b_off, c->b_box, c->bval,
+                    c->lam_fix};
     for (void *p : bufs) (void)hipFree(p);
     delete c;
 }
@@ -282,6 +295,7 @@ int ap_ctx_create(ap_ctx **out, int n_max_atoms, int max_nbr, double skin, void 
     alloc(&c->act, n, 4);
     alloc(&c->stamp, n, 4);
     alloc(&c->cmark, n, 4);
+    alloc(&c->lam_fix, n, 4);
     double **per_atom[] = {&c->g, &c->d, &c->wbar, &c->lam, &c->dlam, &c->Ef, &c->Ep, &c->Et, &c->W, &c->xip};
     for (double **p : per_atom) alloc(p, n, 8);
     alloc(&c->xg, n, sizeof(ap::Rec4));
@@ -328,6 +342,7 @@ int ap_set_potential(ap_ctx *c, const ap_eam_params *eam, const ap_ace_params *a
         sw->lambda_mode != AP_LAMBDA_FAST)
         return set_error(c, AP_E_ARG, "lambda_mode");
     if (sw->indicator != AP_IND_CSP && sw->indicator != AP_IND_MLP) return set_error(c, AP_E_ARG, "indicator");
+    if (sw->mixing != AP_MIX_ENERGY && sw->mixing != AP_MIX_FORCE) return set_error(c, AP_E_ARG, "mixing");
     if (sw->lambda_mode == AP_LAMBDA_COMPUTED && (!(sw->d_hi > sw->d_lo) || !(sw->r_w > 1.0)))
         return set_error(c, AP_E_ARG, "switching parameters need d_hi > d_lo and r_w > 1 A");
     int rc = ace_setup(c, ace);
@@ -378,6 +393,32 @@ int ap_set_csp_list(ap_ctx *c, int n, int n_csp, const int32_t *csp_list) {
     if (!c) return AP_E_ARG;
     if (n <= 0 || n > c->n_cap || !csp_list) return set_error(c, AP_E_ARG, "n or csp_list");
     int rc = install_csp(c, n, n_csp, csp_list);
+    return rc;
+}
+
+__global__ void k_copy_fix(const int32_t *src, int n, int *dst, int *flags) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int v = src[i];
+    if (v < -1 || v > 1) {
+        atomicOr(&flags[1], kErrLamFix);
+        v = -1;
+    }
+    dst[i] = v;
+}
+
+int ap_set_lambda_fixed(ap_ctx *c, int n, const int32_t *lam_fix) {
+    if (!c) return AP_E_ARG;
+    if (!lam_fix) {
+        c->have_fix = false;
+        return AP_OK;
+    }
+    if (n <= 0 || n > c->n_cap) return set_error(c, AP_E_ARG, "n out of range (1..n_max_atoms)");
+    launch_fill_int(c, c->d_flags + 1, 0, 1);
+    k_copy_fix<<<nblocks(n), kBlock, 0, c->stream>>>(lam_fix, n, c->lam_fix, c->d_flags);
+    int rc = hip_check(c, hipGetLastError(), "lambda mask");
+    if (!rc) rc = sync_and_check(c);
+    c->have_fix = rc == AP_OK;
     return rc;
 }
 

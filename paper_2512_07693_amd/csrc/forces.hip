@@ -72,7 +72,7 @@ __global__ __launch_bounds__(kBlock) void k_dens_desc(const double *__restrict__
                                                       double *__restrict__ Ep, double *__restrict__ Et, int *flags,
                                                       int *__restrict__ chunk_cnt, int *list_gen,
                                                       const double *__restrict__ partials, int nbf, int pstride,
-                                                      double *row_prev) {
+                                                      double *row_prev, const int *__restrict__ lam_fix) {
     // commit of the neighbour-list rebuild flag, after every list kernel of this evaluation (workgroup 0
     // keeps the previous value for the thermo row below)
     __shared__ int s_prev_rebuild, s_prev_S;
@@ -150,8 +150,14 @@ __global__ __launch_bounds__(kBlock) void k_dens_desc(const double *__restrict__
         double l, dl = 0.0, d = 0.0;
         if (switching) {
             d = gs / ws - sp.d0;
-            l = ftrans(d, sp.d_lo, sp.d_hi);
-            dl = ftrans_d(d, sp.d_lo, sp.d_hi);
+            const int fx = lam_fix ? lam_fix[i] : -1;
+            if (fx >= 0) {
+                // a constant switching parameter (App. B, after (B4)): not a function of d, dlambda/dd = 0
+                l = (double)fx;
+            } else {
+                l = ftrans(d, sp.d_lo, sp.d_hi);
+                dl = ftrans_d(d, sp.d_lo, sp.d_hi);
+            }
         } else {
             l = lam_in ? lam_in[i] : lam_const;
             ws = 1.0;
@@ -198,7 +204,7 @@ void launch_dens_desc(ap_ctx *c, int n, const double *box, const EvalFlags &f, c
             c->pos, n, box[0], box[1], box[2], eamp(c->eam), sp, f.switching ? 1 : 0, f.lam_const, lam_in,
             c->nbr_cnt, c->nbr_idx, c->g, c->xg, c->xl, c->eb, c->xe, c->Ef, c->xip, c->wbar, c->d, c->lam, c->dlam,
             c->Ep, c->Et, c->d_flags, count ? c->chunk_cnt : nullptr, c->list_gen, c->partials, force_blocks(n),
-            c->pstride, c->thermo_prev);
+            c->pstride, c->thermo_prev, c->have_fix && f.switching ? c->lam_fix : nullptr);
     };
     if (n <= kCountedCompactMax)
         go(std::integral_constant<int, kDensLanes>());
@@ -301,6 +307,13 @@ __global__ __launch_bounds__(kBlock) void k_compact_chunks(int n, const double *
     }
 }
 
+void launch_compact_marked(ap_ctx *c, int n) {
+    const int nb = (n + kBlock - 1) / kBlock;
+    k_compact_count<<<nb, kBlock, 0, c->stream>>>(n, c->lam, c->mark, c->blk_cnt);
+    launch_scan(c, c->blk_cnt, c->blk_cnt + nb, nb, c->d_flags + 2, nullptr);
+    k_compact_scatter<<<nb, kBlock, 0, c->stream>>>(n, c->lam, c->mark, c->blk_cnt + nb, c->sidx, c->slist);
+}
+
 void launch_compact(ap_ctx *c, int n, const int32_t *subset, int n_subset, bool counted) {
     const int nb = (n + kBlock - 1) / kBlock;
     if (counted && !subset) {
@@ -319,6 +332,48 @@ void launch_compact(ap_ctx *c, int n, const int32_t *subset, int n_subset, bool 
     k_compact_count<<<nb, kBlock, 0, c->stream>>>(n, c->lam, mark, c->blk_cnt);
     launch_scan(c, c->blk_cnt, c->blk_cnt + nb, nb, c->d_flags + 2, nullptr);
     k_compact_scatter<<<nb, kBlock, 0, c->stream>>>(n, c->lam, mark, c->blk_cnt + nb, c->sidx, c->slist);
+}
+
+// ------------------------------------------------------------------------------------------
+// Force mixing, Eq. (3): F^p_i of an atom with lambda_i < 1 needs E^p_k of every atom k within the ACE
+// cutoff of i. mark = 1 selects those atoms and the atoms with lambda < 1 for the ACE kernels; act = 1
+// the atoms whose force has an ACE part (lambda_i < 1), the others take F^f_i alone. The cutoff test
+// has a margin, so the marked set contains every atom the ACE kernels find inside rc (an extra atom
+// only adds zero pair terms).
+// ------------------------------------------------------------------------------------------
+template <int SUB>
+__global__ __launch_bounds__(kBlock) void k_mix_mark(int n, double Lx, double Ly, double Lz, double rc2m,
+                                                     const int32_t *__restrict__ ncount,
+                                                     const int32_t *__restrict__ nidx, const Rec4 *__restrict__ xl,
+                                                     int *__restrict__ mark, int *__restrict__ act) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = t / SUB, sub = t - i * SUB;
+    int near = 0, own = 0;
+    if (i < n) {
+        const Rec4 pi = xl[i];
+        own = pi.w < 1.0;
+        const int cnt = ncount[i];
+        for (int k = sub; k < cnt && !near; k += SUB) {
+            const Rec4 pj = xl[nidx[(size_t)k * n + i]];
+            if (!(pj.w < 1.0)) continue;
+            const double ux = min_image_w(pj.x - pi.x, Lx), uy = min_image_w(pj.y - pi.y, Ly),
+                         uz = min_image_w(pj.z - pi.z, Lz);
+            near = ux * ux + uy * uy + uz * uz < rc2m;
+        }
+    }
+#pragma unroll
+    for (int m = 1; m < SUB; m <<= 1) near |= __shfl_xor(near, m, 64);
+    if (i < n && sub == 0) {
+        mark[i] = own | near;
+        act[i] = own;
+    }
+}
+
+void launch_mix_mark(ap_ctx *c, int n, const double *box) {
+    constexpr int SUB = kLanesPerAtom;
+    const double rcm = c->ace.rc * (1.0 + 1e-9);
+    k_mix_mark<SUB><<<((size_t)n * SUB + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(
+        n, box[0], box[1], box[2], rcm * rcm, c->nbr_cnt, c->nbr_idx, c->xl, c->mark, c->act);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -477,7 +532,8 @@ __device__ __forceinline__ void block_sums(const double *v, double *sh, double *
 // FULL = false: only the EAM-only gather (every atom in that mode), compiled without the full-list loop
 // and the CSP part so that it keeps its own, lower register count. With FP32 pair terms the full kernel
 // is bounded to four workgroups per CU (128 VGPRs, no spills).
-template <typename TF, int SUB, bool FULL>
+// MIX: force mixing, Eq. (3) (an instantiation of its own, so that the conservative kernel keeps its registers).
+template <typename TF, int SUB, bool FULL, bool MIX = false>
 __global__ __launch_bounds__(kBlock, (FULL && sizeof(TF) == 4) ? 4 : 1) void k_force(ForceArgs a) {
     __shared__ double sh[kBlock / 64 * 14];
     // plain block order (as in the W pass): the atoms with a precise atom in reach are contiguous index
@@ -532,7 +588,7 @@ __global__ __launch_bounds__(kBlock, (FULL && sizeof(TF) == 4) ? 4 : 1) void k_f
                     F0 += s * ux;
                     F1 += s * uy;
                     F2 += s * uz;
-                    const double t = -own * ir;
+                    const double t = MIX ? 0.0 : -own * ir;
                     v[0] += t * ux * ux; v[1] += t * ux * uy; v[2] += t * ux * uz;
                     v[3] += t * uy * ux; v[4] += t * uy * uy; v[5] += t * uy * uz;
                     v[6] += t * uz * ux; v[7] += t * uz * uy; v[8] += t * uz * uz;
@@ -569,14 +625,15 @@ __global__ __launch_bounds__(kBlock, (FULL && sizeof(TF) == 4) ? 4 : 1) void k_f
                 if (a.eam_on && r2 < a.ep.rc2) {
                     double zz, dz, ph, dph;
                     eam_pair(a.ep, r, zz, dz, ph, dph);
-                    // lambda_i f_ki - lambda_k f_ik, (S12), along rhat_ki = u / r
+                    // lambda_i f_ki - lambda_k f_ik, (S12), along rhat_ki = u / r (force mixing, Eq. (3):
+                    // lambda_i (f_ki - f_ik), the complete EAM force of i weighted by its own lambda)
                     const double own = li * (xpi * dz + 0.5 * dph);
-                    const double s = own + lj * (qj.x * dz + 0.5 * dph);
+                    const double s = own + (MIX ? li : lj) * (qj.x * dz + 0.5 * dph);
                     F0 += s * ex;
                     F1 += s * ey;
                     F2 += s * ez;
                     // virial of the edge owned by i: -(d(lambda_i E_i)/du)_a u_b
-                    const double t = -own * ir;
+                    const double t = MIX ? 0.0 : -own * ir;
                     v[0] += t * ux * ux; v[1] += t * ux * uy; v[2] += t * ux * uz;
                     v[3] += t * uy * ux; v[4] += t * uy * uy; v[5] += t * uy * uz;
                     v[6] += t * uz * ux; v[7] += t * uz * uy; v[8] += t * uz * uz;
@@ -623,15 +680,16 @@ __global__ __launch_bounds__(kBlock, (FULL && sizeof(TF) == 4) ? 4 : 1) void k_f
                         F0 += wgt * fx;
                         F1 += wgt * fy;
                         F2 += wgt * fz;
-                        v[0] -= wgt * fx * ux; v[1] -= wgt * fx * uy; v[2] -= wgt * fx * uz;
-                        v[3] -= wgt * fy * ux; v[4] -= wgt * fy * uy; v[5] -= wgt * fy * uz;
-                        v[6] -= wgt * fz * ux; v[7] -= wgt * fz * uy; v[8] -= wgt * fz * uz;
+                        const double vw = MIX ? 0.0 : wgt;
+                        v[0] -= vw * fx * ux; v[1] -= vw * fx * uy; v[2] -= vw * fx * uz;
+                        v[3] -= vw * fy * ux; v[4] -= vw * fy * uy; v[5] -= vw * fy * uz;
+                        v[6] -= vw * fz * ux; v[7] -= vw * fz * uy; v[8] -= vw * fz * uz;
                     }
                     if (sj >= 0) {  // precise j: its term for this pair, stored at (k, i)
                         const TF *fr = reinterpret_cast<const TF *>(a.frev);
                         const size_t st = (size_t)a.max_nbr * n, o = (size_t)k * n + i;
                         const double fx = (double)fr[o], fy = (double)fr[st + o], fz = (double)fr[2 * st + o];
-                        const double wgt = 1.0 - lj;
+                        const double wgt = 1.0 - (MIX ? li : lj);
                         F0 -= wgt * fx;
                         F1 -= wgt * fy;
                         F2 -= wgt * fz;
@@ -754,7 +812,7 @@ void launch_force(ap_ctx *c, int n, const double *box, const EvalFlags &f, doubl
     a.ep = eamp(c->eam);
     a.sp = swp(c);
     a.switching = f.switching;
-    a.grad_lambda = f.grad_lambda;
+    a.grad_lambda = f.grad_lambda && !f.force_mix;
     a.eam_on = f.eam_forces;
     a.ace_on = f.ace_forces;
     a.ncount = c->nbr_cnt;
@@ -781,7 +839,7 @@ void launch_force(ap_ctx *c, int n, const double *box, const EvalFlags &f, doubl
     a.partials = c->partials;
     a.pstride = c->pstride;
     a.flags = c->d_flags;
-    a.ind_mlp = f.switching && c->sw.indicator == AP_IND_MLP;
+    a.ind_mlp = f.switching && !f.force_mix && c->sw.indicator == AP_IND_MLP;
     a.hpair = c->hpair;
     a.hrev = c->hrev;
     a.widx = c->widx;
@@ -794,12 +852,19 @@ void launch_force(ap_ctx *c, int n, const double *box, const EvalFlags &f, doubl
     // for every atom; 3: EAM pairs only (short lists) with a per-atom lambda
     a.short_mode = 0;
     if (!sbox && f.switching && f.grad_lambda && c->sw.indicator == AP_IND_CSP) a.short_mode = 1;
+    // force mixing: act (from the mixing marks) is lambda_i < 1; every other atom takes F^f_i alone, which
+    // the EAM-only gather computes with lambda_i = 1 at both ends of each pair
+    if (!sbox && f.force_mix) a.short_mode = 1;
     // the learned indicator needs the marks of the W pass to know who receives grad-g terms
     if (!sbox && f.switching && f.grad_lambda && c->sw.indicator == AP_IND_MLP && csp_marked) a.short_mode = 1;
     if (!sbox && !f.switching && (!f.ace_forces || f.lam_const == 1.0)) a.short_mode = uniform_lambda ? 2 : 3;
     const int nb = force_blocks(n);
     if (a.short_mode == 2)
         k_force<double, kForceLanes, false><<<nb, kBlock, 0, c->stream>>>(a);
+    else if (f.force_mix && a.fp32)
+        k_force<float, kForceLanes, true, true><<<nb, kBlock, 0, c->stream>>>(a);
+    else if (f.force_mix)
+        k_force<double, kForceLanes, true, true><<<nb, kBlock, 0, c->stream>>>(a);
     else if (a.fp32)
         k_force<float, kForceLanes, true><<<nb, kBlock, 0, c->stream>>>(a);
     else

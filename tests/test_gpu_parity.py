@@ -56,6 +56,62 @@ def test_nblist_bit_exact(oracle, cfg1):
         ctx.close()
 
 
+def _oracle_lists(oracle, pos, box, r, cap):
+    """The oracle's neighbour sets as an (n, cap) array, ascending, padded with INT32_MAX."""
+    n = len(pos)
+    cnt = np.zeros(n, np.int32)
+    idx = np.zeros(n * cap, np.int32)
+    rc = oracle.lib().ora_nblist(n, np.ascontiguousarray(pos), np.ascontiguousarray(box, dtype=np.float64),
+                                 float(r), cap, cnt, idx)
+    assert rc == 0
+    idx = idx.reshape(n, cap)
+    idx[np.arange(cap)[None, :] >= cnt[:, None]] = np.iinfo(np.int32).max
+    return cnt, idx
+
+
+@pytest.mark.parametrize("cfg,r_list,max_nbr", [(2, 7.0, 128), (5, 7.0, 160)], ids=["bcc128k", "fcc2M"])
+def test_nblist_bit_exact_full_size(oracle, cfg, r_list, max_nbr):
+    """Every atom's neighbour set at the evaluation's list radius (max(rc, r_w) + skin) of the 128,000-atom
+    and 2,047,229-atom workloads, against the oracle's binned build: the same sets, bit for bit (a pair
+    dropped between the cutoff and the skin would only show once atoms move)."""
+    import torch
+    from paper_2512_07693_amd import ap
+    s = synth.build_system(cfg, with_velocities=False)
+    n = len(s["pos"])
+    _say("nblist full size n=%d r=%.1f" % (n, r_list))
+    ctx = ap.Context(n, max_nbr=max_nbr, skin=s["run"]["skin"])
+    ctx.set_potential(s["eam"], s["ace"], s["sw"])
+    cnt, idx = ctx.nblist_build(to_dev(s["pos"]), s["box"], r_list)
+    big = torch.iinfo(torch.int32).max
+    slot = torch.arange(max_nbr, device="cuda")[None, :]
+    got = torch.where(slot < cnt[:, None].long(), idx.t().long(), big).sort(dim=1).values.int().cpu().numpy()
+    cnt = cnt.cpu().numpy()
+    ctx.close()
+    want_cnt, want = _oracle_lists(oracle, s["pos"], s["box"], r_list, max_nbr)
+    _say("  mean count %.2f, max %d" % (want_cnt.mean(), want_cnt.max()))
+    assert np.array_equal(cnt, want_cnt)
+    assert np.array_equal(got, want)
+
+
+def _near_errors(s, want, F):
+    """FP32 error measures over the atoms that carry FP32 ACE terms: the precise atoms and every atom within
+    the ACE cutoff of one (the rest of the cell is FP64 throughout)."""
+    from scipy.spatial import cKDTree
+    box = np.asarray(s["box"], float)
+    p = np.mod(s["pos"], box)
+    p[p >= box] = 0.0
+    prec = np.nonzero(want["aux"]["lam"] < 1)[0]
+    tree = cKDTree(p, boxsize=box)
+    near = np.zeros(len(p), bool)
+    near[prec] = True
+    for lst in tree.query_ball_point(p[prec], s["ace"]["rc"]):
+        near[lst] = True
+    dF, Fr = F[near] - want["F"][near], want["F"][near]
+    rms = float(np.sqrt((dF ** 2).mean()) / np.sqrt((Fr ** 2).mean()))
+    mx = float(np.abs(dF).max() / np.abs(Fr).max())
+    return int(near.sum()), rms, mx
+
+
 def test_csp_pairs_bit_exact(oracle, cfg1, cfg1_oracle):
     _say("csp pairs cfg1")
     ctx, csp = make_ctx(cfg1)
@@ -200,6 +256,10 @@ def test_mixed_fp32_full_screw_dipole(oracle):
     _say("  x = %.4f" % x)
     F = soa_to_aos(out["F"])
     _lt("F rms", force_err_rms(F, want["F"]), TOL_F32_FORCE)
+    m, rms, mx = _near_errors(s, want, F)
+    _say("  %d atoms near S" % m)
+    _lt("F rms near", rms, TOL_F32_FORCE)
+    _lt("F max near", mx, TOL_F32_FORCE)
     _lt("E/N", abs(out["E"].item() - want["E"]) / n, TOL_ENERGY)
     _lt("sum F", float(np.abs(F.sum(0)).max()), 1e-9 * n)
     ctx.close()
@@ -242,6 +302,10 @@ def test_mixed_fp32_full_vacancy_clusters(oracle):
     _say("  oracle %.1f s, x = %.4f" % (time.time() - t, x))
     F = soa_to_aos(out["F"])
     _lt("F rms", force_err_rms(F, want["F"]), TOL_F32_FORCE)
+    m, rms, mx = _near_errors(s, want, F)
+    _say("  %d atoms near S" % m)
+    _lt("F rms near", rms, TOL_F32_FORCE)
+    _lt("F max near", mx, TOL_F32_FORCE)
     _lt("E/N", abs(float(out["E"]) - want["E"]) / n, TOL_ENERGY)
     _lt("sum F", float(np.abs(F.sum(0)).max() / np.abs(F).max()), 1e-5)
     ctx.close()
@@ -264,6 +328,10 @@ def test_mixed_fp32_full_fcc_penny_crack(oracle):
     _say("  oracle %.1f s, x = %.4f" % (time.time() - t, x))
     F = soa_to_aos(out["F"])
     _lt("F rms", force_err_rms(F, want["F"]), TOL_F32_FORCE)
+    m, rms, mx = _near_errors(s, want, F)
+    _say("  %d atoms near S" % m)
+    _lt("F rms near", rms, TOL_F32_FORCE)
+    _lt("F max near", mx, TOL_F32_FORCE)
     _lt("E/N", abs(float(out["E"]) - want["E"]) / n, TOL_ENERGY)
     _lt("sum F", float(np.abs(F.sum(0)).max() / np.abs(F).max()), 1e-5)
     ctx.close()
