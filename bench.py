@@ -8,8 +8,13 @@ whole hot path (neighbour-list check/rebuild, CSP, descriptor, lambda, EAM, ACE 
 forces, assembly, reductions, integration), inputs resident in HBM.
 
 Printed: one JSON line with the mixed atom-steps/s (value), the pure-ACE rate on the same GPU and
-potential, the NVE drift, the roofline of the dominant kernel (timed with HIP events on the library's
-stream) and the CPU oracle baseline on a bounded sample.
+potential, the NVE drift over a fixed 1-ps leg, the roofline of the dominant kernel (timed with HIP events
+on the library's stream) and the CPU oracle baseline on a bounded sample; and, as extra keys, the
+conservation contrast of the paper's comparison forces (force mixing, AP without grad lambda, the pure
+models), the time-step study of the per-step energy change, the 2M-atom fcc run and the learned indicator.
+
+`--speedup-map` runs instead the sweep of the speedup over the precise fraction x and the averaging radius
+r_w on a 2M-atom bcc cell with vacancy-interstitial pairs, fitted to Eq. (1).
 """
 import argparse
 import json
@@ -116,40 +121,189 @@ def near_counts(ctx, pos, box, r_list, r_short, max_nbr):
     return int(near.sum().item()), float(cnt_s.double().mean().item())
 
 
-def run_md(ctx, s, pos0, vel0, steps, warmup, profile_steps):
+def run_md(ctx, s, pos0, vel0, steps, warmup, profile_steps, dt=None, final=None):
+    """warmup untimed velocity-Verlet steps, then steps timed between HIP events on the library's stream
+    (kernel groups timed on every PROF_EVERY-th step). final: a dict that receives the end state."""
     import torch
     box = s["box"]
+    dt = s["run"]["dt"] if dt is None else dt
     pos = pos0.clone()
     vel = vel0.clone()
     F = ctx.mixed_energy_forces(pos, box)["F"]
     th_w = None
     if warmup:
-        th_w = ctx.vv_step(pos, vel, F, s["mass"], s["run"]["dt"], warmup, box).cpu().numpy()
+        th_w = ctx.vv_step(pos, vel, F, s["mass"], dt, warmup, box).cpu().numpy()
     stream = ctx.stream
     torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     ctx.set_profiling(True, every=PROF_EVERY)
     t0.record(stream)
-    thermo = ctx.vv_step(pos, vel, F, s["mass"], s["run"]["dt"], steps, box)
+    thermo = ctx.vv_step(pos, vel, F, s["mass"], dt, steps, box)
     t1.record(stream)
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1)
     prof = ctx.get_profile()
     ctx.set_profiling(False)
+    if final is not None:
+        final.update(pos=pos, vel=vel)
     return ms, thermo.cpu().numpy(), prof, th_w
 
 
-def cpu_baseline(s, steps):
+def naive_ace_flops(func):
+    """Floating-point operations per precise atom of the product basis by its plain definition (the count
+    the scope table gives the energy kernel): order 3 costs 4 flop per (m1, m2) term of every function for
+    the value and about three times that for the adjoint, order 2 costs 2 flop per m."""
+    func = np.asarray(func)
+    t3 = 0
+    for n1, l1, n2, l2, n3, l3 in func[func[:, 4] >= 0]:
+        m1 = np.arange(-l1, l1 + 1)[:, None]
+        m2 = np.arange(-l2, l2 + 1)[None, :]
+        t3 += int((np.abs(m1 + m2) <= l3).sum())
+    o2 = func[(func[:, 2] >= 0) & (func[:, 4] < 0)]
+    t2 = int((2 * o2[:, 1] + 1).sum())
+    return float(16 * t3 + 2 * t2), t3, t2
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(s, steps, x):
+    """The FP64 oracle as it stands, on the host: velocity-Verlet steps of the full workload on every core
+    (the reported value), one force evaluation on one core, and the per-atom times of Eq. (1): t^(f) from a
+    pure-EAM evaluation of the workload, t^(p) from pure ACE on a 250-atom cell of the same potential and
+    density, t^(d) as what the mixed evaluation costs beyond x t^(p) + t^(f)."""
+    import synth
     from oracle import oracle as O
+    n = len(s["pos"])
     cores = O.set_threads(0)
+    csp = O.csp_pairs(s["pos_ref"], s["box"], s["sw"]["n_csp"])
     t = time.time()
-    O.velocity_verlet(s, steps)
-    dt = time.time() - t
+    O.velocity_verlet(s, steps, csp=csp)
+    t_vv = time.time() - t
+    t = time.time()
+    O.evaluate(s, csp=csp)
+    t_mix = time.time() - t
+    t = time.time()
+    O.evaluate(s, csp=csp, lam_mode=1)
+    t_eam = time.time() - t
+    small = synth.build_system(2, nc=5, with_velocities=False)
+    t = time.time()
+    O.evaluate(small, lam_mode=0, skip=0)
+    t_ace = (time.time() - t) / len(small["pos"])
+    t_f = t_eam / n
+    t_d = max(0.0, t_mix / n - x * t_ace - t_f)
+    O.set_threads(1)
+    t = time.time()
+    O.evaluate(s, csp=csp)
+    t_one = time.time() - t
+    O.set_threads(0)
     # the velocity_verlet call also evaluates the initial forces once: steps + 1 evaluations
-    return dict(value=len(s["pos"]) * steps / dt, unit="atom-steps/s", cores=int(cores), kind="oracle",
+    return dict(value=n * steps / t_vv, unit="atom-steps/s", cores=int(cores), kind="oracle",
                 sample="%d velocity-Verlet steps (plus the initial force evaluation) of the full %d-atom "
-                       "workload, FP64 oracle in S-skip mode, %.1f s" % (steps, len(s["pos"]), dt))
+                       "workload, FP64 oracle in S-skip mode, %.1f s" % (steps, n, t_vv),
+                cpu_model=cpu_model(),
+                single_core=dict(value=n / t_one, unit="atom-steps/s", cores=1,
+                                 sample="one force evaluation (S-skip) of the full workload, %.1f s" % t_one),
+                per_atom_us=dict(t_precise=t_ace * 1e6, t_fast=t_f * 1e6, t_switch=t_d * 1e6,
+                                 t_mixed=t_mix / n * 1e6,
+                                 note="t_precise from pure ACE on a 250-atom cell of the same potential; "
+                                      "t_switch = t_mixed - x t_precise - t_fast"),
+                speedup_eq1=dict(x=x, s_eq1_paper=t_ace / (x * t_ace + (1 - x) * t_f + t_d),
+                                 s_eq1_all_eam=t_ace / (x * t_ace + t_f + t_d)))
+
+
+def thermo_summary(th, n, dt_ps, every=50):
+    """Drift, energy and momentum change, temperature change, and traces every `every` steps."""
+    kB = 8.617333262e-5
+    e = th[:, 2] / n
+    T = 2.0 * th[:, 1] / ((3 * n - 3) * kB)
+    t = (np.arange(len(e)) + 1) * dt_ps
+    P = th[:, 3:6]
+    dP = np.abs(P - P[0]).max(1)
+    q = max(1, min(100, len(e) // 10))
+    return dict(drift_eV_per_atom_per_ps=float(np.polyfit(t, e, 1)[0]) if len(e) > 2 else 0.0,
+                max_abs_dE_per_atom=float(np.abs(e - e[0]).max()), max_abs_dP=float(dP.max()),
+                dT_K=float(T[-q:].mean() - T[:q].mean()), T_start_K=float(T[:q].mean()),
+                x_mean=float(th[:, 6].mean() / n),
+                trace=dict(step=list(range(0, len(e), every)), dE_per_atom=[float(v) for v in (e - e[0])[::every]],
+                           dP=[float(v) for v in dP[::every]], T_K=[float(v) for v in T[::every]]))
+
+
+def conservation_contrast(s, pos0, vel0, steps):
+    """The paper's NVE contrast (Fig. 5, Fig. S2): the same start integrated with the conservative AP force,
+    the AP force without its grad-lambda terms, force mixing (Eq. (3)), pure EAM and pure ACE."""
+    from paper_2512_07693_amd import ap
+    n = len(s["pos"])
+    variants = (("ap", dict()), ("ap_without_grad_lambda", dict(grad_lambda=False)),
+                ("force_mixing", dict(mixing=ap.AP_MIX_FORCE)), ("eam", dict(lambda_mode=ap.AP_LAMBDA_FAST)),
+                ("ace", dict(lambda_mode=ap.AP_LAMBDA_PRECISE)))
+    out = dict(steps=steps, dt_fs=s["run"]["dt"] * 1e3, workload=s["name"])
+    for name, kw in variants:
+        ctx = ap.Context(n, max_nbr=128, skin=s["run"]["skin"])
+        ctx.set_potential(s["eam"], s["ace"], s["sw"], **kw)
+        if kw.get("lambda_mode", ap.AP_LAMBDA_COMPUTED) == ap.AP_LAMBDA_COMPUTED:
+            ctx.csp_pairs_build(torch_dev(s["pos_ref"]), s["box"], s["sw"]["n_csp"])
+        log("contrast: %s, %d steps ..." % (name, steps))
+        ms, th, _, _ = run_md(ctx, s, pos0, vel0, steps, 0, 0)
+        out[name] = dict(ms_per_step=ms / steps, **thermo_summary(th, n, s["run"]["dt"]))
+        ctx.close()
+    return out
+
+
+def dt_study(s, pos0, vel0, steps, dts_fs=(0.25, 0.5, 1.0, 2.0)):
+    """Per-step energy change against the time step (SM Fig. S3): from one equilibrated state, the mean
+    |E_tot(t + dt) - E_tot(t)| / N over `steps` velocity-Verlet steps at each dt, for AP, EAM and ACE, the
+    slope of its log against log dt over all four and over each interval (velocity Verlet with smooth
+    forces: 3). ACE runs in FP64 here: its FP32 site energies round at about 1e-9 eV/atom per step, which
+    would set a floor under the small time steps."""
+    from paper_2512_07693_amd import ap
+    n = len(s["pos"])
+    out = dict(steps=steps, dt_fs=list(dts_fs), ace_precision="fp64")
+    for name, mode in (("ap", ap.AP_LAMBDA_COMPUTED), ("eam", ap.AP_LAMBDA_FAST), ("ace", ap.AP_LAMBDA_PRECISE)):
+        ctx = ap.Context(n, max_nbr=128, skin=s["run"]["skin"])
+        ctx.set_potential(s["eam"], s["ace"], s["sw"], lambda_mode=mode, precision="fp64")
+        if mode == ap.AP_LAMBDA_COMPUTED:
+            ctx.csp_pairs_build(torch_dev(s["pos_ref"]), s["box"], s["sw"]["n_csp"])
+        de = []
+        for dt_fs in dts_fs:
+            log("dt study: %s dt = %.2f fs ..." % (name, dt_fs))
+            _, th, _, _ = run_md(ctx, s, pos0, vel0, steps, 0, 0, dt=dt_fs * 1e-3)
+            de.append(float(np.abs(np.diff(th[:, 2])).mean() / n))
+        ctx.close()
+        slope = float(np.polyfit(np.log(dts_fs), np.log(de), 1)[0])
+        pair = [float(np.log(de[q + 1] / de[q]) / np.log(dts_fs[q + 1] / dts_fs[q])) for q in range(len(de) - 1)]
+        out[name] = dict(mean_abs_dE_per_step_per_atom=de, loglog_slope=slope, interval_slopes=pair)
+    return out
+
+
+def nbr_build_roofline(ctx, pos, box, r_list, max_nbr, reps=5):
+    """A forced neighbour-list build (cell binning, sort, lists), timed with HIP events: minimal bytes are
+    the positions read once and the list written once (24 + 4 + 4 nnb per atom)."""
+    ctx.set_profiling(True)
+    for _ in range(reps):
+        cnt, _ = ctx.nblist_build(pos, box, r_list, max_nbr)
+    prof = ctx.get_profile()
+    ctx.set_profiling(False)
+    n = pos.shape[1]
+    nnb = float(cnt.double().mean().item())
+    ms = prof["nbr_build"][0]
+    b = n * (24.0 + 4.0 + 4.0 * nnb)
+    return dict(avg_ms=ms, algorithmic_bytes=b, nnb=nnb, GBs=b / (ms * 1e-3) / 1e9,
+                frac=b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, launches=int(prof["nbr_build"][1]))
+
+
+def torch_dev(a):
+    import torch
+    return torch.tensor(np.ascontiguousarray(np.asarray(a, dtype=np.float64).T), device="cuda")
 
 
 def train_indicator(eam, ace, sw, n_cells=200, epochs=150):
@@ -247,6 +401,89 @@ def learned_comparison(steps, warmup):
     return out
 
 
+def speedup_map(r_ws=(6.5, 9.0, 12.0, 16.0), pairs=(4, 16, 64, 256, 1024, 2048), nc=100, steps=10, warmup=5):
+    """Speedup of the mixed loop over pure ACE against the precise fraction x and the averaging radius r_w
+    (Fig. 4 with Eq. (1)): bcc 100^3 = 2,000,000 atoms (sigma = 0.08 A, 300 K) with a growing number of
+    vacancy-interstitial pairs, the potentials of the 128,000-atom workload, and per r_w the thresholds
+    d_lo = mean + 1.25 (max - mean) of d on the defect-free cell, d_hi = d_lo + 1 A^2. Per-atom times:
+    t^(p) from pure ACE, t^(f) from pure EAM on the same cell, t^(d) per r_w from the intercept of the mixed
+    step time against x; Eq. (1) in the form of this build (EAM on every atom) then predicts each point."""
+    import torch
+    import synth
+    from synth import structures as st
+    from paper_2512_07693_amd import ap
+    base = synth.build_system(2, nc=4, with_velocities=False)  # the potentials and run parameters only
+    eam, ace, sw0, mass, skin = base["eam"], base["ace"], base["sw"], base["mass"], base["run"]["skin"]
+    a = 3.16
+    slots = {6.5: 128, 9.0: 320, 12.0: 640, 16.0: 1408}
+    sysd = dict(eam=eam, ace=ace, mass=mass, run=dict(base["run"]))
+
+    def cell(n_pairs, seed):
+        rng = np.random.default_rng(6000 + seed)
+        if n_pairs:
+            ref, box = st.frenkel_pairs(a, nc, n_pairs, rng)
+        else:
+            ref, box = st.bcc(a, nc)
+        pos = st.gaussian_displace(ref, 0.08, rng)
+        vel = st.maxwell_velocities(len(pos), mass, 300.0, rng)
+        return ref, pos, vel, box
+
+    out = dict(n_atoms=2 * nc ** 3, steps=steps, warmup=warmup, r_w=list(r_ws), pairs=list(pairs))
+    # pure models on the defect-free cell
+    ref, pos, vel, box = cell(0, 0)
+    d = dict(sysd, box=box)
+    P, V = torch_dev(pos), torch_dev(vel)
+    times = {}
+    for name, mode, k in (("ace", ap.AP_LAMBDA_PRECISE, 3), ("eam", ap.AP_LAMBDA_FAST, 20)):
+        c = ap.Context(len(pos), max_nbr=128, skin=skin)
+        c.set_potential(eam, ace, sw0, lambda_mode=mode)
+        log("speedup map: pure %s ..." % name)
+        ms, _, _, _ = run_md(c, d, P, V, k, 1, 0)
+        times[name] = ms / k / len(pos)
+        c.close()
+    t_p, t_f = times["ace"], times["eam"]
+    out["t_precise_ns"], out["t_fast_ns"] = t_p * 1e6, t_f * 1e6
+    for r_w in r_ws:
+        m = slots[r_w]
+        # thresholds from the defect-free cell at this radius
+        c = ap.Context(len(pos), max_nbr=m, skin=skin)
+        c.set_potential(eam, ace, dict(sw0, r_w=r_w, d_lo=1.0, d_hi=2.0))
+        c.csp_pairs_build(torch_dev(ref), box, 8)
+        dd = c.switch_eval(P, box)["d"]
+        dmean, dmax = float(dd.mean()), float(dd.max())
+        c.close()
+        d_lo = dmean + 1.25 * (dmax - dmean)
+        sw = dict(sw0, r_w=r_w, d_lo=d_lo, d_hi=d_lo + 1.0)
+        rows = []
+        for k_p in pairs:
+            ref_k, pos_k, vel_k, box_k = cell(k_p, k_p)
+            Pk, Vk = torch_dev(pos_k), torch_dev(vel_k)
+            c = ap.Context(len(pos_k), max_nbr=m, skin=skin)
+            c.set_potential(eam, ace, sw)
+            c.csp_pairs_build(torch_dev(ref_k), box_k, 8)
+            log("speedup map: r_w = %.1f, %d pairs ..." % (r_w, k_p))
+            ms, th, prof, _ = run_md(c, dict(sysd, box=box_k), Pk, Vk, steps, warmup, 0)
+            c.close()
+            n = len(pos_k)
+            x = float(th[:, 6].mean() / n)
+            t_m = ms / steps / n
+            rows.append(dict(pairs=k_p, x=x, ms_per_step=ms / steps, t_mixed_ns=t_m * 1e6, s_measured=t_p / t_m,
+                             kernels={q: round(v[0], 4) for q, v in prof.items()}))
+            del Pk, Vk
+            torch.cuda.empty_cache()
+        xs = np.array([r["x"] for r in rows])
+        tm = np.array([r["t_mixed_ns"] for r in rows]) * 1e-6
+        slope, icpt = np.polyfit(xs, tm, 1)
+        t_d = max(0.0, icpt - t_f)
+        for r in rows:
+            r["s_eq1"] = t_p / (r["x"] * t_p + t_f + t_d)
+            r["rel_err"] = r["s_eq1"] / r["s_measured"] - 1.0
+        out["r_w=%g" % r_w] = dict(d_lo=d_lo, d_hi=d_lo + 1.0, d_mean_bulk=dmean, d_max_bulk=dmax,
+                                   t_switch_ns=t_d * 1e6, t_precise_in_mixed_ns=slope * 1e6, points=rows,
+                                   max_abs_rel_err=float(max(abs(r["rel_err"]) for r in rows)))
+    return out
+
+
 def large_run(steps, warmup, pure_steps):
     """The 2M-atom fcc penny-crack workload: the mixed loop against pure ACE on the same GPU, with the
     per-kernel times and the memory-bound kernels' achieved bandwidth at a working set far above the
@@ -298,6 +535,16 @@ def main():
     ap_.add_argument("--pure-steps", type=int, default=20)
     ap_.add_argument("--cpu-steps", type=int, default=2)
     ap_.add_argument("--no-cpu", action="store_true")
+    ap_.add_argument("--drift-steps", type=int, default=1000,
+                     help="the NVE drift leg: steps fitted after --equil steps of equilibration (independent of "
+                          "--steps)")
+    ap_.add_argument("--equil", type=int, default=200)
+    ap_.add_argument("--contrast-steps", type=int, default=1000,
+                     help="NVE steps of each run of the conservation contrast (0: skip)")
+    ap_.add_argument("--dt-steps", type=int, default=100,
+                     help="steps per time step of the time-step study (0: skip)")
+    ap_.add_argument("--speedup-map", action="store_true",
+                     help="run only the sweep of the speedup over x and r_w (2M-atom bcc, Eq. (1) fit)")
     ap_.add_argument("--large-steps", type=int, default=500,
                      help="NVE steps of the 2M-atom fcc penny-crack run (0: skip)")
     ap_.add_argument("--learned-steps", type=int, default=500,
@@ -324,6 +571,10 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.speedup_map:
+        print(json.dumps(dict(metric="speedup over pure ACE against x and r_w", speedup_map=speedup_map())),
+              flush=True)
+        return
     log("building workload ...")
     s = synth.build_system(2)
     n = len(s["pos"])
@@ -338,12 +589,24 @@ def main():
     log("mixed: %d warmup + %d timed steps ..." % (args.warmup, args.steps))
     ms, thermo, prof, th_w = run_md(ctx, s, pos0, vel0, args.steps, args.warmup, 0)
     value = n * args.steps / (ms / 1e3)
-    nve = drift_fit(thermo, n, s["run"]["dt"])
-    if th_w is not None:
-        # the same fit from the first step on, equilibration transient included
-        nve["from_step_0"] = {k: v for k, v in drift_fit(np.concatenate([th_w, thermo]), n, s["run"]["dt"]).items()
+    window = drift_fit(thermo, n, s["run"]["dt"])
+    log("mixed: %.3f ms/step, %.3e atom-steps/s, x=%.4f" % (ms / args.steps, value, window["x_mean"]))
+    # the drift on a fixed 1-ps leg after a stated equilibration, whatever --steps is (a short window
+    # measures the energy's oscillation, not its drift); also fitted with the transient included
+    log("drift leg: %d + %d steps ..." % (args.equil, args.drift_steps))
+    eq_state = {}
+    _, th_d, _, th_e = run_md(ctx, s, pos0, vel0, args.drift_steps, args.equil, 0, final=eq_state)
+    nve = drift_fit(th_d, n, s["run"]["dt"])
+    nve["equilibration_steps"] = args.equil
+    if th_e is not None:
+        nve["from_step_0"] = {k: v for k, v in drift_fit(np.concatenate([th_e, th_d]), n, s["run"]["dt"]).items()
                               if k in ("drift_eV_per_atom_per_ps", "max_abs_dE_per_atom", "steps", "x_max")}
-    log("mixed: %.3f ms/step, %.3e atom-steps/s, x=%.4f" % (ms / args.steps, value, nve["x_mean"]))
+    nve["bar_eV_per_atom_per_ps"] = 1e-6
+    nve["margin"] = 1e-6 / max(abs(nve["drift_eV_per_atom_per_ps"]), 1e-30)
+    nve["timed_window"] = {k: window[k] for k in ("drift_eV_per_atom_per_ps", "max_abs_dE_per_atom", "steps")}
+    log("drift: %.3e eV/atom/ps over %d steps (%.3e with the transient)" %
+        (nve["drift_eV_per_atom_per_ps"], nve["steps"], nve.get("from_step_0", {}).get("drift_eV_per_atom_per_ps",
+                                                                                          float("nan"))))
 
     # pure ACE: the same potential with lambda == 0 everywhere
     ms_p, value_p, prof_p = None, None, {}
@@ -364,7 +627,7 @@ def main():
         log("pure EAM: 100 timed steps ...")
         ms_f, _, prof_f, _ = run_md(ctx_f, s, pos0, vel0, 100, 5, 0)
         ctx_f.close()
-        x = nve["x_mean"]
+        x = window["x_mean"]
         t_p, t_f, t_m = ms_p / args.pure_steps / n, ms_f / 100 / n, ms / args.steps / n
         sw_ms = sum(prof[k][0] for k in ("csp_value", "compact", "W") if k in prof)
         sw_ms += sum(max(0.0, prof[k][0] - prof_f.get(k, (0.0,))[0]) for k in ("dens_desc",))
@@ -391,7 +654,7 @@ def main():
     cnt_w, _ = ctx.nblist_build(pos0, box, max(s["ace"]["rc"], s["sw"]["r_w"]) + s["run"]["skin"], 128)
     nnb_rc = float(cnt_rc.double().mean().item())
     nnb = float(cnt_w.double().mean().item())
-    n_s = nve["x_mean"] * n
+    n_s = window["x_mean"] * n
     n_near, nnb_short = near_counts(ctx, pos0, box, max(s["ace"]["rc"], s["sw"]["r_w"]) + s["run"]["skin"],
                                     max(s["eam"]["r_rho"], s["eam"]["r_phi"]) + s["run"]["skin"], 128)
     tot = {k: v[0] * v[1] for k, v in prof.items()}
@@ -399,13 +662,21 @@ def main():
     avg_ms, launches = prof[dom]
     ace_per = {"ace_energy": cost["fixed_per_atom"], "ace_basis": nnb_rc * cost["per_neighbor_energy"],
                "ace_pairforce": nnb_rc * cost["per_neighbor_force"]}
+    naive, t3, t2 = naive_ace_flops(s["ace"]["func"])
     if dom in ace_per:
-        per = ace_per[dom]
+        # achieved: the product basis by its plain definition (B2 + B3 + the adjoint, about 20 Mflop per atom
+        # at n_max 12 / l_max 6) over the kernel's time; executed: the flops the coupling-block form performs
+        per = naive if dom == "ace_energy" else ace_per[dom]
         flops = per * n_s
         achieved = flops / (avg_ms * 1e-3) / 1e12
+        ex = ace_per[dom] * n_s / (avg_ms * 1e-3) / 1e12
         roof = dict(bound="alu", achieved=achieved, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
                     frac=achieved / FP32_PEAK_TFLOPS, traffic=measured_traffic(dom), kernel=dom, avg_ms=avg_ms,
-                    work_per_launch="%.4g flop (%.0f precise atoms x %.4g flop)" % (flops, n_s, per))
+                    work_per_launch="%.4g flop (%.0f precise atoms x %.4g flop)" % (flops, n_s, per),
+                    count="algorithmic: 16 x %d order-3 (m1, m2) terms + 2 x %d order-2 terms per atom" % (t3, t2)
+                    if dom == "ace_energy" else "executed",
+                    executed=dict(achieved=ex, frac=ex / FP32_PEAK_TFLOPS, flop_per_atom=ace_per[dom],
+                                  note="flops the coupling-block kernels perform (ap_ace_cost)"))
     else:
         b = algorithmic_bytes(dom, n, nnb, n_s, nnb_rc, s["sw"]["n_csp"], n_near, nnb_short)
         achieved = b / (avg_ms * 1e-3) / 1e9 if b else None
@@ -414,6 +685,9 @@ def main():
                     avg_ms=avg_ms, work_per_launch="%.4g B" % (b or 0))
     kernels = {k: dict(avg_ms=round(v[0], 5), launches=int(v[1]), share=round(tot[k] / sum(tot.values()), 4))
                for k, v in sorted(prof.items(), key=lambda kv: -tot[kv[0]])}
+    r_list = max(s["ace"]["rc"], s["sw"]["r_w"]) + s["run"]["skin"]
+    nbr_roof = nbr_build_roofline(ctx, pos0, box, r_list, 128)
+    log("nbr build: %.1f us, %.0f GB/s" % (nbr_roof["avg_ms"] * 1e3, nbr_roof["GBs"]))
     hbm = {}
     for k in ("dens_desc", "force", "W"):
         if k in prof:
@@ -426,6 +700,14 @@ def main():
             if k in pf:
                 tf = ace_per[k] * ns / (pf[k][0] * 1e-3) / 1e12
                 ace_roof.setdefault(tag, {})[k] = dict(TFLOPs=tf, frac=tf / FP32_PEAK_TFLOPS, avg_ms=pf[k][0])
+
+    contrast = None
+    if args.contrast_steps > 0:
+        # from the state the drift leg ends in (equilibrated), like the paper's runs at room temperature
+        contrast = conservation_contrast(s, eq_state["pos"], eq_state["vel"], args.contrast_steps)
+    dts = None
+    if args.dt_steps > 0:
+        dts = dt_study(s, eq_state["pos"], eq_state["vel"], args.dt_steps)
 
     large = None
     if args.large_steps > 0:
@@ -444,7 +726,7 @@ def main():
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle, %d steps) ..." % args.cpu_steps)
-        cpu = cpu_baseline(s, args.cpu_steps)
+        cpu = cpu_baseline(s, args.cpu_steps, window["x_mean"])
         log("cpu: %.3e atom-steps/s on %d threads" % (cpu["value"], cpu["cores"]))
 
     out = {
@@ -454,7 +736,7 @@ def main():
         "data": "synthetic (seeded; see synth/configs.py)",
         "config": {"workload": s["name"], "n_atoms": n, "lattice": "bcc a=3.16 40^3, screw dipole",
                    "ace_basis": int(len(s["ace"]["func"])), "n_max": 12, "l_max": 6, "r_w": s["sw"]["r_w"],
-                   "dt_fs": 1.0, "x": nve["x_mean"]},
+                   "dt_fs": 1.0, "x": window["x_mean"]},
         "pure_ace": {"value": value_p, "unit": "atom-steps/s", "steps": args.pure_steps,
                      "ms_per_step": ms_p / args.pure_steps if ms_p else None},
         "speedup_vs_pure_ace": value / value_p if value_p else None,
@@ -463,6 +745,9 @@ def main():
         "roofline": roof,
         "ace_roofline": ace_roof,
         "hbm_kernels": hbm,
+        "nbr_build": nbr_roof,
+        "conservation_contrast": contrast,
+        "dt_study": dts,
         "path_counts": {"n_near_precise": n_near, "nnb_list": nnb, "nnb_eam_short": nnb_short, "nnb_ace": nnb_rc},
         "kernels": kernels,
         "kernels_timed_every_nth_step": PROF_EVERY,

@@ -50,6 +50,10 @@ struct AceArgs {
     const int *list_gen;
     const void *c30, *kap0;  // the L = 0 blocks folded into order 2 (null: processed as blocks)
     int gen;
+    // reverse terms: the neighbour's gather reads the term of a pair only inside rc, so it is written for
+    // r^2 < rw2 = rc^2 (1 + 1e-9). When the reverse slots are cached for the list, they are searched for
+    // every pair with r^2 < rrev2 (rslot_reach2: no pair beyond it comes inside rc before the next build)
+    double rw2, rrev2;
     void *fpair;  // [S][max_nbr][3]
     void *frev;   // [3][max_nbr][n]: f of pair (i, j) stored at slot k of i in j's list
     const Rec4 *xl;  // [n] {x, y, z, lambda}
@@ -188,10 +192,10 @@ __device__ __forceinline__ int ace_part_block(int p, int P, int n0, int nblk) {
     return p == 0 ? 0 : n0 + (nblk - n0) * p / P;
 }
 
-// (in FP32 the second bound keeps it at 6 workgroups per CU: with 1,536 resident slots the S atoms of a
-// mixed step take one round)
+// (in FP32 at n_max 12 the second bound keeps it at 6 workgroups per CU: with 1,536 resident slots the S
+// atoms of a mixed step take one round; the smaller bases would spill under it)
 template <typename T, int NMAX, int LMAX>
-__global__ __launch_bounds__(kBlock, sizeof(T) == 4 ? 6 : 1) void k_ace_basis(AceArgs a) {
+__global__ __launch_bounds__(kBlock, (sizeof(T) == 4 && NMAX == 12) ? 6 : 1) void k_ace_basis(AceArgs a) {
     constexpr int NLM = (LMAX + 1) * (LMAX + 1), NA = NMAX * NLM;
     constexpr int V = kAceMaxValid, CH = 64;  // neighbours kept per site; harmonics computed CH at a time
     __shared__ T sR[CH * NMAX], sY[CH * NLM];
@@ -750,6 +754,8 @@ __global__ __launch_bounds__(128) void k_ace_pairforce(AceArgs a) {
             fo[3 * slot] = f0;
             fo[3 * slot + 1] = f1;
             fo[3 * slot + 2] = f2;
+            const bool need = r2 < a.rw2;
+            if (!need && !(a.rslot && !cached && r2 < a.rrev2)) continue;
             // the slot k of i in j's list (lists are symmetric): j's gather reads the term at (k, j),
             // coalesced over j. Loads go out eight at a time so the search is not one long chain.
             int kk = -1;
@@ -769,7 +775,7 @@ __global__ __launch_bounds__(128) void k_ace_pairforce(AceArgs a) {
             }
             if (kk < 0) {
                 atomicOr(&a.flags[1], kErrAsym);
-            } else {
+            } else if (need) {
                 T *fr = (T *)a.frev;
                 const size_t st = (size_t)a.max_nbr * n, o = (size_t)kk * n + j;
                 fr[o] = f0;
@@ -1190,6 +1196,8 @@ int launch_ace(ap_ctx *c, int n, const double *box, int grid_cap, const double *
         a.rslot = sbox ? nullptr : c->rslot;
         a.rstamp = c->rstamp;
         a.list_gen = c->list_gen;
+        a.rw2 = t.rc * t.rc * (1.0 + 1e-9);
+        a.rrev2 = rslot_reach2(c);
     }
 
     a.fpair = c->fpair;

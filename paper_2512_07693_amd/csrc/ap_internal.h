@@ -302,6 +302,17 @@ struct ProfScope {
 };
 void prof_resolve(ap_ctx *c);
 
+// Reverse-slot cache (rslot): the ACE pair kernel and the learned indicator's grad-g kernel, whichever
+// fills an atom's entries first on a list, search every slot whose pair lies within
+// max(ACE cutoff, feature cutoff) + 2 skin: a pair beyond that cannot come inside either cutoff before the
+// next build (every atom stays within skin / 2 of its build position). Squared, with a rounding margin.
+inline double rslot_reach2(const ap_ctx *c) {
+    double r = c->ace.rc;
+    if (c->have_mlp && c->mlp_rc > r) r = c->mlp_rc;
+    r += 2.0 * c->skin;
+    return r * r * (1.0 + 1e-9);
+}
+
 // geometry.hip
 // Buffers of one neighbour-list build: wrapped positions in, build-time positions, flags ([0] gates the
 // build, [1] error bits), the cell arrays, and the list out (counts, short counts, slot-major indices).

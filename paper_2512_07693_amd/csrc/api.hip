@@ -442,7 +442,10 @@ int ap_nblist_build(ap_ctx *c, int n, const double *pos, const ap_box *box, doub
     if (!(r_list > 0) || max_nbr <= 0 || !nbr_count || !nbr_idx) return set_error(c, AP_E_ARG, "list arguments");
     launch_fill_int(c, c->d_flags + 1, 0, 1);
     rc = prepare_positions(c, n, pos, box->L);
-    if (!rc) rc = ensure_list(c, n, box->L, r_list, true);
+    if (!rc) {
+        ProfScope p(c, "nbr_build");  // one forced build: cells, sort, lists
+        rc = ensure_list(c, n, box->L, r_list, true);
+    }
     if (!rc) {
         k_copy_list<<<nblocks(n), kBlock, 0, c->stream>>>(c->nbr_cnt, c->nbr_idx, n, max_nbr, nbr_count, nbr_idx,
                                                           c->d_flags);
@@ -461,7 +464,7 @@ int ap_eam_eval(ap_ctx *c, int n, const double *pos, const int32_t *species, con
     EvalFlags f{false, false, 1.0, true, false};
     launch_fill_int(c, c->d_flags + 1, 0, 1);
     rc = prepare_positions(c, n, pos, box->L);
-    if (!rc) rc = evaluate(c, n, box->L, f, lambda, nullptr, 0, false, E_tot, E_atom, F, virial9, true);
+    if (!rc) rc = evaluate(c, n, box->L, f, lambda, nullptr, 0, false, E_tot, E_atom, F, virial9, false);
     if (!rc) rc = sync_and_check(c);
     return rc;
 }
@@ -509,7 +512,7 @@ int ap_ace_eval(ap_ctx *c, int n, const double *pos, const int32_t *species, con
     EvalFlags f{false, false, 0.0, false, true};
     launch_fill_int(c, c->d_flags + 1, 0, 1);
     rc = prepare_positions(c, n, pos, box->L);
-    if (!rc) rc = evaluate(c, n, box->L, f, nullptr, subset, n_subset, true, E_tot, E_atom, F, virial9, true);
+    if (!rc) rc = evaluate(c, n, box->L, f, nullptr, subset, n_subset, true, E_tot, E_atom, F, virial9, false);
     if (!rc) rc = sync_and_check(c);
     return rc;
 }
@@ -527,7 +530,7 @@ int ap_mixed_energy_forces(ap_ctx *c, int n, const double *pos, const int32_t *s
     launch_fill_int(c, c->d_flags + 1, 0, 1);
     rc = prepare_positions(c, n, pos, box->L);
     const bool run_ace = !(c->sw.lambda_mode == AP_LAMBDA_FAST);
-    if (!rc) rc = evaluate(c, n, box->L, f, nullptr, nullptr, 0, run_ace, E_tot, E_atom, F, virial9, true);
+    if (!rc) rc = evaluate(c, n, box->L, f, nullptr, nullptr, 0, run_ace, E_tot, E_atom, F, virial9, false);
     if (!rc && lambda_out) k_copy_d<<<nblocks(n), kBlock, 0, c->stream>>>(c->lam, lambda_out, n);
     if (!rc) rc = sync_and_check(c);
     return rc;
@@ -672,16 +675,18 @@ int ap_vv_step(ap_ctx *c, int n, double *pos, double *vel, double *F, double mas
     const double hdtm = 0.5 * dt / mass * kConv;
     const int nb = nblocks(n), nbf = force_blocks(n);
     launch_fill_int(c, c->d_flags + 1, 0, 1);
-    // the list must describe these positions: rebuild on the first step of every call
-    bool force = true;
+    // the list of the previous call stays valid while every atom is within skin / 2 of its build position
+    // (the first step's skin check, in k_vv_first, decides); a new n, box or radius rebuilds it anyway
+    bool force = false;
     for (int s = 0; s < n_steps; s++) {
         c->prof_skip = c->prof_every > 1 && s % c->prof_every != 0;
         if (s == 0) {
             ProfScope p(c, "vv_first");
-            // (the first step rebuilds the list anyway: its check and clearing are redone there)
+            // the skin check of the drifted positions against the last build, and the cells of that build's
+            // geometry cleared for a possible rebuild (a new geometry is cleared by the list code itself)
             k_vv_first<<<nb, kBlock, 0, c->stream>>>(pos, vel, F, c->pos, n, hdtm, dt, box->L[0], box->L[1],
                                                      box->L[2], c->pos_build, 0.25 * c->skin * c->skin, c->d_flags,
-                                                     c->cell_cnt, c->cell_fill, 0);
+                                                     c->cell_cnt, c->cell_fill, c->ncell_cur);
         }
         // the force pass applies the second half-kick and sums E_kin and P with the energy, then (but on
         // the last step) the next step's first half-kick, drift and skin check; the density pass of this

@@ -471,6 +471,8 @@ struct ForceArgs {
     const int *sidx;
     const void *fpair, *frev;
     int fp32, max_nbr, n_csp;
+    double ace_rc2;  // reverse ACE terms exist only inside the ACE cutoff
+    double mlp_rc2;  // and reverse grad-g terms only inside the feature cutoff
     const int32_t *csp_t, *rev_start, *rev_code;
     double *E_atom, *F, *partials;  // partials: [16][pstride] per-block sums, column-major
     int pstride;
@@ -664,7 +666,7 @@ __global__ __launch_bounds__(kBlock, (FULL && sizeof(TF) == 4) ? 4 : 1) void k_f
                         v[3] += hy * ux; v[4] += hy * uy; v[5] += hy * uz;
                         v[6] += hz * ux; v[7] += hz * uy; v[8] += hz * uz;
                     }
-                    if (a.widx[j] >= 0) {
+                    if (a.widx[j] >= 0 && r2 < a.mlp_rc2) {
                         const size_t st = (size_t)a.max_nbr * n, o = (size_t)k * n + i;
                         F0 += (double)a.hrev[o];
                         F1 += (double)a.hrev[st + o];
@@ -685,7 +687,7 @@ __global__ __launch_bounds__(kBlock, (FULL && sizeof(TF) == 4) ? 4 : 1) void k_f
                         v[3] -= vw * fy * ux; v[4] -= vw * fy * uy; v[5] -= vw * fy * uz;
                         v[6] -= vw * fz * ux; v[7] -= vw * fz * uy; v[8] -= vw * fz * uz;
                     }
-                    if (sj >= 0) {  // precise j: its term for this pair, stored at (k, i)
+                    if (sj >= 0 && r2 < a.ace_rc2) {  // precise j: its term for this pair, stored at (k, i)
                         const TF *fr = reinterpret_cast<const TF *>(a.frev);
                         const size_t st = (size_t)a.max_nbr * n, o = (size_t)k * n + i;
                         const double fx = (double)fr[o], fy = (double)fr[st + o], fz = (double)fr[2 * st + o];
@@ -829,6 +831,8 @@ void launch_force(ap_ctx *c, int n, const double *box, const EvalFlags &f, doubl
     a.fpair = c->fpair;
     a.frev = c->frev;
     a.fp32 = c->ace.precision == AP_FP32;
+    a.ace_rc2 = c->ace.rc * c->ace.rc;
+    a.mlp_rc2 = c->mlp_rc * c->mlp_rc;
     a.max_nbr = c->max_nbr;
     a.n_csp = c->n_csp;
     a.csp_t = c->csp_t;

@@ -125,6 +125,7 @@ struct MlpArgs {
     // in its slot-th neighbour's list, valid while rstamp[j] == *list_gen
     int *rslot, *rstamp;
     const int *list_gen;
+    double rrev2;     // slots searched when an atom's reverse slots are cached (rslot_reach2)
     float *q;         // [n][16] features (feature mode)
     const double *W;  // [n]
     const int *wlist, *wcount;
@@ -350,6 +351,10 @@ __global__ __launch_bounds__(64) void k_mlp_gradg(MlpArgs a) {
             hp[3 * slot] = h0;
             hp[3 * slot + 1] = h1;
             hp[3 * slot + 2] = h2;
+            // k's gather reads this term only inside the feature cutoff; the cache covers every slot
+            // that can come inside it before the next list build
+            const bool need = r2 < rc2 * (1.0 + 1e-9);
+            if (!need && !(!cached && r2 < a.rrev2)) continue;
             int kk = -1;
             if (cached) {
                 kk = a.rslot[(size_t)j * a.max_nbr + slot];
@@ -367,7 +372,7 @@ __global__ __launch_bounds__(64) void k_mlp_gradg(MlpArgs a) {
             }
             if (kk < 0) {
                 atomicOr(&a.flags[1], kErrAsym);
-            } else {
+            } else if (need) {
                 const size_t st = (size_t)a.max_nbr * n, o2 = (size_t)kk * n + k;
                 a.hrev[o2] = h0;
                 a.hrev[st + o2] = h1;
@@ -576,6 +581,7 @@ static MlpArgs mlp_args(ap_ctx *c, int n, const double *box) {
     a.rslot = c->rslot;
     a.rstamp = c->rstamp;
     a.list_gen = c->list_gen;
+    a.rrev2 = rslot_reach2(c);
     a.q = nullptr;
     a.W = c->W;
     a.wlist = c->wlist;

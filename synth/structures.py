@@ -83,6 +83,20 @@ def penny_crack(pos, box, radius, half_width, centre):
     return remove_atoms(pos, (np.abs(d[:, 2]) < half_width) & (rho2 < radius * radius))
 
 
+def frenkel_pairs(a, nc, n_pairs, rng):
+    """Perfect bcc of nc^3 cells with n_pairs vacancy-interstitial pairs: 2 n_pairs distinct conventional
+    cells are drawn; the first n_pairs lose their corner atom, the other n_pairs gain an atom at the
+    tetrahedral site (a/2, a/4, 0) from their corner. The atom count stays 2 nc^3; every vacancy is
+    removed from its interstitial by the random draw of the cells."""
+    pos, box = bcc(a, nc)
+    cells = rng.choice(nc ** 3, size=2 * n_pairs, replace=False)
+    vac, itl = cells[:n_pairs], cells[n_pairs:]
+    keep = np.ones(len(pos), dtype=bool)
+    keep[2 * vac] = False  # the corner atom of conventional cell c is atom 2 c
+    extra = pos[2 * itl] + np.array([0.5, 0.25, 0.0]) * a
+    return np.concatenate([pos[keep], extra]), box
+
+
 def strain_cell(pos, box, eps):
     """Apply a symmetric strain (3x3, small) to an orthorhombic cell: only the
     diagonal is applied to the box (the cell stays orthorhombic); shear components
