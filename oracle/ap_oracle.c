@@ -19,6 +19,8 @@
  *                                            (S28)-(S29)
  *   differentiable CSP with a fixed list ... (B3) / (S22)
  *   learned indicator g (network) .......... Eq. (6) with a general g, force term (S16)
+ *   ACE coefficient gradient and the vector-Jacobian product of the forces with respect to the
+ *   coefficients (derivatives of the ACE site energy; the paper cites ACE)
  *   velocity Verlet NVE .................... main text, time integration paragraph
  * The paper defines ACE only by reference; the concrete form used here (Chebyshev radial
  * channels, complex spherical harmonics with the Condon-Shortley phase, product basis of
@@ -1338,6 +1340,139 @@ int ora_ace_coeff_grad(int n, const double *pos_in, const double *L, int n_max, 
             dEdc[f] = s;
         else
             dEdb[f - n_funcs] = s;
+    }
+    free(acc);
+    free(ace.w3j);
+    csr_free(&nb);
+    free(pos);
+    return ORA_OK;
+}
+
+/* Tangents of one site along a motion of its neighbour vectors: every u_j moves with the velocity udot_j.
+ * Product rule on the definitions of ace_site:
+ *   Adot_{nlm} = sum_j grad_u [g_n(|u|) Y_l^m(u/|u|)] at u_j . udot_j
+ *   Bdot (order 1) = Adot_{n00};  order 2 = sum_m (-1)^m (Adot_{n1lm} A_{n2l-m} + A_{n1lm} Adot_{n2l-m})
+ *   order 3 = sum (l1 l2 l3; m1 m2 m3) (Adot1 A2 A3 + A1 Adot2 A3 + A1 A2 Adot3)
+ *   the density term: d/dt [xi'(phi2) sqrt(4 pi) A_{n00}]
+ *                    = xi''(phi2) phi2dot sqrt(4 pi) A_{n00} + xi'(phi2) sqrt(4 pi) Adot_{n00},
+ *   phi2dot = sum_n b_n sqrt(4 pi) Adot_{n00}, xi = -emb_A sqrt (xi' = -emb_A / (2 sqrt), xi'' = emb_A / (4 phi2^1.5)).
+ * Outputs: Bdot[n_funcs] (real parts), ddb[n_max] the density-term tangents. */
+static void ace_site_tangent(const ace_t *p, int nn, const double *u, const double *udot, double *Bdot,
+                             double *ddb) {
+    int nmax = p->n_max, nlm = ace_nlm(p), lmax = p->l_max;
+    double complex *A = (double complex *)calloc((size_t)nmax * nlm, sizeof(double complex));
+    double complex *Ad = (double complex *)calloc((size_t)nmax * nlm, sizeof(double complex));
+    double complex *Y = (double complex *)malloc(sizeof(double complex) * (size_t)nlm);
+    double complex *dY = (double complex *)malloc(sizeof(double complex) * 3 * (size_t)nlm);
+    double g[32], dg[32];
+    for (int j = 0; j < nn; j++) {
+        const double *uj = u + 3 * j, *vj = udot + 3 * j;
+        double r = sqrt(sq3(uj));
+        if (r >= p->rc) continue;
+        ora_radial(nmax, p->rc, r, g, dg);
+        ora_ylm_c(lmax, uj, Y, dY);
+        double rdot = (uj[0] * vj[0] + uj[1] * vj[1] + uj[2] * vj[2]) / r; /* d|u|/dt */
+        for (int t = 0; t < nlm; t++) {
+            double complex ydot = dY[3 * t] * vj[0] + dY[3 * t + 1] * vj[1] + dY[3 * t + 2] * vj[2];
+            for (int n = 0; n < nmax; n++) {
+                A[n * nlm + t] += g[n] * Y[t];
+                Ad[n * nlm + t] += dg[n] * rdot * Y[t] + g[n] * ydot;
+            }
+        }
+    }
+#define AA(n, l, m) A[(n) * nlm + (l) * (l) + (l) + (m)]
+#define AD(n, l, m) Ad[(n) * nlm + (l) * (l) + (l) + (m)]
+    for (int f = 0; f < p->n_funcs; f++) {
+        const int *q = p->func + 6 * f;
+        double complex bd = 0.0;
+        if (q[2] < 0) {
+            bd = AD(q[0], 0, 0);
+        } else if (q[4] < 0) {
+            int n1 = q[0], l = q[1], n2 = q[2];
+            for (int m = -l; m <= l; m++) {
+                double sg = (m & 1) ? -1.0 : 1.0;
+                bd += sg * (AD(n1, l, m) * AA(n2, l, -m) + AA(n1, l, m) * AD(n2, l, -m));
+            }
+        } else {
+            int n1 = q[0], l1 = q[1], n2 = q[2], l2 = q[3], n3 = q[4], l3 = q[5];
+            for (int m1 = -l1; m1 <= l1; m1++)
+                for (int m2 = -l2; m2 <= l2; m2++) {
+                    int m3 = -m1 - m2;
+                    if (m3 < -l3 || m3 > l3) continue;
+                    double wv = w3(p, l1, l2, l3, m1, m2);
+                    if (wv == 0.0) continue;
+                    bd += wv * (AD(n1, l1, m1) * AA(n2, l2, m2) * AA(n3, l3, m3) +
+                                AA(n1, l1, m1) * AD(n2, l2, m2) * AA(n3, l3, m3) +
+                                AA(n1, l1, m1) * AA(n2, l2, m2) * AD(n3, l3, m3));
+                }
+        }
+        Bdot[f] = creal(bd);
+    }
+    double phi2 = 0.0, phi2d = 0.0, s4pi = sqrt(4.0 * PI);
+    for (int n = 0; n < nmax; n++) {
+        phi2 += p->b_dens[n] * s4pi * creal(AA(n, 0, 0));
+        phi2d += p->b_dens[n] * s4pi * creal(AD(n, 0, 0));
+    }
+    double d1 = 0.0, d2 = 0.0; /* xi'(phi2), xi''(phi2) */
+    if (phi2 > 0.0) {
+        d1 = -0.5 * p->emb_A / sqrt(phi2);
+        d2 = 0.25 * p->emb_A / (phi2 * sqrt(phi2));
+    }
+    for (int n = 0; n < nmax; n++)
+        ddb[n] = d2 * phi2d * s4pi * creal(AA(n, 0, 0)) + d1 * s4pi * creal(AD(n, 0, 0));
+#undef AA
+#undef AD
+    free(A);
+    free(Ad);
+    free(Y);
+    free(dY);
+}
+
+/* Vector-Jacobian product of the ACE forces with respect to the ACE coefficients, one periodic cell with
+ * constant per-atom weights w_i (the ACE weight 1 - lambda_i of Eq. (4); NULL = 1):
+ *   E = sum_i w_i E^ACE_i,  F_k = -dE/dr_k,  L = sum_k G_k . F_k
+ *   dL/dc_nu = -sum_i w_i Bdot_i,nu,  dL/db_n = -sum_i w_i ddb_i,n
+ * with the tangents of ace_site_tangent for the motion r_k -> r_k + t G_k, i.e. udot_ij = G_j - G_i
+ * (d/dc of F = -grad E is minus the gradient of dE/dc = sum_i w_i B_i). G is AoS [n][3]. */
+int ora_ace_force_vjp(int n, const double *pos_in, const double *L, int n_max, int l_max, double rc, int n_funcs,
+                      const int *func, const double *c, const double *b_dens, double emb_A, const double *weight,
+                      const double *G, double *dLdc, double *dLdb) {
+    int rcode = check_box(L, rc);
+    if (rcode) return rcode;
+    double *pos = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    memcpy(pos, pos_in, sizeof(double) * 3 * (size_t)n);
+    ora_wrap(n, pos, L);
+    csr_t nb;
+    build_csr(n, pos, L, rc, &nb);
+    ace_t ace = {n_max, l_max, n_funcs, rc, func, c, b_dens, emb_A, 0.0, NULL};
+    ace_build_3j(&ace);
+    double *acc = (double *)calloc((size_t)n * (n_funcs + n_max), sizeof(double));
+#pragma omp parallel
+    {
+        double *u = (double *)malloc(sizeof(double) * 3 * 4096);
+        double *ud = (double *)malloc(sizeof(double) * 3 * 4096);
+#pragma omp for schedule(dynamic, 4)
+        for (int i = 0; i < n; i++) {
+            int nn = nb.start[i + 1] - nb.start[i];
+            if (nn > 4096) nn = 4096; /* cannot happen below rc = L/2 for condensed matter */
+            for (int q = 0; q < nn; q++) {
+                int j = nb.idx[nb.start[i] + q];
+                mic(pos, L, i, j, u + 3 * q);
+                for (int a = 0; a < 3; a++) ud[3 * q + a] = G[3 * j + a] - G[3 * i + a];
+            }
+            double *row = acc + (size_t)i * (n_funcs + n_max);
+            ace_site_tangent(&ace, nn, u, ud, row, row + n_funcs);
+        }
+        free(u);
+        free(ud);
+    }
+    for (int f = 0; f < n_funcs + n_max; f++) {
+        double s = 0.0;
+        for (int i = 0; i < n; i++) s -= (weight ? weight[i] : 1.0) * acc[(size_t)i * (n_funcs + n_max) + f];
+        if (f < n_funcs)
+            dLdc[f] = s;
+        else
+            dLdb[f - n_funcs] = s;
     }
     free(acc);
     free(ace.w3j);

@@ -84,6 +84,8 @@ def bind(path):
                          i, _dp]
     L.ora_vv.restype = i
     L.ora_vv_full.argtypes = L.ora_vv.argtypes + [i, C.c_void_p]
+    L.ora_ace_force_vjp.argtypes = [i, _dp, _dp, i, i, d, i, _ip, _dp, _dp, d, C.c_void_p, _dp, _dp, _dp]
+    L.ora_ace_force_vjp.restype = i
     L.ora_vv_full.restype = i
     return L
 
@@ -246,6 +248,18 @@ def ace_coeff_grad(pos, box, ace, weight=None):
     _chk(lib().ora_ace_coeff_grad(n, _f64(pos), _f64(box), *a[:8], w.ctypes.data if w is not None else None,
                                   dEdc, dEdb, Ea), "ora_ace_coeff_grad")
     return dEdc, dEdb, Ea
+
+
+def ace_force_vjp(pos, box, ace, G, weight=None):
+    """dL/dc [n_funcs] and dL/db [n_max] of L = sum_k G_k . F_k, F = -grad sum_i w_i E^ACE_i (G (n, 3))."""
+    n = len(pos)
+    dLdc = np.zeros(len(ace["func"]))
+    dLdb = np.zeros(int(ace["n_max"]))
+    a = _ace_args(ace)
+    w = None if weight is None else _f64(weight)
+    _chk(lib().ora_ace_force_vjp(n, _f64(pos), _f64(box), *a[:8], w.ctypes.data if w is not None else None,
+                                 _f64(G).reshape(-1), dLdc, dLdb), "ora_ace_force_vjp")
+    return dLdc, dLdb
 
 
 def velocity_verlet(sys, n_steps, pos=None, vel=None, csp=None, lam_mode=-1, dt=None, force_mix=0, lam_fix=None):

@@ -236,3 +236,56 @@ def test_constant_lambda_everywhere_is_a_pure_model(oracle, sysd):
     assert np.array_equal(eam["F"], oracle.evaluate(sysd, lam_mode=1)["F"])
     assert np.array_equal(ace["F"], oracle.evaluate(sysd, lam_mode=0)["F"])
     assert np.abs(eam["fam"][2:]).max() == 0 and np.abs(ace["fam"][2:]).max() == 0
+
+
+# ---------------------------------------------------------------------------------------------------
+# Vector-Jacobian product of the ACE forces with respect to the coefficients
+# ---------------------------------------------------------------------------------------------------
+def _vjp_case(oracle):
+    from tests.helpers import small_ace
+    s = small_system(nc=4, sigma=0.12, seed=2)
+    s["ace"] = small_ace(4, 2, seed=5, scale=0.05)
+    G = np.random.default_rng(9).normal(size=s["pos"].shape)
+    return s, G
+
+
+def test_force_vjp_is_directional_derivative_of_dEdc(oracle):
+    """dL/dc = -D_G (sum_i B_i): central differences of the oracle's dE/dc along the displacement G."""
+    s, G = _vjp_case(oracle)
+    dLdc, _ = oracle.ace_force_vjp(s["pos"], s["box"], s["ace"], G)
+    h = 1e-5
+    c1, _, _ = oracle.ace_coeff_grad(s["pos"] + h * G, s["box"], s["ace"])
+    c2, _, _ = oracle.ace_coeff_grad(s["pos"] - h * G, s["box"], s["ace"])
+    fd = -(c1 - c2) / (2 * h)
+    assert np.abs(dLdc - fd).max() < 1e-6 * np.abs(fd).max()
+
+
+def test_force_vjp_equals_forces_of_unit_coefficients(oracle):
+    """F is linear in c: dL/dc_nu = sum_k G_k . F_k with c = e_nu and no embedding, from the oracle's
+    pinned pure-ACE forces."""
+    s, G = _vjp_case(oracle)
+    dLdc, _ = oracle.ace_force_vjp(s["pos"], s["box"], s["ace"], G)
+    nf = len(s["ace"]["c"])
+    for nu in [0, 2, nf // 3, nf // 2, nf - 1]:
+        c = np.zeros(nf)
+        c[nu] = 1.0
+        ace = dict(s["ace"], c=c, b_dens=np.zeros(s["ace"]["n_max"]), emb_A=0.0, E0=0.0)
+        F = oracle.evaluate(dict(s, ace=ace), lam_mode=0)["F"]
+        assert dLdc[nu] == pytest.approx(float((G * F).sum()), rel=1e-10, abs=1e-12)
+
+
+def test_force_vjp_density_coefficients_by_finite_differences(oracle):
+    s, G = _vjp_case(oracle)
+    w = np.random.default_rng(4).uniform(0.2, 1.0, len(s["pos"]))
+    _, dLdb = oracle.ace_force_vjp(s["pos"], s["box"], s["ace"], G)
+    _, dLdb_w = oracle.ace_force_vjp(s["pos"], s["box"], s["ace"], G, weight=w)
+    h = 1e-6
+    for n in range(s["ace"]["n_max"]):
+        b1, b2 = s["ace"]["b_dens"].copy(), s["ace"]["b_dens"].copy()
+        b1[n] += h
+        b2[n] -= h
+        L1 = (G * oracle.evaluate(dict(s, ace=dict(s["ace"], b_dens=b1)), lam_mode=0)["F"]).sum()
+        L2 = (G * oracle.evaluate(dict(s, ace=dict(s["ace"], b_dens=b2)), lam_mode=0)["F"]).sum()
+        assert dLdb[n] == pytest.approx((L1 - L2) / (2 * h), rel=1e-6, abs=1e-8)
+    # constant weights: every atom's share scales by its weight, so the weighted sum differs
+    assert np.abs(dLdb_w - dLdb).max() > 1e-6 * np.abs(dLdb).max()
