@@ -126,6 +126,12 @@ const char *ap_last_error(const ap_ctx *ctx);
  * real-harmonic ACE form are derived here). Must precede every evaluation. */
 int ap_set_potential(ap_ctx *ctx, const ap_eam_params *eam, const ap_ace_params *ace, const ap_switch_params *sw);
 
+/* New ACE coefficients without rebuilding the tables: coeffs (device [n_funcs], the rows of the installed
+ * ap_ace_params.func) and b_dens (device [n_max]), each optional (NULL keeps the installed values). The
+ * result equals ap_set_potential with the same basis and the new values (for fitting loops: no host round
+ * trip). AP_E_ARG when the installed basis repeats a row; AP_E_STATE before ap_set_potential. */
+int ap_set_ace_coefficients(ap_ctx *ctx, const double *coeffs, const double *b_dens);
+
 /* One-time detection of the CSP opposite-neighbour pairs, (B3): for every atom the n_csp
  * nearest neighbours by (|u|^2, index) are paired greedily by the smallest |u_a + u_b|^2 (ties:
  * smaller lower index, then smaller higher index); pairs are written in choice order with the
@@ -194,6 +200,17 @@ int ap_ace_eval(ap_ctx *ctx, int n, const double *pos, const int32_t *species, c
  * where nu indexes the rows of ap_ace_params.func. The coefficients are those of ap_set_potential. */
 int ap_ace_batch_eval(ap_ctx *ctx, int n_struct, const int32_t *offsets, const double *boxes, const double *pos,
                       const double *weight, double *E_struct, double *F, double *dEdc, double *dEdb);
+
+/* Vector-Jacobian product of the batch forces with respect to the ACE coefficients (fitting to forces).
+ * With the batch, weights and F of ap_ace_batch_eval and an upstream gradient G (device [3][n], one
+ * vector per atom), L = sum_k G_k . F_k and, per structure s (its own atoms; the cells are independent):
+ *   dLdc[s][nu] = dL/dc_nu = -sum_{i in s} w_i Bdot_i,nu                   device [n_struct][n_funcs] (opt.)
+ *   dLdb[s][n]  = dL/db_n  = -sum_{i in s} w_i d/dt [xi'(phi2_i) sqrt(4 pi) A_i,n00]  device [n_struct][n_max]
+ * where d/dt, written Bdot, is the derivative along the motion r_k -> r_k + t G_k of the atoms (each
+ * neighbour vector u_ij moves with G_j - G_i): F is linear in c, and d/dc of F = -grad E is minus the
+ * gradient of dE/dc = sum_i w_i B_i. The coefficients are those of ap_set_potential. */
+int ap_ace_batch_force_vjp(ap_ctx *ctx, int n_struct, const int32_t *offsets, const double *boxes, const double *pos,
+                           const double *weight, const double *G, double *dLdc, double *dLdb);
 
 /* The adaptive-precision evaluation: Eq. (4) energies and the conservative force Eq. (5).
  * E_tot [1], E_atom [n], F [3][n], virial9 [9], lambda_out [n]: device, each optional. */

@@ -23,7 +23,8 @@ SYMBOLS = ["ap_ctx_create", "ap_ctx_destroy", "ap_last_error", "ap_set_potential
            "ap_set_csp_list", "ap_nblist_build", "ap_eam_eval", "ap_switch_eval", "ap_ace_eval",
            "ap_mixed_energy_forces", "ap_vv_step", "ap_set_profiling", "ap_get_profile", "ap_ace_cost",
            "ap_ace_batch_eval", "ap_set_mlp", "ap_mlp_features", "ap_mlp_eval", "ap_mlp_loss_grad",
-           "ap_mlp_train", "ap_nblist_build_noalloc", "ap_set_lambda_fixed"]
+           "ap_mlp_train", "ap_nblist_build_noalloc", "ap_set_lambda_fixed", "ap_ace_batch_force_vjp",
+           "ap_set_ace_coefficients"]
 MLP_NQ, MLP_NPARAMS = 16, 5345
 
 
@@ -92,6 +93,9 @@ def lib():
         L.ap_mlp_train.argtypes = [vp, i, vp, vp, i, i, d, i, vp, C.POINTER(C.c_double)]
         L.ap_nblist_build_noalloc.argtypes = [i, vp, C.POINTER(Box), d, i, vp, vp, vp]
         L.ap_set_lambda_fixed.argtypes = [vp, i, vp]
+        L.ap_set_ace_coefficients.argtypes = [vp, vp, vp]
+        L.ap_ace_batch_force_vjp.argtypes = [vp, i, C.POINTER(C.c_int32), C.POINTER(C.c_double), vp, vp, vp, vp,
+                                             vp]
         for s in SYMBOLS:
             if s not in ("ap_ctx_destroy", "ap_last_error"):
                 getattr(L, s).restype = i
@@ -183,6 +187,14 @@ class Context:
         self._chk(lib().ap_set_potential(self.h, C.byref(e), C.byref(a), C.byref(s)))
         self._nf, self._nm = len(func), int(ace["n_max"])
 
+    def set_ace_coefficients(self, coeffs=None, b_dens=None):
+        """New linear / density coefficients (float64 CUDA tensors) into the installed ACE tables."""
+        if coeffs is not None:
+            _dev(coeffs, torch.float64, (self._nf,))
+        if b_dens is not None:
+            _dev(b_dens, torch.float64, (self._nm,))
+        self._chk(lib().ap_set_ace_coefficients(self.h, _ptr(coeffs), _ptr(b_dens)))
+
     def set_lambda_fixed(self, lam_fix):
         """Constant switching parameters: int32 CUDA tensor (n,) of -1 (computed), 0 or 1; None removes."""
         if lam_fix is None:
@@ -265,6 +277,23 @@ class Context:
                                           bx.ctypes.data_as(C.POINTER(C.c_double)), _ptr(pos), _ptr(weight),
                                           _ptr(E), _ptr(F), _ptr(dc), _ptr(db)))
         return dict(E=E, F=F, dEdc=dc, dEdb=db)
+
+    def ace_batch_force_vjp(self, pos, offsets, boxes, G, weight=None):
+        """dL/dc (n_struct, n_funcs) and dL/db (n_struct, n_max) of L = sum_k G_k . F_k over the batch of
+        ace_batch_eval; G: float64 CUDA tensor (3, n)."""
+        off = np.ascontiguousarray(offsets, dtype=np.int32)
+        bx = np.ascontiguousarray(boxes, dtype=np.float64).reshape(-1, 3)
+        ns, n = len(off) - 1, int(off[-1])
+        _dev(pos, torch.float64, (3, n))
+        _dev(G, torch.float64, (3, n))
+        if weight is not None:
+            _dev(weight, torch.float64, (n,))
+        dc = self._zeros(ns, self._nf)
+        db = self._zeros(ns, self._nm)
+        self._chk(lib().ap_ace_batch_force_vjp(self.h, ns, off.ctypes.data_as(C.POINTER(C.c_int32)),
+                                               bx.ctypes.data_as(C.POINTER(C.c_double)), _ptr(pos), _ptr(weight),
+                                               _ptr(G), _ptr(dc), _ptr(db)))
+        return dc, db
 
     # ---- learned indicator ----
     def set_mlp(self, params, rc=5.5):

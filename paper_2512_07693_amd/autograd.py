@@ -5,6 +5,8 @@ positions (3, n) and the linear ACE coefficients c (n_funcs,) returns the per-st
 E_s = sum_{i in s} E^p_i. The backward pass uses the library's hand-written adjoint:
   dL/dpos_i = g_{s(i)} * dE_{s(i)}/dpos_i = -g_{s(i)} F_i   (cells are independent)
   dL/dc     = sum_s g_s dE_s/dc,   dE_s/dc_nu = sum_{i in s} B_i,nu
+ACEBatch.forces(positions, c) returns the forces (3, n); its backward pass is the vector-Jacobian product
+of the forces with respect to c (ap_ace_batch_force_vjp), for fitting coefficients to forces.
 Everything runs in the HIP kernels; torch only holds the tensors.
 """
 import numpy as np
@@ -35,6 +37,26 @@ class _ACEEnergyFn(torch.autograd.Function):
         return gpos, gc, None
 
 
+class _ACEForceFn(torch.autograd.Function):
+    """Forces of the batch as a function of the coefficients, for fitting to forces: the backward pass is the
+    library's vector-Jacobian product dL/dc = sum_k G_k . dF_k/dc (positions are data here: no gradient)."""
+
+    @staticmethod
+    def forward(fctx, pos, coeffs, batch):
+        batch._load(coeffs)
+        out = batch.ctx.ace_batch_eval(pos.detach().contiguous(), batch.offsets, batch.boxes, forces=True,
+                                       coeff_grad=False)
+        fctx.pos = pos.detach().contiguous()
+        fctx.batch = batch
+        return out["F"]
+
+    @staticmethod
+    def backward(fctx, gF):
+        dc, _ = fctx.batch.ctx.ace_batch_force_vjp(fctx.pos, fctx.batch.offsets, fctx.batch.boxes,
+                                                   gF.contiguous().double())
+        return None, dc.sum(0), None
+
+
 class ACEBatch:
     """A ragged batch of periodic cells bound to one library context with an ACE potential."""
 
@@ -52,10 +74,17 @@ class ACEBatch:
         self._loaded = None
 
     def _load(self, coeffs):
-        c = coeffs.detach().double().cpu().numpy()
-        if self._loaded is None or not np.array_equal(c, self._loaded):
+        if self._loaded is None:
+            # the tables (couplings, block layout) once; later coefficients go straight into them on the device
+            c = coeffs.detach().double().cpu().numpy()
             self.ctx.set_potential(self.eam, dict(self.ace, c=c), self.sw, lambda_mode=ap.AP_LAMBDA_PRECISE)
-            self._loaded = c.copy()
+            self._loaded = True
+        else:
+            self.ctx.set_ace_coefficients(coeffs.detach().to(self.ctx.device, torch.float64).contiguous())
 
     def __call__(self, pos, coeffs):
         return _ACEEnergyFn.apply(pos, coeffs, self)
+
+    def forces(self, pos, coeffs):
+        """Forces (3, n) of the batch, differentiable with respect to the coefficients."""
+        return _ACEForceFn.apply(pos, coeffs, self)

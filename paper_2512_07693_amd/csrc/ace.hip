@@ -789,6 +789,251 @@ __global__ __launch_bounds__(128) void k_ace_pairforce(AceArgs a) {
 }
 
 // ---------------------------------------------------------------------------------------------
+// Vector-Jacobian product of the forces with respect to the coefficients: for L = sum_k G_k . F_k,
+// dL/dc_nu = -sum_i w_i Bdot_i,nu, where Bdot is the derivative of B_i along the motion r_k -> r_k + t G_k
+// (each neighbour vector u_ij moves with G_j - G_i), and dL/db_n the same for xi'(phi2) sqrt(4 pi) A_n00.
+// ---------------------------------------------------------------------------------------------
+// Per atom: Adot[n][lm] = sum_j [g_n'(r) (uhat . t) Y_lm + g_n(r) (grad_u Y_lm . t)], t = G_j - G_i, into
+// a.gpart (row s). One lane per neighbour inside rc evaluates its radial channels and, order by order, the
+// harmonics and their derivative along t into LDS; the workgroup then sums over the chunk's neighbours.
+template <typename T, int NMAX, int LMAX>
+__global__ __launch_bounds__(kBlock) void k_ace_tangent(AceArgs a, const double *__restrict__ G) {
+    // neighbours per chunk: 64 in FP32, 32 in FP64 (the chunk's tables stay under 64 KB of LDS)
+    constexpr int NLM = (LMAX + 1) * (LMAX + 1), NA = NMAX * NLM, CH = sizeof(T) == 4 ? 64 : 32;
+    __shared__ T sR0[CH * NMAX], sR1[CH * NMAX], sY[CH * NLM], sYd[CH * NLM];
+    __shared__ T sAd[NA];
+    __shared__ int sJ[kAceMaxValid];
+    __shared__ int sCnt[5];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int n = a.n;
+    const int S = *a.scount;
+    const double rc2 = a.rc * a.rc;
+    const T rcT = (T)a.rc;
+    for (int s = blockIdx.x; s < S; s += gridDim.x) {
+        const int i = a.slist[s];
+        const double xi = a.pos[i], yi = a.pos[n + i], zi = a.pos[2 * n + i];
+        double Lx, Ly, Lz;
+        atom_box(a, i, Lx, Ly, Lz);
+        const int cnt = a.ncount[i];
+        if (tid == 0) sCnt[4] = 0;
+        for (int o = tid; o < NA; o += kBlock) sAd[o] = T(0);
+        __syncthreads();
+        // neighbours inside rc, compacted in list order
+        for (int base = 0; base < cnt; base += kBlock) {
+            const int slot = base + tid;
+            bool valid = false;
+            int j = 0;
+            if (slot < cnt) {
+                j = a.nidx[(size_t)slot * n + i];
+                const Rec4 pj = a.xl[j];
+                const double ux = min_image_w(pj.x - xi, Lx), uy = min_image_w(pj.y - yi, Ly),
+                             uz = min_image_w(pj.z - zi, Lz);
+                valid = ux * ux + uy * uy + uz * uz < rc2;
+            }
+            const unsigned long long m = __ballot(valid);
+            if (lane == 0) sCnt[wv] = __popcll(m);
+            __syncthreads();
+            int off = sCnt[4];
+            for (int q = 0; q < wv; q++) off += sCnt[q];
+            const int p = off + __popcll(m & ((1ull << lane) - 1ull));
+            if (valid) {
+                if (p < kAceMaxValid)
+                    sJ[p] = j;
+                else
+                    atomicOr(&a.flags[1], kErrAceNbr);
+            }
+            __syncthreads();
+            if (tid == 0) sCnt[4] += sCnt[0] + sCnt[1] + sCnt[2] + sCnt[3];
+            __syncthreads();
+        }
+        const int nv = min(sCnt[4], kAceMaxValid);
+        const double gxi = G[i], gyi = G[n + i], gzi = G[2 * n + i];
+        for (int v0 = 0; v0 < nv; v0 += CH) {
+            const int nc = min(CH, nv - v0);
+            if (wv == 0 && lane < nc) {
+                const int j = sJ[v0 + lane];
+                const Rec4 pj = a.xl[j];
+                const double ux = min_image_w(pj.x - xi, Lx), uy = min_image_w(pj.y - yi, Ly),
+                             uz = min_image_w(pj.z - zi, Lz);
+                const double rd = sqrt(ux * ux + uy * uy + uz * uz);
+                const T r = (T)rd, ir = (T)(1.0 / rd);
+                const T x = (T)ux * ir, y = (T)uy * ir, z = (T)uz * ir;
+                const T tx = (T)(G[j] - gxi), ty = (T)(G[n + j] - gyi), tz = (T)(G[2 * n + j] - gzi);
+                const T rdot = x * tx + y * ty + z * tz;  // d|u|/dt
+                T g[NMAX], dg[NMAX];
+                radial<T, NMAX>(r, rcT, g, dg);
+#pragma unroll
+                for (int q = 0; q < NMAX; q++) {
+                    sR0[lane * NMAX + q] = g[q];
+                    sR1[lane * NMAX + q] = dg[q] * rdot;
+                }
+                // harmonics order by order (the recurrences of ylm_real_grad): value, and grad_u Y . t =
+                // (grad_p . t - (grad_p . uhat)(uhat . t)) / r for the polynomial p
+                auto put = [&](int lm, T val, T px, T py, T pz) {
+                    const T rad = px * x + py * y + pz * z;
+                    sY[lane * NLM + lm] = val;
+                    sYd[lane * NLM + lm] = (px * tx + py * ty + pz * tz - rad * rdot) * ir;
+                };
+                const T r2c = T(1.4142135623730951);
+                T cp = T(1), sp = T(0), cm = T(1), sm = T(0), dfm = T(1);
+#pragma unroll
+                for (int mm = 0; mm <= LMAX; mm++) {
+                    if (mm > 0) {
+                        cp = cm;
+                        sp = sm;
+                        const T c2 = x * cm - y * sm;
+                        sm = x * sm + y * cm;
+                        cm = c2;
+                        dfm *= T(2 * mm - 1);
+                    }
+                    T q1 = T(0), q2 = T(0), d1 = T(0), d2 = T(0);
+#pragma unroll
+                    for (int l = 0; l <= LMAX; l++) {
+                        if (l < mm) continue;
+                        T q, dq;
+                        if (l == mm) {
+                            q = dfm;
+                            dq = T(0);
+                        } else if (l == mm + 1) {
+                            q = T(2 * mm + 1) * z * q1;
+                            dq = T(2 * mm + 1) * q1;
+                        } else {
+                            const T inv = T(1) / T(l - mm);
+                            q = (T(2 * l - 1) * z * q1 - T(l + mm - 1) * q2) * inv;
+                            dq = (T(2 * l - 1) * (q1 + z * d1) - T(l + mm - 1) * d2) * inv;
+                        }
+                        q2 = q1;
+                        q1 = q;
+                        d2 = d1;
+                        d1 = dq;
+                        if (mm == 0) {
+                            const T k = klm<T>(l, 0);
+                            put(l * l + l, k * q, T(0), T(0), k * dq);
+                        } else {
+                            const T k = r2c * klm<T>(l, mm), kq = k * q, kd = k * dq, fm = T(mm);
+                            put(l * l + l + mm, kq * cm, kq * fm * cp, -kq * fm * sp, kd * cm);
+                            put(l * l + l - mm, kq * sm, kq * fm * sp, kq * fm * cp, kd * sm);
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            for (int o = tid; o < NA; o += kBlock) {
+                const int q = o / NLM, lm = o - q * NLM;
+                T acc = sAd[o];
+                for (int v = 0; v < nc; v++)
+                    acc += sR1[v * NMAX + q] * sY[v * NLM + lm] + sR0[v * NMAX + q] * sYd[v * NLM + lm];
+                sAd[o] = acc;
+            }
+            __syncthreads();
+        }
+        T *out = (T *)a.gpart + (size_t)s * NA;
+        for (int o = tid; o < NA; o += kBlock) out[o] = sAd[o];
+        __syncthreads();
+    }
+}
+
+// Per atom: Bdot of every basis function from A (a.gbuf) and Adot (a.gpart), written with the density
+// tangents into a.bval: orders 1 and 2 directly, order 3 per coupling block from P_M and its tangent
+// Pdot_M = sum kappa (Adot1 A2 + A1 Adot2): Bdot = sum_M Pdot_M[n1 n2] A[n3][L M] + P_M[n1 n2] Adot[n3][L M].
+template <typename T, int NMAX, int LMAX>
+__global__ __launch_bounds__(kBlock) void k_ace_bdot(AceArgs a) {
+    constexpr int NLM = (LMAX + 1) * (LMAX + 1), NA = NMAX * NLM, NN = NMAX * NMAX, MM = 2 * LMAX + 1;
+    __shared__ T sA[NA], sAt[NA], sAd[NA], sAdt[NA];
+    __shared__ T sP[MM * NN], sPd[MM * NN];
+    __shared__ T skv[kKapStage];
+    __shared__ int skc[kKapStage];
+    const int tid = threadIdx.x;
+    const int S = *a.scount;
+    const T *kval = (const T *)a.kval;
+    const double s4pi = 3.5449077018110318;  // sqrt(4 pi)
+    for (int s = blockIdx.x; s < S; s += gridDim.x) {
+        const T *ain = (const T *)a.gbuf + (size_t)s * NA;
+        const T *adin = (const T *)a.gpart + (size_t)s * NA;
+        for (int o = tid; o < NA; o += kBlock) {
+            const int q = o / NLM, lm = o - q * NLM;
+            const T v = ain[o], vd = adin[o];
+            sA[o] = v;
+            sAt[lm * NMAX + q] = v;
+            sAd[o] = vd;
+            sAdt[lm * NMAX + q] = vd;
+        }
+        __syncthreads();
+        T *bout = (T *)a.bval + (size_t)s * a.bstride;
+        for (int q = tid; q < a.ng1; q += kBlock) bout[a.g1[2 * q + 1]] = sAd[a.g1[2 * q] * NLM];
+        for (int q = tid; q < a.ng2; q += kBlock) {
+            const int code = a.g2[2 * q];
+            const int q1 = code & 255, q2 = (code >> 8) & 255, l = code >> 16;
+            T bsum = T(0);
+            for (int m = l * l; m <= l * l + 2 * l; m++)
+                bsum += sAd[q1 * NLM + m] * sA[q2 * NLM + m] + sA[q1 * NLM + m] * sAd[q2 * NLM + m];
+            bout[a.g2[2 * q + 1]] = bsum;
+        }
+        if (tid == 0) {
+            // the density term's tangent (the l = 0 radial sums in FP64): s_n = sqrt(4 pi) A_n00
+            const double *s0 = a.s0buf + (size_t)s * NMAX;
+            double phi2 = 0.0, phi2d = 0.0;
+            for (int q = 0; q < NMAX; q++) {
+                phi2 += a.bdd[q] * s0[q];
+                phi2d += a.bdd[q] * s4pi * (double)sAd[q * NLM];
+            }
+            double d1 = 0.0, d2 = 0.0;
+            if (phi2 > 0.0) {
+                d1 = -0.5 * a.emb_A / sqrt(phi2);
+                d2 = 0.25 * a.emb_A / (phi2 * sqrt(phi2));
+            }
+            for (int q = 0; q < NMAX; q++)
+                bout[a.n_funcs + q] = (T)(d2 * phi2d * s0[q] + d1 * s4pi * (double)sAd[q * NLM]);
+        }
+        for (int b = 0; b < a.nblk; b++) {
+            const int *bk = a.blk + b * kBlkInts;
+            const int L = bk[0];
+            const int nM = 2 * L + 1, bL = L * L + L;
+            const int k0 = bk[4], k1 = bk[4 + nM];
+            __syncthreads();
+            for (int q = k0 + tid; q < k1; q += kBlock) {
+                skc[q - k0] = a.kidx[q];
+                skv[q - k0] = kval[q];
+            }
+            __syncthreads();
+            for (int w = tid; w < nM * NMAX; w += kBlock) {
+                const int Mi = w / NMAX, n1 = w - Mi * NMAX;
+                T P[NMAX], Pd[NMAX];
+#pragma unroll
+                for (int q = 0; q < NMAX; q++) P[q] = Pd[q] = T(0);
+                const int e0 = bk[4 + Mi] - k0, e1 = bk[4 + Mi + 1] - k0;
+                for (int q = e0; q < e1; q++) {
+                    const int code = skc[q];
+                    const T kv = skv[q];
+                    const T a1 = kv * sA[n1 * NLM + (code & 255)], ad1 = kv * sAd[n1 * NLM + (code & 255)];
+                    const T *a2 = sAt + 4 * (code >> 8), *ad2 = sAdt + 4 * (code >> 8);
+#pragma unroll
+                    for (int q2 = 0; q2 < NMAX; q2++) {
+                        P[q2] += a1 * a2[q2];
+                        Pd[q2] += ad1 * a2[q2] + a1 * ad2[q2];
+                    }
+                }
+#pragma unroll
+                for (int q2 = 0; q2 < NMAX; q2++) {
+                    sP[Mi * NN + n1 * NMAX + q2] = P[q2];
+                    sPd[Mi * NN + n1 * NMAX + q2] = Pd[q2];
+                }
+            }
+            __syncthreads();
+            for (int q = bk[46] + tid; q < bk[47]; q += kBlock) {
+                const int code = a.g3[2 * q];
+                const int rem = code & 0xffff, q3 = code >> 16;
+                T bsum = T(0);
+                for (int Mi = 0; Mi < nM; Mi++)
+                    bsum += sPd[Mi * NN + rem] * sA[q3 * NLM + bL + Mi - L] + sP[Mi * NN + rem] * sAd[q3 * NLM + bL + Mi - L];
+                bout[a.g3[2 * q + 1]] = bsum;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
 // Host: tables
 // ---------------------------------------------------------------------------------------------
 static double w3j000(int l1, int l2, int l3) {
@@ -895,7 +1140,61 @@ void ace_free(ap_ctx *c) {
     (void)hipFree(t.blk);
     (void)hipFree(t.c30);
     (void)hipFree(t.kap0);
+    (void)hipFree(t.cmap_f);
+    (void)hipFree(t.cmap_w);
     t = AceTables();
+}
+
+// New coefficients into the installed tables (ap_set_ace_coefficients): every table element takes factor x
+// c[function] from its gather map, in the precision of the tables; the density coefficients likewise.
+template <typename T>
+__global__ void k_coeff_gather(const int *__restrict__ fm, const double *__restrict__ wm, const double *__restrict__ cf,
+                               int nmap, int n1, int n2, int n3, T *c1, double *c1d, T *c2, T *c3, T *c30) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nmap) return;
+    const int f = fm[e];
+    const double v = f >= 0 ? wm[e] * cf[f] : 0.0;
+    if (e < n1) {
+        c1[e] = (T)v;
+        c1d[e] = v;
+    } else if (e < n1 + n2) {
+        c2[e - n1] = (T)v;
+    } else if (e < n1 + n2 + n3) {
+        c3[e - n1 - n2] = (T)v;
+    } else {
+        c30[e - n1 - n2 - n3] = (T)v;
+    }
+}
+
+template <typename T>
+__global__ void k_dens_gather(const double *__restrict__ b, int n, T *bd, double *bdd) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    bd[q] = (T)(b[q] * std::sqrt(4 * kPi));
+    bdd[q] = b[q];
+}
+
+int ace_set_coefficients(ap_ctx *c, const double *cf, const double *b) {
+    AceTables &t = c->ace;
+    if (cf) {
+        if (t.nmap == 0) return set_error(c, AP_E_ARG, "the installed basis has repeated rows: use ap_set_potential");
+        const int g = (t.nmap + kBlock - 1) / kBlock;
+        if (t.precision == AP_FP32)
+            k_coeff_gather<float><<<g, kBlock, 0, c->stream>>>(t.cmap_f, t.cmap_w, cf, t.nmap, t.n_max, t.n_c2, t.n_c3,
+                                                               (float *)t.c1, t.c1d, (float *)t.c2, (float *)t.c3,
+                                                               (float *)t.c30);
+        else
+            k_coeff_gather<double><<<g, kBlock, 0, c->stream>>>(t.cmap_f, t.cmap_w, cf, t.nmap, t.n_max, t.n_c2,
+                                                                t.n_c3, (double *)t.c1, t.c1d, (double *)t.c2,
+                                                                (double *)t.c3, (double *)t.c30);
+    }
+    if (b) {
+        if (t.precision == AP_FP32)
+            k_dens_gather<float><<<1, kBlock, 0, c->stream>>>(b, t.n_max, (float *)t.bd, t.bdd);
+        else
+            k_dens_gather<double><<<1, kBlock, 0, c->stream>>>(b, t.n_max, (double *)t.bd, t.bdd);
+    }
+    return hip_check(c, hipGetLastError(), "coefficients");
 }
 
 int ace_setup(ap_ctx *c, const ap_ace_params *p) {
@@ -931,6 +1230,12 @@ int ace_setup(ap_ctx *c, const ap_ace_params *p) {
                 }
     std::vector<double> c3(blocks.size() * (size_t)N * N * N, 0.0);
     std::vector<char> used(blocks.size(), 0);
+    // where every coefficient lands (for ap_set_ace_coefficients): per table element the function and its
+    // factor, -1 where none (every element takes at most one function: the basis rows are distinct sorted
+    // (n, l) triples)
+    std::vector<int> f1(N, -1), f2((size_t)(Lm + 1) * N * N, -1), f3(blocks.size() * (size_t)N * N * N, -1);
+    std::vector<double> w2((size_t)(Lm + 1) * N * N, 0.0), w3(blocks.size() * (size_t)N * N * N, 0.0);
+    bool map_ok = true;  // false when two rows land on one element (repeated rows): no device update then
     // gradient lists (function index nu with where its B value lives): order 1 (n, nu),
     // order 2 (n1 | n2 << 8 | l << 16, nu), order 3 per block (n1 * N + n2 | n3 << 16, nu)
     std::vector<int> g1, g2;
@@ -941,6 +1246,8 @@ int ace_setup(ap_ctx *c, const ap_ace_params *p) {
         if (r[2] < 0) {
             if (r[0] < 0 || r[0] >= N || r[1] != 0) return set_error(c, AP_E_ARG, "order-1 basis row");
             c1[r[0]] += cf;
+            if (f1[r[0]] >= 0) map_ok = false;
+            f1[r[0]] = f;
             g1.push_back(r[0]);
             g1.push_back(f);
         } else if (r[4] < 0) {
@@ -949,11 +1256,18 @@ int ace_setup(ap_ctx *c, const ap_ace_params *p) {
                 return set_error(c, AP_E_ARG, "order-2 basis row");
             g2.push_back(n1 | (n2 << 8) | (l << 16));
             g2.push_back(f);
+            if (f2[((size_t)l * N + n1) * N + n2] >= 0) map_ok = false;
             if (n1 == n2) {
                 c2[((size_t)l * N + n1) * N + n2] += cf;
+                f2[((size_t)l * N + n1) * N + n2] = f;
+                w2[((size_t)l * N + n1) * N + n2] = 1.0;
             } else {
                 c2[((size_t)l * N + n1) * N + n2] += 0.5 * cf;
                 c2[((size_t)l * N + n2) * N + n1] += 0.5 * cf;
+                for (const size_t e : {((size_t)l * N + n1) * N + n2, ((size_t)l * N + n2) * N + n1}) {
+                    f2[e] = f;
+                    w2[e] = 0.5;
+                }
             }
         } else {
             int ln[3][2] = {{r[1], r[0]}, {r[3], r[2]}, {r[5], r[4]}};
@@ -970,6 +1284,9 @@ int ace_setup(ap_ctx *c, const ap_ace_params *p) {
             const int bi = bindex[(L * (Lm + 1) + l1) * (Lm + 1) + l2];
             if (bi < 0) return set_error(c, AP_E_ARG, "order-3 row violates the triangle or parity rule");
             c3[(((size_t)bi * N + ln[1][1]) * N + ln[2][1]) * N + ln[0][1]] += cf;
+            if (f3[(((size_t)bi * N + ln[1][1]) * N + ln[2][1]) * N + ln[0][1]] >= 0) map_ok = false;
+            f3[(((size_t)bi * N + ln[1][1]) * N + ln[2][1]) * N + ln[0][1]] = f;
+            w3[(((size_t)bi * N + ln[1][1]) * N + ln[2][1]) * N + ln[0][1]] = 1.0;
             used[bi] = 1;
             g3[bi].push_back((ln[1][1] * N + ln[2][1]) | (ln[0][1] << 16));
             g3[bi].push_back(f);
@@ -984,10 +1301,16 @@ int ace_setup(ap_ctx *c, const ap_ace_params *p) {
         for (int n1 = 0; n1 < N; n1++)
             for (int n2 = n1 + 1; n2 < N; n2++)
                 for (int n3 = 0; n3 < N; n3++) {
+                    const size_t eu = bi * (size_t)N * N * N + ((size_t)n1 * N + n2) * N + n3,
+                                 ev = bi * (size_t)N * N * N + ((size_t)n2 * N + n1) * N + n3;
                     double &u = cb[((size_t)n1 * N + n2) * N + n3], &v = cb[((size_t)n2 * N + n1) * N + n3];
                     const double m = 0.5 * (u + v);
                     u = m;
                     v = m;
+                    // both elements take half of the one function that lands on either
+                    const int fu = f3[eu] >= 0 ? f3[eu] : f3[ev];
+                    f3[eu] = f3[ev] = fu;
+                    w3[eu] = w3[ev] = fu >= 0 ? 0.5 : 0.0;
                 }
     }
     std::vector<int> g3flat;
@@ -997,6 +1320,8 @@ int ace_setup(ap_ctx *c, const ap_ace_params *p) {
     std::vector<double> c30((size_t)(Lm + 1) * N * N * N, 0.0), kap0(Lm + 1, 0.0);
     bool fold0 = true;
     std::vector<double> kval, c3u;
+    std::vector<int> f3u, f30((size_t)(Lm + 1) * N * N * N, -1);
+    std::vector<double> w3u, w30((size_t)(Lm + 1) * N * N * N, 0.0);
     int nb = 0;
     for (size_t bi = 0; bi < blocks.size(); bi++) {
         if (!used[bi]) continue;
@@ -1011,6 +1336,10 @@ int ace_setup(ap_ctx *c, const ap_ace_params *p) {
                 kap0[B.l1] = k[0].v;
                 std::copy(c3.begin() + bi * (size_t)N * N * N, c3.begin() + (bi + 1) * (size_t)N * N * N,
                           c30.begin() + (size_t)B.l1 * N * N * N);
+                std::copy(f3.begin() + bi * (size_t)N * N * N, f3.begin() + (bi + 1) * (size_t)N * N * N,
+                          f30.begin() + (size_t)B.l1 * N * N * N);
+                std::copy(w3.begin() + bi * (size_t)N * N * N, w3.begin() + (bi + 1) * (size_t)N * N * N,
+                          w30.begin() + (size_t)B.l1 * N * N * N);
             } else {
                 fold0 = false;
             }
@@ -1021,6 +1350,8 @@ int ace_setup(ap_ctx *c, const ap_ace_params *p) {
         d[2] = B.l2;
         d[3] = (int)c3u.size();
         c3u.insert(c3u.end(), c3.begin() + bi * (size_t)N * N * N, c3.begin() + (bi + 1) * (size_t)N * N * N);
+        f3u.insert(f3u.end(), f3.begin() + bi * (size_t)N * N * N, f3.begin() + (bi + 1) * (size_t)N * N * N);
+        w3u.insert(w3u.end(), w3.begin() + bi * (size_t)N * N * N, w3.begin() + (bi + 1) * (size_t)N * N * N);
         auto emit = [&](int base, int key_lo, int key_hi, int which) {
             for (int key = key_lo; key <= key_hi; key++) {
                 d[base + key - key_lo] = (int)kidx.size();
@@ -1093,6 +1424,25 @@ int ace_setup(ap_ctx *c, const ap_ace_params *p) {
             if (!rc) rc = upload<double>(c, &t.kap0, kap0);
         }
     }
+    // the gather maps of ap_set_ace_coefficients, in table order: c1, c2, c3 (used blocks), c30 when folded
+    {
+        std::vector<int> fm;
+        std::vector<double> wm;
+        auto add = [&](const std::vector<int> &ff, const std::vector<double> &ww) {
+            fm.insert(fm.end(), ff.begin(), ff.end());
+            wm.insert(wm.end(), ww.begin(), ww.end());
+        };
+        add(f1, std::vector<double>(N, 1.0));
+        add(f2, w2);
+        add(f3u, w3u);
+        if (fold0) add(f30, w30);
+        t.nmap = map_ok ? (int)fm.size() : 0;
+        t.n_c2 = (int)f2.size();
+        t.n_c3 = (int)f3u.size();
+        t.n_c30 = fold0 ? (int)f30.size() : 0;
+        if (!rc) rc = up_int(&t.cmap_f, fm);
+        if (!rc) rc = upload<double>(c, (void **)&t.cmap_w, wm);
+    }
     if (!rc) rc = upload<double>(c, (void **)&t.c1d, c1);
     if (!rc) rc = upload<double>(c, (void **)&t.bdd, std::vector<double>(p->b_dens, p->b_dens + N));
     if (rc) return rc;
@@ -1159,7 +1509,71 @@ void ace_cost(const ap_ctx *c, double *fixed, double *per_nbr_energy, double *pe
     *per_nbr_force = NLM * (4.0 * N + 12.0) + 6.0 * N + 20.0 * NLM;
 }
 
+static AceArgs ace_args(ap_ctx *c, int n, const double *box, const double *sbox, bool want_bval);
+
+template <typename T, int NMAX, int LMAX>
+static void launch_vjp_t(ap_ctx *c, AceArgs a, int grid, const double *G) {
+    {
+        ProfScope p(c, "ace_basis");
+        k_ace_basis<T, NMAX, LMAX><<<grid, kBlock, 0, c->stream>>>(a);
+    }
+    {
+        ProfScope p(c, "ace_tangent");
+        k_ace_tangent<T, NMAX, LMAX><<<grid, kBlock, 0, c->stream>>>(a, G);
+    }
+    ProfScope p(c, "ace_bdot");
+    k_ace_bdot<T, NMAX, LMAX><<<grid, kBlock, 0, c->stream>>>(a);
+}
+
+int launch_ace_vjp(ap_ctx *c, int n, const double *box, int grid_cap, const double *sbox, const double *G) {
+    const AceTables &t = c->ace;
+    AceArgs a = ace_args(c, n, box, sbox, true);
+    const int grid = grid_cap < 1 ? 1 : grid_cap;
+    const bool f32 = t.precision == AP_FP32;
+    if (t.n_max == 12) {
+        if (f32)
+            launch_vjp_t<float, 12, 6>(c, a, grid, G);
+        else
+            launch_vjp_t<double, 12, 6>(c, a, grid, G);
+    } else if (t.n_max == 8) {
+        if (f32)
+            launch_vjp_t<float, 8, 4>(c, a, grid, G);
+        else
+            launch_vjp_t<double, 8, 4>(c, a, grid, G);
+    } else {
+        if (f32)
+            launch_vjp_t<float, 4, 2>(c, a, grid, G);
+        else
+            launch_vjp_t<double, 4, 2>(c, a, grid, G);
+    }
+    return hip_check(c, hipGetLastError(), "ace vjp");
+}
+
 int launch_ace(ap_ctx *c, int n, const double *box, int grid_cap, const double *sbox, bool want_bval) {
+    const AceTables &t = c->ace;
+    AceArgs a = ace_args(c, n, box, sbox, want_bval);
+    const int grid = grid_cap < 1 ? 1 : grid_cap;
+    const bool f32 = t.precision == AP_FP32;
+    if (t.n_max == 12) {
+        if (f32)
+            launch_t<float, 12, 6>(c, a, grid);
+        else
+            launch_t<double, 12, 6>(c, a, grid);
+    } else if (t.n_max == 8) {
+        if (f32)
+            launch_t<float, 8, 4>(c, a, grid);
+        else
+            launch_t<double, 8, 4>(c, a, grid);
+    } else {
+        if (f32)
+            launch_t<float, 4, 2>(c, a, grid);
+        else
+            launch_t<double, 4, 2>(c, a, grid);
+    }
+    return hip_check(c, hipGetLastError(), "ace");
+}
+
+static AceArgs ace_args(ap_ctx *c, int n, const double *box, const double *sbox, bool want_bval) {
     const AceTables &t = c->ace;
     AceArgs a;
     a.pos = c->pos;
@@ -1227,25 +1641,7 @@ int launch_ace(ap_ctx *c, int n, const double *box, int grid_cap, const double *
     a.g3 = t.g3;
     a.ng1 = t.ng1;
     a.ng2 = t.ng2;
-    const int grid = grid_cap < 1 ? 1 : grid_cap;
-    const bool f32 = t.precision == AP_FP32;
-    if (t.n_max == 12) {
-        if (f32)
-            launch_t<float, 12, 6>(c, a, grid);
-        else
-            launch_t<double, 12, 6>(c, a, grid);
-    } else if (t.n_max == 8) {
-        if (f32)
-            launch_t<float, 8, 4>(c, a, grid);
-        else
-            launch_t<double, 8, 4>(c, a, grid);
-    } else {
-        if (f32)
-            launch_t<float, 4, 2>(c, a, grid);
-        else
-            launch_t<double, 4, 2>(c, a, grid);
-    }
-    return hip_check(c, hipGetLastError(), "ace");
+    return a;
 }
 
 }  // namespace ap

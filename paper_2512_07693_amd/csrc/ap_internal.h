@@ -162,6 +162,11 @@ struct AceTables {
     int *g1 = nullptr, *g2 = nullptr, *g3 = nullptr;  // coefficient-gradient lists (see ace_setup)
     int ng1 = 0, ng2 = 0;
     std::vector<int> h_blk;
+    // gather map of ap_set_ace_coefficients: per element of c1, c2, c3, c30 (in that order) the function
+    // (-1: none) and its factor; nmap = 0 when the basis cannot be updated that way
+    int *cmap_f = nullptr;
+    double *cmap_w = nullptr;
+    int nmap = 0, n_c2 = 0, n_c3 = 0, n_c30 = 0;
 };
 // L, l1, l2, c3 offset, 3 x 14 coupling start offsets (by M, m1, m2), order-3 gradient list range
 constexpr int kBlkInts = 48;
@@ -353,6 +358,11 @@ void ace_free(ap_ctx *c);
 int launch_ace(ap_ctx *c, int n, const double *box, int grid_cap, const double *sbox = nullptr,
                bool want_bval = false);
 void ace_cost(const ap_ctx *c, double *fixed, double *per_nbr_energy, double *per_nbr_force);
+// new linear (device [n_funcs]) and density (device [n_max]) coefficients into the installed tables
+int ace_set_coefficients(ap_ctx *c, const double *cf, const double *b);
+// the atomic basis A, its tangent along the displacement field G (device [3][n]) and the tangents of every
+// basis function and density term, per atom of S into c->bval
+int launch_ace_vjp(ap_ctx *c, int n, const double *box, int grid_cap, const double *sbox, const double *G);
 
 // forces.hip
 struct EvalFlags {
@@ -380,9 +390,10 @@ void launch_W(ap_ctx *c, int n, const double *box, bool stamped, bool csp_marks)
 // indicator an atom neither marked nor flagged active takes the EAM-only gather
 void launch_force(ap_ctx *c, int n, const double *box, const EvalFlags &f, double *E_atom, double *F,
                   const double *sbox = nullptr, bool uniform_lambda = true, bool csp_marked = false);
-// per-structure sums of weight_i x (E^p_i, dE_i/dc, dE_i/db) over a batch (deterministic order)
+// per-structure sums of sign x weight_i x (E^p_i, c->bval rows) over a batch (deterministic order): the
+// coefficient gradients dE_i/dc, dE_i/db, or with sign -1 the force vector-Jacobian product from the tangents
 void launch_struct_reduce(ap_ctx *c, int n, int n_struct, const int *d_off, const double *weight, double *E_struct,
-                          double *dEdc, double *dEdb);
+                          double *dEdc, double *dEdb, double sign = 1.0);
 void launch_reduce(ap_ctx *c, int nblocks, double *E_tot, double *virial9);
 
 int sync_and_check(ap_ctx *c);

@@ -376,6 +376,14 @@ int ap_set_potential(ap_ctx *c, const ap_eam_params *eam, const ap_ace_params *a
     return AP_OK;
 }
 
+int ap_set_ace_coefficients(ap_ctx *c, const double *coeffs, const double *b_dens) {
+    if (!c) return AP_E_ARG;
+    if (!c->have_pot) return set_error(c, AP_E_STATE, "ap_set_potential has not been called");
+    int rc = ace_set_coefficients(c, coeffs, b_dens);
+    if (!rc) rc = sync_and_check(c);
+    return rc;
+}
+
 int ap_csp_pairs_build(ap_ctx *c, int n, const double *pos_ref, const ap_box *box, int n_csp, int32_t *csp_list) {
     int rc = check_common(c, n, pos_ref, box, false);
     if (rc) return rc;
@@ -551,8 +559,10 @@ __global__ void k_batch_fill(int n, const double *weight, const double *pos, dou
     Et[i] = 0.0;
 }
 
-int ap_ace_batch_eval(ap_ctx *c, int n_struct, const int32_t *offsets, const double *boxes, const double *pos,
-                      const double *weight, double *E_struct, double *F, double *dEdc, double *dEdb) {
+// Checks and uploads of a batch of cells, the per-cell lists, the per-atom weights and S = every atom; the
+// per-atom coefficient buffer is sized when want_b. *n_out: the atom count.
+static int batch_prepare(ap_ctx *c, int n_struct, const int32_t *offsets, const double *boxes, const double *pos,
+                         const double *weight, bool want_b, int *n_out) {
     if (!c) return AP_E_ARG;
     if (!c->have_pot) return set_error(c, AP_E_STATE, "ap_set_potential has not been called");
     if (n_struct <= 0 || !offsets || !boxes || !pos) return set_error(c, AP_E_ARG, "batch arguments");
@@ -575,7 +585,6 @@ int ap_ace_batch_eval(ap_ctx *c, int n_struct, const int32_t *offsets, const dou
         if (rc) return rc;
         c->b_cap = n_struct;
     }
-    const bool want_b = dEdc || dEdb;
     const size_t es = c->ace.precision == AP_FP32 ? 4 : 8;
     const size_t bb = (size_t)c->n_cap * (c->ace.n_funcs + c->ace.n_max) * es;
     if (want_b && bb != c->bval_bytes) {
@@ -603,6 +612,16 @@ int ap_ace_batch_eval(ap_ctx *c, int n_struct, const int32_t *offsets, const dou
         ProfScope p(c, "compact");
         launch_compact(c, n, nullptr, 0, false);
     }
+    *n_out = n;
+    return AP_OK;
+}
+
+int ap_ace_batch_eval(ap_ctx *c, int n_struct, const int32_t *offsets, const double *boxes, const double *pos,
+                      const double *weight, double *E_struct, double *F, double *dEdc, double *dEdb) {
+    const bool want_b = dEdc || dEdb;
+    int n = 0;
+    int rc = batch_prepare(c, n_struct, offsets, boxes, pos, weight, want_b, &n);
+    if (rc) return rc;
     rc = launch_ace(c, n, boxes, std::min(n, 8192), c->b_box, want_b);
     if (rc) return rc;
     if (F) {
@@ -615,6 +634,24 @@ int ap_ace_batch_eval(ap_ctx *c, int n_struct, const int32_t *offsets, const dou
         launch_struct_reduce(c, n, n_struct, c->b_off, weight, E_struct, dEdc, dEdb);
     }
     rc = hip_check(c, hipGetLastError(), "batch");
+    if (!rc) rc = sync_and_check(c);
+    return rc;
+}
+
+int ap_ace_batch_force_vjp(ap_ctx *c, int n_struct, const int32_t *offsets, const double *boxes, const double *pos,
+                           const double *weight, const double *G, double *dLdc, double *dLdb) {
+    if (!c) return AP_E_ARG;
+    if (!G || (!dLdc && !dLdb)) return set_error(c, AP_E_ARG, "G and at least one output needed");
+    int n = 0;
+    int rc = batch_prepare(c, n_struct, offsets, boxes, pos, weight, true, &n);
+    if (rc) return rc;
+    rc = launch_ace_vjp(c, n, boxes, std::min(n, 8192), c->b_box, G);
+    if (rc) return rc;
+    {
+        ProfScope p(c, "struct_reduce");
+        launch_struct_reduce(c, n, n_struct, c->b_off, weight, nullptr, dLdc, dLdb, -1.0);
+    }
+    rc = hip_check(c, hipGetLastError(), "batch vjp");
     if (!rc) rc = sync_and_check(c);
     return rc;
 }

@@ -907,7 +907,7 @@ template <typename TB>
 __global__ void k_struct_reduce(int n_struct, int ncol, int n_funcs, const int *__restrict__ off,
                                 const int *__restrict__ sidx, const double *__restrict__ weight,
                                 const double *__restrict__ Ep, const TB *__restrict__ bval, int bstride,
-                                double *E_struct, double *dEdc, double *dEdb) {
+                                double *E_struct, double *dEdc, double *dEdb, double sign) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (long long)n_struct * ncol) return;
     const int s = (int)(t / ncol), col = (int)(t % ncol);
@@ -918,6 +918,7 @@ __global__ void k_struct_reduce(int n_struct, int ncol, int n_funcs, const int *
         const double w = weight ? weight[i] : 1.0;
         acc += w * (col == 0 ? Ep[i] : (double)bval[(size_t)si * bstride + col - 1]);
     }
+    acc *= sign;
     if (col == 0) {
         if (E_struct) E_struct[s] = acc;
     } else if (col - 1 < n_funcs) {
@@ -928,7 +929,7 @@ __global__ void k_struct_reduce(int n_struct, int ncol, int n_funcs, const int *
 }
 
 void launch_struct_reduce(ap_ctx *c, int n, int n_struct, const int *d_off, const double *weight, double *E_struct,
-                          double *dEdc, double *dEdb) {
+                          double *dEdc, double *dEdb, double sign) {
     (void)n;
     const int nf = c->ace.n_funcs, nm = c->ace.n_max;
     const int ncol = (dEdc || dEdb) ? 1 + nf + nm : 1;
@@ -936,10 +937,12 @@ void launch_struct_reduce(ap_ctx *c, int n, int n_struct, const int *d_off, cons
     const int nb = (int)((tot + kBlock - 1) / kBlock);
     if (c->ace.precision == AP_FP32)
         k_struct_reduce<float><<<nb, kBlock, 0, c->stream>>>(n_struct, ncol, nf, d_off, c->sidx, weight, c->Ep,
-                                                            (const float *)c->bval, nf + nm, E_struct, dEdc, dEdb);
+                                                            (const float *)c->bval, nf + nm, E_struct, dEdc, dEdb,
+                                                            sign);
     else
         k_struct_reduce<double><<<nb, kBlock, 0, c->stream>>>(n_struct, ncol, nf, d_off, c->sidx, weight, c->Ep,
-                                                             (const double *)c->bval, nf + nm, E_struct, dEdc, dEdb);
+                                                             (const double *)c->bval, nf + nm, E_struct, dEdc, dEdb,
+                                                             sign);
 }
 
 }  // namespace ap

@@ -104,3 +104,91 @@ def test_autograd_finite_differences_fp64(batch):
         worst = max(worst, abs(fd - gc[f]) / max(1.0, abs(fd)))
     _lt("dL/dc", worst, 1e-6)
     b.ctx.close()
+
+
+def test_force_vjp_matches_oracle(oracle, batch):
+    """dL/dc and dL/db of L = sum_k G_k . F_k on the 64-cell batch (FP32 arithmetic), per structure against the
+    oracle (every fourth cell); the same on three cells in FP64."""
+    import torch
+    from paper_2512_07693_amd.autograd import ACEBatch
+    s, cells, pos, off, boxes = batch
+    G = np.random.default_rng(12).normal(size=pos.shape)
+    for prec, stride, bar_c, bar_b in (("fp32", 4, 2e-5, 2e-5), ("fp64", 21, 1e-11, 1e-11)):
+        _say("force vjp, %s" % prec)
+        ace = dict(s["ace"], precision=prec)
+        b = ACEBatch(ace, off, boxes)
+        b._load(torch.tensor(ace["c"]))
+        dc, db = b.ctx.ace_batch_force_vjp(to_dev(pos), off, boxes, to_dev(G))
+        dc, db = dc.cpu().numpy(), db.cpu().numpy()
+        wc = wb = 0.0
+        for k in range(0, len(cells), stride):
+            p, bx = cells[k]
+            sl = slice(off[k], off[k + 1])
+            want_c, want_b = oracle.ace_force_vjp(p, bx, ace, G[sl])
+            wc = max(wc, float(np.abs(dc[k] - want_c).max() / np.abs(want_c).max()))
+            wb = max(wb, float(np.abs(db[k] - want_b).max() / np.abs(want_b).max()))
+        _lt("dL/dc " + prec, wc, bar_c)
+        _lt("dL/db " + prec, wb, bar_b)
+        b.ctx.close()
+
+
+def test_force_vjp_autograd_finite_differences_fp64(batch):
+    """ACEBatch.forces and its backward pass: the gradient of L = sum G . F with respect to c against central
+    differences of the forward kernels (FP64; F is linear in c)."""
+    import torch
+    from paper_2512_07693_amd.autograd import ACEBatch
+    s, cells, _, _, _ = batch
+    sub = [cells[2], cells[5]]
+    pos = np.concatenate([p for p, _ in sub])
+    off = np.concatenate([[0], np.cumsum([len(p) for p, _ in sub])]).astype(np.int32)
+    boxes = np.array([b for _, b in sub])
+    ace = dict(s["ace"], precision="fp64")
+    b = ACEBatch(ace, off, boxes)
+    P = to_dev(pos)
+    G = torch.tensor(np.random.default_rng(3).normal(size=(3, len(pos))), device=P.device)
+    c = torch.tensor(ace["c"], device=P.device, requires_grad=True)
+    (b.forces(P, c) * G).sum().backward()
+    gc = c.grad.cpu().numpy()
+
+    def loss(cc):
+        with torch.no_grad():
+            return float((b.forces(P, cc) * G).sum())
+
+    worst = 0.0
+    rng = np.random.default_rng(1)
+    for f in list(rng.choice(len(ace["c"]), 8, replace=False)) + [0, 5]:
+        hc = 1e-3
+        c1, c2 = c.detach().clone(), c.detach().clone()
+        c1[f] += hc
+        c2[f] -= hc
+        fd = (loss(c1) - loss(c2)) / (2 * hc)
+        worst = max(worst, abs(fd - gc[f]) / max(1.0, abs(fd)))
+    _lt("dL/dc", worst, 1e-8)
+    b.ctx.close()
+
+
+@pytest.mark.parametrize("cfg,prec", [(1, "fp64"), (2, "fp32")], ids=["n8l4_fp64", "n12l6_fp32"])
+def test_device_coefficient_update_equals_set_potential(cfg, prec):
+    """ap_set_ace_coefficients (new c and b straight into the installed tables on the device) gives the same
+    bits as ap_set_potential with those coefficients."""
+    import torch
+    from paper_2512_07693_amd import ap
+    s = synth.build_system(cfg, nc=5 if cfg == 2 else None)
+    ace = dict(s["ace"], precision=prec)
+    rng = np.random.default_rng(8)
+    c2 = ace["c"] * (1.0 + 0.1 * rng.normal(size=len(ace["c"])))
+    b2 = ace["b_dens"] * 1.05
+    _say("coefficient update n_funcs=%d %s" % (len(c2), prec))
+    P = to_dev(s["pos"])
+    outs = []
+    for mode in ("table", "device"):
+        ctx = ap.Context(len(s["pos"]), max_nbr=128)
+        if mode == "table":
+            ctx.set_potential(s["eam"], dict(ace, c=c2, b_dens=b2), s["sw"], lambda_mode=ap.AP_LAMBDA_PRECISE)
+        else:
+            ctx.set_potential(s["eam"], ace, s["sw"], lambda_mode=ap.AP_LAMBDA_PRECISE)
+            ctx.set_ace_coefficients(torch.tensor(c2, device="cuda"), torch.tensor(b2, device="cuda"))
+        o = ctx.ace_eval(P, s["box"])
+        outs.append((o["E_atom"].cpu().numpy(), o["F"].cpu().numpy()))
+        ctx.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
