@@ -158,7 +158,7 @@ int ap_nblist_build(ap_ctx *ctx, int n, const double *pos, const ap_box *box, do
 
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc): the neighbour sets of ap_nblist_build without a context. The
- * library's scratch for it (wrapped positions, cell arrays and records, flags; 13.5 MiB) is one static
+ * library's scratch for it (wrapped positions, cell arrays and records, flags; 11.0 MiB) is one static
  * device array per GPU, held until the process ends; the call allocates nothing. Limits: n <= 131072
  * atoms and at most 131072 cells (cells of edge >= r_list, floor(L / r_list) per axis); larger inputs
  * return AP_E_ARG before anything is launched. Same arguments and output layout as ap_nblist_build

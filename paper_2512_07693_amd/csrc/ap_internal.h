@@ -177,6 +177,14 @@ struct alignas(32) Rec4 {
     double x, y, z, w;
 };
 
+// A list-build candidate in cell order: its wrapped position rounded to FP32 and its index (16 bytes). The
+// FP32 distance only sorts pairs into certainly inside, certainly outside and too close to call; the last
+// are decided from the FP64 positions.
+struct alignas(16) CandRec {
+    float x, y, z;
+    int j;
+};
+
 struct Geometry {
     double L[3];
     int nc[3];
@@ -219,7 +227,7 @@ struct ap_ctx {
     int ncell_cap = 0;
     int ncell_cur = 0;  // cells of the geometry of the last list build
     int *cell_of = nullptr, *cell_cnt = nullptr, *cell_start = nullptr, *cell_fill = nullptr, *cell_atoms = nullptr;
-    ap::Rec4 *cell_rec = nullptr;  // [n] {x, y, z, index} of the atoms in cell order (the list build's candidates)
+    ap::CandRec *cell_rec = nullptr;  // [n] the atoms in cell order (the list build's candidates)
     int *scan_tmp = nullptr;
 
     // neighbour list (slot-major)
@@ -326,7 +334,7 @@ struct ListBufs {
     double *pos_build;
     int *flags;
     int *cell_of, *cell_cnt, *cell_start, *cell_fill, *cell_atoms;
-    Rec4 *cell_rec;
+    CandRec *cell_rec;
     int32_t *ncount, *nshort, *nidx;
 };
 // cells of edge >= r_list (one cell per axis below three); false when r_list >= half a box length

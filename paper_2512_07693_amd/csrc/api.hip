@@ -285,7 +285,7 @@ int ap_ctx_create(ap_ctx **out, int n_max_atoms, int max_nbr, double skin, void 
     alloc(&c->d_flags, 8, 4);
     alloc(&c->cell_of, n + 1, 4);
     alloc(&c->cell_atoms, n, 4);
-    alloc(&c->cell_rec, n, sizeof(ap::Rec4));
+    alloc(&c->cell_rec, n, sizeof(ap::CandRec));
     alloc(&c->nbr_cnt, n, 4);
     alloc(&c->nbr_idx, n * max_nbr, 4);
     alloc(&c->rslot, n * max_nbr, 4);

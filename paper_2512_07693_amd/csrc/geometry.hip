@@ -109,11 +109,11 @@ __global__ void k_cell_fill(int n, const int *cell_of, const int *start, int *fi
 }
 
 // Every cell's atoms sorted by index (the fill order above is not deterministic), a wavefront per cell:
-// each lane ranks its atom against the others of the cell. The sorted cell also gets its records
-// {x, y, z, index}, which the list build reads in cell order. A cell of more than 64 atoms is
+// each lane ranks its atom against the others of the cell. The sorted cell also gets its candidate
+// records (FP32 position, index), which the list build reads in cell order. A cell of more than 64 atoms is
 // insertion-sorted by its first lane.
 __global__ void k_cell_sort(int ncell, const int *start, const int *cnt, int *atoms, const double *__restrict__ pos,
-                            int n, Rec4 *__restrict__ rec, const int *flags) {
+                            int n, CandRec *__restrict__ rec, const int *flags) {
     if (flags[0] == 0) return;
     const int lane = threadIdx.x & 63;
     const int cc = (int)(((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
@@ -126,7 +126,7 @@ __global__ void k_cell_sort(int ncell, const int *start, const int *cnt, int *at
         for (int u = 0; u < m; u++) rank += __shfl(v, u, 64) < v;
         if (lane < m) {
             a[rank] = v;
-            rec[b + rank] = Rec4{pos[v], pos[n + v], pos[2 * n + v], (double)v};
+            rec[b + rank] = CandRec{(float)pos[v], (float)pos[n + v], (float)pos[2 * n + v], v};
         }
         return;
     }
@@ -143,23 +143,35 @@ __global__ void k_cell_sort(int ncell, const int *start, const int *cnt, int *at
     __threadfence_block();
     for (int p = lane; p < m; p += 64) {
         const int v = a[p];
-        rec[b + p] = Rec4{pos[v], pos[n + v], pos[2 * n + v], (double)v};
+        rec[b + p] = CandRec{(float)pos[v], (float)pos[n + v], (float)pos[2 * n + v], v};
     }
 }
 
 // One pass over the 27 cells per atom, SUB lanes per atom: in each round the SUB lanes test SUB
-// consecutive candidates of a cell, and a ballot gives every hit its rank among the group's hits, so
-// the slots come out in the order of a sequential scan (cells in a fixed order, atoms of a cell by
-// index). The neighbours inside r_short are written from the front of the slot array, those between
+// consecutive candidates of a column of cells (the three cells of a (dx, dy) column are consecutive in
+// the cell order), and a ballot gives every hit its rank among the group's hits, so the slots come out in
+// the order of a sequential scan (columns in a fixed order, cells by z, atoms of a cell by index). The neighbours inside r_short are written from the front of the slot array, those between
 // r_short and r_list from its back; the back part is then moved down behind the front part (a forward
 // copy: it only moves to lower slots). ncount_short = the front part.
+// The test runs on the candidates' FP32 records with the periodic image of the cell (a shift of the
+// atom's position by a box length where the stencil wraps): a squared distance below r^2 - delta is
+// inside, one at or above r^2 + delta outside (delta bounds the FP32 error, Thresh below); the rare pair
+// in between is decided in FP64 from the positions with the minimum-image difference, the same test as
+// the oracle's, so the sets are exact. A dimension with a single cell takes the FP32 minimum image per
+// candidate instead of the cell's (WRAP).
 // STAGE: the workgroup's lists are assembled in LDS ([max_nbr][kBlock / SUB] ints, dynamic shared memory)
 // and written out row by row, each row of its atoms one contiguous run, instead of as scattered 4-byte
 // stores into the slot-major array.
-template <int SUB, bool STAGE>
-__global__ __launch_bounds__(kBlock) void k_nbr_build(const double *__restrict__ pos, int n, Geometry g, double r2,
-                                                      double rs2, const int *__restrict__ start,
-                                                      const int *__restrict__ cnt, const Rec4 *__restrict__ rec,
+struct Thresh {
+    float lo, hi;    // r_list^2 -/+ delta
+    float slo, shi;  // r_short^2 -/+ delta
+    double r2, rs2;  // the exact squares
+};
+
+template <int SUB, bool STAGE, bool WRAP>
+__global__ __launch_bounds__(kBlock) void k_nbr_build(const double *__restrict__ pos, int n, Geometry g, Thresh th,
+                                                      const int *__restrict__ start,
+                                                      const int *__restrict__ cnt, const CandRec *__restrict__ rec,
                                                       const int *__restrict__ cell_of, int max_nbr,
                                                       int32_t *__restrict__ ncount, int32_t *__restrict__ ncount_short,
                                                       int32_t *__restrict__ nidx, double *__restrict__ pos_build,
@@ -181,6 +193,8 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(const double *__restrict__
     };
     auto get = [&](int slot) { return STAGE ? tile[slot * APB + al] : nidx[(size_t)slot * n + i]; };
     const int gbase = (threadIdx.x & 63) - sub;  // first lane of this atom's group in the wavefront
+    const unsigned long long grp = (SUB == 64 ? ~0ull : ((1ull << SUB) - 1ull)) << gbase;
+    const unsigned long long below = ((1ull << (threadIdx.x & 63)) - 1ull) & grp;
     const bool live = i < n;
     double xi = 0.0, yi = 0.0, zi = 0.0;
     int c0 = 0, c1 = 0, c2 = 0;
@@ -193,52 +207,124 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(const double *__restrict__
         c1 = (cc / g.nc[2]) % g.nc[1];
         c2 = cc % g.nc[2];
     }
+    const float Lf[3] = {(float)g.L[0], (float)g.L[1], (float)g.L[2]};
+    const float hLf[3] = {0.5f * Lf[0], 0.5f * Lf[1], 0.5f * Lf[2]};
     int ks = 0, kl = 0;  // front (short) and back (long) counts, the same on every lane of the group
     const int rx = g.nc[0] > 1 ? 1 : 0, ry = g.nc[1] > 1 ? 1 : 0, rz = g.nc[2] > 1 ? 1 : 0;
-    for (int dx = -rx; dx <= rx; dx++)
-        for (int dy = -ry; dy <= ry; dy++)
-            for (int dz = -rz; dz <= rz; dz++) {
+    // one candidate against the atom's image (xs, ys, zs): inside the short radius, between it and r_list
+    auto test = [&](const CandRec &cr, bool valid, float xs, float ys, float zs, bool &hs, bool &hl) {
+        hs = hl = false;
+        if (!valid) return;
+        float ux = cr.x - xs, uy = cr.y - ys, uz = cr.z - zs;
+        if (WRAP) {
+            if (!rx) ux = ux > hLf[0] ? ux - Lf[0] : (ux < -hLf[0] ? ux + Lf[0] : ux);
+            if (!ry) uy = uy > hLf[1] ? uy - Lf[1] : (uy < -hLf[1] ? uy + Lf[1] : uy);
+            if (!rz) uz = uz > hLf[2] ? uz - Lf[2] : (uz < -hLf[2] ? uz + Lf[2] : uz);
+        }
+        const float d2 = ux * ux + uy * uy + uz * uz;
+        const bool other = cr.j != i;
+        const bool in = other && d2 < th.lo, maybe = other && d2 < th.hi;
+        const bool sin = d2 < th.slo, smaybe = d2 < th.shi;
+        hs = in && sin;
+        hl = in && !smaybe;
+        if (__builtin_expect((maybe && !in) || (in && smaybe && !sin), 0)) {
+            // too close to call in FP32: the FP64 test on the positions
+            const int j = cr.j;
+            const double vx = min_image_w(pos[j] - xi, g.L[0]);
+            const double vy = min_image_w(pos[n + j] - yi, g.L[1]);
+            const double vz = min_image_w(pos[2 * n + j] - zi, g.L[2]);
+            const double d2x = norm2_nofma(vx, vy, vz);
+            hs = d2x < th.r2 && d2x < th.rs2;
+            hl = d2x < th.r2 && !(d2x < th.rs2);
+        }
+    };
+    // the group's hits of one round into their slots, in lane order
+    auto record = [&](bool hs, bool hl, int j) {
+        const unsigned long long ms = __ballot(hs), ml = __ballot(hl);
+        // a slot outside [0, max_nbr) only happens on overflow, which is flagged below
+        if (hs) {
+            const int sl = ks + __popcll(ms & below);
+            if (sl < max_nbr) put(sl, j);
+        }
+        if (hl) {
+            const int sl = max_nbr - 1 - kl - __popcll(ml & below);
+            if (sl >= 0) put(sl, j);
+        }
+        ks += __popcll(ms & grp);
+        kl += __popcll(ml & grp);
+    };
+    // the candidates [b, e) of consecutive cells, two rounds per iteration (two loads in flight)
+    auto scan = [&](int b, int e, float xs, float ys, float zs) {
+        for (int p0 = b; p0 < e; p0 += 2 * SUB) {
+            const int pa = p0 + sub, pb = p0 + SUB + sub;
+            // both loads unconditional (clamped into [p0, e)), so that they are in flight together
+            const CandRec ca = rec[pa < e ? pa : e - 1];
+            const CandRec cb = rec[pb < e ? pb : e - 1];
+            bool hs, hl;
+            test(ca, pa < e, xs, ys, zs, hs, hl);
+            record(hs, hl, ca.j);
+            if (p0 + SUB < e) {  // the group's second round
+                test(cb, pb < e, xs, ys, zs, hs, hl);
+                record(hs, hl, cb.j);
+            }
+        }
+    };
+    // columns (dx, dy) of the stencil; a column's cells are consecutive in z and so in the cell order, one
+    // range of candidates, or two where the column wraps in z (each with its own image)
+    for (int dx = -rx; dx <= rx; dx++) {
+        int x = c0 + dx;
+        double sx = 0.0;  // the atom's image relative to the cell's candidates
+        if (x < 0) {
+            x += g.nc[0];
+            sx = g.L[0];
+        } else if (x >= g.nc[0]) {
+            x -= g.nc[0];
+            sx = -g.L[0];
+        }
+        const float xs = (float)(xi + sx);
+        for (int dy = -ry; dy <= ry; dy++) {
+            int y = c1 + dy;
+            double sy = 0.0;
+            if (y < 0) {
+                y += g.nc[1];
+                sy = g.L[1];
+            } else if (y >= g.nc[1]) {
+                y -= g.nc[1];
+                sy = -g.L[1];
+            }
+            const float ys = (float)(yi + sy);
+            const int q0 = (x * g.nc[1] + y) * g.nc[2];  // the column's first cell
+            int z0 = c2 - rz, z1 = c2 + rz;
+            if (z0 < 0) {
+                // cell nc - 1 (seen through the lower face) first, then cells 0 .. z1
                 int b = 0, e = 0;
                 if (live) {
-                    int x = c0 + dx, y = c1 + dy, z = c2 + dz;
-                    x += x < 0 ? g.nc[0] : (x >= g.nc[0] ? -g.nc[0] : 0);
-                    y += y < 0 ? g.nc[1] : (y >= g.nc[1] ? -g.nc[1] : 0);
-                    z += z < 0 ? g.nc[2] : (z >= g.nc[2] ? -g.nc[2] : 0);
-                    const int q = (x * g.nc[1] + y) * g.nc[2] + z;
-                    b = start[q];
-                    e = b + cnt[q];
+                    b = start[q0 + g.nc[2] - 1];
+                    e = b + cnt[q0 + g.nc[2] - 1];
                 }
-                // every lane of a group runs the same rounds (b and e are the group's)
-                for (int p0 = b; p0 < e; p0 += SUB) {
-                    const int p = p0 + sub;
-                    bool hs = false, hl = false;
-                    int j = -1;
-                    if (p < e) {
-                        const Rec4 cr = rec[p];  // the candidate's position and index, in cell order
-                        j = (int)cr.w;
-                        if (j != i) {
-                            // (positions are wrapped, so a difference lies in (-L, L): the select
-                            // takes the image d - L rint(d / L) takes, without its division, except
-                            // within an ulp of |d| = L / 2, where both images are farther than r_list)
-                            const double ux = min_image_w(cr.x - xi, g.L[0]);
-                            const double uy = min_image_w(cr.y - yi, g.L[1]);
-                            const double uz = min_image_w(cr.z - zi, g.L[2]);
-                            const double d2 = norm2_nofma(ux, uy, uz);
-                            hs = d2 < r2 && d2 < rs2;
-                            hl = d2 < r2 && !(d2 < rs2);
-                        }
-                    }
-                    const unsigned long long ms = __ballot(hs), ml = __ballot(hl);
-                    const unsigned long long grp = (SUB == 64 ? ~0ull : ((1ull << SUB) - 1ull)) << gbase;
-                    const unsigned long long below = ((1ull << (threadIdx.x & 63)) - 1ull) & grp;
-                    // hits before this one in scan order: the front and back parts never meet
-                    const bool room = ks + kl + __popcll((ms | ml) & below) < max_nbr;
-                    if (hs && room) put(ks + __popcll(ms & below), j);
-                    if (hl && room) put(max_nbr - 1 - kl - __popcll(ml & below), j);
-                    ks += __popcll(ms & grp);
-                    kl += __popcll(ml & grp);
-                }
+                scan(b, e, xs, ys, (float)(zi + g.L[2]));
+                z0 = 0;
             }
+            const int zt = z1 < g.nc[2] ? z1 : g.nc[2] - 1;
+            {
+                int b = 0, e = 0;
+                if (live) {
+                    b = start[q0 + z0];
+                    e = start[q0 + zt] + cnt[q0 + zt];
+                }
+                scan(b, e, xs, ys, (float)zi);
+            }
+            if (z1 >= g.nc[2]) {
+                // cell 0 seen through the upper face
+                int b = 0, e = 0;
+                if (live) {
+                    b = start[q0];
+                    e = b + cnt[q0];
+                }
+                scan(b, e, xs, ys, (float)(zi - g.L[2]));
+            }
+        }
+    }
     int k = ks + kl;
     if (live && k <= max_nbr) {
         // the back part [max_nbr - kl, max_nbr) moves down to [ks, ks + kl), ks <= max_nbr - kl, in
@@ -306,6 +392,29 @@ static int make_geometry(ap_ctx *c, const double *box, double r_list, Geometry &
     return AP_OK;
 }
 
+// The FP32 test's margins. Each coordinate of a record is within half an FP32 ulp of L of its FP64 value,
+// the shifted atom position (below 2 L) within one ulp of L, and the difference and, for a single-cell
+// dimension, its wrap by the rounded box length add at most another ulp of L: e <= 3 ulp(L) per component. The squared distance then errs by at most 2 e (|ux| + |uy| + |uz|) + 3 e^2
+// <= 2 sqrt(3) r e + 3 e^2, plus the rounding of the three products and two sums (<= 3 ulp(r^2) with FMA
+// contraction); delta is twice that bound, and the FP32 thresholds are rounded outward.
+static float ulp32(double v) { return (float)std::ldexp(1.0, std::ilogb(v) - 23); }
+static Thresh list_thresholds(const Geometry &g, double r_list, double r_short) {
+    const double Lm = std::max(g.L[0], std::max(g.L[1], g.L[2]));
+    auto margin = [&](double r) {
+        const double e = 3.0 * ulp32(Lm);
+        return 2.0 * (2.0 * std::sqrt(3.0) * r * e + 3.0 * e * e + 3.0 * ulp32(std::max(r * r, 1e-30)));
+    };
+    const double r2 = r_list * r_list, rs2 = r_short * r_short, dl = margin(r_list), ds = margin(r_short);
+    Thresh th;
+    th.lo = std::nextafter((float)(r2 - dl), 0.0f);
+    th.hi = std::nextafter((float)(r2 + dl), INFINITY);
+    th.slo = std::nextafter((float)(rs2 - ds), 0.0f);
+    th.shi = std::nextafter((float)(rs2 + ds), INFINITY);
+    th.r2 = r2;
+    th.rs2 = rs2;
+    return th;
+}
+
 // The cell binning and list kernels of one build of the wrapped positions b.pos, gated by b.flags[0]
 // (nothing happens unless it is set; the caller has cleared the cell counts and fills): cell ids and
 // counts, their exclusive scan, the cells' atoms sorted by index with their records, then the lists.
@@ -319,14 +428,21 @@ void launch_list_kernels(hipStream_t s, int n, const Geometry &g, double r_list,
         g.ncell, b.cell_start, b.cell_cnt, b.cell_atoms, b.pos, n, b.cell_rec, b.flags);
     constexpr int SUB = 8;  // lanes per atom in the list build
     const int lgrid = (int)(((size_t)n * SUB + kBlock - 1) / kBlock);
-    if (max_nbr <= 256)  // (at most 32 KB of staged lists per workgroup)
-        k_nbr_build<SUB, true><<<lgrid, kBlock, (size_t)max_nbr * (kBlock / SUB) * sizeof(int), s>>>(
-            b.pos, n, g, r_list * r_list, r_short * r_short, b.cell_start, b.cell_cnt, b.cell_rec, b.cell_of, max_nbr,
-            b.ncount, b.nshort, b.nidx, b.pos_build, b.flags);
+    const Thresh th = list_thresholds(g, r_list, r_short);
+    const size_t lds = (size_t)max_nbr * (kBlock / SUB) * sizeof(int);
+    const bool wrap = g.nc[0] == 1 || g.nc[1] == 1 || g.nc[2] == 1;
+    // (at most 32 KB of staged lists per workgroup)
+#define AP_NBR_ARGS b.pos, n, g, th, b.cell_start, b.cell_cnt, b.cell_rec, b.cell_of, max_nbr, b.ncount, b.nshort, \
+                    b.nidx, b.pos_build, b.flags
+    if (max_nbr <= 256 && !wrap)
+        k_nbr_build<SUB, true, false><<<lgrid, kBlock, lds, s>>>(AP_NBR_ARGS);
+    else if (max_nbr <= 256)
+        k_nbr_build<SUB, true, true><<<lgrid, kBlock, lds, s>>>(AP_NBR_ARGS);
+    else if (!wrap)
+        k_nbr_build<SUB, false, false><<<lgrid, kBlock, 0, s>>>(AP_NBR_ARGS);
     else
-        k_nbr_build<SUB, false><<<lgrid, kBlock, 0, s>>>(b.pos, n, g, r_list * r_list, r_short * r_short,
-                                                        b.cell_start, b.cell_cnt, b.cell_rec, b.cell_of, max_nbr,
-                                                        b.ncount, b.nshort, b.nidx, b.pos_build, b.flags);
+        k_nbr_build<SUB, false, true><<<lgrid, kBlock, 0, s>>>(AP_NBR_ARGS);
+#undef AP_NBR_ARGS
 }
 
 // The stream-ordered pieces of a context-free list build: wrapped positions and fills.

@@ -16,7 +16,7 @@ constexpr int kNoAllocMaxDevices = 64;
 constexpr size_t kRound = 256;
 constexpr size_t rnd(size_t b) { return (b + kRound - 1) / kRound * kRound; }
 constexpr size_t kOffRec = 0;
-constexpr size_t kOffPos = kOffRec + rnd(sizeof(Rec4) * kNoAllocMaxAtoms);
+constexpr size_t kOffPos = kOffRec + rnd(sizeof(CandRec) * kNoAllocMaxAtoms);
 constexpr size_t kOffPosBuild = kOffPos + rnd(3 * sizeof(double) * kNoAllocMaxAtoms);
 constexpr size_t kOffCellOf = kOffPosBuild + rnd(3 * sizeof(double) * kNoAllocMaxAtoms);
 constexpr size_t kOffCellAtoms = kOffCellOf + rnd(sizeof(int) * kNoAllocMaxAtoms);
@@ -25,7 +25,7 @@ constexpr size_t kOffCnt = kOffShort + rnd(sizeof(int) * kNoAllocMaxAtoms);
 constexpr size_t kOffStart = kOffCnt + rnd(sizeof(int) * kNoAllocMaxCells);
 constexpr size_t kOffFill = kOffStart + rnd(sizeof(int) * (kNoAllocMaxCells + 1));
 constexpr size_t kOffFlags = kOffFill + rnd(sizeof(int) * kNoAllocMaxCells);
-constexpr size_t kScratchBytes = kOffFlags + rnd(sizeof(int) * 8);  // 13.5 MiB
+constexpr size_t kScratchBytes = kOffFlags + rnd(sizeof(int) * 8);  // 11.0 MiB
 
 // One copy per GPU, held until the process ends. Host code never passes this name to a kernel (on the
 // host it is only a stand-in); it uses the device address looked up per device below.
@@ -83,7 +83,7 @@ extern "C" int ap_nblist_build_noalloc(int n, const double *pos, const ap_box *b
                      reinterpret_cast<int *>(sb + kOffStart),
                      cell_fill,
                      reinterpret_cast<int *>(sb + kOffCellAtoms),
-                     reinterpret_cast<Rec4 *>(sb + kOffRec),
+                     reinterpret_cast<CandRec *>(sb + kOffRec),
                      nbr_count,
                      reinterpret_cast<int32_t *>(sb + kOffShort),
                      nbr_idx};
