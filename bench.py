@@ -549,6 +549,9 @@ def main():
                      help="NVE steps of the 2M-atom fcc penny-crack run (0: skip)")
     ap_.add_argument("--learned-steps", type=int, default=500,
                      help="NVE steps of the learned-indicator comparison on the 1M-atom workload (0: skip)")
+    ap_.add_argument("--profile-run", action="store_true",
+                     help="only the timed mixed loop and (with --pure-steps > 0) the pure-ACE loop, for profiler "
+                          "and counter runs; prints one line of timings")
     ap_.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                      help="only copy a MIB-sized buffer 5 times (calibrates the HBM byte counters)")
     args = ap_.parse_args()
@@ -591,6 +594,16 @@ def main():
     value = n * args.steps / (ms / 1e3)
     window = drift_fit(thermo, n, s["run"]["dt"])
     log("mixed: %.3f ms/step, %.3e atom-steps/s, x=%.4f" % (ms / args.steps, value, window["x_mean"]))
+    if args.profile_run:
+        out = dict(mixed_ms_per_step=ms / args.steps, x=window["x_mean"])
+        if args.pure_steps > 0:
+            ctx_p = ap.Context(n, max_nbr=128, skin=s["run"]["skin"])
+            ctx_p.set_potential(s["eam"], s["ace"], s["sw"], lambda_mode=ap.AP_LAMBDA_PRECISE)
+            ms_p, _, _, _ = run_md(ctx_p, s, pos0, vel0, args.pure_steps, 1, 0)
+            out["pure_ace_ms_per_step"] = ms_p / args.pure_steps
+            ctx_p.close()
+        print(json.dumps(out), flush=True)
+        return
     # the drift on a fixed 1-ps leg after a stated equilibration, whatever --steps is (a short window
     # measures the energy's oscillation, not its drift); also fitted with the transient included
     log("drift leg: %d + %d steps ..." % (args.equil, args.drift_steps))
