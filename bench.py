@@ -334,7 +334,7 @@ def train_indicator(eam, ace, sw, n_cells=200, epochs=150):
                         loss_last=float(hist[-1]), target_var=float(T.var()))
 
 
-def learned_comparison(steps, warmup):
+def learned_comparison(steps, warmup, cal_iters=6):
     """Vacancy-cluster workload (1M atoms): CSP against the trained network at the same precise
     fraction x, on drift, force error near the clusters (against pure ACE) and atom-steps/s."""
     import torch
@@ -373,31 +373,67 @@ def learned_comparison(steps, warmup):
 
     out = dict(workload=s["name"], n_atoms=n, removed_sites=int(len(removed)), atoms_near=int(near.sum()),
                training=train)
-    c = ctx_for(ap.AP_IND_CSP, s["sw"])
-    x_csp = float((c.switch_eval(pos0, box)["lam"] < 1).double().mean())
-    lo, hi = 1e-4, 10.0
-    cm = ctx_for(ap.AP_IND_MLP, dict(s["sw"], d_lo=1.0, d_hi=2.0))
-    for _ in range(40):  # thresholds of the network (eV; d_hi = 2 d_lo) bisected to CSP's x
-        mid = np.sqrt(lo * hi)
-        cm.set_potential(s["eam"], s["ace"], dict(s["sw"], d_lo=mid, d_hi=2 * mid), indicator=ap.AP_IND_MLP)
-        x = float((cm.switch_eval(pos0, box)["lam"] < 1).double().mean())
-        lo, hi = (mid, hi) if x > x_csp else (lo, mid)
-    cm.set_potential(s["eam"], s["ace"], dict(s["sw"], d_lo=hi, d_hi=2 * hi), indicator=ap.AP_IND_MLP)
-    for name, ctx in (("csp", c), ("learned", cm)):
+
+    def leg(name, ctx, final=None):
         F = ctx.mixed_energy_forces(pos0, box)["F"].cpu().numpy().T
         log("learned indicator: %s run, %d + %d steps ..." % (name, warmup, steps))
-        ms, thermo, prof, th_w = run_md(ctx, s, pos0, vel0, steps, warmup, 0)
+        ms, thermo, prof, th_w = run_md(ctx, s, pos0, vel0, steps, warmup, 0, final=final)
         nve = drift_fit(thermo, n, s["run"]["dt"])
-        out[name] = dict(x0=float((ctx.switch_eval(pos0, box)["lam"] < 1).double().mean()),
-                         value=n * steps / (ms / 1e3), ms_per_step=ms / steps,
-                         force_rmse_near=float(np.sqrt(((F - Fref)[near] ** 2).sum(1).mean())),
-                         force_rmse_all=float(np.sqrt(((F - Fref) ** 2).sum(1).mean())),
-                         drift_eV_per_atom_per_ps=nve["drift_eV_per_atom_per_ps"],
-                         max_abs_dE_per_atom=nve["max_abs_dE_per_atom"], x_mean=nve["x_mean"],
-                         kernels={k: round(v[0], 5) for k, v in prof.items()})
-        if name == "learned":
-            out[name]["d_lo"] = float(hi)
-        ctx.close()
+        return dict(x0=float((ctx.switch_eval(pos0, box)["lam"] < 1).double().mean()),
+                    value=n * steps / (ms / 1e3), ms_per_step=ms / steps,
+                    force_rmse_near=float(np.sqrt(((F - Fref)[near] ** 2).sum(1).mean())),
+                    force_rmse_all=float(np.sqrt(((F - Fref) ** 2).sum(1).mean())),
+                    drift_eV_per_atom_per_ps=nve["drift_eV_per_atom_per_ps"],
+                    max_abs_dE_per_atom=nve["max_abs_dE_per_atom"], x_mean=nve["x_mean"],
+                    kernels={k: round(v[0], 5) for k, v in prof.items()})
+
+    # The network's thresholds (d_lo, d_hi = 2 d_lo) are set on the ensemble its own dynamics produce: where
+    # ACE acts the structure relaxes toward ACE's minimum and |E^ACE - E^EAM|, which the network predicts,
+    # grows there (x rises along a run), so a threshold matched to CSP's x on the starting frame gives twice
+    # CSP's mean x over the run, and one matched on CSP's own thermalised frame almost none. A geometric
+    # bisection between those two brackets on the mean x of learned runs of the measured length (warmup +
+    # steps from the same start) matches CSP's mean x over its run.
+    c = ctx_for(ap.AP_IND_CSP, s["sw"])
+    fin = {}
+    out["csp"] = leg("csp", c, final=fin)
+    pos_t = fin["pos"]
+    x_csp0 = float((c.switch_eval(pos0, box)["lam"] < 1).double().mean())
+    x_csp_t = float((c.switch_eval(pos_t, box)["lam"] < 1).double().mean())
+    c.close()
+    cm = ctx_for(ap.AP_IND_MLP, dict(s["sw"], d_lo=1.0, d_hi=2.0))
+
+    def set_thr(d):
+        cm.set_potential(s["eam"], s["ace"], dict(s["sw"], d_lo=d, d_hi=2 * d), indicator=ap.AP_IND_MLP)
+
+    def match_frame(P, x_target):
+        lo, hi = 1e-4, 10.0
+        for _ in range(40):
+            mid = np.sqrt(lo * hi)
+            set_thr(mid)
+            x = float((cm.switch_eval(P, box)["lam"] < 1).double().mean())
+            lo, hi = (mid, hi) if x > x_target else (lo, mid)
+        return hi
+
+    d_a, d_b = match_frame(pos0, x_csp0), match_frame(pos_t, x_csp_t)
+    lo, hi = min(d_a, d_b), max(d_a, d_b)
+    x_target = out["csp"]["x_mean"]
+    cal = []
+    for _ in range(cal_iters):
+        mid = np.sqrt(lo * hi)
+        set_thr(mid)
+        _, th, _, _ = run_md(cm, s, pos0, vel0, steps, warmup, 0)
+        xm = float(th[:, 6].mean() / n)
+        cal.append(dict(d_lo=float(mid), x_mean=xm))
+        lo, hi = (mid, hi) if xm > x_target else (lo, mid)
+    d_lo = min(cal, key=lambda e: abs(np.log(max(e["x_mean"], 1e-12) / x_target)))["d_lo"]
+    set_thr(d_lo)
+    out["learned"] = leg("learned", cm)
+    out["learned"]["d_lo"] = float(d_lo)
+    cm.close()
+    out["threshold_calibration"] = dict(bracket=[float(d_a), float(d_b)], steps=steps, warmup=warmup,
+                                        x_target=x_target, iterations=cal)
+    out["x_mean_ratio"] = out["learned"]["x_mean"] / max(out["csp"]["x_mean"], 1e-30)
+    out["step_ratio"] = out["learned"]["ms_per_step"] / out["csp"]["ms_per_step"]
     return out
 
 
@@ -545,9 +581,9 @@ def main():
                      help="steps per time step of the time-step study (0: skip)")
     ap_.add_argument("--speedup-map", action="store_true",
                      help="run only the sweep of the speedup over x and r_w (2M-atom bcc, Eq. (1) fit)")
-    ap_.add_argument("--large-steps", type=int, default=500,
+    ap_.add_argument("--large-steps", type=int, default=1000,
                      help="NVE steps of the 2M-atom fcc penny-crack run (0: skip)")
-    ap_.add_argument("--learned-steps", type=int, default=500,
+    ap_.add_argument("--learned-steps", type=int, default=1000,
                      help="NVE steps of the learned-indicator comparison on the 1M-atom workload (0: skip)")
     ap_.add_argument("--profile-run", action="store_true",
                      help="only the timed mixed loop and (with --pure-steps > 0) the pure-ACE loop, for profiler "

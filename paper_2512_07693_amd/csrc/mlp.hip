@@ -12,7 +12,8 @@
 // Parameter block (AP_MLP_NPARAMS floats): mu[16] sig[16] W1[64][16] b1[64] W2[64][64] b2[64] w3[64] b3.
 //
 // Kernels:
-//   k_mlp_indicator  one thread per atom: features, forward pass, g (or the features alone)
+//   k_mlp_indicator  one thread per atom for the features, then the forward pass of the wavefront's 64
+//                    atoms on the matrix cores; g (or the features alone)
 //   k_mlp_eval       one thread per sample: g and dg/dq from given features
 //   k_mlp_gradg      one wavefront per atom with W_j != 0: features, backward pass (a hidden unit per
 //                    lane), and h_jk = W_j dg_j/du_jk per neighbour slot, stored at (j, slot) and
@@ -34,6 +35,11 @@ static_assert(kNP == AP_MLP_NPARAMS, "parameter block layout");
 constexpr int kTZ = 0, kTH1 = 16, kTD1 = 80, kTH2 = 144, kTD2 = 208, kTGO = 272, kTLOSS = 273, kTRows = 274;
 
 __device__ __forceinline__ float sigm(float a) { return 1.0f / (1.0f + expf(-a)); }
+// the logistic function with the hardware exponential and reciprocal (about 1e-6 relative), for the
+// indicator's forward pass; training and the input gradient keep the library's expf and division
+__device__ __forceinline__ float sigm_fast(float a) {
+    return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * a));
+}
 __device__ __forceinline__ float silu_d(float a) {
     const float s = sigm(a);
     return s * (1.0f + a * (1.0f - s));
@@ -82,29 +88,6 @@ __device__ __forceinline__ void site_features(const double *__restrict__ pos, in
         }
 }
 
-// Forward pass of one sample with the parameters in LDS; returns o.
-__device__ __forceinline__ float mlp_forward(const float *__restrict__ P, const float *q) {
-    float z[kNQ];
-#pragma unroll
-    for (int f = 0; f < kNQ; f++) z[f] = (q[f] - P[kMU + f]) / P[kSIG + f];
-    float h1[kNH];
-#pragma unroll
-    for (int c = 0; c < kNH; c++) {
-        float a = P[kB1 + c];
-#pragma unroll
-        for (int f = 0; f < kNQ; f++) a += P[kW1 + c * kNQ + f] * z[f];
-        h1[c] = a * sigm(a);
-    }
-    float o = P[kB3];
-    for (int c = 0; c < kNH; c++) {
-        float a = P[kB2 + c];
-#pragma unroll
-        for (int k = 0; k < kNH; k++) a += P[kW2 + c * kNH + k] * h1[k];
-        o += P[kW3 + c] * (a * sigm(a));
-    }
-    return o;
-}
-
 __device__ __forceinline__ void load_params(float *sP, const float *__restrict__ P) {
     for (int q = threadIdx.x; q < kNP; q += blockDim.x) sP[q] = P[q];
     __syncthreads();
@@ -133,19 +116,138 @@ struct MlpArgs {
     int *flags;
 };
 
-__global__ __launch_bounds__(kBlock) void k_mlp_indicator(MlpArgs a, int features_only) {
-    __shared__ float sP[kNP];
-    if (!features_only) load_params(sP, a.P);
-    const int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (i >= a.n) return;
-    float q[kNQ], A[48];
-    site_features(a.pos, a.n, i, a.L[0], a.L[1], a.L[2], a.ncount, a.nidx, a.rc, q, A);
-    if (features_only) {
+// The indicator kernel's copy of the parameters in LDS: the weight matrices transposed with rows of 68
+// floats, so that a matrix-core operand read (16 consecutive outputs per row, four rows apart by 68) touches
+// 64 different banks.
+constexpr int kTS = 68;
+constexpr int kMmu = 0, kMsig = 16, kMb1 = 32, kMb2 = kMb1 + kNH, kMw3 = kMb2 + kNH, kMb3 = kMw3 + kNH,
+              kMW1t = 228, kMW2t = kMW1t + kNQ * kTS, kMNP = kMW2t + kNH * kTS;
+static_assert(kMb3 < kMW1t, "indicator parameter layout");
+__device__ __forceinline__ void load_params_t(float *sM, const float *__restrict__ P) {
+    for (int q = threadIdx.x; q < kNQ; q += blockDim.x) {
+        sM[kMmu + q] = P[kMU + q];
+        sM[kMsig + q] = P[kSIG + q];
+    }
+    for (int q = threadIdx.x; q < kNH; q += blockDim.x) {
+        sM[kMb1 + q] = P[kB1 + q];
+        sM[kMb2 + q] = P[kB2 + q];
+        sM[kMw3 + q] = P[kW3 + q];
+    }
+    if (threadIdx.x == 0) sM[kMb3] = P[kB3];
+    for (int q = threadIdx.x; q < kNH * kNQ; q += blockDim.x) {  // W1[h][f] -> W1t[f][h]
+        const int h = q / kNQ, f = q - h * kNQ;
+        sM[kMW1t + f * kTS + h] = P[kW1 + q];
+    }
+    for (int q = threadIdx.x; q < kNH * kNH; q += blockDim.x) {  // W2[o][h] -> W2t[h][o]
+        const int o = q / kNH, h = q - o * kNH;
+        sM[kMW2t + h * kTS + o] = P[kW2 + q];
+    }
+    __syncthreads();
+}
+
+// The network on the wavefront's 64 atoms at once, on the matrix cores (16x16x4 FP32 tiles), transposed so
+// that the first layer's accumulators serve directly as the second layer's operand:
+//   H1^T[h][a] = silu(W1 Z^T + b1)   (4 x 4 tiles of (h, a), k = feature)
+//   H2^T[o][a] = silu(W2 H1^T + b2)  (per output tile, k = h taken in the accumulators' row order)
+//   o_a = w3 . H2^T[:, a] + b3
+// Z (64 x 16) goes through LDS (each lane holds its own atom's row); the weights are read from LDS. Lane l
+// supplies A[l % 16][l / 16] and B[l / 16][l % 16] and receives C[4 (l / 16) + j][l % 16].
+__device__ __forceinline__ float mlp_forward_wave(const float *__restrict__ P, float *__restrict__ sZ,
+                                                  const float *z) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const int lane = threadIdx.x & 63, lc = lane & 15, lr = lane >> 4;
+    constexpr int ZS = kNQ + 1;  // padded row of Z in LDS
 #pragma unroll
-        for (int f = 0; f < kNQ; f++) a.q[(size_t)i * kNQ + f] = q[f];
+    for (int f = 0; f < kNQ; f++) sZ[lane * ZS + f] = z[f];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    f4 h1[4][4];  // [h tile][atom tile]
+#pragma unroll
+    for (int rt = 0; rt < 4; rt++) {
+        // the four atom tiles share each weight operand and are independent chains
+        f4 acc[4];
+#pragma unroll
+        for (int ct = 0; ct < 4; ct++) acc[ct] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < kNQ / 4; ks++) {
+            const float x = P[kMW1t + (4 * ks + lr) * kTS + 16 * rt + lc];
+#pragma unroll
+            for (int ct = 0; ct < 4; ct++)
+                acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, sZ[(16 * ct + lc) * ZS + 4 * ks + lr], acc[ct], 0,
+                                                               0, 0);
+        }
+#pragma unroll
+        for (int ct = 0; ct < 4; ct++) {
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const float v = acc[ct][j] + P[kMb1 + 16 * rt + 4 * lr + j];
+                acc[ct][j] = v * sigm_fast(v);
+            }
+            h1[rt][ct] = acc[ct];
+        }
+    }
+    float part[4] = {0.f, 0.f, 0.f, 0.f};  // per atom tile: this lane's share of w3 . h2
+#pragma unroll
+    for (int ot = 0; ot < 4; ot++) {
+        f4 acc[4];
+#pragma unroll
+        for (int ct = 0; ct < 4; ct++) acc[ct] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int rt = 0; rt < 4; rt++)
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const float x = P[kMW2t + (16 * rt + 4 * lr + j) * kTS + 16 * ot + lc];
+#pragma unroll
+                for (int ct = 0; ct < 4; ct++)
+                    acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, h1[rt][ct][j], acc[ct], 0, 0, 0);
+            }
+#pragma unroll
+        for (int ct = 0; ct < 4; ct++)
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const int o = 16 * ot + 4 * lr + j;
+                const float v = acc[ct][j] + P[kMb2 + o];
+                part[ct] += P[kMw3 + o] * (v * sigm_fast(v));
+            }
+    }
+    // the four lanes of a column hold the partial sums of the same atom: a fixed butterfly over them, then
+    // lane l takes its own atom's (atom l = 16 lr + lc sits in tile ct = lr)
+    float mine = 0.f;
+#pragma unroll
+    for (int ct = 0; ct < 4; ct++) {
+        float v = part[ct];
+        v += __shfl_xor(v, 16, 64);
+        v += __shfl_xor(v, 32, 64);
+        mine = ct == lr ? v : mine;
+    }
+    return mine + P[kMb3];
+}
+
+__global__ __launch_bounds__(kBlock, 4) void k_mlp_indicator(MlpArgs a, int features_only) {
+    __shared__ float sP[kMNP];
+    __shared__ float sZ[kBlock / 64][64 * (kNQ + 1)];
+    if (!features_only) load_params_t(sP, a.P);
+    const int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    // every lane stays to the end: the network runs on whole wavefronts
+    float q[kNQ], A[48];
+    if (i < a.n) {
+        site_features(a.pos, a.n, i, a.L[0], a.L[1], a.L[2], a.ncount, a.nidx, a.rc, q, A);
+    } else {
+#pragma unroll
+        for (int f = 0; f < kNQ; f++) q[f] = features_only ? 0.f : sP[kMmu + f];  // a finite filler row (z = 0)
+    }
+    if (features_only) {
+        if (i < a.n)
+#pragma unroll
+            for (int f = 0; f < kNQ; f++) a.q[(size_t)i * kNQ + f] = q[f];
         return;
     }
-    const float o = mlp_forward(sP, q);
+    float z[kNQ];
+#pragma unroll
+    for (int f = 0; f < kNQ; f++) z[f] = (q[f] - sP[kMmu + f]) / sP[kMsig + f];
+    const float o = mlp_forward_wave(sP, sZ[threadIdx.x >> 6], z);
+    if (i >= a.n) return;
     const float g = softplus(o);
     if (!isfinite(g)) atomicOr(&a.flags[1], kErrNonFinite);
     a.g[i] = (double)g;
