@@ -631,7 +631,8 @@ def main():
     window = drift_fit(thermo, n, s["run"]["dt"])
     log("mixed: %.3f ms/step, %.3e atom-steps/s, x=%.4f" % (ms / args.steps, value, window["x_mean"]))
     if args.profile_run:
-        out = dict(mixed_ms_per_step=ms / args.steps, x=window["x_mean"])
+        out = dict(mixed_ms_per_step=ms / args.steps, x=window["x_mean"],
+                   kernels_ms={k: round(v[0], 5) for k, v in prof.items()})
         if args.pure_steps > 0:
             ctx_p = ap.Context(n, max_nbr=128, skin=s["run"]["skin"])
             ctx_p.set_potential(s["eam"], s["ace"], s["sw"], lambda_mode=ap.AP_LAMBDA_PRECISE)
