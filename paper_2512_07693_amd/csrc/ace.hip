@@ -15,6 +15,8 @@
 // and G = dE/dA (adjoint of the block contractions); writes E^p, E~ of (S17) and G.
 // k_ace_pairforce (one workgroup per S atom, one thread per neighbour slot):
 // f_ji = dE_i/du_ij = sum_{n,lm} G_{nlm} grad_u [g_n(r) Y_lm(uhat)].
+#include <type_traits>
+
 #include "ap_internal.h"
 #include "basis.h"
 
@@ -478,44 +480,56 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
             stage_block<T, NN * NMAX>(B.kc, B.kv, B.C, a.kidx, kval, c3 + bk[3], k0, k1);
             __syncthreads();
             // P_M[n1][n2] = sum kappa A[n1][l1 m1] A[n2][l2 m2]; Q_M[n1][n2] = sum_n3 C A[n3][L M];
-            // one thread per (M, n1) holds the twelve n2 in registers
-            for (int w = tid; w < nM * NMAX; w += kBlock) {
-                const int Mi = w / NMAX, n1 = w - Mi * NMAX;
-                T P[NMAX], Q[NMAX];
+            // one thread per (M, n1, run of NS n2) holds its n2 in registers. The runs are as short as the
+            // workgroup allows (NS = 4 up to 7 values of M, 6 up to 10, else all 12): most blocks have few M,
+            // and a thread's chain over the couplings and C rows, not the lane count, sets the phase's time.
+            auto pq = [&](auto ns) {
+                constexpr int NS = decltype(ns)::value, SPL = NMAX / NS;
+                for (int w = tid; w < nM * NMAX * SPL; w += kBlock) {
+                    const int Mi = w / (NMAX * SPL), rem = w - Mi * (NMAX * SPL), n1 = rem / SPL;
+                    const int o2 = (rem - n1 * SPL) * NS;  // first n2 of the run
+                    T P[NS], Q[NS];
 #pragma unroll
-                for (int q = 0; q < NMAX; q++) P[q] = T(0);
-                const int e0 = bk[4 + Mi] - k0, e1 = bk[4 + Mi + 1] - k0;
-                for (int q = e0; q < e1; q++) {
-                    // (l1 m1 column) | (l2 m2 row of At, in units of four) << 8: the row offset stays a
-                    // visible multiple of four, so its reads are 16-byte vector loads
-                    const int code = B.kc[q];
-                    const T a1 = B.kv[q] * sA[n1 * NLM + (code & 255)];
-                    const T *a2 = sAt + 4 * (code >> 8);
+                    for (int q = 0; q < NS; q++) P[q] = T(0);
+                    const int e0 = bk[4 + Mi] - k0, e1 = bk[4 + Mi + 1] - k0;
+                    for (int q = e0; q < e1; q++) {
+                        // (l1 m1 column) | (l2 m2 row of At, in units of four) << 8: the row offset stays a
+                        // visible multiple of four, so its reads are vector loads
+                        const int code = B.kc[q];
+                        const T a1 = B.kv[q] * sA[n1 * NLM + (code & 255)];
+                        const T *a2 = sAt + 4 * (code >> 8) + o2;
 #pragma unroll
-                    for (int q2 = 0; q2 < NMAX; q2++) P[q2] += a1 * a2[q2];
+                        for (int q2 = 0; q2 < NS; q2++) P[q2] += a1 * a2[q2];
+                    }
+                    const T *a3 = sAt + (bL + Mi - L) * NMAX;
+                    T A3[NMAX];
+#pragma unroll
+                    for (int q = 0; q < NMAX; q++) A3[q] = a3[q];
+                    const T *cr = B.C + n1 * NN + o2 * NMAX;
+#pragma unroll
+                    for (int q2 = 0; q2 < NS; q2++) {
+                        T acc = T(0);
+#pragma unroll
+                        for (int q3 = 0; q3 < NMAX; q3++) acc += cr[q2 * NMAX + q3] * A3[q3];
+                        Q[q2] = acc;
+                    }
+                    T *pp = B.P + Mi * NN + n1 * NMAX + o2, *qq = B.Q + Mi * NN + n1 * NMAX + o2;
+                    T ep = T(0);
+#pragma unroll
+                    for (int q2 = 0; q2 < NS; q2++) {
+                        ep += P[q2] * Q[q2];
+                        pp[q2] = P[q2];
+                        qq[q2] = Q[q2];
+                    }
+                    e += (double)ep;
                 }
-                const T *a3 = sAt + (bL + Mi - L) * NMAX;
-                T A3[NMAX];
-#pragma unroll
-                for (int q = 0; q < NMAX; q++) A3[q] = a3[q];
-                const T *cr = B.C + n1 * NN;
-#pragma unroll
-                for (int q2 = 0; q2 < NMAX; q2++) {
-                    T acc = T(0);
-#pragma unroll
-                    for (int q3 = 0; q3 < NMAX; q3++) acc += cr[q2 * NMAX + q3] * A3[q3];
-                    Q[q2] = acc;
-                }
-                T *pp = B.P + Mi * NN + n1 * NMAX, *qq = B.Q + Mi * NN + n1 * NMAX;
-                T ep = T(0);
-#pragma unroll
-                for (int q2 = 0; q2 < NMAX; q2++) {
-                    ep += P[q2] * Q[q2];
-                    pp[q2] = P[q2];
-                    qq[q2] = Q[q2];
-                }
-                e += (double)ep;
-            }
+            };
+            if (NMAX % 4 == 0 && nM * NMAX * (NMAX / 4) <= kBlock)
+                pq(std::integral_constant<int, (NMAX % 4 == 0 ? 4 : NMAX)>());
+            else if (NMAX % 6 == 0 && nM * NMAX * (NMAX / 6) <= kBlock)
+                pq(std::integral_constant<int, (NMAX % 6 == 0 ? 6 : NMAX)>());
+            else
+                pq(std::integral_constant<int, NMAX>());
             __syncthreads();
             if (bout) {
                 // B of the block's basis functions: sum_M P_M[n1][n2] A_{n3 L M}

@@ -56,6 +56,27 @@ def test_nblist_bit_exact(oracle, cfg1):
         ctx.close()
 
 
+@pytest.mark.parametrize("r,cap", [(9.0, 256), (9.0, 320), (7.0, 320)],
+                         ids=["staged_one_cell", "unstaged_one_cell", "unstaged_3cells"])
+def test_nblist_bit_exact_other_paths(oracle, cfg1, r, cap):
+    """The list build's other instantiations on the 1,024-atom cell (box 25.3 A): with more than 256 slots
+    per atom the lists go straight to memory instead of through LDS; at r = 9 A a box holds only two cells
+    per dimension, so one cell spans it and every candidate takes its own minimum image. Bit-exact sets."""
+    import torch
+    from paper_2512_07693_amd import ap
+    pos = cfg1["pos"]
+    _say("nblist r=%.1f max_nbr=%d n=%d" % (r, cap, len(pos)))
+    ctx = ap.Context(len(pos), max_nbr=cap)
+    cnt, idx = ctx.nblist_build(to_dev(pos), cfg1["box"], r)
+    torch.cuda.synchronize()
+    cnt, idx = cnt.cpu().numpy(), idx.cpu().numpy()
+    want = oracle.nblist(pos, cfg1["box"], r)
+    assert max(len(w) for w in want) > (150 if r > 8 else 80)  # long lists
+    for i in range(len(pos)):
+        assert np.array_equal(np.sort(idx[:cnt[i], i]), want[i]), i
+    ctx.close()
+
+
 def _oracle_lists(oracle, pos, box, r, cap):
     """The oracle's neighbour sets as an (n, cap) array, ascending, padded with INT32_MAX."""
     n = len(pos)
