@@ -82,6 +82,8 @@ int sync_and_check(ap_ctx *c) {
     rc = hip_check(c, hipMemcpy(flags, c->d_flags, sizeof(flags), hipMemcpyDeviceToHost), "flags");
     if (rc) return rc;
     const int e = flags[1];
+    // a list built from non-finite positions, or truncated, is not kept: the next call rebuilds it
+    if (e & (kErrOverflow | kErrAceNbr | kErrAsym | kErrNonFinite)) c->list_r = -1;
     if (e & kErrOverflow) return set_error(c, AP_E_NBR_OVERFLOW, "neighbour count above max_nbr, or index out of range");
     if (e & kErrAceNbr) return set_error(c, AP_E_NBR_OVERFLOW, "more than 128 neighbours inside the ACE cutoff");
     if (e & kErrCsp) return set_error(c, AP_E_CSP, "CSP list invalid or too few neighbours for the CSP pairs");
@@ -229,7 +231,8 @@ __global__ __launch_bounds__(kBlock) void k_vv_first(double *pos, double *vel, c
         ipos[o] = x;
         u[a] = min_image_w(x - pos_build[o], L[a]);
     }
-    if (u[0] * u[0] + u[1] * u[1] + u[2] * u[2] > half_skin2) atomicOr(&flags[0], 1);
+    // (a non-finite displacement also asks for a rebuild)
+    if (!(u[0] * u[0] + u[1] * u[1] + u[2] * u[2] <= half_skin2)) atomicOr(&flags[0], 1);
 }
 
 // The thermo row of the last step of a velocity-Verlet call (the earlier ones are taken by the density

@@ -372,7 +372,7 @@ __global__ void k_skin_check(const double *__restrict__ pos, const double *__res
     double ux = min_image_w(pos[i] - pos_build[i], Lx);
     double uy = min_image_w(pos[n + i] - pos_build[n + i], Ly);
     double uz = min_image_w(pos[2 * n + i] - pos_build[2 * n + i], Lz);
-    if (ux * ux + uy * uy + uz * uz > half_skin2) atomicOr(&flags[0], 1);
+    if (!(ux * ux + uy * uy + uz * uz <= half_skin2)) atomicOr(&flags[0], 1);  // (non-finite: rebuild too)
 }
 
 bool list_geometry(const double *box, double r_list, Geometry &g) {
