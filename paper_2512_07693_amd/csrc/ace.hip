@@ -200,7 +200,8 @@ template <typename T, int NMAX, int LMAX>
 __global__ __launch_bounds__(kBlock, (sizeof(T) == 4 && NMAX == 12) ? 6 : 1) void k_ace_basis(AceArgs a) {
     constexpr int NLM = (LMAX + 1) * (LMAX + 1), NA = NMAX * NLM;
     constexpr int V = kAceMaxValid, CH = 64;  // neighbours kept per site; harmonics computed CH at a time
-    __shared__ T sR[CH * NMAX], sY[CH * NLM];
+    __shared__ alignas(16) T sR[CH * NMAX];  // (rows read as 16-byte vectors)
+    __shared__ T sY[CH * NLM];
     __shared__ T sA[NA];
     __shared__ T sU[V * 4];
     __shared__ double sRd[V], sS[NMAX];
@@ -305,11 +306,23 @@ __global__ __launch_bounds__(kBlock, (sizeof(T) == 4 && NMAX == 12) ? 6 : 1) voi
                 }
             }
             __syncthreads();
-            for (int o = tid; o < NA; o += kBlock) {
-                const int q = o / NLM, lm = o - q * NLM;
-                T acc = sA[o];
-                for (int v = 0; v < nc; v++) acc += sR[v * NMAX + q] * sY[v * NLM + lm];
-                sA[o] = acc;
+            // A[n][lm] += sum_v R[v][n] Y[v][lm]: a thread per (four n, lm), so that each pair of loads (one
+            // 16-byte radial row, one harmonic) feeds four FMAs
+            static_assert(NMAX % 4 == 0, "radial channels in fours");
+            for (int o = tid; o < (NMAX / 4) * NLM; o += kBlock) {
+                const int q4 = o / NLM, lm = o - q4 * NLM;
+                T acc[4];
+#pragma unroll
+                for (int j = 0; j < 4; j++) acc[j] = sA[(4 * q4 + j) * NLM + lm];
+                for (int v = 0; v < nc; v++) {
+                    const T y = sY[v * NLM + lm];
+                    T r4[4];
+                    ld4(sR + v * NMAX + 4 * q4, r4);
+#pragma unroll
+                    for (int j = 0; j < 4; j++) acc[j] += r4[j] * y;
+                }
+#pragma unroll
+                for (int j = 0; j < 4; j++) sA[(4 * q4 + j) * NLM + lm] = acc[j];
             }
             __syncthreads();
         }
