@@ -690,10 +690,18 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
     }
 }
 
+// threads per precise atom in the pair kernel (two wavefronts: one alone per atom, 64 threads, was slower:
+// 27.5 against 23.4 us per mixed step)
+constexpr int kPairThreads = 128;
+
 template <typename T, int NMAX, int LMAX>
-__global__ __launch_bounds__(128) void k_ace_pairforce(AceArgs a) {
-    constexpr int NLM = (LMAX + 1) * (LMAX + 1), NA = NMAX * NLM;
+__global__ __launch_bounds__(kPairThreads) void k_ace_pairforce(AceArgs a) {
+    constexpr int NLM = (LMAX + 1) * (LMAX + 1), NA = NMAX * NLM, NW = kPairThreads / 64;
     __shared__ alignas(16) T sGt[NA];  // G transposed: [lm][n]
+    // the pairs inside rc, compacted: slot, neighbour, u (in T), r^2 (FP64); sPC: wave counts and the total
+    __shared__ int sPS[kAceMaxValid], sPJ[kAceMaxValid], sPC[NW + 1];
+    __shared__ T sPU[4 * kAceMaxValid];
+    __shared__ double sPR2[kAceMaxValid];
     const int n = a.n;
     const int S = *a.scount;
     const double rc2 = a.rc * a.rc;
@@ -724,6 +732,7 @@ __global__ __launch_bounds__(128) void k_ace_pairforce(AceArgs a) {
         // (read by every thread before the barrier; rewritten only after the closing one)
         const int lgen = a.rslot ? *a.list_gen : 0;
         const bool cached = a.rslot && a.rstamp[i] == lgen;
+        if (threadIdx.x == 0) sPC[NW] = 0;
         __syncthreads();
         double Lx, Ly, Lz;
         atom_box(a, i, Lx, Ly, Lz);
@@ -731,16 +740,87 @@ __global__ __launch_bounds__(128) void k_ace_pairforce(AceArgs a) {
         const int cnt = a.ncount[i];
         T *fo = (T *)a.fpair + (size_t)s * a.max_nbr * 3;
         if (a.stamp && threadIdx.x == 0) a.stamp[i] = a.gen;
-        for (int slot = threadIdx.x; slot < cnt; slot += blockDim.x) {
-            const int j = a.nidx[(size_t)slot * n + i];
-            if (a.stamp) a.stamp[j] = a.gen;
-            const Rec4 pj = a.xl[j];
-            const double ux = min_image_w(pj.x - xi, Lx), uy = min_image_w(pj.y - yi, Ly), uz = min_image_w(pj.z - zi, Lz);
-            const double r2 = ux * ux + uy * uy + uz * uz;
+        // the slot k of i in j's list (lists are symmetric): j's gather reads the term of the pair at (k, j),
+        // coalesced over j. Searched eight entries at a time so that the search is not one long chain.
+        auto reverse_slot = [&](int slot, int j) {
+            if (cached) return a.rslot[(size_t)i * a.max_nbr + slot];
+            int kk = -1;
+            const int cj = a.ncount[j];
+            for (int b0 = 0; b0 < cj && kk < 0; b0 += 8) {
+                int v[8];
+#pragma unroll
+                for (int u = 0; u < 8; u++) v[u] = b0 + u < cj ? a.nidx[(size_t)(b0 + u) * n + j] : -1;
+#pragma unroll
+                for (int u = 0; u < 8; u++)
+                    if (v[u] == i && kk < 0) kk = b0 + u;
+            }
+            if (a.rslot) a.rslot[(size_t)i * a.max_nbr + slot] = kk;
+            return kk;
+        };
+        // phase 0: every slot; the pairs inside rc compacted in slot order (ballot prefix) into LDS, the
+        // others get a zero term here (and their reverse slot when the cache is being filled)
+        for (int base = 0; base < cnt; base += kPairThreads) {
+            const int slot = base + threadIdx.x;
+            bool in = false;
+            int j = 0;
+            double ux = 0, uy = 0, uz = 0, r2 = 0;
+            if (slot < cnt) {
+                j = a.nidx[(size_t)slot * n + i];
+                if (a.stamp) a.stamp[j] = a.gen;
+                const Rec4 pj = a.xl[j];
+                ux = min_image_w(pj.x - xi, Lx);
+                uy = min_image_w(pj.y - yi, Ly);
+                uz = min_image_w(pj.z - zi, Lz);
+                r2 = ux * ux + uy * uy + uz * uz;
+                in = r2 < rc2;
+            }
+            const unsigned long long m = __ballot(in);
+            const int wv = threadIdx.x >> 6;
+            if ((threadIdx.x & 63) == 0) sPC[wv] = __popcll(m);
+            __syncthreads();
+            int p = sPC[NW] + __popcll(m & ((1ull << (threadIdx.x & 63)) - 1ull));
+            for (int q = 0; q < wv; q++) p += sPC[q];
+            if (in && p < kAceMaxValid) {
+                sPS[p] = slot;
+                sPJ[p] = j;
+                sPU[4 * p] = (T)ux;
+                sPU[4 * p + 1] = (T)uy;
+                sPU[4 * p + 2] = (T)uz;
+                sPR2[p] = r2;
+            }
+            if (slot < cnt && !in) {
+                fo[3 * slot] = T(0);
+                fo[3 * slot + 1] = T(0);
+                fo[3 * slot + 2] = T(0);
+                // (outside rc the term is zero and the gather does not read it; the cache still wants the
+                // reverse slot of every pair that can come inside rc before the next build)
+                if (r2 < a.rw2 || (a.rslot && !cached && r2 < a.rrev2)) {
+                    const int kk = reverse_slot(slot, j);
+                    if (kk < 0) {
+                        atomicOr(&a.flags[1], kErrAsym);
+                    } else if (r2 < a.rw2) {
+                        T *fr = (T *)a.frev;
+                        const size_t st = (size_t)a.max_nbr * n, o = (size_t)kk * n + j;
+                        fr[o] = T(0);
+                        fr[st + o] = T(0);
+                        fr[2 * st + o] = T(0);
+                    }
+                }
+            }
+            __syncthreads();
+            if (threadIdx.x == 0)
+                for (int q = 0; q < NW; q++) sPC[NW] += sPC[q];
+            __syncthreads();
+        }
+        const int nv = min(sPC[NW], kAceMaxValid);
+        // phase 1: the pair terms of the compacted pairs, every lane busy
+        for (int c = threadIdx.x; c < nv; c += kPairThreads) {
+            const int slot = sPS[c], j = sPJ[c];
+            const double r2 = sPR2[c];
             T f0 = T(0), f1 = T(0), f2 = T(0);
-            if (r2 < rc2) {
+            {
                 const T r = (T)sqrt(r2), ir = T(1) / r;
-                const T x = (T)ux * ir, y = (T)uy * ir, z = (T)uz * ir;
+                const T x = sPU[4 * c] * ir, y = sPU[4 * c + 1] * ir, z = sPU[4 * c + 2] * ir;
                 T g[NMAX], dg[NMAX];
                 radial<T, NMAX>(r, rcT, g, dg);
                 // f = sum_{n, lm} G_{n lm} [g_n'(r) Y_lm uhat + g_n(r) grad_u Y_lm], the harmonics and
@@ -813,23 +893,7 @@ __global__ __launch_bounds__(128) void k_ace_pairforce(AceArgs a) {
             fo[3 * slot + 2] = f2;
             const bool need = r2 < a.rw2;
             if (!need && !(a.rslot && !cached && r2 < a.rrev2)) continue;
-            // the slot k of i in j's list (lists are symmetric): j's gather reads the term at (k, j),
-            // coalesced over j. Loads go out eight at a time so the search is not one long chain.
-            int kk = -1;
-            if (cached) {
-                kk = a.rslot[(size_t)i * a.max_nbr + slot];
-            } else {
-                const int cj = a.ncount[j];
-                for (int b0 = 0; b0 < cj && kk < 0; b0 += 8) {
-                    int v[8];
-#pragma unroll
-                    for (int u = 0; u < 8; u++) v[u] = b0 + u < cj ? a.nidx[(size_t)(b0 + u) * n + j] : -1;
-#pragma unroll
-                    for (int u = 0; u < 8; u++)
-                        if (v[u] == i && kk < 0) kk = b0 + u;
-                }
-                if (a.rslot) a.rslot[(size_t)i * a.max_nbr + slot] = kk;
-            }
+            const int kk = reverse_slot(slot, j);
             if (kk < 0) {
                 atomicOr(&a.flags[1], kErrAsym);
             } else if (need) {
@@ -1540,7 +1604,7 @@ static void launch_t(ap_ctx *c, AceArgs a, int grid) {
         k_ace_energy<T, NMAX, LMAX><<<eg, kBlock, 0, c->stream>>>(a);
     }
     ProfScope p(c, "ace_pairforce");
-    k_ace_pairforce<T, NMAX, LMAX><<<grid, 128, 0, c->stream>>>(a);
+    k_ace_pairforce<T, NMAX, LMAX><<<grid, kPairThreads, 0, c->stream>>>(a);
 }
 
 // Floating-point operations of the ACE kernels, counted from the tables: per S atom independent of
