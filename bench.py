@@ -40,11 +40,11 @@ FP64_PEAK_TFLOPS = 78.6
 # same counters read for a 1 GiB device copy (fetch x2.0, write x1.0), with a digest of the kernel's source
 # file and the shared header at the time: a kernel whose source has changed reports null until re-measured.
 MEASURED_TRAFFIC = {
-    "ace_energy": (10.88e6, "ace.hip", "d416840bb0f0d8ae"),
-    "ace_basis": (10.14e6, "ace.hip", "d416840bb0f0d8ae"),
-    "ace_pairforce": (20.34e6, "ace.hip", "d416840bb0f0d8ae"),
-    "force": (87.37e6, "forces.hip", "2c06fb4532e39170"),
-    "dens_desc": (83.94e6, "forces.hip", "2c06fb4532e39170"),
+    "ace_energy": (10.86e6, "ace.hip", "3c4ab83d687155fc"),
+    "ace_basis": (10.15e6, "ace.hip", "3c4ab83d687155fc"),
+    "ace_pairforce": (20.50e6, "ace.hip", "3c4ab83d687155fc"),
+    "force": (87.43e6, "forces.hip", "2c06fb4532e39170"),
+    "dens_desc": (83.98e6, "forces.hip", "2c06fb4532e39170"),
     "W": (7.55e6, "forces.hip", "2c06fb4532e39170"),
 }
 
