@@ -212,6 +212,29 @@ def test_mixed_is_deterministic(cfg1):
     ctx.close()
 
 
+def test_vv_is_bit_reproducible_full_size():
+    """Two fresh contexts run 30 velocity-Verlet steps of the 128,000-atom workload (FP32 ACE, x = 1 %: more
+    precise atoms than resident energy workgroups, so some atoms run split into parts taken from the device
+    work queue in whatever order the workgroups arrive). Every sum runs in a fixed order, so positions,
+    velocities, forces and the thermo rows agree bit for bit."""
+    import torch
+    s = synth.build_system(2)
+    _say("bit reproducibility, n=%d, 30 steps" % len(s["pos"]))
+    runs = []
+    for _ in range(2):
+        ctx, _ = make_ctx(s)
+        pos, vel = to_dev(s["pos"]), to_dev(s["vel"])
+        F = ctx.mixed_energy_forces(pos, s["box"])["F"]
+        th = ctx.vv_step(pos, vel, F, s["mass"], s["run"]["dt"], 30, s["box"])
+        torch.cuda.synchronize()
+        runs.append([t.cpu().numpy() for t in (pos, vel, F, th)])
+        ctx.close()
+    _say("  precise atoms per step: %d-%d" % (int(runs[0][3][:, 6].min()), int(runs[0][3][:, 6].max())))
+    assert runs[0][3][:, 6].max() > 1024  # the split into parts is exercised
+    for a, b in zip(runs[0], runs[1]):
+        assert np.array_equal(a, b)
+
+
 def test_velocity_verlet_10_steps(oracle, cfg1, cfg1_oracle):
     _say("vv 10 steps cfg1")
     ctx, _ = make_ctx(cfg1)
