@@ -271,6 +271,33 @@ def test_velocity_verlet_across_rebuilds(oracle, cfg1, cfg1_oracle):
     ctx.close()
 
 
+def test_velocity_verlet_time_reversible(cfg1):
+    """Velocity Verlet is time reversible: 100 FP64 steps of the mixed potential (with list rebuilds and atoms
+    entering and leaving S on the way), then the velocities negated and 100 steps more, return every atom to
+    its start and its velocity to minus its start. A pin independent of the oracle."""
+    _say("vv time reversal cfg1")
+    ctx, _ = make_ctx(cfg1)
+    pos, vel = to_dev(cfg1["pos"]), to_dev(cfg1["vel"])
+    p0, v0 = soa_to_aos(pos).copy(), soa_to_aos(vel).copy()
+    F = ctx.mixed_energy_forces(pos, cfg1["box"])["F"]
+    th_f = ctx.vv_step(pos, vel, F, cfg1["mass"], 1e-3, 100, cfg1["box"]).cpu().numpy()
+    d = soa_to_aos(pos) - p0
+    d -= cfg1["box"] * np.rint(d / cfg1["box"])
+    moved = float(np.abs(d).max())
+    vel.neg_()
+    th_b = ctx.vv_step(pos, vel, F, cfg1["mass"], 1e-3, 100, cfg1["box"]).cpu().numpy()
+    _say("  rebuilds forward %d, back %d; largest excursion %.3f A" % (int(th_f[:, 7].sum()), int(th_b[:, 7].sum()),
+                                                                        moved))
+    assert moved > 0.05
+    d = soa_to_aos(pos) - p0
+    d -= cfg1["box"] * np.rint(d / cfg1["box"])
+    _lt("pos", float(np.abs(d).max()), 1e-10)
+    _lt("vel", float(np.abs(soa_to_aos(vel) + v0).max()), 1e-8)
+    # the backward run's total energy retraces the forward run's (thermo rows in reverse order)
+    _lt("E_tot", float(np.abs(th_b[::-1, 2][1:] - th_f[:-1, 2]).max()) / len(p0), 1e-12)
+    ctx.close()
+
+
 def test_ace_fp32_large_basis(oracle):
     """Pure ACE with the n_max 12 / l_max 6 basis (32,686 functions) in FP32 on a 250-atom cell."""
     s = synth.build_system(2, nc=5)
