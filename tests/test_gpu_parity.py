@@ -202,6 +202,22 @@ def test_mixed_fp64_matches_oracle(cfg1, cfg1_oracle):
     ctx.close()
 
 
+def test_mixed_limits_are_bitwise(cfg1):
+    """Eq. (4) with exact weights: the mixed evaluation with lambda forced to 1 is the EAM evaluation, and with
+    lambda forced to 0 the ACE evaluation, bit for bit (energies, per-atom energies and forces)."""
+    _say("mixed limits cfg1")
+    pos = to_dev(cfg1["pos"])
+    for mode, single in ((1, "eam_eval"), (0, "ace_eval")):
+        ctx, _ = make_ctx(cfg1, lambda_mode=mode)
+        mixed = ctx.mixed_energy_forces(pos, cfg1["box"])
+        alone = getattr(ctx, single)(pos, cfg1["box"])
+        for k in ("E", "E_atom", "F"):
+            a, b = mixed[k].cpu().numpy(), alone[k].cpu().numpy()
+            _say("  lambda = %d, %s: max |diff| %.3e" % (mode, k, float(np.abs(a - b).max())))
+            assert np.array_equal(a, b)
+        ctx.close()
+
+
 def test_mixed_is_deterministic(cfg1):
     _say("determinism cfg1")
     ctx, _ = make_ctx(cfg1)
