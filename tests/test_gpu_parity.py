@@ -218,6 +218,63 @@ def test_mixed_limits_are_bitwise(cfg1):
         ctx.close()
 
 
+def test_ace_rotation_invariance_isolated_cluster(cfg1):
+    """The ACE site energies are rotation invariants of the neighbourhood and the forces rotate with it: an
+    isolated cluster cut from the 1,024-atom cell (every atom within 8 A of the cell centre, in a 40 A box) and
+    the same cluster under a random rotation about its centre, pure ACE in FP64. A pin of the real harmonics and
+    their coupling tables that does not go through the oracle."""
+    from tests.helpers import rotation
+    _say("ace rotation invariance, isolated cluster")
+    L = np.asarray(cfg1["box"], dtype=np.float64)
+    p = np.asarray(cfg1["pos"], dtype=np.float64) - 0.5 * L
+    p -= L * np.rint(p / L)
+    u = p[np.einsum("ij,ij->i", p, p) < 64.0]
+    R = rotation(11)
+    box = np.array([40.0, 40.0, 40.0])
+    out = []
+    for q in (u, u @ R.T):
+        s = dict(cfg1, pos=q + 20.0, pos_ref=q + 20.0, box=box)
+        ctx, _ = make_ctx(s, lambda_mode=0)
+        r = ctx.ace_eval(to_dev(s["pos"]), box)
+        out.append({k: r[k].cpu().numpy() for k in ("E", "E_atom")} | {"F": soa_to_aos(r["F"])})
+        ctx.close()
+    _say("  %d atoms" % len(u))
+    _lt("E_atom", _rel(out[1]["E_atom"], out[0]["E_atom"]), 1e-12)
+    _lt("F", force_err_max(out[1]["F"], out[0]["F"] @ R.T), TOL_F64_FORCE)
+    assert np.abs(out[0]["F"]).max() > 0.1  # the surface atoms carry real forces
+
+
+def test_mixed_cubic_rotation(cfg1):
+    """The periodic cell turned by 90 degrees about z, (x, y, z) -> (L - y, x, z), with the same CSP pair list
+    (by atom index): the mixed energies, lambda and per-atom energies are unchanged and the forces turn with
+    the cell."""
+    _say("mixed, cell turned by 90 degrees")
+    L = float(cfg1["box"][0])
+    assert np.allclose(cfg1["box"], L)
+
+    def turn(p):
+        p = np.asarray(p, dtype=np.float64)
+        return np.stack([L - p[:, 1], p[:, 0], p[:, 2]], axis=1)
+
+    ctx, csp = make_ctx(cfg1)
+    a = ctx.mixed_energy_forces(to_dev(cfg1["pos"]), cfg1["box"])
+    a = {k: a[k].cpu().numpy() for k in ("E", "E_atom", "lam")} | {"F": soa_to_aos(a["F"])}
+    ctx.close()
+    s = dict(cfg1, pos=turn(cfg1["pos"]), pos_ref=turn(cfg1["pos_ref"]))
+    ctx, _ = make_ctx(s, build_csp=False)
+    ctx.set_csp_list(csp)
+    b = ctx.mixed_energy_forces(to_dev(s["pos"]), s["box"])
+    b = {k: b[k].cpu().numpy() for k in ("E", "E_atom", "lam")} | {"F": soa_to_aos(b["F"])}
+    ctx.close()
+    Rz = np.array([[0.0, -1.0, 0.0], [1.0, 0.0, 0.0], [0.0, 0.0, 1.0]])
+    _say("  precise atoms %d" % int((a["lam"] < 1).sum()))
+    assert (a["lam"] < 1).sum() > 10
+    _lt("lambda", float(np.abs(b["lam"] - a["lam"]).max()), 1e-10)
+    _lt("E_atom", _rel(b["E_atom"], a["E_atom"]), 1e-12)
+    _lt("E/N", abs(float(b["E"].item()) - float(a["E"].item())) / len(a["lam"]), 1e-12)
+    _lt("F", force_err_max(b["F"], a["F"] @ Rz.T), TOL_F64_FORCE)
+
+
 def test_mixed_is_deterministic(cfg1):
     _say("determinism cfg1")
     ctx, _ = make_ctx(cfg1)
