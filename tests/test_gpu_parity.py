@@ -275,6 +275,51 @@ def test_mixed_cubic_rotation(cfg1):
     _lt("F", force_err_max(b["F"], a["F"] @ Rz.T), TOL_F64_FORCE)
 
 
+def test_mixed_forces_are_minus_energy_gradient(cfg1):
+    """Eq. (5) on the HIP path alone: central differences (h = 1e-4 A) of the mixed energy against the forces,
+    FP64. The switching window is set at the 85th and 97th percentiles of d, so that lambda spans the whole band:
+    atoms at lambda = 0, across 0 < lambda < 1 (where the gradient of lambda acts) and fast atoms next to it."""
+    import torch
+    _say("mixed forces vs central differences of the energy, cfg1")
+    ctx, _ = make_ctx(cfg1)
+    pos = to_dev(cfg1["pos"])
+    d = ctx.switch_eval(pos, cfg1["box"])["d"].cpu().numpy()
+    ctx.close()
+    s = dict(cfg1, sw=dict(cfg1["sw"], d_lo=float(np.quantile(d, 0.85)), d_hi=float(np.quantile(d, 0.97))))
+    ctx, _ = make_ctx(s)
+    out = ctx.mixed_energy_forces(pos, s["box"])
+    lam, F = out["lam"].cpu().numpy(), out["F"].cpu().numpy()
+    band = np.nonzero((lam > 0) & (lam < 1))[0]
+    band = band[np.argsort(lam[band])]
+    inner = np.nonzero(lam == 0)[0]
+    outer = np.nonzero(lam == 1)[0]
+    # the fast atoms nearest to the band, where only the gradient of lambda reaches
+    L = np.asarray(s["box"], float)
+    p = np.asarray(s["pos"], float)
+    dmin = np.full(len(outer), np.inf)
+    for b in band:
+        u = p[outer] - p[b]
+        u -= L * np.rint(u / L)
+        dmin = np.minimum(dmin, np.einsum("ij,ij->i", u, u))
+    assert len(band) >= 6 and len(inner) >= 2
+    picks = (list(inner[:2]) + list(band[[0, len(band) // 4, len(band) // 2, 3 * len(band) // 4, len(band) - 1]])
+             + list(outer[np.argsort(dmin)[:3]]))
+    h, worst = 1e-4, 0.0
+    for i in picks:
+        for c in range(3):
+            e = []
+            for sgn in (1.0, -1.0):
+                q = pos.clone()
+                q[c, i] += sgn * h
+                e.append(ctx.mixed_energy_forces(q, s["box"])["E"].item())
+            fd = -(e[0] - e[1]) / (2 * h)
+            worst = max(worst, abs(fd - F[c, i]) / max(1.0, abs(F[c, i])))
+    torch.cuda.synchronize()
+    ctx.close()
+    _say("  %d atoms (lambda %s)" % (len(picks), " ".join("%.2f" % lam[i] for i in picks)))
+    _lt("|fd - F|", worst, 1e-6)
+
+
 def test_mixed_is_deterministic(cfg1):
     _say("determinism cfg1")
     ctx, _ = make_ctx(cfg1)
