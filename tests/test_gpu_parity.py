@@ -320,6 +320,34 @@ def test_mixed_forces_are_minus_energy_gradient(cfg1):
     _lt("|fd - F|", worst, 1e-6)
 
 
+def test_mixed_virial_is_minus_strain_derivative(cfg1):
+    """The virial of the HIP path against central differences of its own energy under a diagonal affine strain
+    of box and positions (eps = 1e-6), FP64, with the switching window of the gradient test above (lambda
+    spanning the band). The strained cells keep the same CSP pair list by atom index."""
+    _say("mixed virial vs strain derivative, cfg1")
+    ctx, csp = make_ctx(cfg1)
+    pos0 = np.asarray(cfg1["pos"], float)
+    d = ctx.switch_eval(to_dev(pos0), cfg1["box"])["d"].cpu().numpy()
+    ctx.close()
+    s = dict(cfg1, sw=dict(cfg1["sw"], d_lo=float(np.quantile(d, 0.85)), d_hi=float(np.quantile(d, 0.97))))
+    ctx, _ = make_ctx(s, build_csp=False)
+    ctx.set_csp_list(csp)
+    box0 = np.asarray(s["box"], float)
+    W = ctx.mixed_energy_forces(to_dev(pos0), box0)["virial"].cpu().numpy()
+    eps, worst = 1e-6, 0.0
+    for a in range(3):
+        e = []
+        for sgn in (1.0, -1.0):
+            f = np.ones(3)
+            f[a] += sgn * eps
+            e.append(ctx.mixed_energy_forces(to_dev(pos0 * f), box0 * f)["E"].item())
+        fd = -(e[0] - e[1]) / (2 * eps)
+        _say("  W[%d][%d] = %.6f, -dE/deps = %.6f eV" % (a, a, W[a, a], fd))
+        worst = max(worst, abs(fd - W[a, a]) / max(1.0, abs(W[a, a])))
+    ctx.close()
+    _lt("|fd - W|", worst, 1e-5)
+
+
 def test_mixed_is_deterministic(cfg1):
     _say("determinism cfg1")
     ctx, _ = make_ctx(cfg1)
