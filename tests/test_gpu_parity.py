@@ -151,6 +151,32 @@ def test_switching_matches_oracle(cfg1, cfg1_oracle):
     ctx.close()
 
 
+def test_csp_value_closed_forms(cfg1):
+    """The CSP value kernel, (B3), against its closed forms on a perfect bcc lattice (the 1,024-atom cell's
+    lattice, pairs detected on it): g = 0 everywhere; the centre atom moved by delta gives 16 |delta|^2 (four
+    opposite pairs, each |-2 delta|^2); one listed neighbour moved by delta gives |delta|^2 at the centre."""
+    import synth.structures as st
+    _say("csp value closed forms")
+    lat, box = st.bcc(3.16, 8)
+    s = dict(cfg1, pos=lat, pos_ref=lat, box=box)
+    ctx, csp = make_ctx(s)
+    g = ctx.switch_eval(to_dev(lat), box)["g"].cpu().numpy()
+    _lt("g perfect", float(np.abs(g).max()), 1e-24)
+    delta = np.array([0.031, -0.017, 0.023])
+    dd = float(delta @ delta)
+    i = 300
+    p = lat.copy()
+    p[i] += delta
+    g = ctx.switch_eval(to_dev(p), box)["g"].cpu().numpy()
+    _lt("g centre", abs(g[i] - 16.0 * dd) / (16.0 * dd), 1e-12)
+    j = int(csp.cpu().numpy()[i, 3])
+    p = lat.copy()
+    p[j] += delta
+    g = ctx.switch_eval(to_dev(p), box)["g"].cpu().numpy()
+    _lt("g partner", abs(g[i] - dd) / dd, 1e-12)
+    ctx.close()
+
+
 def test_eam_matches_oracle(oracle, cfg1):
     _say("eam_eval cfg1")
     ctx, _ = make_ctx(cfg1, lambda_mode=1)
