@@ -15,7 +15,7 @@
 //   k_mlp_indicator  one thread per atom for the features, then the forward pass of the wavefront's 64
 //                    atoms on the matrix cores; g (or the features alone)
 //   k_mlp_eval       one thread per sample: g and dg/dq from given features
-//   k_mlp_gradg      one wavefront per atom with W_j != 0: features, backward pass (a hidden unit per
+//   k_mlp_gradg      one wavefront per atom with W_j != 0 (four per workgroup): features, backward pass (a hidden unit per
 //                    lane), and h_jk = W_j dg_j/du_jk per neighbour slot, stored at (j, slot) and
 //                    slot-major at (slot of j in k's list, k) for the gather-only force kernel
 //   k_mlp_fb         one thread per training sample: forward and backward, activations written
@@ -316,24 +316,42 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
-// grad-g terms of the atoms with W_j != 0 (one wavefront each)
-__global__ __launch_bounds__(64) void k_mlp_gradg(MlpArgs a) {
+// grad-g terms of the atoms with W_j != 0: kGradgWaves wavefronts per workgroup, one atom each, sharing one
+// copy of the parameters in LDS. Every wavefront of a workgroup runs the same number of rounds (a wavefront
+// without an atom in the last one only takes part in its barriers).
+constexpr int kGradgWaves = 4;
+__global__ __launch_bounds__(64 * kGradgWaves) void k_mlp_gradg(MlpArgs a) {
     __shared__ float sP[kNP];
-    __shared__ float sH[kNH], sD[kNH], sQ[kNQ], sDQ[kNQ], sA[48];
+    // W1 and W2 transposed as well ([f][c] and [k][c]): the forward pass reads them across the lanes
+    // (hidden unit c per lane) like the backward pass reads the originals, each without bank conflicts
+    __shared__ float sW1t[kNQ * kNH], sW2t[kNH * kNH];
+    __shared__ float sHw[kGradgWaves][kNH], sDw[kGradgWaves][kNH], sQw[kGradgWaves][kNQ],
+        sDQw[kGradgWaves][kNQ], sAw[kGradgWaves][48];
+    for (int q = threadIdx.x; q < kNH * kNQ; q += blockDim.x) {
+        const int c = q / kNQ, f = q - c * kNQ;
+        sW1t[f * kNH + c] = a.P[kW1 + q];
+    }
+    for (int q = threadIdx.x; q < kNH * kNH; q += blockDim.x) {
+        const int c = q / kNH, k = q - c * kNH;
+        sW2t[k * kNH + c] = a.P[kW2 + q];
+    }
     load_params(sP, a.P);
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    float *sH = sHw[wv], *sD = sDw[wv], *sQ = sQw[wv], *sDQ = sDQw[wv], *sA = sAw[wv];
     const int n = a.n;
     const double rc2 = a.rc * a.rc;
     const float rcf = (float)a.rc;
     const int nw = *a.wcount;
     const int lgen = *a.list_gen;
-    for (int w = blockIdx.x; w < nw; w += gridDim.x) {
-        const int j = a.wlist[w];
+    for (int base = blockIdx.x * kGradgWaves; base < nw; base += gridDim.x * kGradgWaves) {
+        const int w = base + wv;
+        const bool act = w < nw;
+        const int j = act ? a.wlist[w] : 0;
         // j's reverse slots from the cache when searched on the current list (read before the barriers
         // below; rewritten only after the closing one)
         const bool cached = a.rstamp[j] == lgen;
         const double xj = a.pos[j], yj = a.pos[n + j], zj = a.pos[2 * n + j];
-        const int cnt = a.ncount[j];
+        const int cnt = act ? a.ncount[j] : 0;
         // 1. features: per-lane partial sums over its slots, then a butterfly over the wavefront
         float q8[8], A[48];
 #pragma unroll
@@ -389,11 +407,11 @@ __global__ __launch_bounds__(64) void k_mlp_gradg(MlpArgs a) {
         // 2. network forward and backward, hidden unit `lane` per lane
         float a1 = sP[kB1 + lane];
 #pragma unroll
-        for (int f = 0; f < kNQ; f++) a1 += sP[kW1 + lane * kNQ + f] * sQ[f];
+        for (int f = 0; f < kNQ; f++) a1 += sW1t[f * kNH + lane] * sQ[f];
         sH[lane] = a1 * sigm(a1);
         __syncthreads();
         float a2 = sP[kB2 + lane];
-        for (int k = 0; k < kNH; k++) a2 += sP[kW2 + lane * kNH + k] * sH[k];
+        for (int k = 0; k < kNH; k++) a2 += sW2t[k * kNH + lane] * sH[k];
         const float o = wave_sum(sP[kW3 + lane] * (a2 * sigm(a2))) + sP[kB3];
         const float go = sigm(o);
         sD[lane] = go * sP[kW3 + lane] * silu_d(a2);
@@ -412,7 +430,7 @@ __global__ __launch_bounds__(64) void k_mlp_gradg(MlpArgs a) {
         __syncthreads();
         // 3. h_jk = W_j dg_j/du_jk for every slot; written at (w, slot) and at (slot of j in k's list, k)
         const float Wj = (float)a.W[j];
-        float* hp = a.hpair + (size_t)w * a.max_nbr * 3;
+        float *hp = a.hpair + (size_t)(act ? w : 0) * a.max_nbr * 3;
         for (int slot = lane; slot < cnt; slot += 64) {
             const int k = a.nidx[(size_t)slot * n + j];
             const Rec4 pk = a.xl[k];
@@ -482,7 +500,7 @@ __global__ __launch_bounds__(64) void k_mlp_gradg(MlpArgs a) {
             }
         }
         __syncthreads();
-        if (!cached && threadIdx.x == 0) a.rstamp[j] = lgen;
+        if (act && !cached && lane == 0) a.rstamp[j] = lgen;
     }
 }
 
@@ -705,7 +723,9 @@ void launch_mlp_gradg(ap_ctx *c, int n, const double *box) {
     launch_scan(c, c->blk_cnt, c->blk_cnt + nb, nb, c->d_flags + 4, nullptr);
     k_wscatter<<<nb, kBlock, 0, c->stream>>>(n, c->W, c->blk_cnt + nb, c->widx, c->wlist);
     MlpArgs a = mlp_args(c, n, box);
-    k_mlp_gradg<<<std::max(1, std::min(n, 16384)), 64, 0, c->stream>>>(a);
+    // enough workgroups to fill the GPU (each loads the parameters once), not one per atom
+    k_mlp_gradg<<<std::max(1, std::min((n + kGradgWaves - 1) / kGradgWaves, 2048)), 64 * kGradgWaves, 0,
+                  c->stream>>>(a);
 }
 
 int mlp_alloc(ap_ctx *c) {
