@@ -40,12 +40,12 @@ FP64_PEAK_TFLOPS = 78.6
 # same counters read for a 1 GiB device copy (fetch x2.0, write x1.0), with a digest of the kernel's source
 # file and the shared header at the time: a kernel whose source has changed reports null until re-measured.
 MEASURED_TRAFFIC = {
-    "ace_energy": (10.86e6, "ace.hip", "3c4ab83d687155fc"),
-    "ace_basis": (10.15e6, "ace.hip", "3c4ab83d687155fc"),
-    "ace_pairforce": (20.50e6, "ace.hip", "3c4ab83d687155fc"),
-    "force": (87.43e6, "forces.hip", "2c06fb4532e39170"),
-    "dens_desc": (83.98e6, "forces.hip", "2c06fb4532e39170"),
-    "W": (7.55e6, "forces.hip", "2c06fb4532e39170"),
+    "ace_energy": (10.84e6, "ace.hip", "3c4ab83d687155fc"),
+    "ace_basis": (10.14e6, "ace.hip", "3c4ab83d687155fc"),
+    "ace_pairforce": (19.84e6, "ace.hip", "3c4ab83d687155fc"),
+    "force": (71.50e6, "forces.hip", "b279c4e7dc4db373"),
+    "dens_desc": (83.98e6, "forces.hip", "b279c4e7dc4db373"),
+    "W": (7.55e6, "forces.hip", "b279c4e7dc4db373"),
 }
 
 

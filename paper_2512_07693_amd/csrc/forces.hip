@@ -474,7 +474,8 @@ struct ForceArgs {
     double ace_rc2;  // reverse ACE terms exist only inside the ACE cutoff
     double mlp_rc2;  // and reverse grad-g terms only inside the feature cutoff
     const int32_t *csp_t, *rev_start, *rev_code;
-    double *E_atom, *F, *partials;  // partials: [16][pstride] per-block sums, column-major
+    double *E_atom, *F, *partials;  // partials: [16][pstride] per-tile sums, column-major
+    int ntiles;                     // tiles of kBlock / SUB atoms (force_blocks(n))
     int pstride;
     int *flags;
     const double *sbox;  // per-structure boxes of a batch (null: L)
@@ -535,17 +536,22 @@ __device__ __forceinline__ void block_sums(const double *v, double *sh, double *
 // and the CSP part so that it keeps its own, lower register count. With FP32 pair terms the full kernel
 // is bounded to four workgroups per CU (128 VGPRs, no spills).
 // MIX: force mixing, Eq. (3) (an instantiation of its own, so that the conservative kernel keeps its registers).
+constexpr int kForceChunk = 16;
 template <typename TF, int SUB, bool FULL, bool MIX = false>
 __global__ __launch_bounds__(kBlock, (FULL && sizeof(TF) == 4) ? 4 : 1) void k_force(ForceArgs a) {
     __shared__ double sh[kBlock / 64 * 14];
-    // plain block order (as in the W pass): the atoms with a precise atom in reach are contiguous index
-    // ranges, spread this way over every XCD
-    const int blk = blockIdx.x;
-    const int t = blk * blockDim.x + threadIdx.x;
-    for (int q = t; q < a.ncell; q += gridDim.x * blockDim.x) {  // (with the fused drift)
-        a.cell_cnt[q] = 0;
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < a.ncell; q += gridDim.x * blockDim.x) {
+        a.cell_cnt[q] = 0;  // (with the fused drift)
         a.cell_fill[q] = 0;
     }
+    // Block b runs on XCD b % 8. Each XCD takes chunks of kForceChunk consecutive tiles (kBlock / SUB
+    // atoms each), the chunks dealt round-robin over the XCDs: a chunk's atoms share their neighbours in
+    // that XCD's L2, while the few contiguous index ranges of atoms near S still spread over every XCD.
+    // The grid is a multiple of 8 kForceChunk; blocks past the last tile only clear cells.
+    const int xcd = blockIdx.x & 7, kth = blockIdx.x >> 3;
+    const int blk = ((kth / kForceChunk) * 8 + xcd) * kForceChunk + kth % kForceChunk;
+    if (blk >= a.ntiles) return;
+    const int t = blk * blockDim.x + threadIdx.x;
     const int i = t / SUB, sub = t - i * SUB;  // SUB lanes per atom, slots sub, sub + SUB, ...
     const int n = a.n;
     double F0 = 0, F1 = 0, F2 = 0, Ei = 0;
@@ -862,7 +868,8 @@ void launch_force(ap_ctx *c, int n, const double *box, const EvalFlags &f, doubl
     // the learned indicator needs the marks of the W pass to know who receives grad-g terms
     if (!sbox && f.switching && f.grad_lambda && c->sw.indicator == AP_IND_MLP && csp_marked) a.short_mode = 1;
     if (!sbox && !f.switching && (!f.ace_forces || f.lam_const == 1.0)) a.short_mode = uniform_lambda ? 2 : 3;
-    const int nb = force_blocks(n);
+    a.ntiles = force_blocks(n);
+    const int nb = (a.ntiles + 8 * kForceChunk - 1) / (8 * kForceChunk) * (8 * kForceChunk);
     if (a.short_mode == 2)
         k_force<double, kForceLanes, false><<<nb, kBlock, 0, c->stream>>>(a);
     else if (f.force_mix && a.fp32)
