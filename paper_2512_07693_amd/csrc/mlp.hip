@@ -15,9 +15,9 @@
 //   k_mlp_indicator  one thread per atom for the features, then the forward pass of the wavefront's 64
 //                    atoms on the matrix cores; g (or the features alone)
 //   k_mlp_eval       one thread per sample: g and dg/dq from given features
-//   k_mlp_gradg      one wavefront per atom with W_j != 0 (four per workgroup): features, backward pass (a hidden unit per
-//                    lane), and h_jk = W_j dg_j/du_jk per neighbour slot, stored at (j, slot) and
-//                    slot-major at (slot of j in k's list, k) for the gather-only force kernel
+//   k_mlp_gradg      one wavefront per atom with W_j != 0, four per workgroup: features, backward pass
+//                    (a hidden unit per lane), and h_jk = W_j dg_j/du_jk per neighbour slot, stored at
+//                    (j, slot) and slot-major at (slot of j in k's list, k) for the gather-only force kernel
 //   k_mlp_fb         one thread per training sample: forward and backward, activations written
 //                    feature-major for the weight-gradient reduction
 //   k_mlp_wgrad      one wavefront per parameter: sums over the batch in a fixed order
