@@ -560,6 +560,27 @@ def large_run(steps, warmup, pure_steps):
         out["pure_ace"] = dict(value=n * pure_steps / (ms_p / 1e3), ms_per_step=ms_p / pure_steps)
         out["speedup_vs_pure_ace"] = (ms_p / pure_steps) / (ms / steps)
         cp.close()
+    # the same recipe at x = 0.1 % and 1 %: the precise fraction set by the crack's size (radius 18 and 67 A
+    # instead of 40 A), the switching thresholds unchanged
+    out["x_variants"] = []
+    for radius in (18.0, 67.0):
+        sv = synth.build_system(5, defect=dict(radius=radius))
+        nv = len(sv["pos"])
+        pv = torch.tensor(np.ascontiguousarray(sv["pos"].T), device="cuda")
+        vv = torch.tensor(np.ascontiguousarray(sv["vel"].T), device="cuda")
+        cv = ap.Context(nv, max_nbr=160, skin=sv["run"]["skin"])
+        cv.set_potential(sv["eam"], sv["ace"], sv["sw"])
+        cv.csp_pairs_build(torch.tensor(np.ascontiguousarray(sv["pos_ref"].T), device="cuda"), sv["box"],
+                           sv["sw"]["n_csp"])
+        log("fcc penny crack, radius %.0f A: mixed %d + %d steps ..." % (radius, warmup, steps))
+        msv, thv, _, _ = run_md(cv, sv, pv, vv, steps, warmup, 0)
+        cv.close()
+        nvev = drift_fit(thv, nv, sv["run"]["dt"])
+        e = dict(crack_radius_A=radius, n_atoms=nv, x_mean=nvev["x_mean"], value=nv * steps / (msv / 1e3),
+                 ms_per_step=msv / steps, drift_eV_per_atom_per_ps=nvev["drift_eV_per_atom_per_ps"])
+        if "pure_ace" in out:
+            e["speedup_vs_pure_ace"] = out["pure_ace"]["ms_per_step"] / (msv / steps)
+        out["x_variants"].append(e)
     return out
 
 

@@ -89,7 +89,7 @@ def ace_unit_draw(k, n_funcs):
     return np.random.default_rng(3000 + k).normal(0.0, 1.0, n_funcs)
 
 
-def _structure(rc, k, cal, nc_override=None):
+def _structure(rc, k, cal, nc_override=None, defect_override=None):
     """(pos, box, pos_ref): pos_ref is the lattice with the planted defect, before the seeded
     Gaussian noise; pos = pos_ref + noise. The CSP opposite-neighbour pairs are detected on
     pos_ref (the initial structure)."""
@@ -102,6 +102,7 @@ def _structure(rc, k, cal, nc_override=None):
     if d is not None:
         d = dict(d)
         d.update(cal.get("defect", {}))
+        d.update(defect_override or {})
         if d["kind"] == "screw_dipole":
             b = rc["a"] * np.sqrt(3.0) / 2.0
             off = drng.uniform(-0.25, 0.25, 2) * rc["a"]
@@ -121,10 +122,11 @@ def _structure(rc, k, cal, nc_override=None):
     return pos, box, pos_ref
 
 
-def build_system(k, nc=None, with_velocities=True):
+def build_system(k, nc=None, with_velocities=True, defect=None):
     """Everything workload k feeds the method, as float64/int32 numpy arrays.
 
-    nc overrides the number of cells (smaller test variants of the same recipe).
+    nc overrides the number of cells (smaller test variants of the same recipe); defect overrides entries of
+    the planted defect (e.g. the penny crack's radius, to set the precise fraction x by the defect's size).
     """
     rc = recipe(k)
     cal = load_config(k)
@@ -147,7 +149,7 @@ def build_system(k, nc=None, with_velocities=True):
                run=dict(dt=rc["dt"], steps=rc["steps"], T=rc["T"], skin=rc["skin"]))
     if rc["lattice"] == "batch":
         return out
-    pos, box, pos_ref = _structure(rc, k, cal, nc)
+    pos, box, pos_ref = _structure(rc, k, cal, nc, defect)
     out.update(pos=pos, box=box, pos_ref=pos_ref)
     if with_velocities:
         out["vel"] = st.maxwell_velocities(len(pos), rc["mass"], rc["T"], np.random.default_rng(4000 + k))
