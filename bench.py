@@ -206,10 +206,12 @@ def cpu_baseline(s, steps, x):
     O.evaluate(s, csp=csp)
     t_one = time.time() - t
     O.set_threads(0)
-    # the velocity_verlet call also evaluates the initial forces once: steps + 1 evaluations
-    return dict(value=n * steps / t_vv, unit="atom-steps/s", cores=int(cores), kind="oracle",
-                sample="%d velocity-Verlet steps (plus the initial force evaluation) of the full %d-atom "
-                       "workload, FP64 oracle in S-skip mode, %.1f s" % (steps, n, t_vv),
+    # the velocity_verlet call also evaluates the initial forces once (steps + 1 evaluations): that
+    # evaluation, timed on its own above, is taken out
+    t_steps = max(t_vv - t_mix, 1e-9)
+    return dict(value=n * steps / t_steps, unit="atom-steps/s", cores=int(cores), kind="oracle",
+                sample="%d velocity-Verlet steps of the full %d-atom workload, FP64 oracle in S-skip mode, "
+                       "%.1f s (%.1f s with the initial force evaluation)" % (steps, n, t_steps, t_vv),
                 cpu_model=cpu_model(),
                 single_core=dict(value=n / t_one, unit="atom-steps/s", cores=1,
                                  sample="one force evaluation (S-skip) of the full workload, %.1f s" % t_one),
@@ -590,7 +592,7 @@ def main():
     ap_.add_argument("--steps", type=int, default=1000)
     ap_.add_argument("--warmup", type=int, default=200)
     ap_.add_argument("--pure-steps", type=int, default=20)
-    ap_.add_argument("--cpu-steps", type=int, default=2)
+    ap_.add_argument("--cpu-steps", type=int, default=16)
     ap_.add_argument("--no-cpu", action="store_true")
     ap_.add_argument("--drift-steps", type=int, default=1000,
                      help="the NVE drift leg: steps fitted after --equil steps of equilibration (independent of "
