@@ -476,6 +476,7 @@ struct ForceArgs {
     const int32_t *csp_t, *rev_start, *rev_code;
     double *E_atom, *F, *partials;  // partials: [16][pstride] per-tile sums, column-major
     int ntiles;                     // tiles of kBlock / SUB atoms (force_blocks(n))
+    int split_grid, half_grid;      // two grid halves (tiles with full-list atoms first), each half_grid blocks
     int pstride;
     int *flags;
     const double *sbox;  // per-structure boxes of a batch (null: L)
@@ -547,13 +548,23 @@ __global__ __launch_bounds__(kBlock, (FULL && sizeof(TF) == 4) ? 4 : 1) void k_f
     // Block b runs on XCD b % 8. Each XCD takes chunks of kForceChunk consecutive tiles (kBlock / SUB
     // atoms each), the chunks dealt round-robin over the XCDs: a chunk's atoms share their neighbours in
     // that XCD's L2, while the few contiguous index ranges of atoms near S still spread over every XCD.
-    // The grid is a multiple of 8 kForceChunk; blocks past the last tile only clear cells.
-    const int xcd = blockIdx.x & 7, kth = blockIdx.x >> 3;
+    // A grid half is a multiple of 8 kForceChunk; blocks past the last tile only clear cells.
+    // With the EAM-only gather (short_mode 1) the grid has two halves over the same tiles: a tile with an
+    // atom on the full-list path is taken by the first half, which is dispatched first, so that those few
+    // long tiles run alongside the many short ones instead of after them; the others by the second half.
+    const int half = a.split_grid && (int)blockIdx.x >= a.half_grid ? 1 : 0;
+    const int bb = (int)blockIdx.x - half * a.half_grid;
+    const int xcd = bb & 7, kth = bb >> 3;
     const int blk = ((kth / kForceChunk) * 8 + xcd) * kForceChunk + kth % kForceChunk;
     if (blk >= a.ntiles) return;
     const int t = blk * blockDim.x + threadIdx.x;
     const int i = t / SUB, sub = t - i * SUB;  // SUB lanes per atom, slots sub, sub + SUB, ...
     const int n = a.n;
+    if (a.split_grid) {
+        // (the negation of the EAM-only test below)
+        const bool full = i < n && (a.act[i] || (a.ind_mlp && a.cmark[i] == a.cgen));
+        if ((__syncthreads_or(full) != 0) != (half == 0)) return;  // (the same answer on every thread)
+    }
     double F0 = 0, F1 = 0, F2 = 0, Ei = 0;
     double v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     const bool gl = a.switching && a.grad_lambda;
@@ -869,7 +880,9 @@ void launch_force(ap_ctx *c, int n, const double *box, const EvalFlags &f, doubl
     if (!sbox && f.switching && f.grad_lambda && c->sw.indicator == AP_IND_MLP && csp_marked) a.short_mode = 1;
     if (!sbox && !f.switching && (!f.ace_forces || f.lam_const == 1.0)) a.short_mode = uniform_lambda ? 2 : 3;
     a.ntiles = force_blocks(n);
-    const int nb = (a.ntiles + 8 * kForceChunk - 1) / (8 * kForceChunk) * (8 * kForceChunk);
+    a.half_grid = (a.ntiles + 8 * kForceChunk - 1) / (8 * kForceChunk) * (8 * kForceChunk);
+    a.split_grid = a.short_mode == 1 ? 1 : 0;
+    const int nb = a.split_grid ? 2 * a.half_grid : a.half_grid;
     if (a.short_mode == 2)
         k_force<double, kForceLanes, false><<<nb, kBlock, 0, c->stream>>>(a);
     else if (f.force_mix && a.fp32)
