@@ -549,9 +549,10 @@ __global__ __launch_bounds__(kBlock, (FULL && sizeof(TF) == 4) ? 4 : 1) void k_f
     // atoms each), the chunks dealt round-robin over the XCDs: a chunk's atoms share their neighbours in
     // that XCD's L2, while the few contiguous index ranges of atoms near S still spread over every XCD.
     // A grid half is a multiple of 8 kForceChunk; blocks past the last tile only clear cells.
-    // With the EAM-only gather (short_mode 1) the grid has two halves over the same tiles: a tile with an
-    // atom on the full-list path is taken by the first half, which is dispatched first, so that those few
-    // long tiles run alongside the many short ones instead of after them; the others by the second half.
+    // With the EAM-only gather (short_mode 1, up to 2^18 atoms) the grid has two halves over the same tiles:
+    // a tile with an atom on the full-list path is taken by the first half, which is dispatched first, so
+    // that those few long tiles run alongside the many short ones instead of after them; the others by the
+    // second half.
     const int half = a.split_grid && (int)blockIdx.x >= a.half_grid ? 1 : 0;
     const int bb = (int)blockIdx.x - half * a.half_grid;
     const int xcd = bb & 7, kth = bb >> 3;
@@ -881,7 +882,9 @@ void launch_force(ap_ctx *c, int n, const double *box, const EvalFlags &f, doubl
     if (!sbox && !f.switching && (!f.ace_forces || f.lam_const == 1.0)) a.short_mode = uniform_lambda ? 2 : 3;
     a.ntiles = force_blocks(n);
     a.half_grid = (a.ntiles + 8 * kForceChunk - 1) / (8 * kForceChunk) * (8 * kForceChunk);
-    a.split_grid = a.short_mode == 1 ? 1 : 0;
+    // (above 2^18 atoms the first half's tens of thousands of empty blocks cost more than the overlap gains:
+    // force pass 0.70 -> 0.76 ms at 2M atoms, 0.36 -> 0.37 ms at 1M)
+    a.split_grid = a.short_mode == 1 && n <= kCountedCompactMax ? 1 : 0;
     const int nb = a.split_grid ? 2 * a.half_grid : a.half_grid;
     if (a.short_mode == 2)
         k_force<double, kForceLanes, false><<<nb, kBlock, 0, c->stream>>>(a);
