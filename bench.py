@@ -43,9 +43,9 @@ MEASURED_TRAFFIC = {
     "ace_energy": (10.84e6, "ace.hip", "3c4ab83d687155fc"),
     "ace_basis": (10.14e6, "ace.hip", "3c4ab83d687155fc"),
     "ace_pairforce": (19.84e6, "ace.hip", "3c4ab83d687155fc"),
-    "force": (71.79e6, "forces.hip", "90729b8d2afc650a"),
-    "dens_desc": (83.98e6, "forces.hip", "90729b8d2afc650a"),
-    "W": (7.55e6, "forces.hip", "90729b8d2afc650a"),
+    "force": (71.74e6, "forces.hip", "3a2f3edd2bbe5615"),
+    "dens_desc": (84.15e6, "forces.hip", "3a2f3edd2bbe5615"),
+    "W": (7.55e6, "forces.hip", "3a2f3edd2bbe5615"),
 }
 
 
