@@ -335,36 +335,40 @@ __global__ __launch_bounds__(kBlock, (sizeof(T) == 4 && NMAX == 12) ? 6 : 1) voi
 
 // Per S atom, from its basis A: orders 1-3 with the embedding, the site energy, and the adjoint
 // G = dE/dA (written over A in the adjoint buffer).
-// sum_{q in [e0, e1)} kv[q] (row_q . At_q) for the coupling adjoints: code kc[q] = (row offset) | (At row) << 12,
-// both in units of four elements; row_q starts at rows + 4 (code & 4095) + roff. Two couplings per iteration,
-// so that their row loads are in flight together; the sum still runs in q order (four per iteration take the
-// kernel past 128 VGPRs, to three workgroups per CU: 245 -> 324 us per mixed step).
+// sum_{q in [e0, e1)} kv[q] (row_q . At_q) for the coupling adjoints: code kc[q] = (byte offset of the row of
+// At) | (byte offset of the matrix in rows) << 16, both multiples of 16 (the host writes them for the tables'
+// precision): an At row address is one mask, a matrix row one add of the upper half; row_q starts roff elements
+// into its matrix. The rows are read as 16-byte vectors. Two couplings per iteration, so that their row loads
+// are in flight together; the sum still runs in q and k order (four per iteration take the kernel past 128
+// VGPRs, to three workgroups per CU: 245 -> 324 us per mixed step).
+template <typename T, int NMAX>
+__device__ __forceinline__ T row_dot(const char *rb, const char *ab, unsigned code) {
+    const T *r = reinterpret_cast<const T *>(rb + (code >> 16)), *at = reinterpret_cast<const T *>(ab + (code & 0xffffu));
+    T s = T(0);
+#pragma unroll
+    for (int k = 0; k < NMAX; k += 4) {
+        T r4[4], a4[4];
+        ld4(r + k, r4);
+        ld4(at + k, a4);
+#pragma unroll
+        for (int u = 0; u < 4; u++) s += r4[u] * a4[u];
+    }
+    return s;
+}
 template <typename T, int NMAX>
 __device__ __forceinline__ T coupling_sum(const int *kc, const T *kv, const T *rows, int roff, const T *At, int e0,
                                           int e1) {
+    static_assert(NMAX % 4 == 0, "rows of 16-byte vectors");
+    const char *rb = reinterpret_cast<const char *>(rows + roff), *ab = reinterpret_cast<const char *>(At);
     T acc = T(0);
     int q = e0;
     for (; q + 1 < e1; q += 2) {
-        const int c0 = kc[q], c1 = kc[q + 1];
-        const T *r0 = rows + 4 * (c0 & 4095) + roff, *r1 = rows + 4 * (c1 & 4095) + roff;
-        const T *a0 = At + 4 * (c0 >> 12), *a1 = At + 4 * (c1 >> 12);
-        T s0 = T(0), s1 = T(0);
-#pragma unroll
-        for (int k = 0; k < NMAX; k++) {
-            s0 += r0[k] * a0[k];
-            s1 += r1[k] * a1[k];
-        }
+        const T s0 = row_dot<T, NMAX>(rb, ab, (unsigned)kc[q]);
+        const T s1 = row_dot<T, NMAX>(rb, ab, (unsigned)kc[q + 1]);
         acc += kv[q] * s0;
         acc += kv[q + 1] * s1;
     }
-    if (q < e1) {
-        const int c0 = kc[q];
-        const T *r0 = rows + 4 * (c0 & 4095) + roff, *a0 = At + 4 * (c0 >> 12);
-        T s0 = T(0);
-#pragma unroll
-        for (int k = 0; k < NMAX; k++) s0 += r0[k] * a0[k];
-        acc += kv[q] * s0;
-    }
+    if (q < e1) acc += kv[q] * row_dot<T, NMAX>(rb, ab, (unsigned)kc[q]);
     return acc;
 }
 
@@ -646,7 +650,7 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
             auto adj1 = [&](T scale) {
                 for (int w = tid; w < NMAX * n1m; w += kBlock) {
                     const int i1 = w / NMAX, q1 = w - i1 * NMAX;
-                    // codes: (Q_M offset) | (l2 m2 row of At) << 12, in units of four
+                    // codes: (l2 m2 row of At) | (Q_M offset) << 16, in bytes
                     const T acc = coupling_sum<T, NMAX>(B.kc, B.kv, B.Q, q1 * NMAX, sAt, bk[18 + i1] - k0,
                                                         bk[18 + i1 + 1] - k0);
                     sG[q1 * NLM + b1 + i1 - l1] += scale * acc;
@@ -670,7 +674,7 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
             // dE/dA[n2][l2 m2] = sum kappa sum_n1 Q_M[n1][n2] A[n1][l1 m1]
             for (int w = tid; w < NMAX * n2m; w += kBlock) {
                 const int i2 = w / NMAX, q2 = w - i2 * NMAX;
-                // codes: (Q_M offset) | (l1 m1 row of At) << 12, in units of four; rows of Q_M transposed
+                // codes: (l1 m1 row of At) | (Q_M offset) << 16, in bytes; rows of Q_M transposed
                 const T acc = coupling_sum<T, NMAX>(B.kc, B.kv, B.P, q2 * NMAX, sAt, bk[32 + i2] - k0,
                                                     bk[32 + i2 + 1] - k0);
                 sG[q2 * NLM + b2 + i2 - l2] += acc;
@@ -1438,6 +1442,9 @@ int ace_setup(ap_ctx *c, const ap_ace_params *p) {
     // keep only blocks with coefficients; build coupling tables in three orderings
     std::vector<int> hblk;
     std::vector<int> kidx;
+    const int esz = p->precision == AP_FP32 ? 4 : 8;  // element size of the tables' precision
+    if (N % 4 != 0 || (2 * Lm + 1) * N * N * esz >= (1 << 16))
+        return set_error(c, AP_E_ARG, "n_max must be a multiple of 4 and at most 12");
     std::vector<double> c30((size_t)(Lm + 1) * N * N * N, 0.0), kap0(Lm + 1, 0.0);
     bool fold0 = true;
     std::vector<double> kval, c3u;
@@ -1480,11 +1487,13 @@ int ace_setup(ap_ctx *c, const ap_ace_params *p) {
                     const int kv = which == 0 ? e.M : (which == 1 ? e.m1 : e.m2);
                     if (kv != key) continue;
                     // LDS offsets the kernel uses directly: by M, the column l1 m1 of A and the row
-                    // l2 m2 of its transpose; by m1 (m2), the matrix Q_M and the row l2 m2 (l1 m1)
+                    // l2 m2 of its transpose (the row in units of four elements); by m1 (m2), the byte offsets
+                    // of the row l2 m2 (l1 m1) of the transpose and, in the upper half, of the matrix Q_M,
+                    // multiples of 16 below 2^16 (n_max is a multiple of 4 and at most 12)
                     const int c1 = B.l1 * B.l1 + B.l1 + e.m1, c2 = B.l2 * B.l2 + B.l2 + e.m2;
-                    // (offsets of rows and matrices in units of four elements; n_max is a multiple of 4)
-                    const int qm = (e.M + B.L) * N * N / 4, r1 = c1 * N / 4, r2 = c2 * N / 4;
-                    kidx.push_back(which == 0 ? c1 | (r2 << 8) : (which == 1 ? qm | (r2 << 12) : qm | (r1 << 12)));
+                    const int r2 = c2 * N / 4;
+                    const int qmb = (e.M + B.L) * N * N * esz, r1b = c1 * N * esz, r2b = c2 * N * esz;
+                    kidx.push_back(which == 0 ? c1 | (r2 << 8) : (which == 1 ? r2b | (qmb << 16) : r1b | (qmb << 16)));
                     kval.push_back(e.v);
                 }
             }
