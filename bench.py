@@ -40,9 +40,9 @@ FP64_PEAK_TFLOPS = 78.6
 # same counters read for a 1 GiB device copy (fetch x2.0, write x1.0), with a digest of the kernel's source
 # file and the shared header at the time: a kernel whose source has changed reports null until re-measured.
 MEASURED_TRAFFIC = {
-    "ace_energy": (10.84e6, "ace.hip", "3c4ab83d687155fc"),
-    "ace_basis": (10.14e6, "ace.hip", "3c4ab83d687155fc"),
-    "ace_pairforce": (19.84e6, "ace.hip", "3c4ab83d687155fc"),
+    "ace_energy": (10.80e6, "ace.hip", "6090388ef879b4a4"),
+    "ace_basis": (10.14e6, "ace.hip", "6090388ef879b4a4"),
+    "ace_pairforce": (19.84e6, "ace.hip", "6090388ef879b4a4"),
     "force": (71.74e6, "forces.hip", "3a2f3edd2bbe5615"),
     "dens_desc": (84.15e6, "forces.hip", "3a2f3edd2bbe5615"),
     "W": (7.55e6, "forces.hip", "3a2f3edd2bbe5615"),
