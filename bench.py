@@ -38,7 +38,8 @@ FP64_PEAK_TFLOPS = 78.6
 
 # HBM bytes per launch from the FETCH_SIZE and WRITE_SIZE counter passes on this workload, scaled by what the
 # same counters read for a 1 GiB device copy (fetch x2.0, write x1.0), with a digest of the kernel's source
-# file and the shared header at the time: a kernel whose source has changed reports null until re-measured.
+# file, the list build (its slot order decides how the gathers fall on cache lines) and the shared header at
+# the time: a kernel whose sources have changed reports null until re-measured.
 MEASURED_TRAFFIC = {
     "ace_energy": (10.80e6, "ace.hip", "6090388ef879b4a4"),
     "ace_basis": (10.14e6, "ace.hip", "6090388ef879b4a4"),
@@ -56,7 +57,7 @@ def measured_traffic(kernel):
     b, src, digest = MEASURED_TRAFFIC[kernel]
     root = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2512_07693_amd", "csrc")
     h = hashlib.sha256()
-    for f in (src, "ap_internal.h"):
+    for f in (src, "geometry.hip", "ap_internal.h"):
         with open(os.path.join(root, f), "rb") as fh:
             h.update(fh.read())
     return b if h.hexdigest()[:16] == digest else None

@@ -149,9 +149,10 @@ __global__ void k_cell_sort(int ncell, const int *start, const int *cnt, int *at
 
 // One pass over the 27 cells per atom, SUB lanes per atom: in each round the SUB lanes test SUB
 // consecutive candidates of a column of cells (the three cells of a (dx, dy) column are consecutive in
-// the cell order), and a ballot gives every hit its rank among the group's hits, so the slots come out in
-// the order of a sequential scan (columns in a fixed order, cells by z, atoms of a cell by index). The neighbours inside r_short are written from the front of the slot array, those between
-// r_short and r_list from its back; the back part is then moved down behind the front part (a forward
+// the cell order), and a ballot gives every hit its rank among the group's hits, so the slots fill in the
+// order of a sequential scan (columns in a fixed order, cells by z, atoms of a cell by index). The
+// neighbours inside r_short are written from the front of the slot array, those between r_short and
+// r_list from its back; the back part is then moved down behind the front part (a forward
 // copy: it only moves to lower slots). ncount_short = the front part.
 // The test runs on the candidates' FP32 records with the periodic image of the cell (a shift of the
 // atom's position by a box length where the stencil wraps): a squared distance below r^2 - delta is
@@ -159,9 +160,9 @@ __global__ void k_cell_sort(int ncell, const int *start, const int *cnt, int *at
 // in between is decided in FP64 from the positions with the minimum-image difference, the same test as
 // the oracle's, so the sets are exact. A dimension with a single cell takes the FP32 minimum image per
 // candidate instead of the cell's (WRAP).
-// STAGE: the workgroup's lists are assembled in LDS ([max_nbr][kBlock / SUB] ints, dynamic shared memory)
-// and written out row by row, each row of its atoms one contiguous run, instead of as scattered 4-byte
-// stores into the slot-major array.
+// STAGE: the workgroup's lists are assembled in LDS ([max_nbr][kBlock / SUB] ints, dynamic shared memory),
+// and each of the two parts goes out to the slot-major array in ascending atom index. Without STAGE (more
+// than 256 slots per atom) the lists stay in scan order.
 struct Thresh {
     float lo, hi;    // r_list^2 -/+ delta
     float slo, shi;  // r_short^2 -/+ delta
@@ -179,7 +180,6 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(const double *__restrict__
     static_assert(SUB > 0 && 64 % SUB == 0, "lane groups inside a wavefront");
     constexpr int APB = kBlock / SUB;  // atoms per workgroup
     extern __shared__ int tile[];      // STAGE: slot s of local atom a at tile[s * APB + a]
-    __shared__ int scnt[APB];
     if (flags[0] == 0) return;         // the same for every workgroup
     const int lb = xcd_block(blockIdx.x, gridDim.x);
     const int t = lb * blockDim.x + threadIdx.x;
@@ -335,14 +335,56 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(const double *__restrict__
         }
     }
     if (STAGE) {
-        if (sub == 0) scnt[al] = live ? min(k, max_nbr) : 0;
         __syncthreads();
-        int kmax = 0;
-        for (int q = 0; q < APB; q++) kmax = max(kmax, scnt[q]);
-        const int i0 = lb * APB;
-        for (int e = threadIdx.x; e < kmax * APB; e += blockDim.x) {
-            const int sl = e / APB, aa = e - sl * APB;
-            if (i0 + aa < n && sl < scnt[aa]) nidx[(size_t)sl * n + i0 + aa] = tile[sl * APB + aa];
+        // each part of the list, [0, ks) and [ks, k), goes out in ascending atom index: a lane counts, for
+        // each of its entries, the entries of the same part before it in that order (the index, then the
+        // slot), and stores the entry at that rank. Atoms numbered along the lattice then have their lists
+        // in step: a slot of consecutive atoms names consecutive records, which the gathers of every pass
+        // over the lists read as a few cache lines. (An overflowed list is written as it stands.)
+        if (live && k <= max_nbr) {
+            if (n <= (1 << 24)) {
+                // one unsigned key per slot, the index above the slot (slots < 256 here), so that a single
+                // compare orders the entries and no two share a rank (the group's lanes are one wavefront,
+                // whose LDS accesses complete in program order)
+                for (int p = sub; p < k; p += SUB) tile[p * APB + al] = (int)(((unsigned)tile[p * APB + al] << 8) | p);
+                // a lane ranks four entries of a part per pass over that part
+                auto rank_part = [&](int lo, int hi) {
+                    for (int p0 = lo + sub; p0 < hi; p0 += 4 * SUB) {
+                        unsigned key[4];
+                        int r[4];
+#pragma unroll
+                        for (int j = 0; j < 4; j++) {
+                            const int p = p0 + j * SUB;
+                            key[j] = p < hi ? (unsigned)tile[p * APB + al] : 0u;
+                            r[j] = lo;
+                        }
+#pragma unroll 4
+                        for (int q = lo; q < hi; q++) {
+                            const unsigned u = (unsigned)tile[q * APB + al];
+#pragma unroll
+                            for (int j = 0; j < 4; j++) r[j] += (int)(u < key[j]);
+                        }
+#pragma unroll
+                        for (int j = 0; j < 4; j++)
+                            if (p0 + j * SUB < hi) nidx[(size_t)r[j] * n + i] = (int)(key[j] >> 8);
+                    }
+                };
+                rank_part(0, ks);
+                rank_part(ks, k);
+            } else {
+                for (int p = sub; p < k; p += SUB) {
+                    const int lo = p < ks ? 0 : ks, hi = p < ks ? ks : k;
+                    const int v = tile[p * APB + al];
+                    int r = lo;
+                    for (int q = lo; q < hi; q++) {
+                        const int u = tile[q * APB + al];
+                        r += (u < v || (u == v && q < p)) ? 1 : 0;
+                    }
+                    nidx[(size_t)r * n + i] = v;
+                }
+            }
+        } else if (live) {
+            for (int p = sub; p < max_nbr; p += SUB) nidx[(size_t)p * n + i] = tile[p * APB + al];
         }
     }
     if (!live || sub != 0) return;
