@@ -152,7 +152,9 @@ int ap_set_lambda_fixed(ap_ctx *ctx, int n, const int32_t *lam_fix);
 
 /* Neighbour sets at radius r_list (strict |u|^2 < r_list^2, minimum image, positions wrapped
  * into the box first): nbr_count device [n]; nbr_idx device [max_nbr][n] (slot-major: the k-th
- * neighbour of atom i is nbr_idx[k * n + i]); order within a set is unspecified but fixed. */
+ * neighbour of atom i is nbr_idx[k * n + i]). Slot order, with max_nbr <= 256: the neighbours inside
+ * max(r_rho, r_phi) + skin of the context's EAM come first, then the rest, each part in ascending atom
+ * index; with more slots, the order of a scan of the 27 cells. */
 int ap_nblist_build(ap_ctx *ctx, int n, const double *pos, const ap_box *box, double r_list, int max_nbr,
                     int32_t *nbr_count, int32_t *nbr_idx);
 
@@ -163,7 +165,8 @@ int ap_nblist_build(ap_ctx *ctx, int n, const double *pos, const ap_box *box, do
  * atoms and at most 131072 cells (cells of edge >= r_list, floor(L / r_list) per axis); larger inputs
  * return AP_E_ARG before anything is launched. Same arguments and output layout as ap_nblist_build
  * (pos, nbr_count, nbr_idx device; box host; strict |u|^2 < r_list^2 after wrapping); the slots of an
- * atom hold its neighbours in the order of a scan of the 27 cells. hip_stream: a hipStream_t (NULL =
+ * atom hold its neighbours in ascending atom index when max_nbr <= 256, else in the order of a scan of
+ * the 27 cells. hip_stream: a hipStream_t (NULL =
  * default stream); the call synchronises it to report overflow (AP_E_NBR_OVERFLOW). Calls that overlap
  * on one GPU (other threads or streams) share the scratch and race: serialise them. Errors are read
  * with ap_last_error(NULL). */

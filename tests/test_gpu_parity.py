@@ -114,6 +114,44 @@ def test_nblist_bit_exact_full_size(oracle, cfg, r_list, max_nbr):
     assert np.array_equal(got, want)
 
 
+def test_nblist_parts_in_index_order():
+    """The list build's slot order on the 128,000-atom workload: every atom's list holds first the neighbours
+    inside max(r_rho, r_phi) + skin, then the rest, and each of the two parts is in ascending atom index (lists of
+    up to 256 slots). Distances from the positions in FP64 (atoms with a pair within 1e-9 A^2 of the
+    part boundary are left out)."""
+    import torch
+    from paper_2512_07693_amd import ap
+    s = synth.build_system(2, with_velocities=False)
+    n, r_list, cap = len(s["pos"]), 7.0, 128
+    _say("nblist order n=%d" % n)
+    ctx = ap.Context(n, max_nbr=cap, skin=s["run"]["skin"])
+    ctx.set_potential(s["eam"], s["ace"], s["sw"])
+    cnt, idx = ctx.nblist_build(to_dev(s["pos"]), s["box"], r_list)
+    torch.cuda.synchronize()
+    cnt, idx = cnt.cpu().numpy(), idx.cpu().numpy()
+    ctx.close()
+    rs2 = (max(s["eam"]["r_rho"], s["eam"]["r_phi"]) + s["run"]["skin"]) ** 2
+    box = np.asarray(s["box"], float)
+    pos = np.asarray(s["pos"], float)
+    valid = np.arange(cap)[:, None] < cnt[None, :]
+    inner = np.zeros((cap, n), bool)
+    border = np.zeros(n, bool)
+    for q in range(cap):
+        u = pos[np.where(valid[q], idx[q], 0)] - pos
+        u -= box * np.rint(u / box)
+        d2 = (u * u).sum(axis=1)
+        inner[q] = valid[q] & (d2 < rs2)
+        border |= valid[q] & (np.abs(d2 - rs2) < 1e-9)
+    ks = inner.sum(axis=0)
+    # the inner part is a prefix of every list
+    assert np.array_equal(inner[:, ~border], (np.arange(cap)[:, None] < ks[None, :])[:, ~border])
+    # within each part the indices rise from slot to slot
+    pair = valid[1:] & (np.arange(1, cap)[:, None] != ks[None, :])
+    rise = idx[1:].astype(np.int64) > idx[:-1].astype(np.int64)
+    assert np.all(rise | ~pair)
+    assert int(border.sum()) < n // 100 and ks.min() > 0 and (cnt - ks).min() > 0
+
+
 def _near_errors(s, want, F):
     """FP32 error measures over the atoms that carry FP32 ACE terms: the precise atoms and every atom within
     the ACE cutoff of one (the rest of the cell is FP64 throughout)."""
