@@ -346,7 +346,8 @@ __global__ __launch_bounds__(kBlock) void k_nbr_build(const double *__restrict__
                 // one unsigned key per slot, the index above the slot (slots < 256 here), so that a single
                 // compare orders the entries and no two share a rank (the group's lanes are one wavefront,
                 // whose LDS accesses complete in program order)
-                for (int p = sub; p < k; p += SUB) tile[p * APB + al] = (int)(((unsigned)tile[p * APB + al] << 8) | p);
+                for (int p = sub; p < k; p += SUB)
+                    tile[p * APB + al] = (int)(((unsigned)tile[p * APB + al] << 8) | p);
                 // a lane ranks four entries of a part per pass over that part
                 auto rank_part = [&](int lo, int hi) {
                     for (int p0 = lo + sub; p0 < hi; p0 += 4 * SUB) {
@@ -436,9 +437,10 @@ static int make_geometry(ap_ctx *c, const double *box, double r_list, Geometry &
 
 // The FP32 test's margins. Each coordinate of a record is within half an FP32 ulp of L of its FP64 value,
 // the shifted atom position (below 2 L) within one ulp of L, and the difference and, for a single-cell
-// dimension, its wrap by the rounded box length add at most another ulp of L: e <= 3 ulp(L) per component. The squared distance then errs by at most 2 e (|ux| + |uy| + |uz|) + 3 e^2
-// <= 2 sqrt(3) r e + 3 e^2, plus the rounding of the three products and two sums (<= 3 ulp(r^2) with FMA
-// contraction); delta is twice that bound, and the FP32 thresholds are rounded outward.
+// dimension, its wrap by the rounded box length add at most another ulp of L: e <= 3 ulp(L) per component.
+// The squared distance then errs by at most 2 e (|ux| + |uy| + |uz|) + 3 e^2 <= 2 sqrt(3) r e + 3 e^2, plus
+// the rounding of the three products and two sums (<= 3 ulp(r^2) with FMA contraction); delta is twice that
+// bound, and the FP32 thresholds are rounded outward.
 static float ulp32(double v) { return (float)std::ldexp(1.0, std::ilogb(v) - 23); }
 static Thresh list_thresholds(const Geometry &g, double r_list, double r_short) {
     const double Lm = std::max(g.L[0], std::max(g.L[1], g.L[2]));
