@@ -168,25 +168,49 @@ __device__ __forceinline__ void ld4(const T *p, T *o) {
 // Work plan of the energy kernel. The per-atom time is a chain of dependent block steps, about as long
 // with one workgroup on a CU as with four (0.20 against 0.23 ms at n_max 12, l_max 6). So the atoms
 // that fill whole rounds of the resident workgroups (slots) are taken whole, and the remaining R atoms
-// of a last, partial round are split into P = min(kMaxParts, slots / R) parts of their coupling blocks,
-// so that the P R parts fill that round: atoms s < whole are one work item each, atom whole + r is the
-// P items whole + P r + p. (P is also capped so that the extra parts' rows fit the scratch rows.)
-// Computed from the device-side S alone, the same way by the energy kernel and by the pair kernel that
-// adds the parts.
+// of a last, partial round are split into parts of their coupling blocks that fill that round: P =
+// min(kMaxParts, slots / R) parts each, and the first E = slots - P R of them one part more where P + 1
+// parts are allowed, so that every slot gets a part and most parts are the smaller ones. (P, and the
+// extra part, are also capped so that the parts' rows fit the scratch rows.) Items: atoms s < whole one
+// each; then the parts of the P-part atoms (the larger parts, handed out first), then those of the
+// (P + 1)-part atoms. Computed from the device-side S alone, the same way by the energy kernel and by
+// the pair kernel that adds the parts.
 constexpr int kMaxParts = 4;
-__device__ __forceinline__ void ace_plan(int S, int slots, int cap, int &whole, int &items, int &parts) {
+struct AcePlan {
+    int whole, items, R, P, E;  // split atoms: whole + r for r < R; r < E has P + 1 parts, the rest P
+};
+__device__ __forceinline__ AcePlan ace_plan(int S, int slots, int cap) {
+    AcePlan q;
     const int R = S % slots;
     int P = R > 0 ? slots / R : 1;
     if (P > kMaxParts) P = kMaxParts;
     if (P > 1 && (long long)(P - 1) * R > cap) P = 1 + cap / R;
     if (P >= 2) {
-        whole = S - R;
-        items = whole + P * R;
-        parts = P;
+        q.whole = S - R;
+        q.R = R;
+        q.P = P;
+        q.E = P + 1 <= kMaxParts && (long long)P * R <= cap ? min(R, slots - P * R) : 0;
+        q.items = q.whole + P * R + q.E;
     } else {
-        whole = S;
-        items = S;
-        parts = 1;
+        q.whole = S;
+        q.items = S;
+        q.R = 0;
+        q.P = 1;
+        q.E = 0;
+    }
+    return q;
+}
+__device__ __forceinline__ int ace_parts_of(const AcePlan &q, int r) { return r < q.E ? q.P + 1 : q.P; }
+// split item u (its index after the whole atoms) -> atom whole + r, part h
+__device__ __forceinline__ void ace_item(const AcePlan &q, int u, int &r, int &h) {
+    const int big = (q.R - q.E) * q.P;
+    if (u < big) {
+        r = q.E + u / q.P;
+        h = u - (r - q.E) * q.P;
+    } else {
+        const int v = u - big;
+        r = v / (q.P + 1);
+        h = v - r * (q.P + 1);
     }
 }
 // first coupling block of part p of P: equal shares of the blocks after the n0 leading L = 0 ones
@@ -391,9 +415,8 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
     const T *c1 = (const T *)a.c1, *bd = (const T *)a.bd, *c2 = (const T *)a.c2, *c3 = (const T *)a.c3;
     const T *kval = (const T *)a.kval;
     const int S = *a.scount;
-    int whole, items, parts;
-    ace_plan(S, a.slots, a.gstride, whole, items, parts);
-    const int R = S - whole;
+    const AcePlan pl = ace_plan(S, a.slots, a.gstride);
+    const int whole = pl.whole, items = pl.items, R = pl.R;
     // a persistent grid: workgroup b takes item b, then the next items in order from a device counter
     // (zeroed by the basis kernel): whole atoms first, then the parts. Part 0 takes orders 1-2 and its
     // share of the blocks, the other parts theirs; each item writes its own dE/dA and energy, added by
@@ -401,7 +424,9 @@ __global__ __launch_bounds__(kBlock) void k_ace_energy(AceArgs a) {
     __shared__ int sItem;
     for (int w = blockIdx.x; w < items;) {
         const bool K2 = w >= whole;
-        const int r = K2 ? (w - whole) / parts : 0, h = K2 ? (w - whole) - r * parts : 0;
+        int r = 0, h = 0;
+        if (K2) ace_item(pl, w - whole, r, h);
+        const int parts = K2 ? ace_parts_of(pl, r) : 1;
         const int s = K2 ? whole + r : w;
         const T *ain = (const T *)a.gbuf + (size_t)s * NA;
         for (int o = tid; o < NA; o += kBlock) {
@@ -713,9 +738,8 @@ __global__ __launch_bounds__(kPairThreads) void k_ace_pairforce(AceArgs a) {
     for (int s = blockIdx.x; s < S; s += gridDim.x) {
         const int i = a.slist[s];
         // G = dE/dA and the site energy from the energy kernel's parts, added in part order
-        int whole, items, parts;
-        ace_plan(S, a.slots, a.gstride, whole, items, parts);
-        const int P = s >= whole ? parts : 1, R = S - whole, r = s - whole;
+        const AcePlan pl = ace_plan(S, a.slots, a.gstride);
+        const int R = pl.R, r = s - pl.whole, P = s >= pl.whole ? ace_parts_of(pl, r) : 1;
         const T *g0 = (const T *)a.gpart + (size_t)s * NA;
         for (int o = threadIdx.x; o < NA; o += blockDim.x) {
             const int q = o / NLM, lm = o - q * NLM;
