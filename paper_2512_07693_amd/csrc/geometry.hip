@@ -771,19 +771,19 @@ int install_csp(ap_ctx *c, int n, int n_csp, const int32_t *list) {
 }
 
 // g_i = sum over the stored pairs (a, b) of |u_ia + u_ib|^2 (division-free minimum images: the pairs are
-// nearest neighbours, far from |d| = L / 2). NC > 0: the list width as a constant, so that the loop unrolls
-// and all of an atom's gathers are in flight at once (the sum keeps its order); NC = 0: n_csp at run time.
+// nearest neighbours, far from |d| = L / 2). NC, the list width (8 or 12, the widths the library accepts),
+// is a constant so that the loop unrolls and all of an atom's gathers are in flight at once (the sum keeps
+// its order).
 template <int NC>
 __global__ __launch_bounds__(kBlock) void k_csp_value(const double *__restrict__ pos, int n, double Lx, double Ly,
-                                                      double Lz, int n_csp, const int32_t *__restrict__ lt,
+                                                      double Lz, const int32_t *__restrict__ lt,
                                                       double *__restrict__ g, Rec4 *__restrict__ xg) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
     double s = 0.0;
-    const int np = NC > 0 ? NC / 2 : n_csp / 2;
 #pragma unroll
-    for (int p = 0; p < np; p++) {
+    for (int p = 0; p < NC / 2; p++) {
         const int a = lt[(size_t)(2 * p) * n + i], b = lt[(size_t)(2 * p + 1) * n + i];
         double vx = min_image_w(pos[a] - xi, Lx) + min_image_w(pos[b] - xi, Lx);
         double vy = min_image_w(pos[n + a] - yi, Ly) + min_image_w(pos[n + b] - yi, Ly);
@@ -796,13 +796,10 @@ __global__ __launch_bounds__(kBlock) void k_csp_value(const double *__restrict__
 
 void launch_csp_value(ap_ctx *c, int n, const double *box) {
     const int nb = (n + kBlock - 1) / kBlock;
-    if (c->n_csp == 8)
-        k_csp_value<8><<<nb, kBlock, 0, c->stream>>>(c->pos, n, box[0], box[1], box[2], 8, c->csp_t, c->g, c->xg);
-    else if (c->n_csp == 12)
-        k_csp_value<12><<<nb, kBlock, 0, c->stream>>>(c->pos, n, box[0], box[1], box[2], 12, c->csp_t, c->g, c->xg);
+    if (c->n_csp == 12)
+        k_csp_value<12><<<nb, kBlock, 0, c->stream>>>(c->pos, n, box[0], box[1], box[2], c->csp_t, c->g, c->xg);
     else
-        k_csp_value<0><<<nb, kBlock, 0, c->stream>>>(c->pos, n, box[0], box[1], box[2], c->n_csp, c->csp_t, c->g,
-                                                     c->xg);
+        k_csp_value<8><<<nb, kBlock, 0, c->stream>>>(c->pos, n, box[0], box[1], box[2], c->csp_t, c->g, c->xg);
 }
 
 }  // namespace ap
