@@ -189,15 +189,19 @@ def test_switching_matches_oracle(cfg1, cfg1_oracle):
     ctx.close()
 
 
-def test_csp_value_closed_forms(cfg1):
-    """The CSP value kernel, (B3), against its closed forms on a perfect bcc lattice (the 1,024-atom cell's
-    lattice, pairs detected on it): g = 0 everywhere; the centre atom moved by delta gives 16 |delta|^2 (four
-    opposite pairs, each |-2 delta|^2); one listed neighbour moved by delta gives |delta|^2 at the centre."""
+@pytest.mark.parametrize("lattice", ["bcc", "fcc"])
+def test_csp_value_closed_forms(cfg1, lattice):
+    """The CSP value kernel, (B3), against its closed forms on a perfect lattice (bcc a = 3.16 A, 8^3 cells, or
+    fcc a = 3.61 A, 6^3 cells; pairs detected on it): g = 0 everywhere; the centre atom moved by delta gives
+    4 (n_csp / 2) |delta|^2 (each opposite pair |-2 delta|^2: 16 |delta|^2 with 8 entries, 24 with 12); one
+    listed neighbour moved by delta gives |delta|^2 at the centre."""
     import synth.structures as st
-    _say("csp value closed forms")
-    lat, box = st.bcc(3.16, 8)
-    s = dict(cfg1, pos=lat, pos_ref=lat, box=box)
-    ctx, csp = make_ctx(s)
+    _say("csp value closed forms, %s" % lattice)
+    lat, box = st.bcc(3.16, 8) if lattice == "bcc" else st.fcc(3.61, 6)
+    n_csp = 8 if lattice == "bcc" else 12
+    s = dict(cfg1, pos=lat, pos_ref=lat, box=box, sw=dict(cfg1["sw"], n_csp=n_csp))
+    ctx, csp = make_ctx(s, max_nbr=160)  # (fcc: 134 neighbours at the 7 A list radius)
+    assert csp.shape[1] == n_csp
     g = ctx.switch_eval(to_dev(lat), box)["g"].cpu().numpy()
     _lt("g perfect", float(np.abs(g).max()), 1e-24)
     delta = np.array([0.031, -0.017, 0.023])
@@ -206,7 +210,8 @@ def test_csp_value_closed_forms(cfg1):
     p = lat.copy()
     p[i] += delta
     g = ctx.switch_eval(to_dev(p), box)["g"].cpu().numpy()
-    _lt("g centre", abs(g[i] - 16.0 * dd) / (16.0 * dd), 1e-12)
+    want = 2.0 * n_csp * dd
+    _lt("g centre", abs(g[i] - want) / want, 1e-12)
     j = int(csp.cpu().numpy()[i, 3])
     p = lat.copy()
     p[j] += delta
